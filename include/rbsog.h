@@ -1,0 +1,208 @@
+/*
+ * rbsog.h - C ABI of the MI355X (gfx950) random batch sum-of-Gaussians (RBSOG)
+ * electrostatics library: forces, energy and the Coulomb pressure tensor of a
+ * periodic, charge-neutral point-charge system, one evaluation per MD step.
+ *
+ * Method: Jiang, Liang, Zhou, "Random batch sum-of-Gaussians method for
+ * molecular dynamics simulation of particle systems in the NPT ensemble",
+ * arXiv:2602.23582.  One step is Algorithm 1, steps 2-6:
+ *   rbsog_sample_modes  - steps 2-3: Metropolis-Hastings sampling of P Fourier
+ *                         modes from the radial proposal (App. D, eq.
+ *                         samplingP) and their measure recalibration to the
+ *                         non-radial target (Sec. 3.2, eq. samplingPnr);
+ *   rbsog_force_virial  - steps 4-6: short-range SOG force, virial and energy
+ *                         by cell lists (eqs. force_SOG, P_short, U_short),
+ *                         structure factors of the distinct modes (eq. rho_k),
+ *                         random-batch long-range force (eq. f_approx) and the
+ *                         long-range estimators (eqs. P_approx_r, P_approx_nr);
+ *   rbsog_pressure      - step 6: the total Coulomb pressure tensor
+ *                         P^N + P^{F,r*} + P^{F,nr*}.
+ *
+ * Conventions
+ *  - Orthorhombic cells h = diag(Lx, Ly, Lz) (Sec. 2.1 with a diagonal h).
+ *  - Units: lengths in Angstrom, charges in e; every energy, force and
+ *    pressure is multiplied by params.coulomb_k (1.0 = Gaussian units as in
+ *    the paper).  Tinfoil boundary conditions (Theorem 1).
+ *  - Positions may lie anywhere; they are wrapped into the cell internally.
+ *  - Arrays named host_* are host memory.  Position and force arrays may be
+ *    host or device memory (detected per call); device arrays give the fast
+ *    path.  The caller owns every array passed in or out; the context owns
+ *    its device buffers, which it allocates in rbsog_setup and frees in
+ *    rbsog_destroy.
+ *  - Every call returns RBSOG_OK (0) or a negative error code; on error the
+ *    outputs are undefined and rbsog_last_error() describes the failure.
+ *  - A context is not thread-safe; contexts are independent of each other.
+ *  - Order per step: rbsog_sample_modes -> rbsog_force_virial -> rbsog_pressure.
+ *    Work is queued on the stream given to rbsog_setup; calls that return host
+ *    values synchronise that stream.
+ */
+#ifndef RBSOG_H
+#define RBSOG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBSOG_OK 0
+#define RBSOG_EINVAL (-1)   /* null pointer, bad size or count, NaN/Inf input       */
+#define RBSOG_ENEUTRAL (-2) /* |sum q| > 1e-10 sum |q| (charge neutrality, Sec. 2.2) */
+#define RBSOG_EBOX (-3)     /* non-positive box or rc > min(L)/2                     */
+#define RBSOG_ENOMEM (-4)   /* device or host allocation failed                      */
+#define RBSOG_EDEVICE (-5)  /* a HIP call failed (its message is kept)               */
+#define RBSOG_ESTATE (-6)   /* call out of order                                     */
+#define RBSOG_EAGAIN (-7)   /* batch admission refused (memory budget or slots)      */
+
+#define RBSOG_PREC_FP64 0  /* every kernel in double precision                     */
+#define RBSOG_PREC_FP32C 1 /* FP32 arithmetic, FP64 partial sums and reductions     */
+
+#define RBSOG_RECAL_PRINTED 0  /* recalibration chain as printed in Sec. 3.2      */
+#define RBSOG_RECAL_EXCHANGE 1 /* swap of the two chain states on acceptance      */
+
+#define RBSOG_MAX_M 64
+
+typedef struct rbsog_ctx rbsog_ctx;
+
+/*
+ * Splitting and sampling parameters (Algorithm 1, "Require").
+ *  b, sigma, omega  SOG base b = b~ > 1, width sigma = sigma~ > 0 and the
+ *                   narrowest-Gaussian factor omega = omega~ (Sec. 2.2 and
+ *                   3.1; Theorem 2).  omega <= 0 asks for the C0 root of the
+ *                   1/r^3 split at rc (eq. continuity).
+ *  M                Gaussians kept, M = M~ (Theorem 2), 1..RBSOG_MAX_M.
+ *  rc               short-range cutoff, 0 < rc <= min(L)/2.
+ *  P                samples per chain (Sec. 3.2: P^r = P^nr = P), 1..65536.
+ *  seed, system_id  key and stream of the counter-based generator; one step is
+ *                   a pure function of (seed, system_id, step, box, positions).
+ *                   system_id and step must be < 2^32.
+ *  coulomb_k        prefactor applied to every energy, force and pressure.
+ *  precision        RBSOG_PREC_FP64 or RBSOG_PREC_FP32C.
+ *  recalibration    RBSOG_RECAL_PRINTED or RBSOG_RECAL_EXCHANGE.
+ */
+typedef struct rbsog_params {
+    double b;
+    double sigma;
+    double omega;
+    int32_t M;
+    double rc;
+    int32_t P;
+    uint64_t seed;
+    uint64_t system_id;
+    double coulomb_k;
+    int32_t precision;
+    int32_t recalibration;
+    int32_t reserved[6];
+} rbsog_params;
+
+/*
+ * Fill *p with Table 1, row 2 (b~ = 1.62976708826776469, sigma~ =
+ * 3.270345668108471, omega~ = 1.007806979343806 at r_c = 9 A; the row the
+ * paper uses in all runs) rescaled to the cutoff rc by sigma = sigma9 * rc / 9
+ * (the split is scale covariant), M = 10 (the pressure column's M~), P = 100,
+ * seed 0, system 0, coulomb_k 1, FP32C, printed recalibration.
+ * Returns RBSOG_EINVAL if p is NULL or rc <= 0.
+ */
+int rbsog_params_init(rbsog_params *p, double rc);
+
+/*
+ * Create a context for one system of n point charges.
+ *  host_q[n]    charges (copied; must sum to zero, Sec. 2.2).
+ *  host_box[3]  initial box edges (validated against rc).
+ *  hip_stream   hipStream_t on which all work of this context is queued
+ *               (NULL = the null stream).
+ *  out          receives the context.
+ * Allocates the context's device buffers (about 120 bytes per atom in FP32C,
+ * 200 in FP64, plus per-cell and per-mode arrays).
+ */
+int rbsog_setup(const rbsog_params *params, int64_t n, const double *host_q,
+                const double host_box[3], void *hip_stream, rbsog_ctx **out);
+
+/*
+ * Algorithm 1 steps 2-3 for this step and box: computes S^r and S^nr (eqs. Sr,
+ * Snr; Poisson forms of Prop. 1 where they converge faster) on the host, then
+ * runs both Metropolis-Hastings chains on the device (one workgroup) and
+ * builds the set of distinct modes with their multiplicities.
+ *  step             step index (< 2^32), part of the generator counter.
+ *  host_box[3]      box of this step.
+ *  host_m_r[3P], host_m_nr[3P]  optional (NULL): the sampled integer modes of
+ *                   both chains, row per sample (forces a stream sync).
+ *  host_S[2]        optional (NULL): S^r, S^nr.
+ */
+int rbsog_sample_modes(rbsog_ctx *ctx, int64_t step, const double host_box[3],
+                       int32_t *host_m_r, int32_t *host_m_nr, double host_S[2]);
+
+/*
+ * Algorithm 1 steps 4-6 for the positions x, y, z (n each, FP64, the caller's
+ * atom order, any periodic image) in the box of the last rbsog_sample_modes:
+ * writes the total force F = F^N + F^{F*} into fx, fy, fz (n each, FP64,
+ * overwritten).  host_energy[3] (optional) receives U^N, U^{F*}, U_self
+ * (U = U^N + U^{F*} - U_self, eq. couldecomp); host_vir[6] (optional) the
+ * short-range virial sum (xx, yy, zz, xy, xz, yz), i.e. V P^N.  Requesting
+ * either synchronises the stream; with both NULL the call only queues work.
+ */
+int rbsog_force_virial(rbsog_ctx *ctx, const double *x, const double *y, const double *z,
+                       double *fx, double *fy, double *fz, double host_energy[3],
+                       double host_vir[6]);
+
+/*
+ * Coulomb pressure tensor of the last rbsog_force_virial (Algorithm 1 step 6):
+ * host_P[9] (row-major) = P^N + P^{F,r*} + P^{F,nr*}; host_parts[27]
+ * (optional) = P^N, P^{F,r*}, P^{F,nr*}, each row-major.  Synchronises.
+ */
+int rbsog_pressure(rbsog_ctx *ctx, double host_P[9], double host_parts[27]);
+
+/*
+ * Isotropic or anisotropic box rescale in FP64 on the device (NPT update of
+ * Algorithm 1 step 7 for a diagonal h): r <- mu r for the n positions (device
+ * arrays) and host_box <- mu host_box.  Fractional coordinates, hence the
+ * structure factors, are unchanged (Theorem 1).
+ */
+int rbsog_rescale(rbsog_ctx *ctx, const double host_mu[3], double *x, double *y, double *z,
+                  double host_box[3]);
+
+/* Free the context and its device buffers (NULL is a no-op). */
+int rbsog_destroy(rbsog_ctx *ctx);
+
+/* Static message for an error code. */
+const char *rbsog_strerror(int code);
+
+/* Message of the context's last failure ("" if none); valid until the next call. */
+const char *rbsog_last_error(const rbsog_ctx *ctx);
+
+/*
+ * Inspection (tests and tools).
+ *  rbsog_debug_cells: cell id of every atom (caller order) from the last
+ *    rbsog_force_virial, cell = cx + nx (cy + ny cz) with cx = (u nx) >> 32
+ *    and u the 32-bit fixed-point fractional coordinate; host_ncell[3] gets
+ *    (nx, ny, nz).  host_cell may be NULL.
+ *  rbsog_debug_modes: number of distinct modes; host_modes[3*cap] their
+ *    integer vectors, host_counts[2*cap] their multiplicities in the r- and
+ *    nr-chains, host_rho[2*cap] (after rbsog_force_virial) Re, Im of rho.
+ *    Any output may be NULL; at most cap entries are written.
+ */
+int rbsog_debug_cells(rbsog_ctx *ctx, int32_t *host_cell, int32_t host_ncell[3]);
+int rbsog_debug_modes(rbsog_ctx *ctx, int32_t cap, int32_t *host_nd, int32_t *host_modes,
+                      int32_t *host_counts, double *host_rho);
+
+/*
+ * Per-kernel device timing with HIP events on the context's stream.
+ * rbsog_set_timing(ctx, 1) starts recording every kernel launch of
+ * rbsog_sample_modes and rbsog_force_virial; rbsog_get_timing writes, for
+ * each kernel k < cap, its name into host_names[k] (up to 31 chars + NUL,
+ * 32 bytes per entry), total milliseconds into host_ms[k] and launch count
+ * into host_count[k], returning the number of kernels through *host_nk.
+ * Reading synchronises; rbsog_set_timing(ctx, 0) stops and clears.
+ */
+int rbsog_set_timing(rbsog_ctx *ctx, int on);
+int rbsog_get_timing(rbsog_ctx *ctx, int32_t cap, int32_t *host_nk, char *host_names,
+                     double *host_ms, int64_t *host_count);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int rbsog_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBSOG_H */

@@ -1,0 +1,1244 @@
+// HIP kernels of the RBSOG library for gfx950 (CDNA4, wave64).
+//
+// One force/pressure evaluation (Algorithm 1, steps 2-6) runs as
+//   k_sampler                       - both MH chains and the distinct-mode set (one workgroup, FP64)
+//   k_zero, k_fix, k_scan_*, k_fill_blocks, k_scatter, k_order
+//                                   - fixed-point fractional coordinates, cell binning, stable sort
+//   k_pair                          - short-range SOG force, virial and energy over cell lists
+//   k_sk                            - structure factors of the distinct modes (per-block partials)
+//   k_rho_reduce, k_estimators      - FP64 combine, estimator coefficients, pressure and energy
+//   k_force                         - long-range force scatter, total force in caller order
+// Every reduction has a fixed order, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "rbsog_impl.hpp"
+
+namespace rbsog {
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// ----------------------------------------------------------------------------
+// Precision forms
+// ----------------------------------------------------------------------------
+
+// FP32C: 32-bit fixed-point fractional coordinates (exact minimum image and
+// exact integer phases), FP32 arithmetic, FP64 partial sums.
+struct F32 {
+    using real = float;
+    using fix = uint32_t;
+    using sfix = int32_t;
+    struct alignas(16) Rec {
+        uint32_t x, y, z;
+        float q;
+    };
+};
+
+// FP64: 64-bit fixed point, double arithmetic throughout.
+struct F64 {
+    using real = double;
+    using fix = uint64_t;
+    using sfix = int64_t;
+    struct alignas(16) Rec {
+        uint64_t x, y, z;
+        double q;
+    };
+};
+
+// per-mode data for the force scatter: integer mode, wave vector, A = a Im rho,
+// B = a Re rho with a = (S/(P V)) c^r / |k|^2
+template <class real>
+struct alignas(16) Coef {
+    int32_t mx, my, mz, pad;
+    real kx, ky, kz, A, B;
+};
+
+__device__ inline float fix_to_real(int32_t v, float scale) { return static_cast<float>(v) * scale; }
+__device__ inline double fix_to_real(int64_t v, double scale) { return static_cast<double>(v) * scale; }
+
+template <class T>
+__device__ inline T wave_sum(T v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline int wave_max(int v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline int wave_min(int v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the sampler's draws
+// ----------------------------------------------------------------------------
+
+__device__ inline uint4 philox4x32_10(uint4 c, uint2 k)
+{
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// (0,1) uniform from the top 52 bits of a 64-bit word
+__device__ inline double unit_open(uint32_t hi, uint32_t lo)
+{
+    const uint64_t w = (static_cast<uint64_t>(hi) << 32) | lo;
+    return (static_cast<double>(w >> 12) + 0.5) * 0x1.0p-52;
+}
+
+struct SampArgs {
+    double L[3];
+    int P, M, variant;
+    uint32_t key0, key1, step, sys;
+    const SogTables *tab;
+    int32_t *mraw;     // m_r (P x 3) then m_nr (P x 3)
+    int4 *modes;       // distinct modes
+    int32_t *cnt;      // [kMaxModes] r multiplicities, then [kMaxModes] nr
+    StepResults *res;  // nd, status, acceptance counts
+};
+
+__device__ void draw_normals(const SampArgs &a, uint32_t t, uint32_t sxy, uint32_t sz, double z[3])
+{
+#pragma clang fp contract(off)
+    const uint2 key = make_uint2(a.key0, a.key1);
+    const uint4 o1 = philox4x32_10(make_uint4(t, sxy, a.step, a.sys), key);
+    const uint4 o2 = philox4x32_10(make_uint4(t, sz, a.step, a.sys), key);
+    const double u1 = unit_open(o1.x, o1.y), u2 = unit_open(o1.z, o1.w);
+    const double u3 = unit_open(o2.x, o2.y), u4 = unit_open(o2.z, o2.w);
+    const double r1 = sqrt(-2.0 * log(u1));
+    const double r2 = sqrt(-2.0 * log(u3));
+    z[0] = r1 * cos(2.0 * kPi * u2);
+    z[1] = r1 * sin(2.0 * kPi * u2);
+    z[2] = r2 * cos(2.0 * kPi * u4);
+}
+
+// App. D: m*_xi = round(h^T u) with u_xi ~ N(0, 1/(2 pi^2 s0^2)), i.e. round(sig_xi z_xi)
+__device__ void round_proposal(const SampArgs &a, const double z[3], int m[3])
+{
+#pragma clang fp contract(off)
+    const double s0 = a.tab->s[0];
+    for (int d = 0; d < 3; ++d) {
+        const double sig = a.L[d] / (sqrt(2.0) * kPi * s0);
+        double v = round(sig * z[d]);
+        v = fmin(fmax(v, -1073741824.0), 1073741824.0);
+        m[d] = static_cast<int>(v);
+    }
+}
+
+// importance weight w = P^r(m)/q(m) (unnormalised, 0 at m = 0) and the
+// recalibration ratio R = P^nr(m)/P^r(m) (unnormalised)
+__device__ void mode_weights(const SampArgs &a, const int m[3], double *w, double *R)
+{
+#pragma clang fp contract(off)
+    if (m[0] == 0 && m[1] == 0 && m[2] == 0) {
+        *w = 0.0;
+        *R = 0.0;
+        return;
+    }
+    double k2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double k = 2.0 * kPi * m[d] / a.L[d];
+        k2 += k * k;
+    }
+    const SogTables *t = a.tab;
+    double a5 = 0.0, a7 = 0.0;
+    for (int l = 0; l < a.M; ++l) {
+        const double e = exp(-t->s[l] * t->s[l] * k2 / 4.0);
+        a5 += t->wt[l] * t->s5[l] * e;
+        a7 += t->wt[l] * t->s7[l] * e;
+    }
+    const double target = k2 * a5;
+    double q = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        const double sig = a.L[d] / (sqrt(2.0) * kPi * t->s[0]);
+        const double c = 1.0 / (sqrt(2.0) * sig);
+        double qd;
+        if (m[d] == 0) {
+            qd = erf(0.5 * c);
+        } else {
+            const double am = fabs(static_cast<double>(m[d]));
+            qd = 0.5 * (erfc((am - 0.5) * c) - erfc((am + 0.5) * c));
+        }
+        q *= qd;
+    }
+    *w = target / q;
+    *R = k2 * a7 / a5;
+}
+
+// Algorithm 1 steps 2-3 for one system, one workgroup of 256 threads.
+// Slot 0 holds the chain's initial state, slot t+1 the t-th proposal.
+__global__ __launch_bounds__(256) void k_sampler(SampArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ int3 s_mode[kMaxP + 1];
+    __shared__ double s_w[kMaxP + 1], s_R[kMaxP + 1];
+    __shared__ double s_ur[kMaxP], s_unr[kMaxP];
+    __shared__ int16_t s_sr[kMaxP], s_snr[kMaxP];
+    __shared__ int16_t s_rep[kMaxP + 1], s_didx[kMaxP + 1];
+    __shared__ uint8_t s_used[kMaxP + 1];
+    __shared__ int s_cnt_r[kMaxP + 1], s_cnt_nr[kMaxP + 1];
+    __shared__ int s_init, s_nd;
+    __shared__ long long s_acc[2];
+
+    const int tid = threadIdx.x;
+    const int P = a.P;
+    if (tid == 0) s_init = 64;
+    __syncthreads();
+    // initial state: first nonzero draw of the initial-state streams (3, 4)
+    if (tid < 64) {
+        double z[3];
+        int m[3];
+        draw_normals(a, static_cast<uint32_t>(tid), 3u, 4u, z);
+        round_proposal(a, z, m);
+        const bool nz = (m[0] | m[1] | m[2]) != 0;
+        const unsigned long long ball = __ballot(nz);
+        const int first = ball ? __ffsll(ball) - 1 : 64;
+        if (tid == first) {
+            s_mode[0] = make_int3(m[0], m[1], m[2]);
+            mode_weights(a, m, &s_w[0], &s_R[0]);
+            s_init = first;
+        }
+    }
+    for (int t = tid; t < P; t += blockDim.x) {
+        double z[3];
+        int m[3];
+        draw_normals(a, static_cast<uint32_t>(t), 0u, 1u, z);
+        round_proposal(a, z, m);
+        s_mode[t + 1] = make_int3(m[0], m[1], m[2]);
+        mode_weights(a, m, &s_w[t + 1], &s_R[t + 1]);
+        const uint4 o = philox4x32_10(make_uint4(static_cast<uint32_t>(t), 2u, a.step, a.sys),
+                                      make_uint2(a.key0, a.key1));
+        s_ur[t] = unit_open(o.x, o.y);
+        s_unr[t] = unit_open(o.z, o.w);
+    }
+    for (int s = tid; s <= P; s += blockDim.x) {
+        s_used[s] = 0;
+        s_cnt_r[s] = 0;
+        s_cnt_nr[s] = 0;
+    }
+    __syncthreads();
+    if (s_init >= 64) {
+        if (tid == 0) {
+            a.res->status = -1;
+            a.res->nd = 0;
+        }
+        return;
+    }
+    // the chains are sequential: one lane walks them
+    if (tid == 0) {
+        long long acc_r = 0, acc_nr = 0;
+        int cur = 0;
+        double wcur = s_w[0];
+        if (a.variant == RBSOG_RECAL_EXCHANGE) {
+            int zs = 0;
+            double rz = 0.0;
+            for (int t = 0; t < P; ++t) {
+                if (s_ur[t] < s_w[t + 1] / wcur) {
+                    cur = t + 1;
+                    wcur = s_w[t + 1];
+                    ++acc_r;
+                }
+                if (t == 0) {
+                    zs = cur;
+                    rz = s_R[zs];
+                }
+                const double rx = s_R[cur];
+                if (s_unr[t] < rx / rz) {
+                    const int tmp = cur;
+                    cur = zs;
+                    zs = tmp;
+                    wcur = s_w[cur];
+                    rz = rx;
+                    ++acc_nr;
+                }
+                s_sr[t] = static_cast<int16_t>(cur);
+                s_snr[t] = static_cast<int16_t>(zs);
+            }
+        } else {
+            for (int t = 0; t < P; ++t) {
+                if (s_ur[t] < s_w[t + 1] / wcur) {
+                    cur = t + 1;
+                    wcur = s_w[t + 1];
+                    ++acc_r;
+                }
+                s_sr[t] = static_cast<int16_t>(cur);
+            }
+            int zs = s_sr[0];
+            double rz = s_R[zs];
+            for (int t = 0; t < P; ++t) {
+                const int prop = s_sr[t];
+                if (s_unr[t] < s_R[prop] / rz) {
+                    zs = prop;
+                    rz = s_R[prop];
+                    ++acc_nr;
+                }
+                s_snr[t] = static_cast<int16_t>(zs);
+            }
+        }
+        s_acc[0] = acc_r;
+        s_acc[1] = acc_nr;
+    }
+    __syncthreads();
+    for (int t = tid; t < P; t += blockDim.x) {
+        s_used[s_sr[t]] = 1;
+        s_used[s_snr[t]] = 1;
+    }
+    __syncthreads();
+    // representative of each used slot: the first used slot with the same mode
+    for (int s = tid; s <= P; s += blockDim.x) {
+        int rep = s;
+        if (s_used[s]) {
+            const int3 ms = s_mode[s];
+            for (int u = 0; u < s; ++u) {
+                if (s_used[u] && s_mode[u].x == ms.x && s_mode[u].y == ms.y && s_mode[u].z == ms.z) {
+                    rep = u;
+                    break;
+                }
+            }
+        }
+        s_rep[s] = static_cast<int16_t>(rep);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int nd = 0;
+        for (int s = 0; s <= P; ++s) {
+            if (s_used[s] && s_rep[s] == s) {
+                s_didx[s] = static_cast<int16_t>(nd);
+                a.modes[nd] = make_int4(s_mode[s].x, s_mode[s].y, s_mode[s].z, 0);
+                ++nd;
+            }
+        }
+        s_nd = nd;
+    }
+    __syncthreads();
+    for (int t = tid; t < P; t += blockDim.x) {
+        atomicAdd(&s_cnt_r[s_didx[s_rep[s_sr[t]]]], 1);
+        atomicAdd(&s_cnt_nr[s_didx[s_rep[s_snr[t]]]], 1);
+        const int3 mr = s_mode[s_sr[t]], mn = s_mode[s_snr[t]];
+        a.mraw[3 * t] = mr.x;
+        a.mraw[3 * t + 1] = mr.y;
+        a.mraw[3 * t + 2] = mr.z;
+        a.mraw[3 * (P + t)] = mn.x;
+        a.mraw[3 * (P + t) + 1] = mn.y;
+        a.mraw[3 * (P + t) + 2] = mn.z;
+    }
+    __syncthreads();
+    for (int d = tid; d < kMaxModes; d += blockDim.x) {
+        const bool in = d < s_nd;
+        a.cnt[d] = in ? s_cnt_r[d] : 0;
+        a.cnt[kMaxModes + d] = in ? s_cnt_nr[d] : 0;
+    }
+    if (tid == 0) {
+        a.res->nd = s_nd;
+        a.res->status = 0;
+        a.res->acc_r = s_acc[0];
+        a.res->acc_nr = s_acc[1];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Fixed point, binning and the stable cell sort
+// ----------------------------------------------------------------------------
+
+__global__ void k_zero(int32_t *a, int32_t *b, int64_t m)
+{
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i < m) {
+        a[i] = 0;
+        b[i] = 0;
+    }
+}
+
+// s = x (1/L) wrapped into [0,1) by subtracting floor(s); u = s 2^bits; the
+// 32-bit cell coordinate is (u32 n) >> 32 with u32 the top 32 bits of u.
+template <class T>
+__global__ void k_fix(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                      const double *__restrict__ z, double ilx, double ily, double ilz, int nx, int ny,
+                      int nz, typename T::fix *__restrict__ u, int32_t *__restrict__ cell,
+                      int32_t *__restrict__ count)
+{
+#pragma clang fp contract(off)
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    const double p[3] = {x[i], y[i], z[i]};
+    const double il[3] = {ilx, ily, ilz};
+    const int nc[3] = {nx, ny, nz};
+    uint32_t c[3];
+    for (int d = 0; d < 3; ++d) {
+        double s = p[d] * il[d];
+        s -= floor(s);
+        uint32_t top;
+        if constexpr (sizeof(typename T::fix) == 4) {
+            top = static_cast<uint32_t>(static_cast<uint64_t>(s * 4294967296.0) & 0xFFFFFFFFull);
+            u[d * n + i] = top;
+        } else {
+            if (s >= 1.0) s -= 1.0;
+            const uint64_t v = static_cast<uint64_t>(s * 18446744073709551616.0);
+            u[d * n + i] = v;
+            top = static_cast<uint32_t>(v >> 32);
+        }
+        c[d] = static_cast<uint32_t>((static_cast<uint64_t>(top) * static_cast<uint32_t>(nc[d])) >> 32);
+    }
+    const int32_t id = static_cast<int32_t>(c[0] + static_cast<uint32_t>(nx) * (c[1] + static_cast<uint32_t>(ny) * c[2]));
+    cell[i] = id;
+    atomicAdd(&count[id], 1);
+}
+
+// Three-pass exclusive scan of the per-cell counts (and of the per-cell number
+// of 64-atom pair blocks) over m cells; 1024 cells per block, at most 1024 blocks.
+constexpr int kScanBlock = 1024;
+
+__device__ inline void block_scan_256(int *s_a, int tid)
+{
+    // Hillis-Steele inclusive scan over 256 ints in shared memory
+    for (int o = 1; o < 256; o <<= 1) {
+        const int v = tid >= o ? s_a[tid - o] : 0;
+        __syncthreads();
+        s_a[tid] += v;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_local(const int32_t *__restrict__ count, int64_t m,
+                                                    int32_t *__restrict__ start, int32_t *__restrict__ bstart,
+                                                    int32_t *__restrict__ nblk, int32_t *__restrict__ sums)
+{
+    __shared__ int s_a[256], s_b[256];
+    const int tid = threadIdx.x;
+    const int64_t base = blockIdx.x * static_cast<int64_t>(kScanBlock) + 4 * tid;
+    int va[4], vb[4], ta = 0, tb = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = base + k;
+        const int c = i < m ? count[i] : 0;
+        va[k] = c;
+        vb[k] = (c + kPairWave - 1) / kPairWave;
+        if (i < m) nblk[i] = vb[k];
+        ta += va[k];
+        tb += vb[k];
+    }
+    s_a[tid] = ta;
+    s_b[tid] = tb;
+    __syncthreads();
+    block_scan_256(s_a, tid);
+    block_scan_256(s_b, tid);
+    int ea = s_a[tid] - ta, eb = s_b[tid] - tb;
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = base + k;
+        if (i < m) {
+            start[i] = ea;
+            bstart[i] = eb;
+        }
+        ea += va[k];
+        eb += vb[k];
+    }
+    if (tid == 255) {
+        sums[2 * blockIdx.x] = s_a[255];
+        sums[2 * blockIdx.x + 1] = s_b[255];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(int32_t *sums, int nb)
+{
+    __shared__ int s_a[256], s_b[256];
+    const int tid = threadIdx.x;
+    int va[4], vb[4], ta = 0, tb = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int i = 4 * tid + k;
+        va[k] = i < nb ? sums[2 * i] : 0;
+        vb[k] = i < nb ? sums[2 * i + 1] : 0;
+        ta += va[k];
+        tb += vb[k];
+    }
+    s_a[tid] = ta;
+    s_b[tid] = tb;
+    __syncthreads();
+    block_scan_256(s_a, tid);
+    block_scan_256(s_b, tid);
+    int ea = s_a[tid] - ta, eb = s_b[tid] - tb;
+    __syncthreads();
+    for (int k = 0; k < 4; ++k) {
+        const int i = 4 * tid + k;
+        if (i < nb) {
+            sums[2 * i] = ea;
+            sums[2 * i + 1] = eb;
+        }
+        ea += va[k];
+        eb += vb[k];
+    }
+    if (tid == 255) {
+        sums[2 * 1024] = ea;      // grand totals
+        sums[2 * 1024 + 1] = eb;
+    }
+}
+
+__global__ void k_scan_add(int32_t *__restrict__ start, int32_t *__restrict__ bstart, const int32_t *__restrict__ sums,
+                           int64_t m)
+{
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i < m) {
+        const int64_t b = i / kScanBlock;
+        start[i] += sums[2 * b];
+        bstart[i] += sums[2 * b + 1];
+    } else if (i == m) {
+        start[m] = sums[2 * 1024];
+        bstart[m] = sums[2 * 1024 + 1];
+    }
+}
+
+__global__ void k_fill_blocks(const int32_t *__restrict__ nblk, const int32_t *__restrict__ bstart, int64_t m,
+                              int2 *__restrict__ blocks)
+{
+    const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (c >= m) return;
+    const int b0 = bstart[c];
+    for (int k = 0; k < nblk[c]; ++k) blocks[b0 + k] = make_int2(static_cast<int>(c), k);
+}
+
+__global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell, const int32_t *__restrict__ start,
+                          int32_t *__restrict__ cursor, int32_t *__restrict__ perm_tmp)
+{
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell[i];
+    perm_tmp[start[c] + atomicAdd(&cursor[c], 1)] = static_cast<int32_t>(i);
+}
+
+// Within each cell, atoms keep the caller's order: the slot of atom i is the
+// cell start plus the number of atoms of its cell with a smaller index.
+template <class T>
+__global__ void k_order(int64_t n, const int32_t *__restrict__ perm_tmp, const int32_t *__restrict__ cell,
+                        const int32_t *__restrict__ start, const typename T::fix *__restrict__ u,
+                        const typename T::real *__restrict__ q, int32_t *__restrict__ perm,
+                        typename T::Rec *__restrict__ rec)
+{
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (t >= n) return;
+    const int i = perm_tmp[t];
+    const int c = cell[i];
+    const int s0 = start[c], s1 = start[c + 1];
+    int rank = 0;
+    for (int j = s0; j < s1; ++j) rank += perm_tmp[j] < i;
+    const int slot = s0 + rank;
+    perm[slot] = i;
+    typename T::Rec r;
+    r.x = u[i];
+    r.y = u[n + i];
+    r.z = u[2 * n + i];
+    r.q = q[i];
+    rec[slot] = r;
+}
+
+// ----------------------------------------------------------------------------
+// Short-range pair kernel
+// ----------------------------------------------------------------------------
+//
+// One wavefront owns up to 64 atoms of one cell (a "pair block") and walks the
+// 27 neighbouring cells (full shell: every pair is evaluated from both sides,
+// so no atomics and a fixed summation order).  Candidates are staged 64 at a
+// time in LDS and tested against r_c by every lane (phase A); each lane
+// appends the indices of its in-cutoff partners to its own ring in LDS.  Once
+// every lane holds enough entries, all lanes evaluate the same number of pairs
+// (phase B), so the expensive kernel runs on full wavefronts.
+
+struct PairArgs {
+    int64_t n;
+    int nx, ny, nz;
+    double Lx, Ly, Lz;
+    const int32_t *start;
+    const int32_t *bstart;
+    const int2 *blocks;
+    int64_t ncells;
+    const void *rec;
+    const SogTables *tab;
+    void *fsr;       // short-range force, sorted order, 3 planes of n
+    double *part;    // 8 doubles per block: vir xx yy zz xy xz yz, U, 0
+};
+
+template <class T>
+struct PairAcc {
+    using real = typename T::real;
+    real fx = 0, fy = 0, fz = 0, vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0, u = 0;
+};
+
+// The SOG short-range kernels of one pair: N~(r) = 1/r^3 - sum wt_l e_l for
+// the force and the virial (eqs. force_SOG, P_short; 2 w_l/s_l^2 = wt_l) and
+// N(r) = 1/r - sum w_l e_l for the energy (eq. U_short), e_l = exp(-r^2/s_l^2).
+template <class T>
+__device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Rec &rj, typename T::real sx,
+                                 typename T::real sy, typename T::real sz, const SogTables *__restrict__ tab, int M,
+                                 PairAcc<T> &acc)
+{
+    using real = typename T::real;
+    using sfix = typename T::sfix;
+    const real dx = fix_to_real(static_cast<sfix>(ri.x - rj.x), sx);
+    const real dy = fix_to_real(static_cast<sfix>(ri.y - rj.y), sy);
+    const real dz = fix_to_real(static_cast<sfix>(ri.z - rj.z), sz);
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    real swt = 0, sw = 0, rinv;
+    if constexpr (sizeof(real) == 4) {
+        rinv = __builtin_amdgcn_rsqf(r2);
+        for (int l = 0; l < M; ++l) {
+            const float e = __builtin_amdgcn_exp2f(r2 * tab->c32[l]);
+            swt += tab->wt32[l] * e;
+            sw += tab->w32[l] * e;
+        }
+    } else {
+        rinv = 1.0 / sqrt(r2);
+        for (int l = 0; l < M; ++l) {
+            const double e = exp(-r2 * tab->inv_s2[l]);
+            swt += tab->wt[l] * e;
+            sw += tab->w[l] * e;
+        }
+    }
+    const real qq = ri.q * rj.q;
+    const real f = qq * (rinv * rinv * rinv - swt);
+    const real fdx = f * dx, fdy = f * dy, fdz = f * dz;
+    acc.fx += fdx;
+    acc.fy += fdy;
+    acc.fz += fdz;
+    acc.vxx += fdx * dx;
+    acc.vyy += fdy * dy;
+    acc.vzz += fdz * dz;
+    acc.vxy += fdx * dy;
+    acc.vxz += fdx * dz;
+    acc.vyz += fdy * dz;
+    acc.u += qq * (rinv - sw);
+}
+
+template <class T>
+__device__ inline typename T::real r2_of(const typename T::Rec &ri, const typename T::Rec &rj, typename T::real sx,
+                                         typename T::real sy, typename T::real sz)
+{
+    using real = typename T::real;
+    using sfix = typename T::sfix;
+    const real dx = fix_to_real(static_cast<sfix>(ri.x - rj.x), sx);
+    const real dy = fix_to_real(static_cast<sfix>(ri.y - rj.y), sy);
+    const real dz = fix_to_real(static_cast<sfix>(ri.z - rj.z), sz);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+template <class T, int CAP>
+__global__ __launch_bounds__(64) void k_pair(PairArgs a)
+{
+    using real = typename T::real;
+    using Rec = typename T::Rec;
+    __shared__ Rec s_tile[64];
+    __shared__ int32_t s_ring[CAP * 64];
+
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    const int nb_total = a.bstart[a.ncells];
+    double *part = a.part + 8 * static_cast<int64_t>(b);
+    if (b >= nb_total) {
+        if (lane < 8) part[lane] = 0.0;
+        return;
+    }
+    const Rec *__restrict__ rec = static_cast<const Rec *>(a.rec);
+    const SogTables *__restrict__ tab = a.tab;
+    const int M = tab->M;
+    real sx, sy, sz, rc2;
+    if constexpr (sizeof(real) == 4) {
+        sx = static_cast<float>(a.Lx * 0x1.0p-32);
+        sy = static_cast<float>(a.Ly * 0x1.0p-32);
+        sz = static_cast<float>(a.Lz * 0x1.0p-32);
+        rc2 = tab->rc2_32;
+    } else {
+        sx = a.Lx * 0x1.0p-64;
+        sy = a.Ly * 0x1.0p-64;
+        sz = a.Lz * 0x1.0p-64;
+        rc2 = tab->rc2;
+    }
+    const int2 cb = a.blocks[b];
+    const int c = cb.x;
+    const int cs = a.start[c], ce = a.start[c + 1];
+    const int i = cs + cb.y * kPairWave + lane;
+    const bool valid = i < ce;
+    Rec ri{};
+    if (valid) ri = rec[i];
+    const int cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / (a.nx * a.ny);
+    const int ox = a.nx >= 3 ? 1 : 0, oy = a.ny >= 3 ? 1 : 0, oz = a.nz >= 3 ? 1 : 0;
+
+    double fx = 0, fy = 0, fz = 0, v[6] = {0, 0, 0, 0, 0, 0}, uu = 0;
+    int wp = 0, rp = 0;
+
+    auto drain = [&](int k_lane, int k_max) {
+        PairAcc<T> acc;
+        for (int e = 0; e < k_max; ++e) {
+            if (e < k_lane) {
+                const int j = s_ring[((rp + e) & (CAP - 1)) * 64 + lane];
+                const Rec rj = rec[j];
+                pair_eval<T>(ri, rj, sx, sy, sz, tab, M, acc);
+            }
+        }
+        rp += k_lane;
+        fx += acc.fx;
+        fy += acc.fy;
+        fz += acc.fz;
+        v[0] += acc.vxx;
+        v[1] += acc.vyy;
+        v[2] += acc.vzz;
+        v[3] += acc.vxy;
+        v[4] += acc.vxz;
+        v[5] += acc.vyz;
+        uu += acc.u;
+    };
+
+    for (int dz = -oz; dz <= oz; ++dz) {
+        const int jz = (cz + dz + a.nz) % a.nz;
+        for (int dy = -oy; dy <= oy; ++dy) {
+            const int jy = (cy + dy + a.ny) % a.ny;
+            for (int dx = -ox; dx <= ox; ++dx) {
+                const int jx = (cx + dx + a.nx) % a.nx;
+                const int jc = jx + a.nx * (jy + a.ny * jz);
+                const int js = a.start[jc], je = a.start[jc + 1];
+                for (int t0 = js; t0 < je; t0 += 64) {
+                    const int cnt = min(64, je - t0);
+                    if (lane < cnt) s_tile[lane] = rec[t0 + lane];
+                    __syncthreads();
+                    for (int s = 0; s < cnt; ++s) {
+                        const Rec rj = s_tile[s];
+                        const real r2 = r2_of<T>(ri, rj, sx, sy, sz);
+                        if (valid && r2 < rc2 && t0 + s != i) {
+                            s_ring[(wp & (CAP - 1)) * 64 + lane] = t0 + s;
+                            ++wp;
+                        }
+                    }
+                    __syncthreads();
+                    const int pend = wp - rp;
+                    const int mx = wave_max(pend);
+                    const int mn = wave_min(valid ? pend : INT_MAX);
+                    if (mx > CAP - 64) {
+                        drain(pend, mx);
+                    } else if (mn >= 32) {
+                        drain(valid ? mn : 0, mn);
+                    }
+                }
+            }
+        }
+    }
+    {
+        const int pend = wp - rp;
+        drain(pend, wave_max(pend));
+    }
+    if (valid) {
+        real *fsr = static_cast<real *>(a.fsr);
+        fsr[i] = static_cast<real>(fx);
+        fsr[a.n + i] = static_cast<real>(fy);
+        fsr[2 * a.n + i] = static_cast<real>(fz);
+    }
+    // full shell: each pair was seen from both sides
+    double out[7] = {0.5 * v[0], 0.5 * v[1], 0.5 * v[2], 0.5 * v[3], 0.5 * v[4], 0.5 * v[5], 0.5 * uu};
+    for (int k = 0; k < 7; ++k) out[k] = wave_sum(out[k]);
+    if (lane == 0) {
+        for (int k = 0; k < 7; ++k) part[k] = out[k];
+        part[7] = 0.0;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Structure factors rho_d = sum_j q_j exp(2 pi i m_d . s_j)   (eq. rho_k)
+// ----------------------------------------------------------------------------
+//
+// The phase m.u mod 2^32 of the 32-bit fixed-point fractional coordinate u is
+// exact: with u = 2^16 h + l (h, l < 2^16) it is ((m.h) << 16) + m.l, six
+// 24-bit multiply-adds.  The hardware sine and cosine take the phase in
+// revolutions.  Each workgroup owns kSkChunk atoms; its 256 threads are
+// (mode, slice) pairs, and the per-mode partial of the workgroup goes to
+// global memory in FP64.
+
+struct SkArgs {
+    int64_t n;
+    const void *rec;
+    const int4 *modes;
+    const StepResults *res;
+    double *part;  // [blocks][kMaxModes] x 2
+};
+
+struct alignas(16) SkAtom32 {
+    int hx, hy, hz;
+    float q;
+    int lx, ly, lz, pad;
+};
+
+__device__ inline void phase_sincos32(const int4 &m, const SkAtom32 &at, float &s, float &c)
+{
+    const uint32_t hi = static_cast<uint32_t>(__mul24(m.x, at.hx) + __mul24(m.y, at.hy) + __mul24(m.z, at.hz));
+    const uint32_t lo = static_cast<uint32_t>(__mul24(m.x, at.lx) + __mul24(m.y, at.ly) + __mul24(m.z, at.lz));
+    const uint32_t ph = (hi << 16) + lo;
+    const float rev = static_cast<float>(static_cast<int32_t>(ph)) * 0x1.0p-32f;
+    s = __builtin_amdgcn_sinf(rev);
+    c = __builtin_amdgcn_cosf(rev);
+}
+
+__device__ inline void phase_sincos64(const int4 &m, const F64::Rec &r, double &s, double &c)
+{
+    const uint64_t ph = static_cast<uint64_t>(static_cast<int64_t>(m.x)) * r.x +
+                        static_cast<uint64_t>(static_cast<int64_t>(m.y)) * r.y +
+                        static_cast<uint64_t>(static_cast<int64_t>(m.z)) * r.z;
+    const double rev = static_cast<double>(static_cast<int64_t>(ph)) * 0x1.0p-64;
+    sincospi(2.0 * rev, &s, &c);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_sk(SkArgs a)
+{
+    using Atom = typename std::conditional<sizeof(typename T::real) == 4, SkAtom32, typename T::Rec>::type;
+    __shared__ Atom s_at[256];
+    __shared__ double s_red[2][256];
+    const int tid = threadIdx.x;
+    const int nd = a.res->nd;
+    const int64_t a0 = blockIdx.x * static_cast<int64_t>(kSkChunk);
+    const int64_t a1 = min(a.n, a0 + kSkChunk);
+    const typename T::Rec *__restrict__ rec = static_cast<const typename T::Rec *>(a.rec);
+    const int nsl = nd <= 128 ? max(1, 256 / max(nd, 1)) : 1;
+    const int items = nd <= 128 ? nsl * nd : 256;
+    const int passes = nd <= 128 ? 1 : (nd + 255) / 256;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int d = nd <= 128 ? tid % max(nd, 1) : pass * 256 + tid;
+        const int sl = nd <= 128 ? tid / max(nd, 1) : 0;
+        const bool active = tid < items && d < nd;
+        const int4 m = active ? a.modes[d] : make_int4(0, 0, 0, 0);
+        double accr = 0.0, acci = 0.0;
+        for (int64_t c0 = a0; c0 < a1; c0 += 256) {
+            const int cnt = static_cast<int>(min(static_cast<int64_t>(256), a1 - c0));
+            if (tid < cnt) {
+                const typename T::Rec r = rec[c0 + tid];
+                if constexpr (sizeof(typename T::real) == 4) {
+                    SkAtom32 at;
+                    at.hx = static_cast<int>(r.x >> 16);
+                    at.hy = static_cast<int>(r.y >> 16);
+                    at.hz = static_cast<int>(r.z >> 16);
+                    at.lx = static_cast<int>(r.x & 0xFFFFu);
+                    at.ly = static_cast<int>(r.y & 0xFFFFu);
+                    at.lz = static_cast<int>(r.z & 0xFFFFu);
+                    at.q = r.q;
+                    at.pad = 0;
+                    s_at[tid] = at;
+                } else {
+                    s_at[tid] = r;
+                }
+            }
+            __syncthreads();
+            if (active) {
+                typename T::real sr = 0, si = 0;
+                for (int k = sl; k < cnt; k += nsl) {
+                    const Atom at = s_at[k];
+                    typename T::real sn, cs;
+                    if constexpr (sizeof(typename T::real) == 4) {
+                        phase_sincos32(m, at, sn, cs);
+                    } else {
+                        phase_sincos64(m, at, sn, cs);
+                    }
+                    sr += at.q * cs;
+                    si += at.q * sn;
+                }
+                accr += sr;
+                acci += si;
+            }
+            __syncthreads();
+        }
+        s_red[0][tid] = accr;
+        s_red[1][tid] = acci;
+        __syncthreads();
+        if (tid < 256 && sl == 0 && active) {
+            double r = 0.0, im = 0.0;
+            const int stride = nd <= 128 ? nd : 0;
+            for (int k = 0; k < nsl; ++k) {
+                r += s_red[0][tid + k * stride];
+                im += s_red[1][tid + k * stride];
+            }
+            double *p = a.part + 2 * (blockIdx.x * static_cast<int64_t>(kMaxModes) + d);
+            p[0] = r;
+            p[1] = im;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// FP64 combine: rho per mode, pair-kernel partials
+// ----------------------------------------------------------------------------
+
+__device__ inline double block_sum_256(double v, double *s_tmp)
+{
+    const int tid = threadIdx.x;
+    s_tmp[tid] = v;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (tid < o) s_tmp[tid] += s_tmp[tid + o];
+        __syncthreads();
+    }
+    const double r = s_tmp[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_rho_reduce(const double *__restrict__ part, int64_t nblk,
+                                                    const double *__restrict__ pair_part, int64_t npair,
+                                                    double *__restrict__ rho, StepResults *res)
+{
+    __shared__ double s_tmp[256];
+    const int tid = threadIdx.x;
+    const int d = blockIdx.x;
+    if (d < kMaxModes) {
+        if (d >= res->nd) return;
+        double r = 0.0, im = 0.0;
+        for (int64_t b = tid; b < nblk; b += 256) {
+            const double *p = part + 2 * (b * kMaxModes + d);
+            r += p[0];
+            im += p[1];
+        }
+        r = block_sum_256(r, s_tmp);
+        im = block_sum_256(im, s_tmp);
+        if (tid == 0) {
+            rho[2 * d] = r;
+            rho[2 * d + 1] = im;
+        }
+    } else {
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int64_t b = tid; b < npair; b += 256)
+            for (int k = 0; k < 7; ++k) acc[k] += pair_part[8 * b + k];
+        for (int k = 0; k < 7; ++k) {
+            const double s = block_sum_256(acc[k], s_tmp);
+            if (tid == 0) {
+                if (k < 6) res->vir[k] = s;
+                else res->UN = s;
+            }
+        }
+    }
+}
+
+// Estimators of Sec. 3.2 and App. B over the distinct modes d with
+// multiplicities c^r_d, c^nr_d (one workgroup):
+//   P^{F,r*}  =  S^r/(4 V^2 P) sum_d c^r_d |rho_d|^2/|k_d|^2 I            (eq. P_approx_r)
+//   P^{F,nr*} = -S^nr/(8 V^2 P) sum_d c^nr_d |rho_d|^2 k_d k_d^T/|k_d|^4  (eq. P_approx_nr)
+//   U^{F*}    =  S/(2 V P) sum_d c^r_d |rho_d|^2/|k_d|^2, S = S^r/2
+//   force coefficients a_d = (S/(P V)) c^r_d/|k_d|^2                      (eq. f_approx)
+struct EstArgs {
+    double L[3];
+    double Sr, Snr, ck, Uself;
+    int P;
+    const int4 *modes;
+    const int32_t *cnt;
+    const double *rho;
+    void *coef;
+    int fp64;
+    StepResults *res;
+};
+
+__global__ __launch_bounds__(256) void k_estimators(EstArgs a)
+{
+    __shared__ double s_tmp[256];
+    const int tid = threadIdx.x;
+    const int nd = a.res->nd;
+    const double V = a.L[0] * a.L[1] * a.L[2];
+    const double S = 0.5 * a.Sr;
+    double sr = 0.0, snr[6] = {0, 0, 0, 0, 0, 0};
+    for (int d = tid; d < nd; d += 256) {
+        const int4 m = a.modes[d];
+        const double k[3] = {2.0 * kPi * m.x / a.L[0], 2.0 * kPi * m.y / a.L[1], 2.0 * kPi * m.z / a.L[2]};
+        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        const double re = a.rho[2 * d], im = a.rho[2 * d + 1];
+        const double r2 = re * re + im * im;
+        const int cr = a.cnt[d], cnr = a.cnt[kMaxModes + d];
+        sr += cr * r2 / k2;
+        const double g = cnr * r2 / (k2 * k2);
+        snr[0] += g * k[0] * k[0];
+        snr[1] += g * k[1] * k[1];
+        snr[2] += g * k[2] * k[2];
+        snr[3] += g * k[0] * k[1];
+        snr[4] += g * k[0] * k[2];
+        snr[5] += g * k[1] * k[2];
+        const double ad = S / (a.P * V) * cr / k2;
+        if (a.fp64) {
+            Coef<double> cf;
+            cf.mx = m.x; cf.my = m.y; cf.mz = m.z; cf.pad = 0;
+            cf.kx = k[0]; cf.ky = k[1]; cf.kz = k[2];
+            cf.A = ad * im;
+            cf.B = ad * re;
+            static_cast<Coef<double> *>(a.coef)[d] = cf;
+        } else {
+            Coef<float> cf;
+            cf.mx = m.x; cf.my = m.y; cf.mz = m.z; cf.pad = 0;
+            cf.kx = static_cast<float>(k[0]);
+            cf.ky = static_cast<float>(k[1]);
+            cf.kz = static_cast<float>(k[2]);
+            cf.A = static_cast<float>(ad * im);
+            cf.B = static_cast<float>(ad * re);
+            static_cast<Coef<float> *>(a.coef)[d] = cf;
+        }
+    }
+    sr = block_sum_256(sr, s_tmp);
+    for (int k = 0; k < 6; ++k) snr[k] = block_sum_256(snr[k], s_tmp);
+    if (tid == 0) {
+        StepResults *r = a.res;
+        const double ck = a.ck;
+        const double pr = ck * a.Sr / (4.0 * V * V * a.P) * sr;
+        const double cnr = -ck * a.Snr / (8.0 * V * V * a.P);
+        const int ix[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+        for (int al = 0; al < 3; ++al)
+            for (int be = 0; be < 3; ++be) {
+                const int q = 3 * al + be;
+                r->Pr[q] = al == be ? pr : 0.0;
+                r->Pnr[q] = cnr * snr[ix[al][be]];
+                r->PN[q] = ck * r->vir[ix[al][be]] / V;
+                r->Ptot[q] = r->PN[q] + r->Pr[q] + r->Pnr[q];
+            }
+        r->UF = ck * S / (2.0 * V * a.P) * sr;
+        r->UN = ck * r->UN;
+        for (int k = 0; k < 6; ++k) r->vir[k] *= ck;
+        r->Uself = a.Uself;
+        r->Sr = a.Sr;
+        r->Snr = a.Snr;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Long-range force scatter (eq. f_approx) and the total force in caller order
+// ----------------------------------------------------------------------------
+
+struct ForceArgs {
+    int64_t n;
+    const void *rec;
+    const int32_t *perm;
+    const void *fsr;
+    const void *coef;
+    const StepResults *res;
+    double ck;
+    double *fx, *fy, *fz;
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void k_force(ForceArgs a)
+{
+    using real = typename T::real;
+    const int tid = threadIdx.x;
+    const int nd = a.res->nd;
+    const Coef<real> *__restrict__ s_cf = static_cast<const Coef<real> *>(a.coef);
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + tid;
+    if (t >= a.n) return;
+    const typename T::Rec r = static_cast<const typename T::Rec *>(a.rec)[t];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    if constexpr (sizeof(real) == 4) {
+        SkAtom32 at;
+        at.hx = static_cast<int>(r.x >> 16);
+        at.hy = static_cast<int>(r.y >> 16);
+        at.hz = static_cast<int>(r.z >> 16);
+        at.lx = static_cast<int>(r.x & 0xFFFFu);
+        at.ly = static_cast<int>(r.y & 0xFFFFu);
+        at.lz = static_cast<int>(r.z & 0xFFFFu);
+        at.q = r.q;
+        at.pad = 0;
+        for (int d0 = 0; d0 < nd; d0 += 32) {
+            float hx = 0.f, hy = 0.f, hz = 0.f;
+            const int d1 = min(nd, d0 + 32);
+            for (int d = d0; d < d1; ++d) {
+                const Coef<float> c = s_cf[d];
+                float sn, cs;
+                phase_sincos32(make_int4(c.mx, c.my, c.mz, 0), at, sn, cs);
+                const float g = c.A * cs - c.B * sn;
+                hx += g * c.kx;
+                hy += g * c.ky;
+                hz += g * c.kz;
+            }
+            gx += hx;
+            gy += hy;
+            gz += hz;
+        }
+    } else {
+        for (int d = 0; d < nd; ++d) {
+            const Coef<double> c = s_cf[d];
+            double sn, cs;
+            phase_sincos64(make_int4(c.mx, c.my, c.mz, 0), r, sn, cs);
+            const double g = c.A * cs - c.B * sn;
+            gx += g * c.kx;
+            gy += g * c.ky;
+            gz += g * c.kz;
+        }
+    }
+    const real *fsr = static_cast<const real *>(a.fsr);
+    const double q = static_cast<double>(r.q);
+    const int i = a.perm[t];
+    a.fx[i] = a.ck * (static_cast<double>(fsr[t]) - q * gx);
+    a.fy[i] = a.ck * (static_cast<double>(fsr[a.n + t]) - q * gy);
+    a.fz[i] = a.ck * (static_cast<double>(fsr[2 * a.n + t]) - q * gz);
+}
+
+__global__ void k_rescale(int64_t n, double mx, double my, double mz, double *x, double *y, double *z)
+{
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    x[i] *= mx;
+    y[i] *= my;
+    z[i] *= mz;
+}
+
+inline unsigned grid_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
+
+constexpr int kRingCap = 128;
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Launchers
+// ----------------------------------------------------------------------------
+
+hipError_t launch_sample(rbsog_ctx *c, uint32_t step)
+{
+    SampArgs a{};
+    for (int d = 0; d < 3; ++d) a.L[d] = c->L[d];
+    a.P = c->prm.P;
+    a.M = c->prm.M;
+    a.variant = c->prm.recalibration;
+    a.key0 = static_cast<uint32_t>(c->prm.seed);
+    a.key1 = static_cast<uint32_t>(c->prm.seed >> 32);
+    a.step = step;
+    a.sys = static_cast<uint32_t>(c->prm.system_id);
+    a.tab = c->d_tab;
+    a.mraw = c->d_mraw;
+    a.modes = c->d_modes;
+    a.cnt = c->d_cnt;
+    a.res = c->d_res;
+    timer_begin(c, "sampler");
+    hipLaunchKernelGGL(k_sampler, dim3(1), dim3(256), 0, c->stream, a);
+    timer_end(c, "sampler");
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t bin_and_sort_t(rbsog_ctx *c, const double *x, const double *y, const double *z)
+{
+    const int64_t n = c->n, m = c->ncells;
+    timer_begin(c, "bin");
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(m + 1, 256)), dim3(256), 0, c->stream, c->d_count, c->d_cursor, m + 1);
+    hipLaunchKernelGGL(k_fix<T>, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, x, y, z, 1.0 / c->L[0],
+                       1.0 / c->L[1], 1.0 / c->L[2], c->nc[0], c->nc[1], c->nc[2],
+                       static_cast<typename T::fix *>(c->d_u), c->d_cell, c->d_count);
+    const int nb = static_cast<int>((m + kScanBlock - 1) / kScanBlock);
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, c->stream, c->d_count, m, c->d_start, c->d_bstart,
+                       c->d_nblk, c->d_scan_tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, c->stream, c->d_scan_tmp, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(m + 1, 256)), dim3(256), 0, c->stream, c->d_start, c->d_bstart,
+                       c->d_scan_tmp, m);
+    hipLaunchKernelGGL(k_fill_blocks, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, c->d_nblk, c->d_bstart, m,
+                       c->d_blocks);
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, c->d_cell, c->d_start,
+                       c->d_cursor, c->d_perm_tmp);
+    hipLaunchKernelGGL(k_order<T>, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, c->d_perm_tmp, c->d_cell,
+                       c->d_start, static_cast<const typename T::fix *>(c->d_u),
+                       static_cast<const typename T::real *>(c->d_q), c->d_perm,
+                       static_cast<typename T::Rec *>(c->d_rec));
+    timer_end(c, "bin");
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_and_sort(rbsog_ctx *c, const double *x, const double *y, const double *z)
+{
+    return c->prm.precision == RBSOG_PREC_FP64 ? bin_and_sort_t<F64>(c, x, y, z) : bin_and_sort_t<F32>(c, x, y, z);
+}
+
+template <class T>
+static hipError_t pair_t(rbsog_ctx *c)
+{
+    PairArgs a{};
+    a.n = c->n;
+    a.nx = c->nc[0];
+    a.ny = c->nc[1];
+    a.nz = c->nc[2];
+    a.Lx = c->L[0];
+    a.Ly = c->L[1];
+    a.Lz = c->L[2];
+    a.start = c->d_start;
+    a.bstart = c->d_bstart;
+    a.blocks = c->d_blocks;
+    a.ncells = c->ncells;
+    a.rec = c->d_rec;
+    a.tab = c->d_tab;
+    a.fsr = c->d_fsr;
+    a.part = c->d_pair_part;
+    const int64_t grid = (c->n + kPairWave - 1) / kPairWave + c->ncells;
+    timer_begin(c, "pair");
+    hipLaunchKernelGGL((k_pair<T, kRingCap>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, c->stream, a);
+    timer_end(c, "pair");
+    return hipGetLastError();
+}
+
+hipError_t launch_pair(rbsog_ctx *c)
+{
+    return c->prm.precision == RBSOG_PREC_FP64 ? pair_t<F64>(c) : pair_t<F32>(c);
+}
+
+template <class T>
+static hipError_t kspace_t(rbsog_ctx *c, double *fx, double *fy, double *fz)
+{
+    SkArgs s{};
+    s.n = c->n;
+    s.rec = c->d_rec;
+    s.modes = c->d_modes;
+    s.res = c->d_res;
+    s.part = c->d_rho_part;
+    timer_begin(c, "sk");
+    hipLaunchKernelGGL(k_sk<T>, dim3(static_cast<unsigned>(c->sk_blocks)), dim3(256), 0, c->stream, s);
+    timer_end(c, "sk");
+    const int64_t npair = (c->n + kPairWave - 1) / kPairWave + c->ncells;
+    timer_begin(c, "reduce");
+    hipLaunchKernelGGL(k_rho_reduce, dim3(kMaxModes + 1), dim3(256), 0, c->stream, c->d_rho_part, c->sk_blocks,
+                       c->d_pair_part, npair, c->d_rho, c->d_res);
+    EstArgs e{};
+    for (int d = 0; d < 3; ++d) e.L[d] = c->L[d];
+    e.Sr = c->Sr;
+    e.Snr = c->Snr;
+    e.ck = c->prm.coulomb_k;
+    e.Uself = c->Uself;
+    e.P = c->prm.P;
+    e.modes = c->d_modes;
+    e.cnt = c->d_cnt;
+    e.rho = c->d_rho;
+    e.coef = c->d_coef;
+    e.fp64 = c->prm.precision == RBSOG_PREC_FP64;
+    e.res = c->d_res;
+    hipLaunchKernelGGL(k_estimators, dim3(1), dim3(256), 0, c->stream, e);
+    timer_end(c, "reduce");
+    ForceArgs f{};
+    f.n = c->n;
+    f.rec = c->d_rec;
+    f.perm = c->d_perm;
+    f.fsr = c->d_fsr;
+    f.coef = c->d_coef;
+    f.res = c->d_res;
+    f.ck = c->prm.coulomb_k;
+    f.fx = fx;
+    f.fy = fy;
+    f.fz = fz;
+    timer_begin(c, "force");
+    hipLaunchKernelGGL(k_force<T>, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream, f);
+    timer_end(c, "force");
+    return hipGetLastError();
+}
+
+hipError_t launch_kspace(rbsog_ctx *c, double *fx, double *fy, double *fz)
+{
+    return c->prm.precision == RBSOG_PREC_FP64 ? kspace_t<F64>(c, fx, fy, fz) : kspace_t<F32>(c, fx, fy, fz);
+}
+
+hipError_t launch_rescale(rbsog_ctx *c, const double mu[3], double *x, double *y, double *z)
+{
+    hipLaunchKernelGGL(k_rescale, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream, c->n, mu[0], mu[1], mu[2], x, y,
+                       z);
+    return hipGetLastError();
+}
+
+}  // namespace rbsog

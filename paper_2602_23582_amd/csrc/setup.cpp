@@ -1,0 +1,131 @@
+// Host-side set-up of the RBSOG splitting: SOG weights, the omega~ root, the
+// normalisation constants S^r and S^nr, and the cell grid.  FP64, O(M) work per
+// box, recomputed whenever the box changes.
+#include <cmath>
+
+#include "rbsog_impl.hpp"
+
+namespace rbsog {
+
+namespace {
+constexpr double kPi = 3.141592653589793238462643383279502884;
+// lattice sums stop once the Gaussian factor falls below exp(-kCut)
+constexpr double kCut = 60.0;
+}  // namespace
+
+// Sec. 2.2 (u-series) and Sec. 3.1 (1/r^3 split), with b = b~, sigma = sigma~,
+// M = M~ (Theorem 2): w_l = sqrt(2/pi) log b / (sigma b^l), wt_l = sqrt(2/pi)
+// log b / (sigma b^l)^3, s_l = sqrt(2) sigma b^l; omega multiplies l = 0.
+void sog_tables(const rbsog_params &p, double *w, double *wt, double *s)
+{
+    const double lead = std::sqrt(2.0 / kPi) * std::log(p.b);
+    double width = p.sigma;  // sigma b^l
+    for (int l = 0; l < p.M; ++l) {
+        w[l] = lead / width;
+        wt[l] = lead / (width * width * width);
+        s[l] = std::sqrt(2.0) * width;
+        width *= p.b;
+    }
+    w[0] *= p.omega;
+    wt[0] *= p.omega;
+}
+
+// C0 continuity of the 1/r^3 split at rc (eq. continuity) fixes the factor on
+// the narrowest Gaussian (eq. omega0): it is linear in that factor.
+double omega_c0(double b, double sigma, double rc, int M)
+{
+    rbsog_params p{};
+    p.b = b;
+    p.sigma = sigma;
+    p.omega = 1.0;
+    p.M = M;
+    double w[RBSOG_MAX_M], wt[RBSOG_MAX_M], s[RBSOG_MAX_M];
+    sog_tables(p, w, wt, s);
+    double tail = 0.0;
+    for (int l = M - 1; l >= 1; --l) tail += wt[l] * std::exp(-(rc * rc) / (s[l] * s[l]));
+    return (1.0 / (rc * rc * rc) - tail) / (wt[0] * std::exp(-(rc * rc) / (s[0] * s[0])));
+}
+
+namespace {
+
+// One-dimensional moments sum_n g^j exp(-g^2/a2) over the lattice g = step*n,
+// j = 0, 2, 4.  Every three-dimensional sum below factorises over the axes of
+// an orthorhombic cell.
+void moments_1d(double step, double a2, double mom[3])
+{
+    const int nmax = static_cast<int>(std::ceil(std::sqrt(kCut * a2) / step)) + 1;
+    double m0 = 1.0, m2 = 0.0, m4 = 0.0;  // n = 0 term
+    for (int k = nmax; k >= 1; --k) {
+        const double g2 = (step * k) * (step * k);
+        const double e = std::exp(-g2 / a2);
+        m0 += 2.0 * e;
+        m2 += 2.0 * g2 * e;
+        m4 += 2.0 * g2 * g2 * e;
+    }
+    mom[0] = m0;
+    mom[1] = m2;
+    mom[2] = m4;
+}
+
+// sum over the 3D lattice of (sum_xi g_xi^2)^p exp(-sum g_xi^2 / a2) for
+// p = 0, 1, 2, from the per-axis moments
+void lattice_sums(const double mom[3][3], double out[3])
+{
+    const double a0 = mom[0][0] * mom[1][0] * mom[2][0];
+    double a2 = 0.0, a4 = 0.0;
+    for (int x = 0; x < 3; ++x) {
+        const int y = (x + 1) % 3, z = (x + 2) % 3;
+        a2 += mom[x][1] * mom[y][0] * mom[z][0];
+        a4 += mom[x][2] * mom[y][0] * mom[z][0];
+        a4 += 2.0 * mom[x][1] * mom[y][1] * mom[z][0];
+    }
+    out[0] = a0;
+    out[1] = a2;
+    out[2] = a4;
+}
+
+}  // namespace
+
+// S^r = sum_l H^r_l, S^nr = sum_l H^nr_l (eqs. Sr, Snr).  Per Gaussian the
+// real-space (Poisson, Prop. 1: V wt [6 A0 - 4 A2/s^2] and V wt [60 A0 -
+// 80 A2/s^2 + 16 A4/s^4]) form is used for s_l below the shortest edge, where
+// it needs only a few images and has no cancellation; wider Gaussians use the
+// reciprocal-space sums of |k|^2 and |k|^4 under exp(-s^2 k^2/4) directly.
+void norm_consts(const double L[3], int M, const double *wt, const double *s, double *Sr, double *Snr)
+{
+    const double V = L[0] * L[1] * L[2];
+    const double lmin = std::fmin(L[0], std::fmin(L[1], L[2]));
+    double sr = 0.0, snr = 0.0;
+    for (int l = 0; l < M; ++l) {
+        const double s2 = s[l] * s[l];
+        double mom[3][3], A[3];
+        if (s[l] < lmin) {
+            for (int d = 0; d < 3; ++d) moments_1d(L[d], s2, mom[d]);
+            lattice_sums(mom, A);
+            sr += V * wt[l] * (6.0 * A[0] - 4.0 * A[1] / s2);
+            snr += V * wt[l] * (60.0 * A[0] - 80.0 * A[1] / s2 + 16.0 * A[2] / (s2 * s2));
+        } else {
+            // exp(-s^2 k^2/4) = exp(-k^2/a2) with a2 = 4/s^2, k on the lattice 2 pi m / L
+            for (int d = 0; d < 3; ++d) moments_1d(2.0 * kPi / L[d], 4.0 / s2, mom[d]);
+            lattice_sums(mom, A);
+            const double c = std::pow(kPi, 1.5) * wt[l];
+            const double s5 = s2 * s2 * s[l];
+            sr += c * s5 * A[1];
+            snr += c * s5 * s2 * A[2];
+        }
+    }
+    *Sr = sr;
+    *Snr = snr;
+}
+
+// Cells no narrower than rc (so all partners of an atom lie in the 27 cells
+// around it); a dimension with fewer than three cells is searched whole.
+void cell_grid(const double L[3], double rc, int nc[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        int k = static_cast<int>(std::floor(L[d] / rc));
+        nc[d] = k >= 3 ? k : 1;
+    }
+}
+
+}  // namespace rbsog

@@ -1,0 +1,120 @@
+"""The C-ABI library loads and exports every entry point that include/rbsog.h
+declares; argument validation that happens before any device call.  No
+compute calls (there is no GPU here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbsog.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2602_23582_amd import rbsog
+    if not os.path.exists(rbsog.LIB_PATH):
+        from paper_2602_23582_amd import build
+        build.build_library()
+    return rbsog.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbsog_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_calls_of_the_method():
+    names = _declared_functions()
+    for f in ("rbsog_setup", "rbsog_sample_modes", "rbsog_force_virial", "rbsog_pressure"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2602_23582_amd import rbsog
+    names = _declared_functions()
+    assert set(names) == set(rbsog.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_params_struct_layout_matches_header(lib):
+    from paper_2602_23582_amd import rbsog
+    # doubles and int32/uint64 in declaration order with natural alignment
+    offs = {f[0]: getattr(rbsog.rbsog_params, f[0]).offset for f in rbsog.rbsog_params._fields_}
+    assert offs["b"] == 0 and offs["sigma"] == 8 and offs["omega"] == 16 and offs["M"] == 24
+    assert offs["rc"] == 32 and offs["P"] == 40 and offs["seed"] == 48 and offs["system_id"] == 56
+    assert offs["coulomb_k"] == 64 and offs["precision"] == 72 and offs["recalibration"] == 76
+    assert C.sizeof(rbsog.rbsog_params) == 104
+
+
+def test_params_init_is_table1_row2_scaled(lib):
+    from paper_2602_23582_amd import rbsog
+    p = rbsog.default_params(12.0)
+    assert p.b == 1.62976708826776469
+    assert abs(p.sigma - 3.270345668108471 * 12.0 / 9.0) < 1e-15
+    assert p.omega == 1.007806979343806
+    assert p.M == 10 and p.P == 100 and p.precision == rbsog.PREC_FP32C
+    assert lib.rbsog_params_init(None, 10.0) == -1
+    assert lib.rbsog_params_init(C.byref(p), -1.0) == -1
+
+
+def test_strerror_and_version(lib):
+    assert lib.rbsog_strerror(0) == b"ok"
+    assert lib.rbsog_strerror(-2) == b"charges are not neutral"
+    assert lib.rbsog_version() >= 10000
+
+
+def _setup(lib, q, box, rc=10.0, **kw):
+    from paper_2602_23582_amd import rbsog
+    p = rbsog.default_params(rc)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    h = C.c_void_p()
+    return lib.rbsog_setup(C.byref(p), len(q), rbsog._pd(q), rbsog._pd(box), None, C.byref(h)), h
+
+
+def test_setup_rejects_bad_input_before_touching_the_device(lib):
+    q = np.array([1.0, -1.0, 1.0, -1.0])
+    box = np.array([30.0, 30.0, 30.0])
+    assert _setup(lib, np.array([1.0, -0.9]), box)[0] == -2            # not neutral
+    assert _setup(lib, q, np.array([30.0, 30.0, 19.0]))[0] == -3       # rc > L/2
+    assert _setup(lib, q, np.array([30.0, -1.0, 30.0]))[0] == -3       # negative edge
+    assert _setup(lib, q, np.array([30.0, np.nan, 30.0]))[0] == -1     # NaN box
+    assert _setup(lib, q, box, P=0)[0] == -1
+    assert _setup(lib, q, box, P=1025)[0] == -1
+    assert _setup(lib, q, box, M=0)[0] == -1
+    assert _setup(lib, q, box, M=65)[0] == -1
+    assert _setup(lib, q, box, precision=7)[0] == -1
+    assert _setup(lib, q, box, recalibration=3)[0] == -1
+    assert _setup(lib, q, box, system_id=1 << 33)[0] == -1
+    assert _setup(lib, np.array([1.0, np.inf]), box)[0] == -1
+    # zero atoms
+    from paper_2602_23582_amd import rbsog
+    p = rbsog.default_params(10.0)
+    h = C.c_void_p()
+    assert lib.rbsog_setup(C.byref(p), 0, None, rbsog._pd(box), None, C.byref(h)) == -1
+    assert lib.rbsog_setup(C.byref(p), 4, rbsog._pd(q), rbsog._pd(box), None, None) == -1
+
+
+def test_null_context_calls_are_rejected(lib):
+    assert lib.rbsog_sample_modes(None, 0, None, None, None, None) == -1
+    assert lib.rbsog_pressure(None, None, None) == -1
+    assert lib.rbsog_destroy(None) == 0
+    assert lib.rbsog_last_error(None) == b"null context"
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    from paper_2602_23582_amd import rbsog
+    saved = rbsog._lib
+    rbsog._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="missing"):
+            rbsog.load(str(tmp_path / "nope.so"))
+    finally:
+        rbsog._lib = saved

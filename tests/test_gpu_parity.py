@@ -1,0 +1,292 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Integer outputs (sampled modes, cell ids) must match bit for bit.  Floating
+point results are compared on the same sampled modes: FP64 path within 1e-12,
+FP32C path within 1e-5 (force relative RMS, Frobenius relative pressure error,
+relative energy), the gate stated for the method.
+"""
+import numpy as np
+import pytest
+
+from paper_2602_23582_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+TOL_FP32C = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a visible MI355X"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def rb():
+    from paper_2602_23582_amd import rbsog
+    rbsog.load()
+    return rbsog
+
+
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def gpu_step(torch, ctx, pos, step, box):
+    x, y, z = (_dev(torch, pos[:, k]) for k in range(3))
+    fx, fy, fz = (torch.empty_like(x) for _ in range(3))
+    m_r, m_nr, S = ctx.sample_modes(step, box, return_modes=True)
+    e, v = ctx.force_virial(x, y, z, fx, fy, fz)
+    P, parts = ctx.pressure()
+    F = torch.stack([fx, fy, fz], 1).cpu().numpy()
+    return dict(F=F, UN=e[0], UF=e[1], Uself=e[2], U=e[0] + e[1] - e[2], vir=v, P=P, PN=parts[0],
+                Pr=parts[1], Pnr=parts[2], m_r=m_r, m_nr=m_nr, Sr=S[0], Snr=S[1])
+
+
+def oracle_step(orc, d, box, pos, P, seed, sys, step, variant=0, sample=None):
+    p = orc.sog(d["rc"], row=2, M=10)
+    return orc.rbsog_step(d["q"], pos, box, p, P, seed, sys, step, sample=sample, variant=variant)
+
+
+def check(g, o, tol, what=""):
+    assert np.array_equal(g["m_r"], o["m_r"]), f"{what}: r-chain modes differ"
+    assert np.array_equal(g["m_nr"], o["m_nr"]), f"{what}: nr-chain modes differ"
+    assert abs(g["Sr"] / o["Sr"] - 1) < 1e-13 and abs(g["Snr"] / o["Snr"] - 1) < 1e-13
+    fr = np.sqrt(((g["F"] - o["F"]) ** 2).sum() / (o["F"] ** 2).sum())
+    pn = np.linalg.norm(o["P"])
+    pr = np.linalg.norm(g["P"] - o["P"]) / pn
+    parts = {k: np.linalg.norm(g[k] - o[k]) / pn for k in ("PN", "Pr", "Pnr")}
+    ur = abs(g["U"] - o["U"]) / abs(o["U"])
+    un = abs(g["UN"] - o["UN"]) / abs(o["U"])
+    uf = abs(g["UF"] - o["UF"]) / abs(o["U"])
+    us = abs(g["Uself"] - o["Uself"]) / abs(o["Uself"])
+    msg = f"{what}: F {fr:.2e} P {pr:.2e} parts {parts} U {ur:.2e} UN {un:.2e} UF {uf:.2e} Us {us:.2e}"
+    print(msg, flush=True)
+    assert fr <= tol and pr <= tol and ur <= tol and un <= tol and uf <= tol and us <= tol, msg
+    assert all(v <= tol for v in parts.values()), msg
+
+
+# --------------------------------------------------------------------------
+# bit-exact integer work
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("box,rc,P", [((30.0, 30.0, 30.0), 10.0, 100), ((200.0, 200.0, 500.0), 12.0, 400),
+                                      ((17.1, 17.1, 17.1), 8.55, 50), ((66.88, 66.88, 66.88), 10.0, 1024),
+                                      ((41.0, 23.0, 60.0), 11.0, 200)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_modes_bit_exact(torch, rb, orc, box, rc, P, variant):
+    q = np.array([1.0, -1.0, 0.5, -0.5])
+    box = np.array(box)
+    p = orc.sog(rc, row=2, M=10)
+    for seed, sys in ((1, 0), (12345, 7), (2**40 + 3, 99)):
+        with rb.Context(q, box, rc, P=P, seed=seed, system_id=sys, recalibration=variant) as ctx:
+            for step in (0, 1, 17, 4_000_000_000):
+                m_r, m_nr, S = ctx.sample_modes(step, box, return_modes=True)
+                o_r, o_nr, _ = orc.sample_modes(box, p, P, seed, sys, step, variant)
+                assert np.array_equal(m_r, o_r), (seed, sys, step)
+                assert np.array_equal(m_nr, o_nr), (seed, sys, step)
+                Sr, Snr = orc.norm_consts(box, p)
+                assert abs(S[0] / Sr - 1) < 1e-13 and abs(S[1] / Snr - 1) < 1e-13
+                modes, counts, _ = ctx.debug_modes(with_rho=False)
+                # distinct set: every sampled mode appears once, multiplicities add up to P
+                assert len({tuple(m) for m in modes}) == len(modes)
+                assert counts[:, 0].sum() == P and counts[:, 1].sum() == P
+                lookup = {tuple(m): i for i, m in enumerate(modes)}
+                cr = np.zeros(len(modes), int)
+                cn = np.zeros(len(modes), int)
+                for m in o_r:
+                    cr[lookup[tuple(m)]] += 1
+                for m in o_nr:
+                    cn[lookup[tuple(m)]] += 1
+                assert np.array_equal(cr, counts[:, 0]) and np.array_equal(cn, counts[:, 1])
+
+
+@pytest.mark.parametrize("case", ["lattice", "water", "small"])
+def test_cell_binning_bit_exact(torch, rb, orc, case):
+    d = {"lattice": lambda: W.c1_lattice(jitter=0.2), "water": lambda: W.water_box(n_mol=3000, seed=4),
+         "small": lambda: W.ionic_system(500, seed=3)}[case]()
+    # include images far outside the box and points on the cell faces
+    pos = d["pos"].copy()
+    pos[::7] -= d["L"]
+    pos[1::11] += 2 * d["L"]
+    pos[2, 0] = 0.0
+    pos[3, 1] = d["L"][1]
+    with rb.Context(d["q"], d["L"], d["rc"], P=8) as ctx:
+        gpu_step(torch, ctx, pos, 0, d["L"])
+        cell, nc = ctx.debug_cells()
+    ref = orc.cell_ids(pos, d["L"], nc)
+    assert np.array_equal(cell, ref)
+
+
+# --------------------------------------------------------------------------
+# floating-point parity on identical modes
+# --------------------------------------------------------------------------
+
+def test_fp64_lattice_ten_steps_with_rescale(torch, rb, orc):
+    """1,000 charges, FP64 path, 10 steps on L_n = 30 (1 + 0.001 n), r <- mu r."""
+    d = W.c1_lattice(jitter=0.2)
+    pos0 = d["pos"]
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=5, precision=rb.PREC_FP64) as ctx:
+        for step in range(10):
+            box = W.rescale_schedule(d["L"], step)
+            pos = pos0 * (box / d["L"])
+            g = gpu_step(torch, ctx, pos, step, box)
+            o = oracle_step(orc, d, box, pos, 100, 5, 0, step)
+            check(g, o, TOL_FP64, f"fp64 step {step}")
+
+
+def test_device_rescale_matches_host_rescale(torch, rb):
+    d = W.c1_lattice(jitter=0.2)
+    x, y, z = (_dev(torch, d["pos"][:, k]) for k in range(3))
+    with rb.Context(d["q"], d["L"], d["rc"], P=10) as ctx:
+        mu = np.array([1.001, 1.001, 1.002])
+        box = ctx.rescale(mu, x, y, z)
+        torch.cuda.synchronize()
+    np.testing.assert_array_equal(box, d["L"] * mu)
+    np.testing.assert_array_equal(x.cpu().numpy(), d["pos"][:, 0] * mu[0])
+    np.testing.assert_array_equal(z.cpu().numpy(), d["pos"][:, 2] * mu[2])
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fp32c_lattice(torch, rb, orc, variant):
+    d = W.c1_lattice(jitter=0.2)
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=9, recalibration=variant) as ctx:
+        for step in (0, 3):
+            g = gpu_step(torch, ctx, d["pos"], step, d["L"])
+            o = oracle_step(orc, d, d["L"], d["pos"], 100, 9, 0, step, variant=variant)
+            check(g, o, TOL_FP32C, f"fp32c lattice v{variant} step {step}")
+
+
+def test_fp32c_water_30k(torch, rb, orc):
+    """10,000 three-site molecules at 1 g/cm^3 (L = 66.9 A), rc 10, P 100."""
+    d = W.water_box()
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=2) as ctx:
+        for step in range(3):
+            box = W.rescale_schedule(d["L"], step)
+            pos = d["pos"] * (box / d["L"])
+            g = gpu_step(torch, ctx, pos, step, box)
+            o = oracle_step(orc, d, box, pos, 100, 2, 0, step)
+            check(g, o, TOL_FP32C, f"water step {step}")
+
+
+@pytest.mark.parametrize("P", [100, 400])
+def test_fp32c_small_slab(torch, rb, orc, P):
+    """Anisotropic slab (60 x 60 x 150 A) with dipole layers, rc 12."""
+    d = W.slab(Lx=60.0, n_water=8000, layer_grid=15, seed=6)
+    with rb.Context(d["q"], d["L"], d["rc"], P=P, seed=31) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 4, d["L"])
+    o = oracle_step(orc, d, d["L"], d["pos"], P, 31, 0, 4)
+    check(g, o, TOL_FP32C, f"slab P={P}")
+
+
+@pytest.mark.parametrize("n", [500, 2000, 6000])
+def test_fp32c_small_boxes_collapsed_cells(torch, rb, orc, n):
+    """Served-stream systems: 500 atoms gives L = 17.1 A, rc = L/2, every
+    dimension searched whole; 2,000 and 6,000 give 2 and 3 cells per edge."""
+    d = W.ionic_system(n, seed=n)
+    with rb.Context(d["q"], d["L"], d["rc"], P=d["P"], seed=n, system_id=3) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 1, d["L"])
+    o = oracle_step(orc, d, d["L"], d["pos"], d["P"], n, 3, 1)
+    check(g, o, TOL_FP32C, f"ionic n={n}")
+
+
+def test_rho_of_distinct_modes(torch, rb, orc):
+    d = W.water_box(n_mol=4000, seed=12)
+    with rb.Context(d["q"], d["L"], d["rc"], P=200, seed=3) as ctx:
+        gpu_step(torch, ctx, d["pos"], 0, d["L"])
+        modes, counts, rho = ctx.debug_modes()
+    ref = orc.rho(d["q"], d["pos"], d["L"], modes)
+    scale = np.sqrt(np.sum(d["q"] ** 2))
+    err = np.abs(rho - ref).max() / scale
+    print("rho max err / sqrt(sum q^2):", err)
+    assert err < 1e-6
+
+
+def test_host_arrays_match_device_arrays(torch, rb):
+    d = W.c1_lattice(jitter=0.2)
+    with rb.Context(d["q"], d["L"], d["rc"], P=50, seed=1) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 2, d["L"])
+        x, y, z = (np.ascontiguousarray(d["pos"][:, k]) for k in range(3))
+        fx, fy, fz = (np.zeros(len(x)) for _ in range(3))
+        ctx.sample_modes(2, d["L"])
+        e, v = ctx.force_virial(x, y, z, fx, fy, fz)
+        P, _ = ctx.pressure()
+    np.testing.assert_array_equal(np.stack([fx, fy, fz], 1), g["F"])
+    np.testing.assert_array_equal(P, g["P"])
+
+
+def test_bitwise_reproducible(torch, rb):
+    d = W.water_box(n_mol=5000, seed=8)
+    out = []
+    for _ in range(2):
+        with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=4) as ctx:
+            out.append(gpu_step(torch, ctx, d["pos"], 6, d["L"]))
+    assert np.array_equal(out[0]["F"], out[1]["F"])
+    assert np.array_equal(out[0]["P"], out[1]["P"])
+    assert out[0]["U"] == out[1]["U"]
+
+
+def test_state_errors(torch, rb):
+    d = W.c1_lattice()
+    x, y, z = (_dev(torch, d["pos"][:, k]) for k in range(3))
+    f = [torch.empty_like(x) for _ in range(3)]
+    with rb.Context(d["q"], d["L"], d["rc"], P=10) as ctx:
+        with pytest.raises(rb.RBSOGError) as e:
+            ctx.force_virial(x, y, z, *f)
+        assert e.value.code == -6
+        with pytest.raises(rb.RBSOGError) as e:
+            ctx.pressure()
+        assert e.value.code == -6
+        with pytest.raises(rb.RBSOGError) as e:
+            ctx.sample_modes(0, np.array([30.0, 30.0, 15.0]))
+        assert e.value.code == -3
+        with pytest.raises(rb.RBSOGError) as e:
+            ctx.sample_modes(-1, d["L"])
+        assert e.value.code == -1
+
+
+# --------------------------------------------------------------------------
+# full-size slab (1,000,000 atoms): sampled forces, all rho, full pressure
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def slab_1m():
+    return W.slab()
+
+
+def test_full_size_slab_sampled(torch, rb, orc, slab_1m):
+    d = slab_1m
+    rng = np.random.default_rng(0)
+    smp = np.sort(rng.choice(len(d["q"]), 400, replace=False))
+    smp = np.concatenate([smp, np.arange(990000, 990040)])  # layer atoms
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=11) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 0, d["L"])
+        modes, counts, rho = ctx.debug_modes()
+    p = orc.sog(d["rc"], row=2, M=10)
+    m_r, m_nr, _ = orc.sample_modes(d["L"], p, 100, 11, 0, 0)
+    assert np.array_equal(g["m_r"], m_r) and np.array_equal(g["m_nr"], m_nr)
+    ref = orc.rho(d["q"], d["pos"], d["L"], modes)
+    assert np.abs(rho - ref).max() / np.sqrt(np.sum(d["q"] ** 2)) < 1e-6
+    o = orc.rbsog_step(d["q"], d["pos"], d["L"], p, 100, 11, 0, 0, modes=(m_r, m_nr), sample=smp)
+    Fo = o["F"]
+    Fg = g["F"][smp]
+    fr = np.sqrt(((Fg - Fo) ** 2).sum() / (Fo ** 2).sum())
+    print("1M slab sampled force rel RMS", fr)
+    assert fr < TOL_FP32C
+    # long-range parts are global: compare against the oracle's estimators
+    pn = np.linalg.norm(g["P"])
+    assert np.linalg.norm(g["Pr"] - o["Pr"]) / pn < TOL_FP32C
+    assert np.linalg.norm(g["Pnr"] - o["Pnr"]) / pn < TOL_FP32C
+    assert abs(g["UF"] - o["UF"]) / abs(o["UF"]) < TOL_FP32C
+
+
+@pytest.mark.slow
+def test_full_size_slab_pressure(torch, rb, orc, slab_1m):
+    """Short-range virial and energy of all 1,000,000 atoms against the oracle."""
+    d = slab_1m
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=11) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 0, d["L"])
+    o = oracle_step(orc, d, d["L"], d["pos"], 100, 11, 0, 0)
+    check(g, o, TOL_FP32C, "1M slab full")
