@@ -72,7 +72,7 @@ typedef struct rbsog_ctx rbsog_ctx;
  *                   1/r^3 split at rc (eq. continuity).
  *  M                Gaussians kept, M = M~ (Theorem 2), 1..RBSOG_MAX_M.
  *  rc               short-range cutoff, 0 < rc <= min(L)/2.
- *  P                samples per chain (Sec. 3.2: P^r = P^nr = P), 1..65536.
+ *  P                samples per chain (Sec. 3.2: P^r = P^nr = P), 1..1024.
  *  seed, system_id  key and stream of the counter-based generator; one step is
  *                   a pure function of (seed, system_id, step, box, positions).
  *                   system_id and step must be < 2^32.
@@ -184,6 +184,14 @@ const char *rbsog_last_error(const rbsog_ctx *ctx);
 int rbsog_debug_cells(rbsog_ctx *ctx, int32_t *host_cell, int32_t host_ncell[3]);
 int rbsog_debug_modes(rbsog_ctx *ctx, int32_t cap, int32_t *host_nd, int32_t *host_modes,
                       int32_t *host_counts, double *host_rho);
+
+/*
+ * Counters of the last evaluation (synchronises): host_info[0] = number of
+ * distinct sampled modes (structure factors evaluated), [1] and [2] =
+ * accepted moves of the r-chain and of the recalibration chain, [3] = number
+ * of unordered pairs inside r_c.
+ */
+int rbsog_step_info(rbsog_ctx *ctx, int64_t host_info[4]);
 
 /*
  * Per-kernel device timing with HIP events on the context's stream.

@@ -480,6 +480,19 @@ int rbsog_debug_modes(rbsog_ctx *c, int32_t cap, int32_t *host_nd, int32_t *host
     return RBSOG_OK;
 }
 
+int rbsog_step_info(rbsog_ctx *c, int64_t host_info[4])
+{
+    if (!c || !host_info) return RBSOG_EINVAL;
+    if (c->state < 1) return fail(c, RBSOG_ESTATE, "no sampled modes yet");
+    HIP_TRY(c, hipMemcpyAsync(c->h_res, c->d_res, sizeof(rbsog::StepResults), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    host_info[0] = c->h_res->nd;
+    host_info[1] = c->h_res->acc_r;
+    host_info[2] = c->h_res->acc_nr;
+    host_info[3] = c->state >= 2 ? static_cast<int64_t>(std::llround(c->h_res->npairs)) : 0;
+    return RBSOG_OK;
+}
+
 int rbsog_set_timing(rbsog_ctx *c, int on)
 {
     if (!c) return RBSOG_EINVAL;

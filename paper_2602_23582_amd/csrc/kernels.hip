@@ -546,12 +546,19 @@ __global__ void k_order(int64_t n, const int32_t *__restrict__ perm_tmp, const i
 // ----------------------------------------------------------------------------
 //
 // One wavefront owns up to 64 atoms of one cell (a "pair block") and walks the
-// 27 neighbouring cells (full shell: every pair is evaluated from both sides,
-// so no atomics and a fixed summation order).  Candidates are staged 64 at a
-// time in LDS and tested against r_c by every lane (phase A); each lane
-// appends the indices of its in-cutoff partners to its own ring in LDS.  Once
-// every lane holds enough entries, all lanes evaluate the same number of pairs
-// (phase B), so the expensive kernel runs on full wavefronts.
+// atoms of the 27 neighbouring cells (full shell: every pair is evaluated from
+// both sides, so there are no atomics and the summation order is fixed).  The
+// neighbours arrive as up to 18 contiguous ranges of the sorted arrays (the
+// three cells of a row are adjacent in memory unless the row wraps).  They are
+// staged kChunk at a time in LDS; every lane tests every staged candidate
+// against r_c (phase A, broadcast LDS reads) and appends the LDS index of each
+// partner inside r_c to its own byte list; then all lanes walk their lists
+// (phase B), reading partner records from LDS, so the expensive kernel runs on
+// wavefronts whose lanes all hold a real pair until the shortest list ends.
+
+constexpr int kChunk = 256;   // candidates staged per round (byte indices)
+constexpr int kListCap = 128; // per-lane list capacity between flushes
+constexpr int kMaxRanges = 18;
 
 struct PairArgs {
     int64_t n;
@@ -564,7 +571,7 @@ struct PairArgs {
     const void *rec;
     const SogTables *tab;
     void *fsr;       // short-range force, sorted order, 3 planes of n
-    double *part;    // 8 doubles per block: vir xx yy zz xy xz yz, U, 0
+    double *part;    // 8 doubles per block: vir xx yy zz xy xz yz, U, pair count
 };
 
 template <class T>
@@ -573,34 +580,106 @@ struct PairAcc {
     real fx = 0, fy = 0, fz = 0, vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0, u = 0;
 };
 
+// Splitting weights held in registers for the whole kernel.
+template <class T, int M>
+struct Weights {
+    using real = typename T::real;
+    real c[M], wt[M], w[M];  // exponent factor, 1/r^3-split weight, 1/r-split weight
+    int m = M;
+};
+template <class T>
+struct Weights<T, 0> {  // runtime M: read from the table
+    const SogTables *tab;
+    int m;
+};
+
+template <class T, int M>
+__device__ inline void load_weights(Weights<T, M> &W, const SogTables *__restrict__ tab)
+{
+    if constexpr (M == 0) {
+        W.tab = tab;
+        W.m = tab->M;
+    } else {
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            if constexpr (sizeof(typename T::real) == 4) {
+                W.c[l] = tab->c32[l];
+                W.wt[l] = tab->wt32[l];
+                W.w[l] = tab->w32[l];
+            } else {
+                W.c[l] = -tab->inv_s2[l];
+                W.wt[l] = tab->wt[l];
+                W.w[l] = tab->w[l];
+            }
+        }
+    }
+}
+
+template <class T, int M>
+__device__ inline typename T::real gauss(const Weights<T, M> &W, int l, typename T::real r2, typename T::real &wl)
+{
+    using real = typename T::real;
+    real c, wtl;
+    if constexpr (M == 0) {
+        if constexpr (sizeof(real) == 4) {
+            c = W.tab->c32[l];
+            wtl = W.tab->wt32[l];
+            wl = W.tab->w32[l];
+        } else {
+            c = -W.tab->inv_s2[l];
+            wtl = W.tab->wt[l];
+            wl = W.tab->w[l];
+        }
+    } else {
+        c = W.c[l];
+        wtl = W.wt[l];
+        wl = W.w[l];
+    }
+    real e;
+    if constexpr (sizeof(real) == 4) e = __builtin_amdgcn_exp2f(r2 * c);
+    else e = exp(r2 * c);
+    wl *= e;
+    return wtl * e;
+}
+
+template <class T>
+__device__ inline void displacement(const typename T::Rec &ri, const typename T::Rec &rj, typename T::real sx,
+                                    typename T::real sy, typename T::real sz, typename T::real &dx,
+                                    typename T::real &dy, typename T::real &dz)
+{
+    using sfix = typename T::sfix;
+    dx = fix_to_real(static_cast<sfix>(ri.x - rj.x), sx);
+    dy = fix_to_real(static_cast<sfix>(ri.y - rj.y), sy);
+    dz = fix_to_real(static_cast<sfix>(ri.z - rj.z), sz);
+}
+
 // The SOG short-range kernels of one pair: N~(r) = 1/r^3 - sum wt_l e_l for
 // the force and the virial (eqs. force_SOG, P_short; 2 w_l/s_l^2 = wt_l) and
 // N(r) = 1/r - sum w_l e_l for the energy (eq. U_short), e_l = exp(-r^2/s_l^2).
-template <class T>
+template <class T, int M>
 __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Rec &rj, typename T::real sx,
-                                 typename T::real sy, typename T::real sz, const SogTables *__restrict__ tab, int M,
+                                 typename T::real sy, typename T::real sz, const Weights<T, M> &W,
                                  PairAcc<T> &acc)
 {
     using real = typename T::real;
-    using sfix = typename T::sfix;
-    const real dx = fix_to_real(static_cast<sfix>(ri.x - rj.x), sx);
-    const real dy = fix_to_real(static_cast<sfix>(ri.y - rj.y), sy);
-    const real dz = fix_to_real(static_cast<sfix>(ri.z - rj.z), sz);
+    real dx, dy, dz;
+    displacement<T>(ri, rj, sx, sy, sz, dx, dy, dz);
     const real r2 = dx * dx + dy * dy + dz * dz;
     real swt = 0, sw = 0, rinv;
-    if constexpr (sizeof(real) == 4) {
-        rinv = __builtin_amdgcn_rsqf(r2);
-        for (int l = 0; l < M; ++l) {
-            const float e = __builtin_amdgcn_exp2f(r2 * tab->c32[l]);
-            swt += tab->wt32[l] * e;
-            sw += tab->w32[l] * e;
+    if constexpr (sizeof(real) == 4) rinv = __builtin_amdgcn_rsqf(r2);
+    else rinv = 1.0 / sqrt(r2);
+    if constexpr (M == 0) {
+        for (int l = 0; l < W.m; ++l) {
+            real wl;
+            swt += gauss<T, M>(W, l, r2, wl);
+            sw += wl;
         }
     } else {
-        rinv = 1.0 / sqrt(r2);
+#pragma unroll
         for (int l = 0; l < M; ++l) {
-            const double e = exp(-r2 * tab->inv_s2[l]);
-            swt += tab->wt[l] * e;
-            sw += tab->w[l] * e;
+            real wl;
+            swt += gauss<T, M>(W, l, r2, wl);
+            sw += wl;
         }
     }
     const real qq = ri.q * rj.q;
@@ -618,25 +697,14 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
     acc.u += qq * (rinv - sw);
 }
 
-template <class T>
-__device__ inline typename T::real r2_of(const typename T::Rec &ri, const typename T::Rec &rj, typename T::real sx,
-                                         typename T::real sy, typename T::real sz)
-{
-    using real = typename T::real;
-    using sfix = typename T::sfix;
-    const real dx = fix_to_real(static_cast<sfix>(ri.x - rj.x), sx);
-    const real dy = fix_to_real(static_cast<sfix>(ri.y - rj.y), sy);
-    const real dz = fix_to_real(static_cast<sfix>(ri.z - rj.z), sz);
-    return dx * dx + dy * dy + dz * dz;
-}
-
-template <class T, int CAP>
+template <class T, int M>
 __global__ __launch_bounds__(64) void k_pair(PairArgs a)
 {
     using real = typename T::real;
     using Rec = typename T::Rec;
-    __shared__ Rec s_tile[64];
-    __shared__ int32_t s_ring[CAP * 64];
+    __shared__ Rec s_tile[kChunk];
+    __shared__ uint8_t s_list[kListCap * 64];
+    __shared__ int2 s_rng[kMaxRanges];
 
     const int lane = threadIdx.x;
     const int b = blockIdx.x;
@@ -647,19 +715,19 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
         return;
     }
     const Rec *__restrict__ rec = static_cast<const Rec *>(a.rec);
-    const SogTables *__restrict__ tab = a.tab;
-    const int M = tab->M;
+    Weights<T, M> W;
+    load_weights<T, M>(W, a.tab);
     real sx, sy, sz, rc2;
     if constexpr (sizeof(real) == 4) {
         sx = static_cast<float>(a.Lx * 0x1.0p-32);
         sy = static_cast<float>(a.Ly * 0x1.0p-32);
         sz = static_cast<float>(a.Lz * 0x1.0p-32);
-        rc2 = tab->rc2_32;
+        rc2 = a.tab->rc2_32;
     } else {
         sx = a.Lx * 0x1.0p-64;
         sy = a.Ly * 0x1.0p-64;
         sz = a.Lz * 0x1.0p-64;
-        rc2 = tab->rc2;
+        rc2 = a.tab->rc2;
     }
     const int2 cb = a.blocks[b];
     const int c = cb.x;
@@ -668,22 +736,53 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
     const bool valid = i < ce;
     Rec ri{};
     if (valid) ri = rec[i];
+    const real rc2_lane = valid ? rc2 : static_cast<real>(-1);  // padding lanes find no partner
     const int cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / (a.nx * a.ny);
-    const int ox = a.nx >= 3 ? 1 : 0, oy = a.ny >= 3 ? 1 : 0, oz = a.nz >= 3 ? 1 : 0;
+    const int oy = a.ny >= 3 ? 1 : 0, oz = a.nz >= 3 ? 1 : 0;
 
-    double fx = 0, fy = 0, fz = 0, v[6] = {0, 0, 0, 0, 0, 0}, uu = 0;
-    int wp = 0, rp = 0;
-
-    auto drain = [&](int k_lane, int k_max) {
-        PairAcc<T> acc;
-        for (int e = 0; e < k_max; ++e) {
-            if (e < k_lane) {
-                const int j = s_ring[((rp + e) & (CAP - 1)) * 64 + lane];
-                const Rec rj = rec[j];
-                pair_eval<T>(ri, rj, sx, sy, sz, tab, M, acc);
+    // neighbour ranges: one per row (dy, dz), split where the x-run wraps
+    if (lane == 0) {
+        int nr = 0;
+        for (int dz = -oz; dz <= oz; ++dz) {
+            const int jz = (cz + dz + a.nz) % a.nz;
+            for (int dy = -oy; dy <= oy; ++dy) {
+                const int jy = (cy + dy + a.ny) % a.ny;
+                const int row = a.nx * (jy + a.ny * jz);
+                if (a.nx < 3) {
+                    s_rng[nr++] = make_int2(a.start[row], a.start[row + a.nx]);
+                } else if (cx == 0) {
+                    s_rng[nr++] = make_int2(a.start[row + a.nx - 1], a.start[row + a.nx]);
+                    s_rng[nr++] = make_int2(a.start[row], a.start[row + 2]);
+                } else if (cx == a.nx - 1) {
+                    s_rng[nr++] = make_int2(a.start[row + cx - 1], a.start[row + a.nx]);
+                    s_rng[nr++] = make_int2(a.start[row], a.start[row + 1]);
+                } else {
+                    s_rng[nr++] = make_int2(a.start[row + cx - 1], a.start[row + cx + 2]);
+                }
             }
         }
-        rp += k_lane;
+        for (int k = nr; k < kMaxRanges; ++k) s_rng[k] = make_int2(0, 0);
+    }
+    __syncthreads();
+
+    double fx = 0, fy = 0, fz = 0, v[6] = {0, 0, 0, 0, 0, 0}, uu = 0;
+    int cnt = 0;     // entries in this lane's list
+    int hits = 0;    // in-cutoff partners of this lane's atom
+
+    // phase B: every lane evaluates its listed partners; lanes drop out as their lists end
+    auto flush = [&]() {
+        const int kmax = wave_max(cnt);
+        PairAcc<T> acc;
+        int e = 0;
+        for (; e + 2 <= kmax; e += 2) {
+            const int j0 = s_list[e * 64 + lane], j1 = s_list[(e + 1) * 64 + lane];
+            const Rec r0 = s_tile[j0], r1 = s_tile[j1];
+            if (e < cnt) pair_eval<T, M>(ri, r0, sx, sy, sz, W, acc);
+            if (e + 1 < cnt) pair_eval<T, M>(ri, r1, sx, sy, sz, W, acc);
+        }
+        if (e < kmax && e < cnt) pair_eval<T, M>(ri, s_tile[s_list[e * 64 + lane]], sx, sy, sz, W, acc);
+        hits += cnt;
+        cnt = 0;
         fx += acc.fx;
         fy += acc.fy;
         fz += acc.fz;
@@ -696,42 +795,51 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
         uu += acc.u;
     };
 
-    for (int dz = -oz; dz <= oz; ++dz) {
-        const int jz = (cz + dz + a.nz) % a.nz;
-        for (int dy = -oy; dy <= oy; ++dy) {
-            const int jy = (cy + dy + a.ny) % a.ny;
-            for (int dx = -ox; dx <= ox; ++dx) {
-                const int jx = (cx + dx + a.nx) % a.nx;
-                const int jc = jx + a.nx * (jy + a.ny * jz);
-                const int js = a.start[jc], je = a.start[jc + 1];
-                for (int t0 = js; t0 < je; t0 += 64) {
-                    const int cnt = min(64, je - t0);
-                    if (lane < cnt) s_tile[lane] = rec[t0 + lane];
-                    __syncthreads();
-                    for (int s = 0; s < cnt; ++s) {
-                        const Rec rj = s_tile[s];
-                        const real r2 = r2_of<T>(ri, rj, sx, sy, sz);
-                        if (valid && r2 < rc2 && t0 + s != i) {
-                            s_ring[(wp & (CAP - 1)) * 64 + lane] = t0 + s;
-                            ++wp;
-                        }
-                    }
-                    __syncthreads();
-                    const int pend = wp - rp;
-                    const int mx = wave_max(pend);
-                    const int mn = wave_min(valid ? pend : INT_MAX);
-                    if (mx > CAP - 64) {
-                        drain(pend, mx);
-                    } else if (mn >= 32) {
-                        drain(valid ? mn : 0, mn);
-                    }
-                }
+    int rk = 0, roff = 0;  // current range and offset in it
+    for (;;) {
+        // stage the next chunk of candidates (uniform control flow)
+        int filled = 0;
+        while (filled < kChunk && rk < kMaxRanges) {
+            const int2 r = s_rng[rk];
+            const int len = r.y - r.x - roff;
+            const int take = min(kChunk - filled, len);
+            for (int t = lane; t < take; t += 64) s_tile[filled + t] = rec[r.x + roff + t];
+            filled += take;
+            roff += take;
+            if (roff >= r.y - r.x) {
+                ++rk;
+                roff = 0;
             }
         }
-    }
-    {
-        const int pend = wp - rp;
-        drain(pend, wave_max(pend));
+        if (filled == 0) break;
+        __syncthreads();
+        // phase A: every lane tests every staged candidate; the append is
+        // branch-free (the byte at the list head is overwritten when the test fails)
+        for (int s0 = 0; s0 < filled; s0 += 64) {
+            const int s1 = min(filled, s0 + 64);
+            int s = s0;
+            for (; s + 4 <= s1; s += 4) {
+                const Rec rr[4] = {s_tile[s], s_tile[s + 1], s_tile[s + 2], s_tile[s + 3]};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    real dx, dy, dz;
+                    displacement<T>(ri, rr[k], sx, sy, sz, dx, dy, dz);
+                    const real d2 = dx * dx + dy * dy + dz * dz;
+                    s_list[cnt * 64 + lane] = static_cast<uint8_t>(s + k);
+                    cnt += (d2 < rc2_lane) & (d2 > 0);
+                }
+            }
+            for (; s < s1; ++s) {
+                real dx, dy, dz;
+                displacement<T>(ri, s_tile[s], sx, sy, sz, dx, dy, dz);
+                const real d2 = dx * dx + dy * dy + dz * dz;
+                s_list[cnt * 64 + lane] = static_cast<uint8_t>(s);
+                cnt += (d2 < rc2_lane) & (d2 > 0);
+            }
+            if (wave_max(cnt) > kListCap - 64) flush();
+        }
+        flush();
+        __syncthreads();
     }
     if (valid) {
         real *fsr = static_cast<real *>(a.fsr);
@@ -740,12 +848,10 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
         fsr[2 * a.n + i] = static_cast<real>(fz);
     }
     // full shell: each pair was seen from both sides
-    double out[7] = {0.5 * v[0], 0.5 * v[1], 0.5 * v[2], 0.5 * v[3], 0.5 * v[4], 0.5 * v[5], 0.5 * uu};
-    for (int k = 0; k < 7; ++k) out[k] = wave_sum(out[k]);
-    if (lane == 0) {
-        for (int k = 0; k < 7; ++k) part[k] = out[k];
-        part[7] = 0.0;
-    }
+    double out[8] = {0.5 * v[0], 0.5 * v[1], 0.5 * v[2], 0.5 * v[3], 0.5 * v[4], 0.5 * v[5], 0.5 * uu, 0.5 * hits};
+    for (int k = 0; k < 8; ++k) out[k] = wave_sum(out[k]);
+    if (lane == 0)
+        for (int k = 0; k < 8; ++k) part[k] = out[k];
 }
 
 // ----------------------------------------------------------------------------
@@ -908,14 +1014,15 @@ __global__ __launch_bounds__(256) void k_rho_reduce(const double *__restrict__ p
             rho[2 * d + 1] = im;
         }
     } else {
-        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int64_t b = tid; b < npair; b += 256)
-            for (int k = 0; k < 7; ++k) acc[k] += pair_part[8 * b + k];
-        for (int k = 0; k < 7; ++k) {
+            for (int k = 0; k < 8; ++k) acc[k] += pair_part[8 * b + k];
+        for (int k = 0; k < 8; ++k) {
             const double s = block_sum_256(acc[k], s_tmp);
             if (tid == 0) {
                 if (k < 6) res->vir[k] = s;
-                else res->UN = s;
+                else if (k == 6) res->UN = s;
+                else res->npairs = s;
             }
         }
     }
@@ -1088,8 +1195,6 @@ __global__ void k_rescale(int64_t n, double mx, double my, double mz, double *x,
 
 inline unsigned grid_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
 
-constexpr int kRingCap = 128;
-
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -1171,7 +1276,10 @@ static hipError_t pair_t(rbsog_ctx *c)
     a.part = c->d_pair_part;
     const int64_t grid = (c->n + kPairWave - 1) / kPairWave + c->ncells;
     timer_begin(c, "pair");
-    hipLaunchKernelGGL((k_pair<T, kRingCap>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, c->stream, a);
+    if (c->prm.M == 10)
+        hipLaunchKernelGGL((k_pair<T, 10>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((k_pair<T, 0>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, c->stream, a);
     timer_end(c, "pair");
     return hipGetLastError();
 }

@@ -40,6 +40,7 @@ struct StepResults {
     double Sr, Snr;
     int32_t nd, status;
     int64_t acc_r, acc_nr;
+    double npairs;  // unordered in-cutoff pairs of the last evaluation
 };
 
 struct Timer {

@@ -28,7 +28,7 @@ ERRORS = {0: "RBSOG_OK", -1: "RBSOG_EINVAL", -2: "RBSOG_ENEUTRAL", -3: "RBSOG_EB
 
 EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_force_virial", "rbsog_pressure",
            "rbsog_rescale", "rbsog_destroy", "rbsog_strerror", "rbsog_last_error", "rbsog_debug_cells",
-           "rbsog_debug_modes", "rbsog_set_timing", "rbsog_get_timing", "rbsog_version"]
+           "rbsog_debug_modes", "rbsog_step_info", "rbsog_set_timing", "rbsog_get_timing", "rbsog_version"]
 
 
 class rbsog_params(C.Structure):
@@ -70,6 +70,7 @@ def load(path: str | None = None):
         "rbsog_last_error": (C.c_char_p, [vp]),
         "rbsog_debug_cells": (C.c_int, [vp, pi32, pi32]),
         "rbsog_debug_modes": (C.c_int, [vp, i32, pi32, pi32, pi32, pd]),
+        "rbsog_step_info": (C.c_int, [vp, pi64]),
         "rbsog_set_timing": (C.c_int, [vp, C.c_int]),
         "rbsog_get_timing": (C.c_int, [vp, i32, pi32, C.c_char_p, pd, pi64]),
         "rbsog_version": (C.c_int, []),
@@ -199,6 +200,12 @@ class Context:
                                              _pd(rho) if with_rho else None), "rbsog_debug_modes")
         k = int(nd[0])
         return modes[:k], counts[:k], (rho[:k, 0] + 1j * rho[:k, 1]) if with_rho else None
+
+    def step_info(self):
+        """(distinct modes, r-chain accepts, recalibration accepts, unordered in-cutoff pairs)."""
+        info = np.zeros(4, dtype=np.int64)
+        self._check(load().rbsog_step_info(self._h, info.ctypes.data_as(C.POINTER(C.c_int64))), "rbsog_step_info")
+        return dict(nd=int(info[0]), acc_r=int(info[1]), acc_nr=int(info[2]), npairs=int(info[3]))
 
     def set_timing(self, on=True):
         self._check(load().rbsog_set_timing(self._h, 1 if on else 0), "rbsog_set_timing")

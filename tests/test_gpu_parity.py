@@ -14,6 +14,10 @@ pytestmark = pytest.mark.gpu
 
 TOL_FP64 = 1e-12
 TOL_FP32C = 1e-5
+# Structure factors in FP32C: the hardware sine/cosine (input in revolutions)
+# carry an absolute error of about 2^-21 per term, so |d rho| grows like
+# 2^-21 sqrt(sum q^2) (random signs); the bound allows ~10 sigma over all modes.
+RHO_TOL = 5e-6
 
 
 @pytest.fixture(scope="module")
@@ -201,7 +205,7 @@ def test_rho_of_distinct_modes(torch, rb, orc):
     scale = np.sqrt(np.sum(d["q"] ** 2))
     err = np.abs(rho - ref).max() / scale
     print("rho max err / sqrt(sum q^2):", err)
-    assert err < 1e-6
+    assert err < RHO_TOL
 
 
 def test_host_arrays_match_device_arrays(torch, rb):
@@ -268,7 +272,9 @@ def test_full_size_slab_sampled(torch, rb, orc, slab_1m):
     m_r, m_nr, _ = orc.sample_modes(d["L"], p, 100, 11, 0, 0)
     assert np.array_equal(g["m_r"], m_r) and np.array_equal(g["m_nr"], m_nr)
     ref = orc.rho(d["q"], d["pos"], d["L"], modes)
-    assert np.abs(rho - ref).max() / np.sqrt(np.sum(d["q"] ** 2)) < 1e-6
+    err = np.abs(rho - ref).max() / np.sqrt(np.sum(d["q"] ** 2))
+    print("1M slab rho max err / sqrt(sum q^2):", err)
+    assert err < RHO_TOL
     o = orc.rbsog_step(d["q"], d["pos"], d["L"], p, 100, 11, 0, 0, modes=(m_r, m_nr), sample=smp)
     Fo = o["F"]
     Fg = g["F"][smp]
