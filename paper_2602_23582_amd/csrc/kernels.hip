@@ -547,18 +547,28 @@ __global__ void k_order(int64_t n, const int32_t *__restrict__ perm_tmp, const i
 //
 // One wavefront owns up to 64 atoms of one cell (a "pair block") and walks the
 // atoms of the 27 neighbouring cells (full shell: every pair is evaluated from
-// both sides, so there are no atomics and the summation order is fixed).  The
-// neighbours arrive as up to 18 contiguous ranges of the sorted arrays (the
-// three cells of a row are adjacent in memory unless the row wraps).  They are
-// staged kChunk at a time in LDS; every lane tests every staged candidate
-// against r_c (phase A, broadcast LDS reads) and appends the LDS index of each
-// partner inside r_c to its own byte list; then all lanes walk their lists
-// (phase B), reading partner records from LDS, so the expensive kernel runs on
-// wavefronts whose lanes all hold a real pair until the shortest list ends.
+// both sides, so no atomics and a fixed summation order).  The neighbours are
+// up to 18 contiguous ranges of the sorted arrays (the three cells of a row are
+// adjacent in memory unless the row wraps).  They are staged kChunk at a time
+// in LDS; every lane tests every staged candidate against r_c and appends the
+// LDS index of each partner inside r_c to its own byte list; then all lanes
+// walk their lists, reading partner records from LDS, so the expensive SOG
+// kernel runs on wavefronts whose lanes all hold a real pair until the
+// shortest list ends.
 
-constexpr int kChunk = 256;   // candidates staged per round (byte indices)
-constexpr int kListCap = 128; // per-lane list capacity between flushes
+#ifndef RBSOG_PAIR_CHUNK
+#define RBSOG_PAIR_CHUNK 128
+#endif
+#ifndef RBSOG_PAIR_LISTCAP
+#define RBSOG_PAIR_LISTCAP 96
+#endif
+#ifndef RBSOG_FAST_FILTER
+#define RBSOG_FAST_FILTER 1
+#endif
+constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round (byte indices, <= 256)
+constexpr int kListCap = RBSOG_PAIR_LISTCAP; // per-lane list capacity between flushes (>= 64)
 constexpr int kMaxRanges = 18;
+static_assert(kChunk <= 256 && kChunk % 64 == 0 && kListCap >= 64, "pair tiling");
 
 struct PairArgs {
     int64_t n;
@@ -578,6 +588,7 @@ template <class T>
 struct PairAcc {
     using real = typename T::real;
     real fx = 0, fy = 0, fz = 0, vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0, u = 0;
+    int n = 0;  // pairs inside rc
 };
 
 // Splitting weights held in registers for the whole kernel.
@@ -656,15 +667,18 @@ __device__ inline void displacement(const typename T::Rec &ri, const typename T:
 // The SOG short-range kernels of one pair: N~(r) = 1/r^3 - sum wt_l e_l for
 // the force and the virial (eqs. force_SOG, P_short; 2 w_l/s_l^2 = wt_l) and
 // N(r) = 1/r - sum w_l e_l for the energy (eq. U_short), e_l = exp(-r^2/s_l^2).
+// A listed pair farther than rc (possible only through the padded fast
+// filter) contributes nothing.
 template <class T, int M>
 __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Rec &rj, typename T::real sx,
-                                 typename T::real sy, typename T::real sz, const Weights<T, M> &W,
-                                 PairAcc<T> &acc)
+                                 typename T::real sy, typename T::real sz, typename T::real rc2,
+                                 const Weights<T, M> &W, PairAcc<T> &acc)
 {
     using real = typename T::real;
     real dx, dy, dz;
     displacement<T>(ri, rj, sx, sy, sz, dx, dy, dz);
     const real r2 = dx * dx + dy * dy + dz * dz;
+    const bool inside = r2 < rc2;
     real swt = 0, sw = 0, rinv;
     if constexpr (sizeof(real) == 4) rinv = __builtin_amdgcn_rsqf(r2);
     else rinv = 1.0 / sqrt(r2);
@@ -682,7 +696,8 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
             sw += wl;
         }
     }
-    const real qq = ri.q * rj.q;
+    const real qq = inside ? ri.q * rj.q : static_cast<real>(0);
+    acc.n += inside;
     const real f = qq * (rinv * rinv * rinv - swt);
     const real fdx = f * dx, fdy = f * dy, fdz = f * dz;
     acc.fx += fdx;
@@ -702,9 +717,13 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
 {
     using real = typename T::real;
     using Rec = typename T::Rec;
+    using fix = typename T::fix;
+    using sfix = typename T::sfix;
     __shared__ Rec s_tile[kChunk];
+    __shared__ __attribute__((aligned(16))) float s_rel[3][kChunk];  // filter coordinates (fast filter)
     __shared__ uint8_t s_list[kListCap * 64];
-    __shared__ int2 s_rng[kMaxRanges];
+    __shared__ int s_pre[kMaxRanges + 1];  // flattened-neighbourhood offset of each range
+    __shared__ int s_beg[kMaxRanges];
 
     const int lane = threadIdx.x;
     const int b = blockIdx.x;
@@ -737,39 +756,75 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
     Rec ri{};
     if (valid) ri = rec[i];
     const real rc2_lane = valid ? rc2 : static_cast<real>(-1);  // padding lanes find no partner
+    // Fast filter (FP32, at least 5 cells per edge): candidates are tested in
+    // float coordinates relative to the first atom of the block, o.  With five
+    // or more cells per edge, i and every candidate lie within two cells of o,
+    // well inside half a box, so differences of relative coordinates are
+    // minimum-image displacements.  The filter radius is padded by 1e-3 A for
+    // float rounding; the pair evaluation applies the exact test on fixed-point
+    // differences.
+    constexpr bool kIsF32 = sizeof(real) == 4;
+    const bool fast = RBSOG_FAST_FILTER && kIsF32 && a.nx >= 5 && a.ny >= 5 && a.nz >= 5;
+    const fix ox = static_cast<fix>(__shfl(static_cast<long long>(ri.x), 0, 64));
+    const fix oy_ = static_cast<fix>(__shfl(static_cast<long long>(ri.y), 0, 64));
+    const fix oz_ = static_cast<fix>(__shfl(static_cast<long long>(ri.z), 0, 64));
+    const float rcf = static_cast<float>(sqrt(static_cast<double>(rc2))) + 1e-3f;
+    const float rcf2_lane = valid ? rcf * rcf : -1.0f;
+    const float xi = static_cast<float>(static_cast<sfix>(ri.x - ox)) * static_cast<float>(sx);
+    const float yi = static_cast<float>(static_cast<sfix>(ri.y - oy_)) * static_cast<float>(sy);
+    const float zi = static_cast<float>(static_cast<sfix>(ri.z - oz_)) * static_cast<float>(sz);
     const int cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / (a.nx * a.ny);
     const int oy = a.ny >= 3 ? 1 : 0, oz = a.nz >= 3 ? 1 : 0;
 
-    // neighbour ranges: one per row (dy, dz), split where the x-run wraps
+    // neighbour ranges: one per row (dy, dz), split where the x-run wraps;
+    // they are concatenated into one flattened candidate index
     if (lane == 0) {
         int nr = 0;
+        auto put = [&](int lo, int hi) {
+            s_beg[nr] = lo;
+            s_pre[nr + 1] = hi - lo;  // length for now, prefix sums below
+            ++nr;
+        };
         for (int dz = -oz; dz <= oz; ++dz) {
             const int jz = (cz + dz + a.nz) % a.nz;
             for (int dy = -oy; dy <= oy; ++dy) {
                 const int jy = (cy + dy + a.ny) % a.ny;
                 const int row = a.nx * (jy + a.ny * jz);
                 if (a.nx < 3) {
-                    s_rng[nr++] = make_int2(a.start[row], a.start[row + a.nx]);
+                    put(a.start[row], a.start[row + a.nx]);
                 } else if (cx == 0) {
-                    s_rng[nr++] = make_int2(a.start[row + a.nx - 1], a.start[row + a.nx]);
-                    s_rng[nr++] = make_int2(a.start[row], a.start[row + 2]);
+                    put(a.start[row + a.nx - 1], a.start[row + a.nx]);
+                    put(a.start[row], a.start[row + 2]);
                 } else if (cx == a.nx - 1) {
-                    s_rng[nr++] = make_int2(a.start[row + cx - 1], a.start[row + a.nx]);
-                    s_rng[nr++] = make_int2(a.start[row], a.start[row + 1]);
+                    put(a.start[row + cx - 1], a.start[row + a.nx]);
+                    put(a.start[row], a.start[row + 1]);
                 } else {
-                    s_rng[nr++] = make_int2(a.start[row + cx - 1], a.start[row + cx + 2]);
+                    put(a.start[row + cx - 1], a.start[row + cx + 2]);
                 }
             }
         }
-        for (int k = nr; k < kMaxRanges; ++k) s_rng[k] = make_int2(0, 0);
+        s_pre[0] = 0;
+        for (int k = 0; k < kMaxRanges; ++k) {
+            const int len = k < nr ? s_pre[k + 1] : 0;
+            if (k >= nr) s_beg[k] = 0;
+            s_pre[k + 1] = s_pre[k] + len;
+        }
     }
     __syncthreads();
+    const int total = s_pre[kMaxRanges];
+    // Candidates go to the chunks in groups of 4 consecutive records, group g to
+    // chunk g mod nch: every chunk samples the whole neighbourhood, so each
+    // lane's share of partners is about the same in every chunk and the lists
+    // of a wavefront end together.
+    const int ngroups = (total + 3) / 4;
+    const int gpc = kChunk / 4;
+    const int nch = (ngroups + gpc - 1) / gpc;
 
     double fx = 0, fy = 0, fz = 0, v[6] = {0, 0, 0, 0, 0, 0}, uu = 0;
     int cnt = 0;     // entries in this lane's list
     int hits = 0;    // in-cutoff partners of this lane's atom
 
-    // phase B: every lane evaluates its listed partners; lanes drop out as their lists end
+    // every lane evaluates its listed partners; lanes drop out as their lists end
     auto flush = [&]() {
         const int kmax = wave_max(cnt);
         PairAcc<T> acc;
@@ -777,11 +832,11 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
         for (; e + 2 <= kmax; e += 2) {
             const int j0 = s_list[e * 64 + lane], j1 = s_list[(e + 1) * 64 + lane];
             const Rec r0 = s_tile[j0], r1 = s_tile[j1];
-            if (e < cnt) pair_eval<T, M>(ri, r0, sx, sy, sz, W, acc);
-            if (e + 1 < cnt) pair_eval<T, M>(ri, r1, sx, sy, sz, W, acc);
+            if (e < cnt) pair_eval<T, M>(ri, r0, sx, sy, sz, rc2, W, acc);
+            if (e + 1 < cnt) pair_eval<T, M>(ri, r1, sx, sy, sz, rc2, W, acc);
         }
-        if (e < kmax && e < cnt) pair_eval<T, M>(ri, s_tile[s_list[e * 64 + lane]], sx, sy, sz, W, acc);
-        hits += cnt;
+        if (e < kmax && e < cnt) pair_eval<T, M>(ri, s_tile[s_list[e * 64 + lane]], sx, sy, sz, rc2, W, acc);
+        hits += acc.n;
         cnt = 0;
         fx += acc.fx;
         fy += acc.fy;
@@ -795,46 +850,59 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
         uu += acc.u;
     };
 
-    int rk = 0, roff = 0;  // current range and offset in it
-    for (;;) {
-        // stage the next chunk of candidates (uniform control flow)
-        int filled = 0;
-        while (filled < kChunk && rk < kMaxRanges) {
-            const int2 r = s_rng[rk];
-            const int len = r.y - r.x - roff;
-            const int take = min(kChunk - filled, len);
-            for (int t = lane; t < take; t += 64) s_tile[filled + t] = rec[r.x + roff + t];
-            filled += take;
-            roff += take;
-            if (roff >= r.y - r.x) {
-                ++rk;
-                roff = 0;
+    for (int ch = 0; ch < nch; ++ch) {
+        // this chunk's groups: ch, ch + nch, ...; slots k of the chunk map to
+        // flattened indices 4 (ch + nch (k/4)) + k%4, a prefix of them valid
+        const int ng = ch < ngroups ? (ngroups - ch + nch - 1) / nch : 0;
+        const int glast = ch + nch * (ng - 1);
+        const int filled = ng > 0 ? 4 * (ng - 1) + min(4, total - 4 * glast) : 0;
+        for (int k = lane; k < filled; k += 64) {
+            const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
+            int r = 0;
+            while (r + 1 < kMaxRanges && s_pre[r + 1] <= f) ++r;
+            const Rec rj = rec[s_beg[r] + (f - s_pre[r])];
+            s_tile[k] = rj;
+            if (fast) {
+                s_rel[0][k] = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
+                s_rel[1][k] = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
+                s_rel[2][k] = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
             }
         }
-        if (filled == 0) break;
         __syncthreads();
-        // phase A: every lane tests every staged candidate; the append is
-        // branch-free (the byte at the list head is overwritten when the test fails)
+        // test every staged candidate; the append is branch-free (the byte at
+        // the list head is overwritten when the test fails)
         for (int s0 = 0; s0 < filled; s0 += 64) {
             const int s1 = min(filled, s0 + 64);
             int s = s0;
-            for (; s + 4 <= s1; s += 4) {
-                const Rec rr[4] = {s_tile[s], s_tile[s + 1], s_tile[s + 2], s_tile[s + 3]};
+            if (fast) {
+                for (; s + 4 <= s1; s += 4) {
+                    const float4 X = *reinterpret_cast<const float4 *>(&s_rel[0][s]);
+                    const float4 Y = *reinterpret_cast<const float4 *>(&s_rel[1][s]);
+                    const float4 Z = *reinterpret_cast<const float4 *>(&s_rel[2][s]);
+                    const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w},
+                                zs[4] = {Z.x, Z.y, Z.z, Z.w};
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                    for (int k = 0; k < 4; ++k) {
+                        const float dx = xi - xs[k], dy = yi - ys[k], dz = zi - zs[k];
+                        const float d2 = dx * dx + dy * dy + dz * dz;
+                        s_list[cnt * 64 + lane] = static_cast<uint8_t>(s + k);
+                        cnt += (d2 < rcf2_lane) & (d2 > 0.0f);
+                    }
+                }
+                for (; s < s1; ++s) {
+                    const float dx = xi - s_rel[0][s], dy = yi - s_rel[1][s], dz = zi - s_rel[2][s];
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    s_list[cnt * 64 + lane] = static_cast<uint8_t>(s);
+                    cnt += (d2 < rcf2_lane) & (d2 > 0.0f);
+                }
+            } else {
+                for (; s < s1; ++s) {
                     real dx, dy, dz;
-                    displacement<T>(ri, rr[k], sx, sy, sz, dx, dy, dz);
+                    displacement<T>(ri, s_tile[s], sx, sy, sz, dx, dy, dz);
                     const real d2 = dx * dx + dy * dy + dz * dz;
-                    s_list[cnt * 64 + lane] = static_cast<uint8_t>(s + k);
+                    s_list[cnt * 64 + lane] = static_cast<uint8_t>(s);
                     cnt += (d2 < rc2_lane) & (d2 > 0);
                 }
-            }
-            for (; s < s1; ++s) {
-                real dx, dy, dz;
-                displacement<T>(ri, s_tile[s], sx, sy, sz, dx, dy, dz);
-                const real d2 = dx * dx + dy * dy + dz * dz;
-                s_list[cnt * 64 + lane] = static_cast<uint8_t>(s);
-                cnt += (d2 < rc2_lane) & (d2 > 0);
             }
             if (wave_max(cnt) > kListCap - 64) flush();
         }

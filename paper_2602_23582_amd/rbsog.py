@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librbsog.so")
+LIB_PATH = os.environ.get("RBSOG_LIBRARY") or os.path.join(HERE, "librbsog.so")
 
 PREC_FP64 = 0
 PREC_FP32C = 1
