@@ -80,7 +80,7 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(config, nlaunch_bytes_alg):
+def read_traffic(config):
     """HBM bytes per pair-kernel launch from the committed counter summary, if it
     was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"pair_kernel_{config}_counters.txt")
@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2026)
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after the run, one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU decomposition "
@@ -186,7 +188,7 @@ def main():
     t_pair = pair_ms / max(pair_cnt, 1) * 1e-3
     slots = info["npairs"] * pair_slots(10)
     achieved = slots / t_pair if t_pair > 0 else 0.0
-    traffic = read_traffic(args.config, None)
+    traffic = read_traffic(args.config)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12,
                 "unit": "T VALU-slot/s", "frac": achieved / VALU_SLOTS_PER_S, "traffic": traffic,
                 "kernel": "k_pair", "unordered_pairs_per_launch": info["npairs"],
@@ -210,6 +212,11 @@ def main():
         "distinct_modes": info["nd"],
     }
     ctx.close()
+    if args.calibration_copy_mib > 0:
+        src = torch.ones(args.calibration_copy_mib * 262144, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 
