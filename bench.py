@@ -99,6 +99,36 @@ def read_traffic(config):
         return None
 
 
+PROBE_KINDS = [  # (name, FP32 FMA per iteration, transcendentals per iteration), per lane
+    ("fma", 8, 0), ("exp", 0, 8), ("rsq", 0, 8), ("sin", 0, 8),
+    ("exp+4fma", 32, 8), ("exp+2fma", 16, 8), ("exp+1fma", 8, 8), ("exp+8fma", 64, 8)]
+
+
+def valu_probe(iters=32768, blocks=2048):
+    """Issue rates behind the ALU roofline, measured on this GPU: wave
+    instructions per second of FP32 FMA, of v_exp/v_rsq/v_sin, and of mixes,
+    from paper_2602_23582_amd/csrc/valu_probe.hip (8 independent chains per
+    lane, 4 waves per workgroup)."""
+    import ctypes as C
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2602_23582_amd", "libvaluprobe.so"))
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    waves = blocks * 4
+    simd_cycles_per_s = 256 * 4 * 2.4e9
+    res = {}
+    for kind, (name, nv, nt) in enumerate(PROBE_KINDS):
+        ms = C.c_float()
+        rc = lib.valu_probe(kind, iters, blocks, C.c_void_p(out.data_ptr()), C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"valu_probe kind {kind}: error {rc}")
+        t = ms.value * 1e-3
+        v = waves * iters * nv / t
+        tr = waves * iters * nt / t
+        res[name] = {"ms": ms.value, "valu_per_simd_cycle": v / simd_cycles_per_s,
+                     "trans_per_simd_cycle": tr / simd_cycles_per_s}
+    return res
+
+
 def cpu_baseline(d, P, seed, sample_atoms):
     """The oracle as it stands on a bounded sample: long-range structure factors
     of all atoms for every sampled mode (2P evaluations), short-range and
@@ -137,6 +167,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2026)
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-valu-probe", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -198,6 +229,7 @@ def main():
     for k, per in (("sk", sk_slots), ("force", fo_slots)):
         if k in kernels and kernels[k]["avg_ms"] > 0:
             kernels[k]["frac_valu"] = n * info["nd"] * per / (kernels[k]["avg_ms"] * 1e-3) / VALU_SLOTS_PER_S
+    probe = None if args.no_valu_probe else valu_probe()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d, P, args.seed, args.cpu_sample)
@@ -209,7 +241,7 @@ def main():
                    "precision": "FP32C (FP32 arithmetic, FP64 partial sums and reductions)",
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
-        "distinct_modes": info["nd"],
+        "distinct_modes": info["nd"], "valu_probe": probe,
     }
     ctx.close()
     if args.calibration_copy_mib > 0:

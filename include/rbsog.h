@@ -209,6 +209,145 @@ int rbsog_get_timing(rbsog_ctx *ctx, int32_t cap, int32_t *host_nk, char *host_n
 /* Library version: major * 10000 + minor * 100 + patch. */
 int rbsog_version(void);
 
+/* ========================================================================
+ * Batched form: many independent systems of uneven size evaluated by one set
+ * of launches per step.  Each launch covers every system; workgroups find
+ * their (system, block) in a launch plan, and every reduction runs over one
+ * system's partials in a fixed order, so a system's results are bitwise the
+ * same alone (rbsog_setup, or a batch of one) and in any batch.  One step of
+ * one system is the same computation as the single-system calls above
+ * (Algorithm 1, steps 2-6).
+ * ======================================================================== */
+
+typedef struct rbsog_batch rbsog_batch;
+
+#define RBSOG_SCHED_STATIC 0     /* one workgroup per pair block                     */
+#define RBSOG_SCHED_PERSISTENT 1 /* a fixed grid takes pair blocks from a work queue */
+
+/*
+ * Create a batch of nsys systems (1..65536).
+ *  params[nsys]       per-system parameters (as for rbsog_setup); every system
+ *                     must use the same precision.
+ *  n[nsys]            atoms per system.
+ *  host_q[sum n]      charges, system after system (each system neutral).
+ *  host_boxes[3 nsys] initial box edges.
+ *  hip_stream         stream for all work of the batch (NULL = null stream).
+ * Device memory: one allocation per system, about what rbsog_setup takes.
+ */
+int rbsog_batch_setup(const rbsog_params *params, int32_t nsys, const int64_t *n, const double *host_q,
+                      const double *host_boxes, void *hip_stream, rbsog_batch **out);
+
+/*
+ * One full step of every system: mode sampling, binning, pair kernel,
+ * structure factors, estimators, forces (Algorithm 1 steps 2-6).
+ *  host_steps[nsys]   step index of each system (< 2^32, generator counter).
+ *  host_boxes[3 nsys] box of each system for this step.
+ *  x, y, z            device arrays of sum n positions, system after system.
+ *  fx, fy, fz         device arrays of sum n forces (overwritten).
+ *  host_P[9 nsys]     optional: total pressure tensor of each system.
+ *  host_energy[3 nsys] optional: U^N, U^{F*}, U_self of each system.
+ *  host_info[4 nsys]  optional: the counters of rbsog_step_info per system.
+ * Asking for any host output synchronises the stream.
+ */
+int rbsog_batch_step(rbsog_batch *b, const int64_t *host_steps, const double *host_boxes, const double *x,
+                     const double *y, const double *z, double *fx, double *fy, double *fz, double *host_P,
+                     double *host_energy, int64_t *host_info);
+
+/*
+ * r <- mu_s r for the positions of each system s (device arrays laid out as
+ * in rbsog_batch_step) and host_boxes[3 s + d] <- mu[3 s + d] host_boxes[3 s + d].
+ */
+int rbsog_batch_rescale(rbsog_batch *b, const double *host_mu, double *x, double *y, double *z,
+                        double *host_boxes);
+
+/*
+ * Launch options; none changes any result.
+ *  schedule      RBSOG_SCHED_STATIC or RBSOG_SCHED_PERSISTENT (pair kernel).
+ *  wg_per_cu     workgroups per compute unit of the persistent grid (1..64).
+ *  use_graph     nonzero: rbsog_batch_step replays a captured HIP graph of
+ *                the step's launches (captured again when sizes change).
+ */
+int rbsog_batch_set_options(rbsog_batch *b, int32_t schedule, int32_t wg_per_cu, int32_t use_graph);
+
+/*
+ * Autotuner: times rbsog_batch_step on the given arrays for each launch
+ * option in a fixed candidate list (static; persistent with 4, 8, 16, 32
+ * workgroups per CU), reps steps each after one warm-up, and keeps the
+ * fastest.  host_ms[5] (optional) receives the mean step time of each
+ * candidate, *host_choice (optional) the index chosen.  The forces and the
+ * step's results are those of a regular step.
+ */
+int rbsog_batch_autotune(rbsog_batch *b, const int64_t *host_steps, const double *host_boxes, const double *x,
+                         const double *y, const double *z, double *fx, double *fy, double *fz, int32_t reps,
+                         double *host_ms, int32_t *host_choice);
+
+/* Per-kernel HIP-event timing of the batch's launches (as rbsog_set_timing). */
+int rbsog_batch_set_timing(rbsog_batch *b, int on);
+int rbsog_batch_get_timing(rbsog_batch *b, int32_t cap, int32_t *host_nk, char *host_names, double *host_ms,
+                           int64_t *host_count);
+
+int rbsog_batch_destroy(rbsog_batch *b);
+const char *rbsog_batch_last_error(const rbsog_batch *b);
+
+/* ========================================================================
+ * Served form: a request loop on a worker thread.  A request is one system
+ * and a number of steps under the box law L_k = L_0 (1 + g k) (positions
+ * rescaled by mu_k = (1 + g k)/(1 + g (k - 1)) before step k, k >= 1); it is
+ * admitted when a slot and device memory from the server's pool are free,
+ * its state stays on the device until it completes, and every tick runs one
+ * batched step over all admitted requests, so requests that arrive while
+ * others run join the next tick (continuous batching).  Results are bitwise
+ * those of the same request alone.
+ * ======================================================================== */
+
+typedef struct rbsog_server rbsog_server;
+
+/*
+ * precision      RBSOG_PREC_FP32C or RBSOG_PREC_FP64 (all requests).
+ * pool_bytes     device memory for request state (> 0); admission allocates
+ *                from it first-fit.
+ * max_active     requests per tick (>= 1); 1 serves one request at a time.
+ */
+int rbsog_server_create(int32_t precision, int64_t pool_bytes, int32_t max_active, void *hip_stream,
+                        rbsog_server **out);
+
+/*
+ * Queue a request (copies every input; returns at once).
+ *  params         parameters of the system (params->precision must match).
+ *  n, host_q[n]   charges; host_x, host_y, host_z[n] initial positions.
+ *  host_box[3]    initial box; nsteps >= 1 steps; growth g (L_k = L_0 (1 + g k)).
+ *  *ticket        receives the request's ticket.
+ * Returns RBSOG_EAGAIN if the request can never fit the pool.
+ */
+int rbsog_server_submit(rbsog_server *s, const rbsog_params *params, int64_t n, const double *host_q,
+                        const double *host_x, const double *host_y, const double *host_z,
+                        const double host_box[3], int32_t nsteps, double growth, int64_t *ticket);
+
+/*
+ * Wait up to timeout_s seconds (< 0: forever) for a request; RBSOG_EAGAIN if
+ * it has not completed.  On completion copies out (each optional)
+ *  host_fx, host_fy, host_fz[n]  forces of the last step,
+ *  host_P[9 nsteps]              pressure tensor of every step,
+ *  host_energy[3 nsteps]         U^N, U^{F*}, U_self of every step,
+ *  host_times[3]                 seconds from submission to admission, from
+ *                                submission to completion, and the number of
+ *                                ticks the request shared with others,
+ * and releases the ticket.
+ */
+int rbsog_server_wait(rbsog_server *s, int64_t ticket, double timeout_s, double *host_fx, double *host_fy,
+                      double *host_fz, double *host_P, double *host_energy, double *host_times);
+
+/*
+ * host_stats[8]: requests submitted, completed, ticks run, atom-steps done,
+ * seconds the worker spent in ticks, peak active requests, peak pool bytes
+ * in use, requests waiting now.
+ */
+int rbsog_server_stats(rbsog_server *s, double *host_stats);
+
+/* Stop the worker (finishing the tick in flight) and free everything. */
+int rbsog_server_destroy(rbsog_server *s);
+const char *rbsog_server_last_error(const rbsog_server *s);
+
 #ifdef __cplusplus
 }
 #endif

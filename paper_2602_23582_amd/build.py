@@ -7,14 +7,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbsog.so")
-SOURCES = ["kernels.hip", "setup.cpp", "api.cpp"]
+PROBE_LIB = os.path.join(HERE, "libvaluprobe.so")
+SOURCES = ["kernels.hip", "setup.cpp", "system.cpp", "api.cpp", "batch_api.cpp", "server.cpp"]
 ARCH = os.environ.get("RBSOG_OFFLOAD_ARCH", "gfx950")
 
 
 def hipcc_flags():
     return [
         "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-        # packed FP32 instructions stay off (see the build notes in the design doc)
+        # no packed FP32 instructions: every FP32 operation is issued unpacked
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-function",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
@@ -37,6 +38,12 @@ def build_library(verbose: bool = False, extra=None) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    # the issue-rate probe behind the ALU roofline (separate library)
+    cmd = ["hipcc", *hipcc_flags(), "-shared", os.path.join(CSRC, "valu_probe.hip"), "-o", PROBE_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 

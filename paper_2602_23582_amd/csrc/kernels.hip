@@ -1,18 +1,24 @@
 // HIP kernels of the RBSOG library for gfx950 (CDNA4, wave64).
 //
-// One force/pressure evaluation (Algorithm 1, steps 2-6) runs as
-//   k_sampler                       - both MH chains and the distinct-mode set (one workgroup, FP64)
-//   k_zero, k_fix, k_scan_*, k_fill_blocks, k_scatter, k_order
+// One force/pressure evaluation (Algorithm 1, steps 2-6) of a batch of
+// systems runs as
+//   k_sampler                       - both MH chains and the distinct-mode set (one workgroup per system, FP64)
+//   k_zero, k_fix, k_scan_*, k_scatter, k_order
 //                                   - fixed-point fractional coordinates, cell binning, stable sort
 //   k_pair                          - short-range SOG force, virial and energy over cell lists
 //   k_sk                            - structure factors of the distinct modes (per-block partials)
 //   k_rho_reduce, k_estimators      - FP64 combine, estimator coefficients, pressure and energy
-//   k_force                         - long-range force scatter, total force in caller order
-// Every reduction has a fixed order, so results are bitwise reproducible.
+//   k_force                         - long-range force scatter, total force in the caller's order
+// Each workgroup reads its (system, block) from a launch plan and touches only
+// that system's buffers.  Every reduction runs over one system's partials in
+// a fixed order, so results are bitwise reproducible and do not depend on the
+// other systems of the batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "rbsog_impl.hpp"
 
@@ -56,6 +62,42 @@ struct alignas(16) Coef {
     real kx, ky, kz, A, B;
 };
 
+// Buffer pointers read from a descriptor are generic pointers; accesses made
+// through gp() and gload() are issued as global-memory instructions, and a
+// load whose address is the same for the whole wavefront becomes a scalar load.
+#define RB_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ RB_GLOBAL T *gp(T *p)
+{
+    return (RB_GLOBAL T *)(p);
+}
+template <class T>
+__device__ __forceinline__ const RB_GLOBAL T *gp(const T *p)
+{
+    return (const RB_GLOBAL T *)(p);
+}
+// load of a struct (HIP vector types, records) as whole dwords
+template <class T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "dword multiple");
+    T out;
+    const RB_GLOBAL uint32_t *src = (const RB_GLOBAL uint32_t *)(p);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int k = 0; k < static_cast<int>(sizeof(T) / 4); ++k) dst[k] = src[k];
+    return out;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T *p, const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "dword multiple");
+    RB_GLOBAL uint32_t *dst = (RB_GLOBAL uint32_t *)(p);
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&v);
+#pragma unroll
+    for (int k = 0; k < static_cast<int>(sizeof(T) / 4); ++k) dst[k] = src[k];
+}
+
 __device__ inline float fix_to_real(int32_t v, float scale) { return static_cast<float>(v) * scale; }
 __device__ inline double fix_to_real(int64_t v, double scale) { return static_cast<double>(v) * scale; }
 
@@ -68,11 +110,6 @@ __device__ inline T wave_sum(T v)
 __device__ inline int wave_max(int v)
 {
     for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ inline int wave_min(int v)
-{
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
     return v;
 }
 
@@ -101,12 +138,12 @@ __device__ inline double unit_open(uint32_t hi, uint32_t lo)
 
 struct SampArgs {
     double L[3];
-    int P, M, variant;
+    int P, M, variant, mcap;
     uint32_t key0, key1, step, sys;
     const SogTables *tab;
     int32_t *mraw;     // m_r (P x 3) then m_nr (P x 3)
     int4 *modes;       // distinct modes
-    int32_t *cnt;      // [kMaxModes] r multiplicities, then [kMaxModes] nr
+    int32_t *cnt;      // [mcap] r multiplicities, then [mcap] nr
     StepResults *res;  // nd, status, acceptance counts
 };
 
@@ -178,9 +215,9 @@ __device__ void mode_weights(const SampArgs &a, const int m[3], double *w, doubl
     *R = k2 * a7 / a5;
 }
 
-// Algorithm 1 steps 2-3 for one system, one workgroup of 256 threads.
+// Algorithm 1 steps 2-3 for one system per workgroup of 256 threads.
 // Slot 0 holds the chain's initial state, slot t+1 the t-th proposal.
-__global__ __launch_bounds__(256) void k_sampler(SampArgs a)
+__global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp)
 {
 #pragma clang fp contract(off)
     __shared__ int3 s_mode[kMaxP + 1];
@@ -192,6 +229,24 @@ __global__ __launch_bounds__(256) void k_sampler(SampArgs a)
     __shared__ int s_cnt_r[kMaxP + 1], s_cnt_nr[kMaxP + 1];
     __shared__ int s_init, s_nd;
     __shared__ long long s_acc[2];
+
+    const SysDesc &D = desc[blockIdx.x];
+    const SysStep &St = stp[blockIdx.x];
+    SampArgs a;
+    for (int d = 0; d < 3; ++d) a.L[d] = St.L[d];
+    a.P = D.P;
+    a.M = D.M;
+    a.variant = D.variant;
+    a.mcap = D.mcap;
+    a.key0 = D.key0;
+    a.key1 = D.key1;
+    a.step = St.step;
+    a.sys = D.sys;
+    a.tab = &D.tab;
+    a.mraw = D.mraw;
+    a.modes = D.modes;
+    a.cnt = D.cnt;
+    a.res = D.res;
 
     const int tid = threadIdx.x;
     const int P = a.P;
@@ -336,10 +391,10 @@ __global__ __launch_bounds__(256) void k_sampler(SampArgs a)
         a.mraw[3 * (P + t) + 2] = mn.z;
     }
     __syncthreads();
-    for (int d = tid; d < kMaxModes; d += blockDim.x) {
+    for (int d = tid; d < a.mcap; d += blockDim.x) {
         const bool in = d < s_nd;
         a.cnt[d] = in ? s_cnt_r[d] : 0;
-        a.cnt[kMaxModes + d] = in ? s_cnt_nr[d] : 0;
+        a.cnt[a.mcap + d] = in ? s_cnt_nr[d] : 0;
     }
     if (tid == 0) {
         a.res->nd = s_nd;
@@ -353,32 +408,39 @@ __global__ __launch_bounds__(256) void k_sampler(SampArgs a)
 // Fixed point, binning and the stable cell sort
 // ----------------------------------------------------------------------------
 
-__global__ void k_zero(int32_t *a, int32_t *b, int64_t m)
+// per-cell counters to zero; block 0 also resets the pair work-queue counters
+__global__ __launch_bounds__(kCellBlock) void k_zero(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                     const int2 *__restrict__ plan, int32_t *__restrict__ ctrl)
 {
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (i < m) {
-        a[i] = 0;
-        b[i] = 0;
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const int64_t c = e.y * static_cast<int64_t>(kCellBlock) + threadIdx.x;
+    if (c <= stp[e.x].ncells) {
+        D.count[c] = 0;
+        D.cursor[c] = 0;
     }
+    if (blockIdx.x == 0 && threadIdx.x < 2) ctrl[threadIdx.x] = 0;
 }
 
 // s = x (1/L) wrapped into [0,1) by subtracting floor(s); u = s 2^bits; the
 // 32-bit cell coordinate is (u32 n) >> 32 with u32 the top 32 bits of u.
 template <class T>
-__global__ void k_fix(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                      const double *__restrict__ z, double ilx, double ily, double ilz, int nx, int ny,
-                      int nz, typename T::fix *__restrict__ u, int32_t *__restrict__ cell,
-                      int32_t *__restrict__ count)
+__global__ __launch_bounds__(kAtomBlock) void k_fix(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                    const int2 *__restrict__ plan)
 {
 #pragma clang fp contract(off)
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const SysStep &St = stp[e.x];
+    const int64_t n = D.n;
+    const int64_t i = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
     if (i >= n) return;
-    const double p[3] = {x[i], y[i], z[i]};
-    const double il[3] = {ilx, ily, ilz};
-    const int nc[3] = {nx, ny, nz};
+    const double p[3] = {gp(St.x)[i], gp(St.y)[i], gp(St.z)[i]};
+    const int nc[3] = {St.nc[0], St.nc[1], St.nc[2]};
+    RB_GLOBAL typename T::fix *u = gp(static_cast<typename T::fix *>(D.u));
     uint32_t c[3];
     for (int d = 0; d < 3; ++d) {
-        double s = p[d] * il[d];
+        double s = p[d] * St.iL[d];
         s -= floor(s);
         uint32_t top;
         if constexpr (sizeof(typename T::fix) == 4) {
@@ -392,15 +454,14 @@ __global__ void k_fix(int64_t n, const double *__restrict__ x, const double *__r
         }
         c[d] = static_cast<uint32_t>((static_cast<uint64_t>(top) * static_cast<uint32_t>(nc[d])) >> 32);
     }
-    const int32_t id = static_cast<int32_t>(c[0] + static_cast<uint32_t>(nx) * (c[1] + static_cast<uint32_t>(ny) * c[2]));
-    cell[i] = id;
-    atomicAdd(&count[id], 1);
+    const int32_t id = static_cast<int32_t>(c[0] + static_cast<uint32_t>(nc[0]) * (c[1] + static_cast<uint32_t>(nc[1]) * c[2]));
+    gp(D.cell)[i] = id;
+    atomicAdd(&D.count[id], 1);
 }
 
-// Three-pass exclusive scan of the per-cell counts (and of the per-cell number
-// of 64-atom pair blocks) over m cells; 1024 cells per block, at most 1024 blocks.
-constexpr int kScanBlock = 1024;
-
+// Two-level exclusive scan of the per-cell counts (and of the per-cell number
+// of 64-atom pair blocks) of each system: kScanBlock cells per workgroup, at
+// most 1024 workgroups per system.
 __device__ inline void block_scan_256(int *s_a, int tid)
 {
     // Hillis-Steele inclusive scan over 256 ints in shared memory
@@ -412,20 +473,22 @@ __device__ inline void block_scan_256(int *s_a, int tid)
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_local(const int32_t *__restrict__ count, int64_t m,
-                                                    int32_t *__restrict__ start, int32_t *__restrict__ bstart,
-                                                    int32_t *__restrict__ nblk, int32_t *__restrict__ sums)
+__global__ __launch_bounds__(256) void k_scan_local(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                    const int2 *__restrict__ plan)
 {
     __shared__ int s_a[256], s_b[256];
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const int64_t m = stp[e.x].ncells;
     const int tid = threadIdx.x;
-    const int64_t base = blockIdx.x * static_cast<int64_t>(kScanBlock) + 4 * tid;
+    const int64_t base = e.y * static_cast<int64_t>(kScanBlock) + 4 * tid;
     int va[4], vb[4], ta = 0, tb = 0;
     for (int k = 0; k < 4; ++k) {
         const int64_t i = base + k;
-        const int c = i < m ? count[i] : 0;
+        const int c = i < m ? D.count[i] : 0;
         va[k] = c;
         vb[k] = (c + kPairWave - 1) / kPairWave;
-        if (i < m) nblk[i] = vb[k];
+        if (i < m) D.nblk[i] = vb[k];
         ta += va[k];
         tb += vb[k];
     }
@@ -438,21 +501,25 @@ __global__ __launch_bounds__(256) void k_scan_local(const int32_t *__restrict__ 
     for (int k = 0; k < 4; ++k) {
         const int64_t i = base + k;
         if (i < m) {
-            start[i] = ea;
-            bstart[i] = eb;
+            D.start[i] = ea;
+            D.bstart[i] = eb;
         }
         ea += va[k];
         eb += vb[k];
     }
     if (tid == 255) {
-        sums[2 * blockIdx.x] = s_a[255];
-        sums[2 * blockIdx.x + 1] = s_b[255];
+        D.scan_tmp[2 * e.y] = s_a[255];
+        D.scan_tmp[2 * e.y + 1] = s_b[255];
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_top(int32_t *sums, int nb)
+// one workgroup per system: exclusive scan of the block sums
+__global__ __launch_bounds__(256) void k_scan_top(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp)
 {
     __shared__ int s_a[256], s_b[256];
+    const SysDesc &D = desc[blockIdx.x];
+    const int nb = static_cast<int>((stp[blockIdx.x].ncells + kScanBlock - 1) / kScanBlock);
+    int32_t *sums = D.scan_tmp;
     const int tid = threadIdx.x;
     int va[4], vb[4], ta = 0, tb = 0;
     for (int k = 0; k < 4; ++k) {
@@ -484,61 +551,64 @@ __global__ __launch_bounds__(256) void k_scan_top(int32_t *sums, int nb)
     }
 }
 
-__global__ void k_scan_add(int32_t *__restrict__ start, int32_t *__restrict__ bstart, const int32_t *__restrict__ sums,
-                           int64_t m)
+// final starts, and the pair-block table (cell, sub-block) of each cell
+__global__ __launch_bounds__(kCellBlock) void k_scan_add(const SysDesc *__restrict__ desc,
+                                                         const SysStep *__restrict__ stp,
+                                                         const int2 *__restrict__ plan)
 {
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const int64_t m = stp[e.x].ncells;
+    const int64_t i = e.y * static_cast<int64_t>(kCellBlock) + threadIdx.x;
+    const int32_t *sums = D.scan_tmp;
     if (i < m) {
         const int64_t b = i / kScanBlock;
-        start[i] += sums[2 * b];
-        bstart[i] += sums[2 * b + 1];
+        D.start[i] += sums[2 * b];
+        const int b0 = D.bstart[i] + sums[2 * b + 1];
+        D.bstart[i] = b0;
+        const int nb = D.nblk[i];
+        for (int k = 0; k < nb; ++k) D.blocks[b0 + k] = make_int2(static_cast<int>(i), k);
     } else if (i == m) {
-        start[m] = sums[2 * 1024];
-        bstart[m] = sums[2 * 1024 + 1];
+        D.start[m] = sums[2 * 1024];
+        D.bstart[m] = sums[2 * 1024 + 1];
     }
 }
 
-__global__ void k_fill_blocks(const int32_t *__restrict__ nblk, const int32_t *__restrict__ bstart, int64_t m,
-                              int2 *__restrict__ blocks)
+__global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restrict__ desc, const int2 *__restrict__ plan)
 {
-    const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (c >= m) return;
-    const int b0 = bstart[c];
-    for (int k = 0; k < nblk[c]; ++k) blocks[b0 + k] = make_int2(static_cast<int>(c), k);
-}
-
-__global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell, const int32_t *__restrict__ start,
-                          int32_t *__restrict__ cursor, int32_t *__restrict__ perm_tmp)
-{
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (i >= n) return;
-    const int c = cell[i];
-    perm_tmp[start[c] + atomicAdd(&cursor[c], 1)] = static_cast<int32_t>(i);
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const int64_t i = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
+    if (i >= D.n) return;
+    const int c = gp(D.cell)[i];
+    gp(D.perm_tmp)[gp(D.start)[c] + atomicAdd(&D.cursor[c], 1)] = static_cast<int32_t>(i);
 }
 
 // Within each cell, atoms keep the caller's order: the slot of atom i is the
 // cell start plus the number of atoms of its cell with a smaller index.
 template <class T>
-__global__ void k_order(int64_t n, const int32_t *__restrict__ perm_tmp, const int32_t *__restrict__ cell,
-                        const int32_t *__restrict__ start, const typename T::fix *__restrict__ u,
-                        const typename T::real *__restrict__ q, int32_t *__restrict__ perm,
-                        typename T::Rec *__restrict__ rec)
+__global__ __launch_bounds__(kAtomBlock) void k_order(const SysDesc *__restrict__ desc, const int2 *__restrict__ plan)
 {
-    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const int64_t n = D.n;
+    const int64_t t = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
     if (t >= n) return;
+    const RB_GLOBAL int32_t *perm_tmp = gp(D.perm_tmp);
     const int i = perm_tmp[t];
-    const int c = cell[i];
-    const int s0 = start[c], s1 = start[c + 1];
+    const int c = gp(D.cell)[i];
+    const int s0 = gp(D.start)[c], s1 = gp(D.start)[c + 1];
     int rank = 0;
     for (int j = s0; j < s1; ++j) rank += perm_tmp[j] < i;
     const int slot = s0 + rank;
-    perm[slot] = i;
+    gp(D.perm)[slot] = i;
+    const RB_GLOBAL typename T::fix *u = gp(static_cast<const typename T::fix *>(D.u));
     typename T::Rec r;
     r.x = u[i];
     r.y = u[n + i];
     r.z = u[2 * n + i];
-    r.q = q[i];
-    rec[slot] = r;
+    r.q = gp(static_cast<const typename T::real *>(D.q))[i];
+    gstore(static_cast<typename T::Rec *>(D.rec) + slot, r);
 }
 
 // ----------------------------------------------------------------------------
@@ -569,20 +639,6 @@ constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round (byt
 constexpr int kListCap = RBSOG_PAIR_LISTCAP; // per-lane list capacity between flushes (>= 64)
 constexpr int kMaxRanges = 18;
 static_assert(kChunk <= 256 && kChunk % 64 == 0 && kListCap >= 64, "pair tiling");
-
-struct PairArgs {
-    int64_t n;
-    int nx, ny, nz;
-    double Lx, Ly, Lz;
-    const int32_t *start;
-    const int32_t *bstart;
-    const int2 *blocks;
-    int64_t ncells;
-    const void *rec;
-    const SogTables *tab;
-    void *fsr;       // short-range force, sorted order, 3 planes of n
-    double *part;    // 8 doubles per block: vir xx yy zz xy xz yz, U, pair count
-};
 
 template <class T>
 struct PairAcc {
@@ -712,49 +768,52 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
     acc.u += qq * (rinv - sw);
 }
 
+template <class T>
+struct PairShared {
+    typename T::Rec tile[kChunk];
+    __attribute__((aligned(16))) float rel[3][kChunk];  // filter coordinates (fast filter)
+    uint8_t list[kListCap * 64];
+    int pre[kMaxRanges + 1];  // flattened-neighbourhood offset of each range
+    int beg[kMaxRanges];
+};
+
+// One pair block b of system D (one wavefront).
 template <class T, int M>
-__global__ __launch_bounds__(64) void k_pair(PairArgs a)
+__device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, const SysStep &St, int b)
 {
     using real = typename T::real;
     using Rec = typename T::Rec;
     using fix = typename T::fix;
     using sfix = typename T::sfix;
-    __shared__ Rec s_tile[kChunk];
-    __shared__ __attribute__((aligned(16))) float s_rel[3][kChunk];  // filter coordinates (fast filter)
-    __shared__ uint8_t s_list[kListCap * 64];
-    __shared__ int s_pre[kMaxRanges + 1];  // flattened-neighbourhood offset of each range
-    __shared__ int s_beg[kMaxRanges];
-
     const int lane = threadIdx.x;
-    const int b = blockIdx.x;
-    const int nb_total = a.bstart[a.ncells];
-    double *part = a.part + 8 * static_cast<int64_t>(b);
-    if (b >= nb_total) {
-        if (lane < 8) part[lane] = 0.0;
-        return;
-    }
-    const Rec *__restrict__ rec = static_cast<const Rec *>(a.rec);
+    const int ncells = St.ncells;
+    const int nb_total = gp(D.bstart)[ncells];
+    double *part = D.pair_part + 8 * static_cast<int64_t>(b);
+    if (b >= nb_total) return;  // slot beyond this step's blocks: the reduction never reads it
+    const Rec *__restrict__ rec = static_cast<const Rec *>(D.rec);
     Weights<T, M> W;
-    load_weights<T, M>(W, a.tab);
+    load_weights<T, M>(W, &D.tab);
+    const int nx = St.nc[0], ny = St.nc[1], nz = St.nc[2];
     real sx, sy, sz, rc2;
     if constexpr (sizeof(real) == 4) {
-        sx = static_cast<float>(a.Lx * 0x1.0p-32);
-        sy = static_cast<float>(a.Ly * 0x1.0p-32);
-        sz = static_cast<float>(a.Lz * 0x1.0p-32);
-        rc2 = a.tab->rc2_32;
+        sx = static_cast<float>(St.L[0] * 0x1.0p-32);
+        sy = static_cast<float>(St.L[1] * 0x1.0p-32);
+        sz = static_cast<float>(St.L[2] * 0x1.0p-32);
+        rc2 = D.tab.rc2_32;
     } else {
-        sx = a.Lx * 0x1.0p-64;
-        sy = a.Ly * 0x1.0p-64;
-        sz = a.Lz * 0x1.0p-64;
-        rc2 = a.tab->rc2;
+        sx = St.L[0] * 0x1.0p-64;
+        sy = St.L[1] * 0x1.0p-64;
+        sz = St.L[2] * 0x1.0p-64;
+        rc2 = D.tab.rc2;
     }
-    const int2 cb = a.blocks[b];
+    const RB_GLOBAL int32_t *start = gp(D.start);
+    const int2 cb = gload(D.blocks + b);
     const int c = cb.x;
-    const int cs = a.start[c], ce = a.start[c + 1];
+    const int cs = start[c], ce = start[c + 1];
     const int i = cs + cb.y * kPairWave + lane;
     const bool valid = i < ce;
     Rec ri{};
-    if (valid) ri = rec[i];
+    if (valid) ri = gload(rec + i);
     const real rc2_lane = valid ? rc2 : static_cast<real>(-1);  // padding lanes find no partner
     // Fast filter (FP32, at least 5 cells per edge): candidates are tested in
     // float coordinates relative to the first atom of the block, o.  With five
@@ -764,7 +823,7 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
     // float rounding; the pair evaluation applies the exact test on fixed-point
     // differences.
     constexpr bool kIsF32 = sizeof(real) == 4;
-    const bool fast = RBSOG_FAST_FILTER && kIsF32 && a.nx >= 5 && a.ny >= 5 && a.nz >= 5;
+    const bool fast = RBSOG_FAST_FILTER && kIsF32 && nx >= 5 && ny >= 5 && nz >= 5;
     const fix ox = static_cast<fix>(__shfl(static_cast<long long>(ri.x), 0, 64));
     const fix oy_ = static_cast<fix>(__shfl(static_cast<long long>(ri.y), 0, 64));
     const fix oz_ = static_cast<fix>(__shfl(static_cast<long long>(ri.z), 0, 64));
@@ -773,45 +832,45 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
     const float xi = static_cast<float>(static_cast<sfix>(ri.x - ox)) * static_cast<float>(sx);
     const float yi = static_cast<float>(static_cast<sfix>(ri.y - oy_)) * static_cast<float>(sy);
     const float zi = static_cast<float>(static_cast<sfix>(ri.z - oz_)) * static_cast<float>(sz);
-    const int cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / (a.nx * a.ny);
-    const int oy = a.ny >= 3 ? 1 : 0, oz = a.nz >= 3 ? 1 : 0;
+    const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+    const int oy = ny >= 3 ? 1 : 0, oz = nz >= 3 ? 1 : 0;
 
     // neighbour ranges: one per row (dy, dz), split where the x-run wraps;
     // they are concatenated into one flattened candidate index
     if (lane == 0) {
         int nr = 0;
         auto put = [&](int lo, int hi) {
-            s_beg[nr] = lo;
-            s_pre[nr + 1] = hi - lo;  // length for now, prefix sums below
+            sh.beg[nr] = lo;
+            sh.pre[nr + 1] = hi - lo;  // length for now, prefix sums below
             ++nr;
         };
         for (int dz = -oz; dz <= oz; ++dz) {
-            const int jz = (cz + dz + a.nz) % a.nz;
+            const int jz = (cz + dz + nz) % nz;
             for (int dy = -oy; dy <= oy; ++dy) {
-                const int jy = (cy + dy + a.ny) % a.ny;
-                const int row = a.nx * (jy + a.ny * jz);
-                if (a.nx < 3) {
-                    put(a.start[row], a.start[row + a.nx]);
+                const int jy = (cy + dy + ny) % ny;
+                const int row = nx * (jy + ny * jz);
+                if (nx < 3) {
+                    put(start[row], start[row + nx]);
                 } else if (cx == 0) {
-                    put(a.start[row + a.nx - 1], a.start[row + a.nx]);
-                    put(a.start[row], a.start[row + 2]);
-                } else if (cx == a.nx - 1) {
-                    put(a.start[row + cx - 1], a.start[row + a.nx]);
-                    put(a.start[row], a.start[row + 1]);
+                    put(start[row + nx - 1], start[row + nx]);
+                    put(start[row], start[row + 2]);
+                } else if (cx == nx - 1) {
+                    put(start[row + cx - 1], start[row + nx]);
+                    put(start[row], start[row + 1]);
                 } else {
-                    put(a.start[row + cx - 1], a.start[row + cx + 2]);
+                    put(start[row + cx - 1], start[row + cx + 2]);
                 }
             }
         }
-        s_pre[0] = 0;
+        sh.pre[0] = 0;
         for (int k = 0; k < kMaxRanges; ++k) {
-            const int len = k < nr ? s_pre[k + 1] : 0;
-            if (k >= nr) s_beg[k] = 0;
-            s_pre[k + 1] = s_pre[k] + len;
+            const int len = k < nr ? sh.pre[k + 1] : 0;
+            if (k >= nr) sh.beg[k] = 0;
+            sh.pre[k + 1] = sh.pre[k] + len;
         }
     }
     __syncthreads();
-    const int total = s_pre[kMaxRanges];
+    const int total = sh.pre[kMaxRanges];
     // Candidates go to the chunks in groups of 4 consecutive records, group g to
     // chunk g mod nch: every chunk samples the whole neighbourhood, so each
     // lane's share of partners is about the same in every chunk and the lists
@@ -830,12 +889,12 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
         PairAcc<T> acc;
         int e = 0;
         for (; e + 2 <= kmax; e += 2) {
-            const int j0 = s_list[e * 64 + lane], j1 = s_list[(e + 1) * 64 + lane];
-            const Rec r0 = s_tile[j0], r1 = s_tile[j1];
+            const int j0 = sh.list[e * 64 + lane], j1 = sh.list[(e + 1) * 64 + lane];
+            const Rec r0 = sh.tile[j0], r1 = sh.tile[j1];
             if (e < cnt) pair_eval<T, M>(ri, r0, sx, sy, sz, rc2, W, acc);
             if (e + 1 < cnt) pair_eval<T, M>(ri, r1, sx, sy, sz, rc2, W, acc);
         }
-        if (e < kmax && e < cnt) pair_eval<T, M>(ri, s_tile[s_list[e * 64 + lane]], sx, sy, sz, rc2, W, acc);
+        if (e < kmax && e < cnt) pair_eval<T, M>(ri, sh.tile[sh.list[e * 64 + lane]], sx, sy, sz, rc2, W, acc);
         hits += acc.n;
         cnt = 0;
         fx += acc.fx;
@@ -859,13 +918,13 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
         for (int k = lane; k < filled; k += 64) {
             const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
             int r = 0;
-            while (r + 1 < kMaxRanges && s_pre[r + 1] <= f) ++r;
-            const Rec rj = rec[s_beg[r] + (f - s_pre[r])];
-            s_tile[k] = rj;
+            while (r + 1 < kMaxRanges && sh.pre[r + 1] <= f) ++r;
+            const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
+            sh.tile[k] = rj;
             if (fast) {
-                s_rel[0][k] = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
-                s_rel[1][k] = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
-                s_rel[2][k] = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
+                sh.rel[0][k] = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
+                sh.rel[1][k] = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
+                sh.rel[2][k] = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
             }
         }
         __syncthreads();
@@ -876,31 +935,31 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
             int s = s0;
             if (fast) {
                 for (; s + 4 <= s1; s += 4) {
-                    const float4 X = *reinterpret_cast<const float4 *>(&s_rel[0][s]);
-                    const float4 Y = *reinterpret_cast<const float4 *>(&s_rel[1][s]);
-                    const float4 Z = *reinterpret_cast<const float4 *>(&s_rel[2][s]);
+                    const float4 X = *reinterpret_cast<const float4 *>(&sh.rel[0][s]);
+                    const float4 Y = *reinterpret_cast<const float4 *>(&sh.rel[1][s]);
+                    const float4 Z = *reinterpret_cast<const float4 *>(&sh.rel[2][s]);
                     const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w},
                                 zs[4] = {Z.x, Z.y, Z.z, Z.w};
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const float dx = xi - xs[k], dy = yi - ys[k], dz = zi - zs[k];
                         const float d2 = dx * dx + dy * dy + dz * dz;
-                        s_list[cnt * 64 + lane] = static_cast<uint8_t>(s + k);
+                        sh.list[cnt * 64 + lane] = static_cast<uint8_t>(s + k);
                         cnt += (d2 < rcf2_lane) & (d2 > 0.0f);
                     }
                 }
                 for (; s < s1; ++s) {
-                    const float dx = xi - s_rel[0][s], dy = yi - s_rel[1][s], dz = zi - s_rel[2][s];
+                    const float dx = xi - sh.rel[0][s], dy = yi - sh.rel[1][s], dz = zi - sh.rel[2][s];
                     const float d2 = dx * dx + dy * dy + dz * dz;
-                    s_list[cnt * 64 + lane] = static_cast<uint8_t>(s);
+                    sh.list[cnt * 64 + lane] = static_cast<uint8_t>(s);
                     cnt += (d2 < rcf2_lane) & (d2 > 0.0f);
                 }
             } else {
                 for (; s < s1; ++s) {
                     real dx, dy, dz;
-                    displacement<T>(ri, s_tile[s], sx, sy, sz, dx, dy, dz);
+                    displacement<T>(ri, sh.tile[s], sx, sy, sz, dx, dy, dz);
                     const real d2 = dx * dx + dy * dy + dz * dz;
-                    s_list[cnt * 64 + lane] = static_cast<uint8_t>(s);
+                    sh.list[cnt * 64 + lane] = static_cast<uint8_t>(s);
                     cnt += (d2 < rc2_lane) & (d2 > 0);
                 }
             }
@@ -910,16 +969,45 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
         __syncthreads();
     }
     if (valid) {
-        real *fsr = static_cast<real *>(a.fsr);
+        RB_GLOBAL real *fsr = gp(static_cast<real *>(D.fsr));
         fsr[i] = static_cast<real>(fx);
-        fsr[a.n + i] = static_cast<real>(fy);
-        fsr[2 * a.n + i] = static_cast<real>(fz);
+        fsr[D.n + i] = static_cast<real>(fy);
+        fsr[2 * D.n + i] = static_cast<real>(fz);
     }
     // full shell: each pair was seen from both sides
     double out[8] = {0.5 * v[0], 0.5 * v[1], 0.5 * v[2], 0.5 * v[3], 0.5 * v[4], 0.5 * v[5], 0.5 * uu, 0.5 * hits};
     for (int k = 0; k < 8; ++k) out[k] = wave_sum(out[k]);
     if (lane == 0)
-        for (int k = 0; k < 8; ++k) part[k] = out[k];
+        for (int k = 0; k < 8; ++k) gp(part)[k] = out[k];
+}
+
+// Static schedule: workgroup g runs plan entry g.
+template <class T, int M>
+__global__ __launch_bounds__(64) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                             const int2 *__restrict__ plan)
+{
+    __shared__ PairShared<T> sh;
+    const int2 e = plan[blockIdx.x];
+    pair_block<T, M>(sh, desc[e.x], stp[e.x], e.y);
+}
+
+// Persistent schedule: a fixed number of workgroups take plan entries from a
+// global counter (zeroed by k_zero) until all nitems are taken; every
+// workgroup leaves once the counter has passed nitems.
+template <class T, int M>
+__global__ __launch_bounds__(64) void k_pair_queue(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                   const int2 *__restrict__ plan, int nitems, int32_t *ctrl)
+{
+    __shared__ PairShared<T> sh;
+    for (;;) {
+        int idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(&ctrl[0], 1);
+        idx = __shfl(idx, 0, 64);
+        if (idx >= nitems) break;
+        const int2 e = plan[idx];
+        pair_block<T, M>(sh, desc[e.x], stp[e.x], e.y);
+        __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -929,17 +1017,9 @@ __global__ __launch_bounds__(64) void k_pair(PairArgs a)
 // The phase m.u mod 2^32 of the 32-bit fixed-point fractional coordinate u is
 // exact: with u = 2^16 h + l (h, l < 2^16) it is ((m.h) << 16) + m.l, six
 // 24-bit multiply-adds.  The hardware sine and cosine take the phase in
-// revolutions.  Each workgroup owns kSkChunk atoms; its 256 threads are
-// (mode, slice) pairs, and the per-mode partial of the workgroup goes to
-// global memory in FP64.
-
-struct SkArgs {
-    int64_t n;
-    const void *rec;
-    const int4 *modes;
-    const StepResults *res;
-    double *part;  // [blocks][kMaxModes] x 2
-};
+// revolutions.  Each workgroup owns kSkChunk atoms of one system; its 256
+// threads are (mode, slice) pairs, and the per-mode partial of the workgroup
+// goes to global memory in FP64.
 
 struct alignas(16) SkAtom32 {
     int hx, hy, hz;
@@ -966,17 +1046,33 @@ __device__ inline void phase_sincos64(const int4 &m, const F64::Rec &r, double &
     sincospi(2.0 * rev, &s, &c);
 }
 
+__device__ inline SkAtom32 split_atom(const F32::Rec &r)
+{
+    SkAtom32 at;
+    at.hx = static_cast<int>(r.x >> 16);
+    at.hy = static_cast<int>(r.y >> 16);
+    at.hz = static_cast<int>(r.z >> 16);
+    at.lx = static_cast<int>(r.x & 0xFFFFu);
+    at.ly = static_cast<int>(r.y & 0xFFFFu);
+    at.lz = static_cast<int>(r.z & 0xFFFFu);
+    at.q = r.q;
+    at.pad = 0;
+    return at;
+}
+
 template <class T>
-__global__ __launch_bounds__(256) void k_sk(SkArgs a)
+__global__ __launch_bounds__(256) void k_sk(const SysDesc *__restrict__ desc, const int2 *__restrict__ plan)
 {
     using Atom = typename std::conditional<sizeof(typename T::real) == 4, SkAtom32, typename T::Rec>::type;
     __shared__ Atom s_at[256];
     __shared__ double s_red[2][256];
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
     const int tid = threadIdx.x;
-    const int nd = a.res->nd;
-    const int64_t a0 = blockIdx.x * static_cast<int64_t>(kSkChunk);
-    const int64_t a1 = min(a.n, a0 + kSkChunk);
-    const typename T::Rec *__restrict__ rec = static_cast<const typename T::Rec *>(a.rec);
+    const int nd = gp(D.res)->nd;
+    const int64_t a0 = e.y * static_cast<int64_t>(kSkChunk);
+    const int64_t a1 = min(D.n, a0 + kSkChunk);
+    const typename T::Rec *__restrict__ rec = static_cast<const typename T::Rec *>(D.rec);
     const int nsl = nd <= 128 ? max(1, 256 / max(nd, 1)) : 1;
     const int items = nd <= 128 ? nsl * nd : 256;
     const int passes = nd <= 128 ? 1 : (nd + 255) / 256;
@@ -984,26 +1080,14 @@ __global__ __launch_bounds__(256) void k_sk(SkArgs a)
         const int d = nd <= 128 ? tid % max(nd, 1) : pass * 256 + tid;
         const int sl = nd <= 128 ? tid / max(nd, 1) : 0;
         const bool active = tid < items && d < nd;
-        const int4 m = active ? a.modes[d] : make_int4(0, 0, 0, 0);
+        const int4 m = active ? gload(D.modes + d) : make_int4(0, 0, 0, 0);
         double accr = 0.0, acci = 0.0;
         for (int64_t c0 = a0; c0 < a1; c0 += 256) {
             const int cnt = static_cast<int>(min(static_cast<int64_t>(256), a1 - c0));
             if (tid < cnt) {
-                const typename T::Rec r = rec[c0 + tid];
-                if constexpr (sizeof(typename T::real) == 4) {
-                    SkAtom32 at;
-                    at.hx = static_cast<int>(r.x >> 16);
-                    at.hy = static_cast<int>(r.y >> 16);
-                    at.hz = static_cast<int>(r.z >> 16);
-                    at.lx = static_cast<int>(r.x & 0xFFFFu);
-                    at.ly = static_cast<int>(r.y & 0xFFFFu);
-                    at.lz = static_cast<int>(r.z & 0xFFFFu);
-                    at.q = r.q;
-                    at.pad = 0;
-                    s_at[tid] = at;
-                } else {
-                    s_at[tid] = r;
-                }
+                const typename T::Rec r = gload(rec + c0 + tid);
+                if constexpr (sizeof(typename T::real) == 4) s_at[tid] = split_atom(r);
+                else s_at[tid] = r;
             }
             __syncthreads();
             if (active) {
@@ -1027,14 +1111,14 @@ __global__ __launch_bounds__(256) void k_sk(SkArgs a)
         s_red[0][tid] = accr;
         s_red[1][tid] = acci;
         __syncthreads();
-        if (tid < 256 && sl == 0 && active) {
+        if (sl == 0 && active) {
             double r = 0.0, im = 0.0;
             const int stride = nd <= 128 ? nd : 0;
             for (int k = 0; k < nsl; ++k) {
                 r += s_red[0][tid + k * stride];
                 im += s_red[1][tid + k * stride];
             }
-            double *p = a.part + 2 * (blockIdx.x * static_cast<int64_t>(kMaxModes) + d);
+            RB_GLOBAL double *p = gp(D.rho_part) + 2 * (e.y * static_cast<int64_t>(D.mcap) + d);
             p[0] = r;
             p[1] = im;
         }
@@ -1060,31 +1144,38 @@ __device__ inline double block_sum_256(double v, double *s_tmp)
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_rho_reduce(const double *__restrict__ part, int64_t nblk,
-                                                    const double *__restrict__ pair_part, int64_t npair,
-                                                    double *__restrict__ rho, StepResults *res)
+// plan entry (s, k): k < mcap sums mode k over the structure-factor blocks,
+// k == mcap sums the pair-kernel partials
+__global__ __launch_bounds__(256) void k_rho_reduce(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                    const int2 *__restrict__ plan)
 {
     __shared__ double s_tmp[256];
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
     const int tid = threadIdx.x;
-    const int d = blockIdx.x;
-    if (d < kMaxModes) {
-        if (d >= res->nd) return;
+    const int d = e.y;
+    StepResults *res = D.res;
+    if (d < D.mcap) {
+        if (d >= gp(res)->nd) return;
         double r = 0.0, im = 0.0;
-        for (int64_t b = tid; b < nblk; b += 256) {
-            const double *p = part + 2 * (b * kMaxModes + d);
+        const RB_GLOBAL double *rp = gp(D.rho_part);
+        for (int64_t b = tid; b < D.sk_blocks; b += 256) {
+            const RB_GLOBAL double *p = rp + 2 * (b * D.mcap + d);
             r += p[0];
             im += p[1];
         }
         r = block_sum_256(r, s_tmp);
         im = block_sum_256(im, s_tmp);
         if (tid == 0) {
-            rho[2 * d] = r;
-            rho[2 * d + 1] = im;
+            D.rho[2 * d] = r;
+            D.rho[2 * d + 1] = im;
         }
     } else {
+        const int64_t npair = gp(D.bstart)[stp[e.x].ncells];
+        const RB_GLOBAL double *pp = gp(D.pair_part);
         double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int64_t b = tid; b < npair; b += 256)
-            for (int k = 0; k < 8; ++k) acc[k] += pair_part[8 * b + k];
+            for (int k = 0; k < 8; ++k) acc[k] += pp[8 * b + k];
         for (int k = 0; k < 8; ++k) {
             const double s = block_sum_256(acc[k], s_tmp);
             if (tid == 0) {
@@ -1097,38 +1188,31 @@ __global__ __launch_bounds__(256) void k_rho_reduce(const double *__restrict__ p
 }
 
 // Estimators of Sec. 3.2 and App. B over the distinct modes d with
-// multiplicities c^r_d, c^nr_d (one workgroup):
+// multiplicities c^r_d, c^nr_d (one workgroup per system):
 //   P^{F,r*}  =  S^r/(4 V^2 P) sum_d c^r_d |rho_d|^2/|k_d|^2 I            (eq. P_approx_r)
 //   P^{F,nr*} = -S^nr/(8 V^2 P) sum_d c^nr_d |rho_d|^2 k_d k_d^T/|k_d|^4  (eq. P_approx_nr)
 //   U^{F*}    =  S/(2 V P) sum_d c^r_d |rho_d|^2/|k_d|^2, S = S^r/2
 //   force coefficients a_d = (S/(P V)) c^r_d/|k_d|^2                      (eq. f_approx)
-struct EstArgs {
-    double L[3];
-    double Sr, Snr, ck, Uself;
-    int P;
-    const int4 *modes;
-    const int32_t *cnt;
-    const double *rho;
-    void *coef;
-    int fp64;
-    StepResults *res;
-};
-
-__global__ __launch_bounds__(256) void k_estimators(EstArgs a)
+template <class T>
+__global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp)
 {
     __shared__ double s_tmp[256];
+    const SysDesc &D = desc[blockIdx.x];
+    const SysStep &St = stp[blockIdx.x];
     const int tid = threadIdx.x;
-    const int nd = a.res->nd;
-    const double V = a.L[0] * a.L[1] * a.L[2];
-    const double S = 0.5 * a.Sr;
+    const int nd = gp(D.res)->nd;
+    const double L[3] = {St.L[0], St.L[1], St.L[2]};
+    const double V = L[0] * L[1] * L[2];
+    const double S = 0.5 * St.Sr;
+    const int P = D.P;
     double sr = 0.0, snr[6] = {0, 0, 0, 0, 0, 0};
     for (int d = tid; d < nd; d += 256) {
-        const int4 m = a.modes[d];
-        const double k[3] = {2.0 * kPi * m.x / a.L[0], 2.0 * kPi * m.y / a.L[1], 2.0 * kPi * m.z / a.L[2]};
+        const int4 m = D.modes[d];
+        const double k[3] = {2.0 * kPi * m.x / L[0], 2.0 * kPi * m.y / L[1], 2.0 * kPi * m.z / L[2]};
         const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-        const double re = a.rho[2 * d], im = a.rho[2 * d + 1];
+        const double re = D.rho[2 * d], im = D.rho[2 * d + 1];
         const double r2 = re * re + im * im;
-        const int cr = a.cnt[d], cnr = a.cnt[kMaxModes + d];
+        const int cr = D.cnt[d], cnr = D.cnt[D.mcap + d];
         sr += cr * r2 / k2;
         const double g = cnr * r2 / (k2 * k2);
         snr[0] += g * k[0] * k[0];
@@ -1137,32 +1221,27 @@ __global__ __launch_bounds__(256) void k_estimators(EstArgs a)
         snr[3] += g * k[0] * k[1];
         snr[4] += g * k[0] * k[2];
         snr[5] += g * k[1] * k[2];
-        const double ad = S / (a.P * V) * cr / k2;
-        if (a.fp64) {
-            Coef<double> cf;
-            cf.mx = m.x; cf.my = m.y; cf.mz = m.z; cf.pad = 0;
-            cf.kx = k[0]; cf.ky = k[1]; cf.kz = k[2];
-            cf.A = ad * im;
-            cf.B = ad * re;
-            static_cast<Coef<double> *>(a.coef)[d] = cf;
-        } else {
-            Coef<float> cf;
-            cf.mx = m.x; cf.my = m.y; cf.mz = m.z; cf.pad = 0;
-            cf.kx = static_cast<float>(k[0]);
-            cf.ky = static_cast<float>(k[1]);
-            cf.kz = static_cast<float>(k[2]);
-            cf.A = static_cast<float>(ad * im);
-            cf.B = static_cast<float>(ad * re);
-            static_cast<Coef<float> *>(a.coef)[d] = cf;
-        }
+        const double ad = S / (P * V) * cr / k2;
+        using real = typename T::real;
+        Coef<real> cf;
+        cf.mx = m.x;
+        cf.my = m.y;
+        cf.mz = m.z;
+        cf.pad = 0;
+        cf.kx = static_cast<real>(k[0]);
+        cf.ky = static_cast<real>(k[1]);
+        cf.kz = static_cast<real>(k[2]);
+        cf.A = static_cast<real>(ad * im);
+        cf.B = static_cast<real>(ad * re);
+        static_cast<Coef<real> *>(D.coef)[d] = cf;
     }
     sr = block_sum_256(sr, s_tmp);
     for (int k = 0; k < 6; ++k) snr[k] = block_sum_256(snr[k], s_tmp);
     if (tid == 0) {
-        StepResults *r = a.res;
-        const double ck = a.ck;
-        const double pr = ck * a.Sr / (4.0 * V * V * a.P) * sr;
-        const double cnr = -ck * a.Snr / (8.0 * V * V * a.P);
+        StepResults *r = D.res;
+        const double ck = D.ck;
+        const double pr = ck * St.Sr / (4.0 * V * V * P) * sr;
+        const double cnr = -ck * St.Snr / (8.0 * V * V * P);
         const int ix[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
         for (int al = 0; al < 3; ++al)
             for (int be = 0; be < 3; ++be) {
@@ -1172,12 +1251,12 @@ __global__ __launch_bounds__(256) void k_estimators(EstArgs a)
                 r->PN[q] = ck * r->vir[ix[al][be]] / V;
                 r->Ptot[q] = r->PN[q] + r->Pr[q] + r->Pnr[q];
             }
-        r->UF = ck * S / (2.0 * V * a.P) * sr;
+        r->UF = ck * S / (2.0 * V * P) * sr;
         r->UN = ck * r->UN;
         for (int k = 0; k < 6; ++k) r->vir[k] *= ck;
-        r->Uself = a.Uself;
-        r->Sr = a.Sr;
-        r->Snr = a.Snr;
+        r->Uself = D.Uself;
+        r->Sr = St.Sr;
+        r->Snr = St.Snr;
     }
 }
 
@@ -1185,43 +1264,28 @@ __global__ __launch_bounds__(256) void k_estimators(EstArgs a)
 // Long-range force scatter (eq. f_approx) and the total force in caller order
 // ----------------------------------------------------------------------------
 
-struct ForceArgs {
-    int64_t n;
-    const void *rec;
-    const int32_t *perm;
-    const void *fsr;
-    const void *coef;
-    const StepResults *res;
-    double ck;
-    double *fx, *fy, *fz;
-};
-
 template <class T>
-__global__ __launch_bounds__(256) void k_force(ForceArgs a)
+__global__ __launch_bounds__(kAtomBlock) void k_force(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                      const int2 *__restrict__ plan)
 {
     using real = typename T::real;
-    const int tid = threadIdx.x;
-    const int nd = a.res->nd;
-    const Coef<real> *__restrict__ s_cf = static_cast<const Coef<real> *>(a.coef);
-    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + tid;
-    if (t >= a.n) return;
-    const typename T::Rec r = static_cast<const typename T::Rec *>(a.rec)[t];
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const SysStep &St = stp[e.x];
+    const int64_t n = D.n;
+    const int nd = gp(D.res)->nd;
+    const Coef<real> *cf = static_cast<const Coef<real> *>(D.coef);
+    const int64_t t = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
+    if (t >= n) return;
+    const typename T::Rec r = gload(static_cast<const typename T::Rec *>(D.rec) + t);
     double gx = 0.0, gy = 0.0, gz = 0.0;
     if constexpr (sizeof(real) == 4) {
-        SkAtom32 at;
-        at.hx = static_cast<int>(r.x >> 16);
-        at.hy = static_cast<int>(r.y >> 16);
-        at.hz = static_cast<int>(r.z >> 16);
-        at.lx = static_cast<int>(r.x & 0xFFFFu);
-        at.ly = static_cast<int>(r.y & 0xFFFFu);
-        at.lz = static_cast<int>(r.z & 0xFFFFu);
-        at.q = r.q;
-        at.pad = 0;
+        const SkAtom32 at = split_atom(r);
         for (int d0 = 0; d0 < nd; d0 += 32) {
             float hx = 0.f, hy = 0.f, hz = 0.f;
             const int d1 = min(nd, d0 + 32);
             for (int d = d0; d < d1; ++d) {
-                const Coef<float> c = s_cf[d];
+                const Coef<float> c = gload(cf + d);
                 float sn, cs;
                 phase_sincos32(make_int4(c.mx, c.my, c.mz, 0), at, sn, cs);
                 const float g = c.A * cs - c.B * sn;
@@ -1235,7 +1299,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a)
         }
     } else {
         for (int d = 0; d < nd; ++d) {
-            const Coef<double> c = s_cf[d];
+            const Coef<double> c = gload(cf + d);
             double sn, cs;
             phase_sincos64(make_int4(c.mx, c.my, c.mz, 0), r, sn, cs);
             const double g = c.A * cs - c.B * sn;
@@ -1244,176 +1308,139 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a)
             gz += g * c.kz;
         }
     }
-    const real *fsr = static_cast<const real *>(a.fsr);
+    const RB_GLOBAL real *fsr = gp(static_cast<const real *>(D.fsr));
     const double q = static_cast<double>(r.q);
-    const int i = a.perm[t];
-    a.fx[i] = a.ck * (static_cast<double>(fsr[t]) - q * gx);
-    a.fy[i] = a.ck * (static_cast<double>(fsr[a.n + t]) - q * gy);
-    a.fz[i] = a.ck * (static_cast<double>(fsr[2 * a.n + t]) - q * gz);
+    const int i = gp(D.perm)[t];
+    const double ck = D.ck;
+    gp(St.fx)[i] = ck * (static_cast<double>(fsr[t]) - q * gx);
+    gp(St.fy)[i] = ck * (static_cast<double>(fsr[n + t]) - q * gy);
+    gp(St.fz)[i] = ck * (static_cast<double>(fsr[2 * n + t]) - q * gz);
 }
 
-__global__ void k_rescale(int64_t n, double mx, double my, double mz, double *x, double *y, double *z)
+// r <- mu r (FP64) for the positions of each system
+__global__ __launch_bounds__(kAtomBlock) void k_rescale(const SysDesc *__restrict__ desc,
+                                                        const SysStep *__restrict__ stp,
+                                                        const int2 *__restrict__ plan)
 {
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (i >= n) return;
-    x[i] *= mx;
-    y[i] *= my;
-    z[i] *= mz;
+    const int2 e = plan[blockIdx.x];
+    const SysStep &St = stp[e.x];
+    const int64_t i = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
+    if (i >= desc[e.x].n) return;
+    RB_GLOBAL double *x = gp(const_cast<double *>(St.x)), *y = gp(const_cast<double *>(St.y)),
+                     *z = gp(const_cast<double *>(St.z));
+    x[i] *= St.mu[0];
+    y[i] *= St.mu[1];
+    z[i] *= St.mu[2];
 }
 
-inline unsigned grid_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
+inline const int2 *plan_ptr(const Batch &b, PlanKind k) { return b.d_plan + b.plan_off[k]; }
+inline unsigned plan_grid(const Batch &b, PlanKind k) { return static_cast<unsigned>(b.plan_len[k]); }
+inline unsigned nsys(const Batch &b) { return static_cast<unsigned>(b.sys.size()); }
 
 }  // namespace
 
 // ----------------------------------------------------------------------------
-// Launchers
+// Launchers (every launch covers all systems of the batch)
 // ----------------------------------------------------------------------------
 
-hipError_t launch_sample(rbsog_ctx *c, uint32_t step)
+hipError_t launch_sample(Batch &b)
 {
-    SampArgs a{};
-    for (int d = 0; d < 3; ++d) a.L[d] = c->L[d];
-    a.P = c->prm.P;
-    a.M = c->prm.M;
-    a.variant = c->prm.recalibration;
-    a.key0 = static_cast<uint32_t>(c->prm.seed);
-    a.key1 = static_cast<uint32_t>(c->prm.seed >> 32);
-    a.step = step;
-    a.sys = static_cast<uint32_t>(c->prm.system_id);
-    a.tab = c->d_tab;
-    a.mraw = c->d_mraw;
-    a.modes = c->d_modes;
-    a.cnt = c->d_cnt;
-    a.res = c->d_res;
-    timer_begin(c, "sampler");
-    hipLaunchKernelGGL(k_sampler, dim3(1), dim3(256), 0, c->stream, a);
-    timer_end(c, "sampler");
+    if (b.sys.empty()) return hipSuccess;
+    timer_begin(b, "sampler");
+    hipLaunchKernelGGL(k_sampler, dim3(nsys(b)), dim3(256), 0, b.stream, b.d_desc, b.d_step);
+    timer_end(b, "sampler");
     return hipGetLastError();
 }
 
 template <class T>
-static hipError_t bin_and_sort_t(rbsog_ctx *c, const double *x, const double *y, const double *z)
+static hipError_t bin_and_sort_t(Batch &b)
 {
-    const int64_t n = c->n, m = c->ncells;
-    timer_begin(c, "bin");
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(m + 1, 256)), dim3(256), 0, c->stream, c->d_count, c->d_cursor, m + 1);
-    hipLaunchKernelGGL(k_fix<T>, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, x, y, z, 1.0 / c->L[0],
-                       1.0 / c->L[1], 1.0 / c->L[2], c->nc[0], c->nc[1], c->nc[2],
-                       static_cast<typename T::fix *>(c->d_u), c->d_cell, c->d_count);
-    const int nb = static_cast<int>((m + kScanBlock - 1) / kScanBlock);
-    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, c->stream, c->d_count, m, c->d_start, c->d_bstart,
-                       c->d_nblk, c->d_scan_tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, c->stream, c->d_scan_tmp, nb);
-    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(m + 1, 256)), dim3(256), 0, c->stream, c->d_start, c->d_bstart,
-                       c->d_scan_tmp, m);
-    hipLaunchKernelGGL(k_fill_blocks, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, c->d_nblk, c->d_bstart, m,
-                       c->d_blocks);
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, c->d_cell, c->d_start,
-                       c->d_cursor, c->d_perm_tmp);
-    hipLaunchKernelGGL(k_order<T>, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, c->d_perm_tmp, c->d_cell,
-                       c->d_start, static_cast<const typename T::fix *>(c->d_u),
-                       static_cast<const typename T::real *>(c->d_q), c->d_perm,
-                       static_cast<typename T::Rec *>(c->d_rec));
-    timer_end(c, "bin");
+    timer_begin(b, "bin");
+    hipLaunchKernelGGL(k_zero, dim3(plan_grid(b, kPlanCells)), dim3(kCellBlock), 0, b.stream, b.d_desc, b.d_step,
+                       plan_ptr(b, kPlanCells), b.d_ctrl);
+    hipLaunchKernelGGL(k_fix<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc, b.d_step,
+                       plan_ptr(b, kPlanAtoms));
+    hipLaunchKernelGGL(k_scan_local, dim3(plan_grid(b, kPlanScan)), dim3(256), 0, b.stream, b.d_desc, b.d_step,
+                       plan_ptr(b, kPlanScan));
+    hipLaunchKernelGGL(k_scan_top, dim3(nsys(b)), dim3(256), 0, b.stream, b.d_desc, b.d_step);
+    hipLaunchKernelGGL(k_scan_add, dim3(plan_grid(b, kPlanCells)), dim3(kCellBlock), 0, b.stream, b.d_desc, b.d_step,
+                       plan_ptr(b, kPlanCells));
+    hipLaunchKernelGGL(k_scatter, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
+                       plan_ptr(b, kPlanAtoms));
+    hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
+                       plan_ptr(b, kPlanAtoms));
+    timer_end(b, "bin");
     return hipGetLastError();
 }
 
-hipError_t launch_bin_and_sort(rbsog_ctx *c, const double *x, const double *y, const double *z)
+hipError_t launch_bin_and_sort(Batch &b)
 {
-    return c->prm.precision == RBSOG_PREC_FP64 ? bin_and_sort_t<F64>(c, x, y, z) : bin_and_sort_t<F32>(c, x, y, z);
+    if (b.sys.empty()) return hipSuccess;
+    return b.precision == RBSOG_PREC_FP64 ? bin_and_sort_t<F64>(b) : bin_and_sort_t<F32>(b);
+}
+
+template <class T, int M>
+static void pair_launch(Batch &b, int64_t first, int64_t items, int queue)
+{
+    if (items <= 0) return;
+    const int2 *plan = plan_ptr(b, kPlanPair) + first;
+    if (b.pair_schedule == kPairPersistent) {
+        const int64_t wgs = std::min<int64_t>(items, static_cast<int64_t>(b.num_cu) * b.pair_wg_per_cu);
+        hipLaunchKernelGGL((k_pair_queue<T, M>), dim3(static_cast<unsigned>(wgs)), dim3(64), 0, b.stream, b.d_desc,
+                           b.d_step, plan, static_cast<int>(items), b.d_ctrl + queue);
+    } else {
+        hipLaunchKernelGGL((k_pair<T, M>), dim3(static_cast<unsigned>(items)), dim3(64), 0, b.stream, b.d_desc,
+                           b.d_step, plan);
+    }
 }
 
 template <class T>
-static hipError_t pair_t(rbsog_ctx *c)
+static hipError_t pair_t(Batch &b)
 {
-    PairArgs a{};
-    a.n = c->n;
-    a.nx = c->nc[0];
-    a.ny = c->nc[1];
-    a.nz = c->nc[2];
-    a.Lx = c->L[0];
-    a.Ly = c->L[1];
-    a.Lz = c->L[2];
-    a.start = c->d_start;
-    a.bstart = c->d_bstart;
-    a.blocks = c->d_blocks;
-    a.ncells = c->ncells;
-    a.rec = c->d_rec;
-    a.tab = c->d_tab;
-    a.fsr = c->d_fsr;
-    a.part = c->d_pair_part;
-    const int64_t grid = (c->n + kPairWave - 1) / kPairWave + c->ncells;
-    timer_begin(c, "pair");
-    if (c->prm.M == 10)
-        hipLaunchKernelGGL((k_pair<T, 10>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, c->stream, a);
-    else
-        hipLaunchKernelGGL((k_pair<T, 0>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, c->stream, a);
-    timer_end(c, "pair");
+    // systems with M = 10 (the pressure column of Table 1) run the
+    // instantiation with the weights in registers, the others the runtime-M one
+    timer_begin(b, "pair");
+    pair_launch<T, 10>(b, 0, b.pair_m10, 0);
+    pair_launch<T, 0>(b, b.pair_m10, b.plan_len[kPlanPair] - b.pair_m10, 1);
+    timer_end(b, "pair");
     return hipGetLastError();
 }
 
-hipError_t launch_pair(rbsog_ctx *c)
+hipError_t launch_pair(Batch &b)
 {
-    return c->prm.precision == RBSOG_PREC_FP64 ? pair_t<F64>(c) : pair_t<F32>(c);
+    if (b.sys.empty() || b.plan_len[kPlanPair] == 0) return hipSuccess;
+    return b.precision == RBSOG_PREC_FP64 ? pair_t<F64>(b) : pair_t<F32>(b);
 }
 
 template <class T>
-static hipError_t kspace_t(rbsog_ctx *c, double *fx, double *fy, double *fz)
+static hipError_t kspace_t(Batch &b)
 {
-    SkArgs s{};
-    s.n = c->n;
-    s.rec = c->d_rec;
-    s.modes = c->d_modes;
-    s.res = c->d_res;
-    s.part = c->d_rho_part;
-    timer_begin(c, "sk");
-    hipLaunchKernelGGL(k_sk<T>, dim3(static_cast<unsigned>(c->sk_blocks)), dim3(256), 0, c->stream, s);
-    timer_end(c, "sk");
-    const int64_t npair = (c->n + kPairWave - 1) / kPairWave + c->ncells;
-    timer_begin(c, "reduce");
-    hipLaunchKernelGGL(k_rho_reduce, dim3(kMaxModes + 1), dim3(256), 0, c->stream, c->d_rho_part, c->sk_blocks,
-                       c->d_pair_part, npair, c->d_rho, c->d_res);
-    EstArgs e{};
-    for (int d = 0; d < 3; ++d) e.L[d] = c->L[d];
-    e.Sr = c->Sr;
-    e.Snr = c->Snr;
-    e.ck = c->prm.coulomb_k;
-    e.Uself = c->Uself;
-    e.P = c->prm.P;
-    e.modes = c->d_modes;
-    e.cnt = c->d_cnt;
-    e.rho = c->d_rho;
-    e.coef = c->d_coef;
-    e.fp64 = c->prm.precision == RBSOG_PREC_FP64;
-    e.res = c->d_res;
-    hipLaunchKernelGGL(k_estimators, dim3(1), dim3(256), 0, c->stream, e);
-    timer_end(c, "reduce");
-    ForceArgs f{};
-    f.n = c->n;
-    f.rec = c->d_rec;
-    f.perm = c->d_perm;
-    f.fsr = c->d_fsr;
-    f.coef = c->d_coef;
-    f.res = c->d_res;
-    f.ck = c->prm.coulomb_k;
-    f.fx = fx;
-    f.fy = fy;
-    f.fz = fz;
-    timer_begin(c, "force");
-    hipLaunchKernelGGL(k_force<T>, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream, f);
-    timer_end(c, "force");
+    timer_begin(b, "sk");
+    hipLaunchKernelGGL(k_sk<T>, dim3(plan_grid(b, kPlanSk)), dim3(256), 0, b.stream, b.d_desc, plan_ptr(b, kPlanSk));
+    timer_end(b, "sk");
+    timer_begin(b, "reduce");
+    hipLaunchKernelGGL(k_rho_reduce, dim3(plan_grid(b, kPlanReduce)), dim3(256), 0, b.stream, b.d_desc, b.d_step,
+                       plan_ptr(b, kPlanReduce));
+    hipLaunchKernelGGL(k_estimators<T>, dim3(nsys(b)), dim3(256), 0, b.stream, b.d_desc, b.d_step);
+    timer_end(b, "reduce");
+    timer_begin(b, "force");
+    hipLaunchKernelGGL(k_force<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc, b.d_step,
+                       plan_ptr(b, kPlanAtoms));
+    timer_end(b, "force");
     return hipGetLastError();
 }
 
-hipError_t launch_kspace(rbsog_ctx *c, double *fx, double *fy, double *fz)
+hipError_t launch_kspace(Batch &b)
 {
-    return c->prm.precision == RBSOG_PREC_FP64 ? kspace_t<F64>(c, fx, fy, fz) : kspace_t<F32>(c, fx, fy, fz);
+    if (b.sys.empty()) return hipSuccess;
+    return b.precision == RBSOG_PREC_FP64 ? kspace_t<F64>(b) : kspace_t<F32>(b);
 }
 
-hipError_t launch_rescale(rbsog_ctx *c, const double mu[3], double *x, double *y, double *z)
+hipError_t launch_rescale(Batch &b)
 {
-    hipLaunchKernelGGL(k_rescale, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream, c->n, mu[0], mu[1], mu[2], x, y,
-                       z);
+    if (b.sys.empty()) return hipSuccess;
+    hipLaunchKernelGGL(k_rescale, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc, b.d_step,
+                       plan_ptr(b, kPlanAtoms));
     return hipGetLastError();
 }
 

@@ -1,4 +1,14 @@
 // Internal declarations of the RBSOG HIP library (not part of the C ABI).
+//
+// Every kernel works on a batch of independent systems.  A system is described
+// by a SysDesc (splitting tables, sizes, device buffers; written when the
+// system joins a batch or its buffers move) and a SysStep (box, scale factors,
+// normalisation constants, cell grid, step index and the caller's position and
+// force arrays; written every step).  Kernels find their system and their
+// block within it through a launch plan: one (system, block) entry per
+// workgroup, built on the host from sizes it knows.  A system's arithmetic
+// never depends on the other systems in the batch, so one system alone and the
+// same system in any batch give bitwise identical results.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,6 +25,10 @@ constexpr int kMaxP = 1024;        // samples per chain handled by the one-workg
 constexpr int kMaxModes = kMaxP + 1; // distinct modes: accepted proposals plus the initial state
 constexpr int kPairWave = 64;      // i-atoms per pair-kernel wavefront
 constexpr int kSkChunk = 1024;     // atoms per structure-factor workgroup
+constexpr int kAtomBlock = 256;    // atoms per workgroup of the per-atom kernels
+constexpr int kCellBlock = 256;    // cells per workgroup of the per-cell kernels
+constexpr int kScanBlock = 1024;   // cells per workgroup of the local scan
+constexpr int64_t kMaxCells = int64_t(1024) * kScanBlock;  // cells per system (two-level scan)
 constexpr int kMaxTimed = 24;
 
 // SOG tables read by the kernels (device memory, uniform loads).
@@ -28,11 +42,11 @@ struct SogTables {
     float w32[RBSOG_MAX_M], wt32[RBSOG_MAX_M], c32[RBSOG_MAX_M];
     float rc2_32;
     float pad32;
-    // sampler: s_l^2/4, wt_l s_l^5, wt_l s_l^7 are formed inside the sampler from these
+    // sampler: s_l, and wt_l s_l^5, wt_l s_l^7 are formed from s5, s7
     double s[RBSOG_MAX_M], s5[RBSOG_MAX_M], s7[RBSOG_MAX_M];
 };
 
-// Results of one step, written on the device, read by the host.
+// Results of one step of one system, written on the device, read by the host.
 struct StepResults {
     double UN, UF, Uself, pad0;
     double vir[6];        // short-range virial sum (xx yy zz xy xz yz)
@@ -43,6 +57,53 @@ struct StepResults {
     double npairs;  // unordered in-cutoff pairs of the last evaluation
 };
 
+// Static description of one system (device copy read by every kernel).
+struct SysDesc {
+    SogTables tab;
+    int64_t n;            // atoms
+    int64_t pair_cap;     // pair-block slots allocated: ceil(n/64) + ncells_cap
+    int64_t sk_blocks;    // structure-factor workgroups: ceil(n/kSkChunk)
+    int64_t ncells_cap;   // cells allocated
+    int32_t P, M, variant, mcap;  // mcap = P + 1: stride of the per-mode arrays
+    uint32_t key0, key1, sys, pad;
+    double ck, Uself;
+    // internal device buffers
+    const void *q;        // charges, system order (float or double)
+    void *u;              // fixed-point fractional coordinates (3 SoA planes of n)
+    int32_t *cell;        // cell of each atom
+    int32_t *count, *cursor, *start, *nblk, *bstart;  // per cell [ncells_cap + 1]
+    int32_t *scan_tmp;    // [2 * 1024 + 2] block sums of the two-level scan
+    int2 *blocks;         // pair-block table (cell, sub-block) [pair_cap]
+    int32_t *perm_tmp, *perm;  // cell-sorted slot -> system atom index
+    void *rec;            // sorted records (fixed-point position + charge)
+    void *fsr;            // short-range force, sorted order (3 SoA planes)
+    double *pair_part;    // 8 doubles per pair block
+    int32_t *mraw;        // m_r then m_nr, P x 3 each
+    int4 *modes;          // distinct modes [mcap]
+    int32_t *cnt;         // multiplicities: r-chain [mcap], nr-chain [mcap]
+    double *rho_part;     // [sk_blocks][mcap] x (re, im)
+    double *rho;          // [mcap] x (re, im)
+    void *coef;           // per-mode force coefficients [mcap]
+    StepResults *res;     // this system's slot of the batch results
+};
+
+// Per-step data of one system (rewritten by the host every step).
+struct SysStep {
+    double L[3];
+    double iL[3];         // 1/L, rounded once on the host
+    double mu[3];         // scale factors of the next rescale
+    double Sr, Snr;
+    int32_t nc[3];
+    int32_t ncells;
+    uint32_t step;
+    int32_t pad[3];
+    const double *x, *y, *z;  // positions (device, system order)
+    double *fx, *fy, *fz;     // forces (device, system order)
+};
+
+// Plans: one entry (system index, block index within the system) per workgroup.
+enum PlanKind { kPlanAtoms, kPlanCells, kPlanScan, kPlanPair, kPlanSk, kPlanReduce, kNumPlans };
+
 struct Timer {
     std::string name;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -51,80 +112,128 @@ struct Timer {
     int64_t count = 0;
 };
 
-}  // namespace rbsog
+// Pair-kernel schedules (none changes any result).
+enum PairSchedule {
+    kPairStatic = 0,      // one workgroup per pair-block slot
+    kPairPersistent = 1,  // workgroups pull pair blocks from a global counter
+};
 
-struct rbsog_ctx {
+// One system on the host: parameters, splitting tables, box state and buffers.
+struct System {
     rbsog_params prm{};
     int64_t n = 0;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    std::string err;
-
-    // host copies of the splitting tables and constants
     double w[RBSOG_MAX_M]{}, wt[RBSOG_MAX_M]{}, s[RBSOG_MAX_M]{};
     double q2sum = 0.0, Uself = 0.0;
-
-    // current box and derived quantities
+    SogTables tab{};
+    // box state
     double L[3]{};
     double Sr = 0.0, Snr = 0.0;
     int nc[3]{1, 1, 1};
-    int64_t ncells = 0, ncells_cap = 0;
-    int state = 0;  // 0: set up, 1: modes sampled, 2: forces computed
-    int64_t step = 0;
-
-    // device buffers
-    rbsog::SogTables *d_tab = nullptr;
-    void *d_q = nullptr;          // charges, caller order (float or double)
-    void *d_u = nullptr;          // fixed-point fractional coordinates, caller order (3 SoA planes)
-    int32_t *d_cell = nullptr;    // cell of each atom, caller order
-    int32_t *d_count = nullptr;   // atoms per cell        [ncells_cap + 1]
-    int32_t *d_cursor = nullptr;  // scatter cursors       [ncells_cap + 1]
-    int32_t *d_start = nullptr;   // first slot per cell   [ncells_cap + 1]
-    int32_t *d_nblk = nullptr;    // pair blocks per cell  [ncells_cap + 1]
-    int32_t *d_bstart = nullptr;  // first pair block per cell [ncells_cap + 1]
-    int32_t *d_scan_tmp = nullptr;
-    int2 *d_blocks = nullptr;     // pair block table (cell, sub-block)
-    int64_t pair_grid_cap = 0;
-    int32_t *d_perm_tmp = nullptr;
-    int32_t *d_perm = nullptr;    // sorted slot -> caller index
-    void *d_rec = nullptr;        // sorted records (fixed-point position + charge)
-    void *d_fsr = nullptr;        // short-range force, sorted order (3 SoA planes)
-    double *d_pair_part = nullptr;  // 8 doubles per pair workgroup
-    // sampler and modes
-    int32_t *d_mraw = nullptr;    // m_r then m_nr, P x 3 each
-    int4 *d_modes = nullptr;      // distinct modes
-    int32_t *d_cnt = nullptr;     // multiplicities: r-chain [kMaxModes], nr-chain [kMaxModes]
-    double *d_rho_part = nullptr; // [sk blocks][kMaxModes] x (re, im)
-    double *d_rho = nullptr;      // [kMaxModes] x (re, im)
-    void *d_coef = nullptr;       // per-mode force coefficients
-    rbsog::StepResults *d_res = nullptr;
-    rbsog::StepResults *h_res = nullptr;  // pinned
-    int64_t sk_blocks = 0;
-    // host staging for host-memory positions and forces
-    double *d_stage = nullptr;
-
-    // timing
-    bool timing = false;
-    std::vector<rbsog::Timer> timers;
+    int64_t ncells = 0;
+    // device memory: atom-sized part (fixed) and cell-sized part (grows with the grid)
+    void *atom_mem = nullptr;
+    size_t atom_bytes = 0;
+    void *cell_mem = nullptr;
+    size_t cell_bytes = 0;
+    int64_t ncells_cap = 0;
+    bool own_mem = true;  // false: the memory belongs to a pool
+    SysDesc desc{};       // host copy of the device descriptor
+    SysStep stp{};        // host copy of the per-step data
 };
 
-namespace rbsog {
+// A batch of systems sharing one stream and one set of launches.
+struct Batch {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int precision = RBSOG_PREC_FP32C;
+    std::vector<System *> sys;
+    // device arrays and their pinned host mirrors
+    SysDesc *d_desc = nullptr, *h_desc = nullptr;
+    SysStep *d_step = nullptr;
+    static constexpr int kStepRing = 4;        // pinned per-step buffers used in turn
+    SysStep *h_step[kStepRing] = {};
+    hipEvent_t step_ev[kStepRing] = {};
+    bool step_ev_used[kStepRing] = {};
+    int step_slot = 0;
+    StepResults *d_res = nullptr, *h_res = nullptr;
+    int2 *d_plan = nullptr, *h_plan = nullptr;
+    int32_t *d_ctrl = nullptr;  // [0], [1]: work-queue counters of the two pair launches
+    int64_t cap_sys = 0, cap_plan = 0;
+    int64_t plan_off[kNumPlans]{}, plan_len[kNumPlans]{};
+    int64_t pair_m10 = 0;  // leading pair-plan entries that belong to systems with M = 10
+    bool desc_dirty = true, plan_dirty = true;
+    std::vector<int64_t> plan_key;  // sizes the plans were built for
+    // event that guards the pinned descriptor and plan mirrors
+    hipEvent_t up_done = nullptr;
+    bool up_pending = false;
+    // options
+    int pair_schedule = kPairStatic;
+    int pair_wg_per_cu = 8;
+    int num_cu = 256;
+    // graph of the whole step (batch form)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<int64_t> graph_key;
+    // timing
+    bool timing = false;
+    std::vector<Timer> timers;
+};
 
-// host-side setup helpers (setup.cpp)
+// ---------------------------------------------------------------------------
+// host-side set-up helpers (setup.cpp)
 void sog_tables(const rbsog_params &p, double *w, double *wt, double *s);
 double omega_c0(double b, double sigma, double rc, int M);
 void norm_consts(const double L[3], int M, const double *wt, const double *s, double *Sr, double *Snr);
 void cell_grid(const double L[3], double rc, int nc[3]);
 
-// kernel launchers (kernels.hip); each returns a hipError_t
-hipError_t launch_sample(rbsog_ctx *c, uint32_t step);
-hipError_t launch_bin_and_sort(rbsog_ctx *c, const double *x, const double *y, const double *z);
-hipError_t launch_pair(rbsog_ctx *c);
-hipError_t launch_kspace(rbsog_ctx *c, double *fx, double *fy, double *fz);
-hipError_t launch_rescale(rbsog_ctx *c, const double mu[3], double *x, double *y, double *z);
+// ---------------------------------------------------------------------------
+// systems and batches (system.cpp)
 
-// timing hooks used by the launchers
-void timer_begin(rbsog_ctx *c, const char *name);
-void timer_end(rbsog_ctx *c, const char *name);
+// Validate parameters and charges, fill the tables; no device work.
+int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_q, const double box[3],
+                std::string &err);
+// Check a box against the cutoff.
+int check_box(const double *box, double rc, std::string &err);
+// Bytes of the atom-sized and cell-sized device parts of a system.
+size_t system_atom_bytes(const rbsog_params &p, int64_t n);
+size_t system_cell_bytes(int64_t n, int64_t ncells_cap);
+// Point the descriptor into memory the caller provides (aligned to 256 bytes).
+void system_carve_atoms(System &s, void *mem);
+void system_carve_cells(System &s, void *mem, int64_t ncells_cap);
+// Allocate (own_mem) or re-carve the buffers; grows the cell part to the grid.
+int system_alloc(System &s, std::string &err);
+int system_ensure_cells(System &s, std::string &err);
+void system_free(System &s);
+// Upload the charges (FP32 or FP64 copy) on the stream.
+int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err);
+// New box: grid, S^r, S^nr.
+void system_set_box(System &s, const double box[3]);
+// Cells needed by a box.
+int64_t cells_for_box(const double box[3], double rc);
+
+int batch_init(Batch &b, hipStream_t stream, int precision, std::string &err);
+void batch_free(Batch &b);
+// Replace the batch's systems (descriptors and plans are rebuilt on the next upload).
+int batch_set_systems(Batch &b, const std::vector<System *> &sys, std::string &err);
+// Copy descriptors (if changed), per-step data and plans (if sizes changed) to the device.
+int batch_upload(Batch &b, std::string &err);
+// Results of every system to the host (synchronises).
+int batch_fetch_results(Batch &b, std::string &err);
+// Per-kernel HIP-event timing of the batch's launches.
+void batch_set_timing(Batch &b, bool on);
+int batch_get_timing(Batch &b, int32_t cap, int32_t *host_nk, char *host_names, double *host_ms,
+                     int64_t *host_count, std::string &err);
+
+// ---------------------------------------------------------------------------
+// kernel launchers (kernels.hip); each returns a hipError_t
+hipError_t launch_sample(Batch &b);
+hipError_t launch_bin_and_sort(Batch &b);
+hipError_t launch_pair(Batch &b);
+hipError_t launch_kspace(Batch &b);
+hipError_t launch_rescale(Batch &b);
+
+// timing hooks used by the launchers (system.cpp)
+void timer_begin(Batch &b, const char *name);
+void timer_end(Batch &b, const char *name);
 
 }  // namespace rbsog

@@ -1,0 +1,528 @@
+// Served form: a request loop on a worker thread with continuous batching.
+//
+// A request is one system and a number of steps.  Admission is first come,
+// first served: the head of the queue is admitted when a slot is free and its
+// device state (positions, forces and every per-system buffer, sized for the
+// largest cell grid its box schedule reaches) fits first-fit into the
+// server's memory pool.  Every tick runs one batched step over all admitted
+// requests, each at its own step index; a request that completes releases its
+// memory, and requests that arrived meanwhile join the next tick.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rbsog_impl.hpp"
+
+using rbsog::Batch;
+using rbsog::System;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over offsets of one device allocation.
+class Pool {
+public:
+    void reset(size_t bytes)
+    {
+        free_.clear();
+        free_[0] = bytes;
+        used_ = 0;
+        peak_ = 0;
+    }
+    bool alloc(size_t bytes, size_t &off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                off = it->first;
+                const size_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t peak() const { return peak_; }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t used_ = 0, peak_ = 0;
+};
+
+struct Request {
+    int64_t ticket = 0;
+    int64_t n = 0;
+    int nsteps = 1;
+    double growth = 0.0;
+    std::vector<double> q, x, y, z;  // inputs, freed once uploaded
+    std::vector<double> boxes;       // box of every step (3 nsteps)
+    std::vector<double> mus;         // scale factor before every step (1 at k = 0)
+    int64_t max_cells = 0;
+    size_t bytes = 0, off = 0;
+    System sys;
+    double *d_pos = nullptr, *d_frc = nullptr;
+    int k = 0;  // next step
+    std::vector<double> P, U, fx, fy, fz;
+    Clock::time_point t_submit, t_admit, t_done;
+    int shared_ticks = 0;
+    bool done = false;
+    int status = RBSOG_OK;
+};
+
+}  // namespace
+
+struct rbsog_server {
+    int precision = RBSOG_PREC_FP32C;
+    size_t pool_bytes = 0;
+    int max_active = 1;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char *pool_mem = nullptr;
+    Pool pool;
+    Batch batch;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> pending;
+    std::vector<Request *> active;
+    std::unordered_map<int64_t, std::unique_ptr<Request>> requests;
+    int64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    // statistics
+    int64_t submitted = 0, completed = 0, ticks = 0, peak_active = 0;
+    double atom_steps = 0.0, busy_s = 0.0;
+    std::string err, worker_err;
+};
+
+namespace {
+
+size_t request_bytes(const rbsog_params &p, int64_t n, int64_t max_cells)
+{
+    return align_up(rbsog::system_atom_bytes(p, n)) + align_up(rbsog::system_cell_bytes(n, max_cells)) +
+           2 * align_up(3 * n * sizeof(double));
+}
+
+// Upload an admitted request's state into its pool memory.
+int admit(rbsog_server *sv, Request *r, std::string &err)
+{
+    char *base = sv->pool_mem + r->off;
+    System &s = r->sys;
+    s.own_mem = false;
+    rbsog::system_carve_atoms(s, base);
+    base += align_up(rbsog::system_atom_bytes(s.prm, s.n));
+    rbsog::system_carve_cells(s, base, r->max_cells);
+    base += align_up(rbsog::system_cell_bytes(s.n, r->max_cells));
+    r->d_pos = reinterpret_cast<double *>(base);
+    base += align_up(3 * r->n * sizeof(double));
+    r->d_frc = reinterpret_cast<double *>(base);
+    int rc = rbsog::system_upload_q(s, r->q.data(), sv->stream, err);
+    if (rc) return rc;
+    const int64_t n = r->n;
+    hipError_t e = hipMemcpyAsync(r->d_pos, r->x.data(), n * sizeof(double), hipMemcpyHostToDevice, sv->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->d_pos + n, r->y.data(), n * sizeof(double), hipMemcpyHostToDevice, sv->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->d_pos + 2 * n, r->z.data(), n * sizeof(double), hipMemcpyHostToDevice, sv->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+    if (e != hipSuccess) {
+        err = std::string("request upload: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    std::vector<double>().swap(r->q);
+    std::vector<double>().swap(r->x);
+    std::vector<double>().swap(r->y);
+    std::vector<double>().swap(r->z);
+    r->t_admit = Clock::now();
+    return RBSOG_OK;
+}
+
+// One batched step over every active request.
+int tick(rbsog_server *sv, std::string &err)
+{
+    Batch &bt = sv->batch;
+    // rescale before step k >= 1 (mu = 1 at k = 0 leaves positions unchanged)
+    for (Request *r : sv->active) {
+        rbsog::SysStep &t = r->sys.stp;
+        for (int d = 0; d < 3; ++d) t.mu[d] = r->mus[r->k];
+        t.x = r->d_pos;
+        t.y = r->d_pos + r->n;
+        t.z = r->d_pos + 2 * r->n;
+    }
+    int rc = rbsog::batch_upload(bt, err);
+    if (rc) return rc;
+    hipError_t e = rbsog::launch_rescale(bt);
+    if (e != hipSuccess) {
+        err = std::string("rescale: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    for (Request *r : sv->active) {
+        System &s = r->sys;
+        rbsog::system_set_box(s, &r->boxes[3 * r->k]);
+        if (s.ncells > s.ncells_cap) {
+            err = "cell grid outgrew its reservation";
+            return RBSOG_EBOX;
+        }
+        rbsog::SysStep &t = s.stp;
+        t.step = static_cast<uint32_t>(r->k);
+        t.fx = r->d_frc;
+        t.fy = r->d_frc + r->n;
+        t.fz = r->d_frc + 2 * r->n;
+    }
+    rc = rbsog::batch_upload(bt, err);
+    if (rc) return rc;
+    e = rbsog::launch_sample(bt);
+    if (e == hipSuccess) e = rbsog::launch_bin_and_sort(bt);
+    if (e == hipSuccess) e = rbsog::launch_pair(bt);
+    if (e == hipSuccess) e = rbsog::launch_kspace(bt);
+    if (e != hipSuccess) {
+        err = std::string("step launch: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    rc = rbsog::batch_fetch_results(bt, err);
+    if (rc) return rc;
+    const bool shared = sv->active.size() > 1;
+    for (size_t i = 0; i < sv->active.size(); ++i) {
+        Request *r = sv->active[i];
+        const rbsog::StepResults &res = bt.h_res[i];
+        if (res.status != 0) {
+            err = "sampler found no nonzero initial state";
+            return RBSOG_EDEVICE;
+        }
+        for (int k = 0; k < 9; ++k) r->P[9 * r->k + k] = res.Ptot[k];
+        r->U[3 * r->k] = res.UN;
+        r->U[3 * r->k + 1] = res.UF;
+        r->U[3 * r->k + 2] = res.Uself;
+        r->shared_ticks += shared;
+        sv->atom_steps += static_cast<double>(r->n);
+        r->k += 1;
+    }
+    return RBSOG_OK;
+}
+
+// Copy the forces of finished requests out and release their memory.
+int retire(rbsog_server *sv, std::vector<Request *> &finished, std::string &err)
+{
+    for (Request *r : sv->active) {
+        if (r->k < r->nsteps) continue;
+        const int64_t n = r->n;
+        r->fx.resize(n);
+        r->fy.resize(n);
+        r->fz.resize(n);
+        hipError_t e = hipMemcpyAsync(r->fx.data(), r->d_frc, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->fy.data(), r->d_frc + n, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->fz.data(), r->d_frc + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost,
+                               sv->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+        if (e != hipSuccess) {
+            err = std::string("force copy: ") + hipGetErrorString(e);
+            return RBSOG_EDEVICE;
+        }
+        finished.push_back(r);
+    }
+    return RBSOG_OK;
+}
+
+void worker_main(rbsog_server *sv)
+{
+    (void)hipSetDevice(sv->device);
+    std::string err;
+    for (;;) {
+        std::vector<Request *> admitted;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty() || !sv->active.empty(); });
+            if (sv->stop) break;
+            while (!sv->pending.empty() &&
+                   static_cast<int>(sv->active.size() + admitted.size()) < sv->max_active) {
+                Request *r = sv->pending.front();
+                size_t off = 0;
+                if (!sv->pool.alloc(r->bytes, off)) break;
+                r->off = off;
+                sv->pending.pop_front();
+                admitted.push_back(r);
+            }
+        }
+        const Clock::time_point t0 = Clock::now();
+        int rc = RBSOG_OK;
+        for (Request *r : admitted) {
+            if (rc == RBSOG_OK) rc = admit(sv, r, err);
+        }
+        std::vector<Request *> finished;
+        if (rc == RBSOG_OK) {
+            sv->active.insert(sv->active.end(), admitted.begin(), admitted.end());
+            std::vector<System *> sys;
+            for (Request *r : sv->active) sys.push_back(&r->sys);
+            if (!admitted.empty() || sv->batch.sys.size() != sys.size()) rc = rbsog::batch_set_systems(sv->batch, sys, err);
+            if (rc == RBSOG_OK) rc = tick(sv, err);
+            if (rc == RBSOG_OK) rc = retire(sv, finished, err);
+        }
+        const Clock::time_point t1 = Clock::now();
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->busy_s += std::chrono::duration<double>(t1 - t0).count();
+        sv->ticks += 1;
+        sv->peak_active = std::max<int64_t>(sv->peak_active, static_cast<int64_t>(sv->active.size()));
+        if (rc != RBSOG_OK) {
+            // a failed tick fails every request it held; the worker stops
+            sv->worker_err = err;
+            for (Request *r : sv->active) {
+                r->status = rc;
+                r->done = true;
+            }
+            for (Request *r : admitted) {
+                r->status = rc;
+                r->done = true;
+            }
+            sv->active.clear();
+            sv->cv_done.notify_all();
+            break;
+        }
+        for (Request *r : finished) {
+            r->t_done = t1;
+            r->done = true;
+            sv->pool.release(r->off, r->bytes);
+            sv->completed += 1;
+        }
+        if (!finished.empty()) {
+            sv->active.erase(std::remove_if(sv->active.begin(), sv->active.end(), [](Request *r) { return r->done; }),
+                             sv->active.end());
+            std::vector<System *> sys;
+            for (Request *r : sv->active) sys.push_back(&r->sys);
+            std::string e2;
+            if (rbsog::batch_set_systems(sv->batch, sys, e2) != RBSOG_OK) {
+                sv->worker_err = e2;
+                break;
+            }
+            sv->cv_done.notify_all();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int rbsog_server_create(int32_t precision, int64_t pool_bytes, int32_t max_active, void *hip_stream,
+                        rbsog_server **out)
+{
+    if (!out) return RBSOG_EINVAL;
+    *out = nullptr;
+    if ((precision != RBSOG_PREC_FP32C && precision != RBSOG_PREC_FP64) || pool_bytes <= 0 || max_active < 1 ||
+        max_active > 65536)
+        return RBSOG_EINVAL;
+    rbsog_server *sv = new (std::nothrow) rbsog_server;
+    if (!sv) return RBSOG_ENOMEM;
+    sv->precision = precision;
+    sv->pool_bytes = static_cast<size_t>(pool_bytes);
+    sv->max_active = max_active;
+    sv->stream = static_cast<hipStream_t>(hip_stream);
+    std::string err;
+    int rc = rbsog::batch_init(sv->batch, sv->stream, precision, err);
+    if (rc == RBSOG_OK && hipGetDevice(&sv->device) != hipSuccess) rc = RBSOG_EDEVICE;
+    if (rc == RBSOG_OK && hipMalloc(reinterpret_cast<void **>(&sv->pool_mem), sv->pool_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = RBSOG_ENOMEM;
+    }
+    if (rc != RBSOG_OK) {
+        rbsog::batch_free(sv->batch);
+        delete sv;
+        return rc;
+    }
+    sv->pool.reset(sv->pool_bytes);
+    sv->worker = std::thread(worker_main, sv);
+    *out = sv;
+    return RBSOG_OK;
+}
+
+int rbsog_server_submit(rbsog_server *sv, const rbsog_params *params, int64_t n, const double *host_q,
+                        const double *host_x, const double *host_y, const double *host_z, const double host_box[3],
+                        int32_t nsteps, double growth, int64_t *ticket)
+{
+    if (!sv) return RBSOG_EINVAL;
+    if (!params || !host_q || !host_x || !host_y || !host_z || !host_box || !ticket || nsteps < 1 ||
+        !std::isfinite(growth)) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->err = "null argument or bad step count";
+        return RBSOG_EINVAL;
+    }
+    if (params->precision != sv->precision) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->err = "request precision differs from the server's";
+        return RBSOG_EINVAL;
+    }
+    std::unique_ptr<Request> r(new (std::nothrow) Request);
+    if (!r) return RBSOG_ENOMEM;
+    std::string err;
+    int rc = rbsog::system_init(r->sys, *params, n, host_q, host_box, err);
+    // boxes of every step: L_k = L_{k-1} mu_k, mu_k = (1 + g k)/(1 + g (k - 1))
+    if (rc == RBSOG_OK) {
+        r->boxes.resize(3 * static_cast<size_t>(nsteps));
+        r->mus.resize(nsteps);
+        double L[3] = {host_box[0], host_box[1], host_box[2]};
+        for (int k = 0; k < nsteps && rc == RBSOG_OK; ++k) {
+            const double m = k == 0 ? 1.0 : (1.0 + growth * k) / (1.0 + growth * (k - 1));
+            if (!(m > 0.0) || !std::isfinite(m)) {
+                err = "box law gives a non-positive scale factor";
+                rc = RBSOG_EINVAL;
+                break;
+            }
+            r->mus[k] = m;
+            for (int d = 0; d < 3; ++d) {
+                if (k > 0) L[d] *= m;
+                r->boxes[3 * k + d] = L[d];
+            }
+            rc = rbsog::check_box(L, params->rc, err);
+            r->max_cells = std::max(r->max_cells, rbsog::cells_for_box(L, params->rc));
+        }
+    }
+    if (rc == RBSOG_OK) {
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(host_x[i]) || !std::isfinite(host_y[i]) || !std::isfinite(host_z[i])) {
+                err = "positions have NaN/Inf";
+                rc = RBSOG_EINVAL;
+                break;
+            }
+    }
+    if (rc == RBSOG_OK) {
+        r->bytes = request_bytes(r->sys.prm, n, r->max_cells);
+        if (r->bytes > sv->pool_bytes) {
+            err = "request needs more device memory than the pool holds";
+            rc = RBSOG_EAGAIN;
+        }
+    }
+    if (rc != RBSOG_OK) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->err = err;
+        return rc;
+    }
+    r->n = n;
+    r->nsteps = nsteps;
+    r->growth = growth;
+    r->q.assign(host_q, host_q + n);
+    r->x.assign(host_x, host_x + n);
+    r->y.assign(host_y, host_y + n);
+    r->z.assign(host_z, host_z + n);
+    r->P.assign(9 * static_cast<size_t>(nsteps), 0.0);
+    r->U.assign(3 * static_cast<size_t>(nsteps), 0.0);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop || !sv->worker_err.empty()) {
+        sv->err = "server is stopped: " + sv->worker_err;
+        return RBSOG_ESTATE;
+    }
+    r->ticket = sv->next_ticket++;
+    r->t_submit = Clock::now();
+    *ticket = r->ticket;
+    sv->pending.push_back(r.get());
+    sv->requests.emplace(r->ticket, std::move(r));
+    sv->submitted += 1;
+    sv->cv_work.notify_one();
+    return RBSOG_OK;
+}
+
+int rbsog_server_wait(rbsog_server *sv, int64_t ticket, double timeout_s, double *host_fx, double *host_fy,
+                      double *host_fz, double *host_P, double *host_energy, double *host_times)
+{
+    if (!sv) return RBSOG_EINVAL;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->requests.find(ticket);
+    if (it == sv->requests.end()) {
+        sv->err = "unknown ticket";
+        return RBSOG_EINVAL;
+    }
+    Request *r = it->second.get();
+    auto ready = [&] { return r->done; };
+    if (timeout_s < 0) {
+        sv->cv_done.wait(lk, ready);
+    } else if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+        return RBSOG_EAGAIN;
+    }
+    if (r->status != RBSOG_OK) {
+        sv->err = "request failed: " + sv->worker_err;
+        const int st = r->status;
+        sv->requests.erase(it);
+        return st;
+    }
+    const int64_t n = r->n;
+    if (host_fx) std::memcpy(host_fx, r->fx.data(), n * sizeof(double));
+    if (host_fy) std::memcpy(host_fy, r->fy.data(), n * sizeof(double));
+    if (host_fz) std::memcpy(host_fz, r->fz.data(), n * sizeof(double));
+    if (host_P) std::memcpy(host_P, r->P.data(), r->P.size() * sizeof(double));
+    if (host_energy) std::memcpy(host_energy, r->U.data(), r->U.size() * sizeof(double));
+    if (host_times) {
+        host_times[0] = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+        host_times[1] = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+        host_times[2] = r->shared_ticks;
+    }
+    sv->requests.erase(it);
+    return RBSOG_OK;
+}
+
+int rbsog_server_stats(rbsog_server *sv, double *host_stats)
+{
+    if (!sv || !host_stats) return RBSOG_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    host_stats[0] = static_cast<double>(sv->submitted);
+    host_stats[1] = static_cast<double>(sv->completed);
+    host_stats[2] = static_cast<double>(sv->ticks);
+    host_stats[3] = sv->atom_steps;
+    host_stats[4] = sv->busy_s;
+    host_stats[5] = static_cast<double>(sv->peak_active);
+    host_stats[6] = static_cast<double>(sv->pool.peak());
+    host_stats[7] = static_cast<double>(sv->pending.size());
+    return RBSOG_OK;
+}
+
+int rbsog_server_destroy(rbsog_server *sv)
+{
+    if (!sv) return RBSOG_OK;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    (void)hipStreamSynchronize(sv->stream);
+    rbsog::batch_free(sv->batch);
+    if (sv->pool_mem) (void)hipFree(sv->pool_mem);
+    delete sv;
+    return RBSOG_OK;
+}
+
+const char *rbsog_server_last_error(const rbsog_server *sv) { return sv ? sv->err.c_str() : "null server"; }
+
+}  // extern "C"

@@ -1,0 +1,671 @@
+// Systems and batches on the host: validation, splitting tables, device
+// buffer layout, descriptors, launch plans and their uploads, event timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rbsog_impl.hpp"
+
+namespace rbsog {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_fp64(const rbsog_params &p) { return p.precision == RBSOG_PREC_FP64; }
+
+// byte sizes of the per-atom and per-mode buffers, in carving order
+struct AtomLayout {
+    size_t q, u, cell, perm_tmp, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, coef, scan_tmp;
+    size_t total() const
+    {
+        return q + u + cell + perm_tmp + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + coef + scan_tmp;
+    }
+};
+
+AtomLayout atom_layout(const rbsog_params &p, int64_t n)
+{
+    const bool f64 = is_fp64(p);
+    const size_t rsz = f64 ? 8 : 4, fsz = f64 ? 8 : 4, recsz = f64 ? 32 : 16;
+    const size_t mcap = static_cast<size_t>(p.P) + 1;
+    const size_t skb = static_cast<size_t>((n + kSkChunk - 1) / kSkChunk);
+    AtomLayout a{};
+    a.q = align_up(n * rsz);
+    a.u = align_up(3 * n * fsz);
+    a.cell = align_up(n * 4);
+    a.perm_tmp = align_up(n * 4);
+    a.perm = align_up(n * 4);
+    a.rec = align_up(n * recsz);
+    a.fsr = align_up(3 * n * rsz);
+    a.mraw = align_up(6 * static_cast<size_t>(p.P) * 4);
+    a.modes = align_up(mcap * sizeof(int4));
+    a.cnt = align_up(2 * mcap * 4);
+    a.rho_part = align_up(skb * mcap * 16);
+    a.rho = align_up(mcap * 16);
+    a.coef = align_up(mcap * 64);
+    a.scan_tmp = align_up((2 * 1024 + 2) * 4);
+    return a;
+}
+
+}  // namespace
+
+int check_box(const double *box, double rc, std::string &err)
+{
+    if (!box) {
+        err = "box is NULL";
+        return RBSOG_EINVAL;
+    }
+    if (!std::isfinite(box[0]) || !std::isfinite(box[1]) || !std::isfinite(box[2])) {
+        err = "box has NaN/Inf";
+        return RBSOG_EINVAL;
+    }
+    if (box[0] <= 0 || box[1] <= 0 || box[2] <= 0) {
+        err = "box edges must be positive";
+        return RBSOG_EBOX;
+    }
+    const double lmin = std::min(box[0], std::min(box[1], box[2]));
+    if (rc > 0.5 * lmin) {
+        err = "cutoff exceeds half the shortest box edge";
+        return RBSOG_EBOX;
+    }
+    int nc[3];
+    cell_grid(box, rc, nc);
+    if (static_cast<int64_t>(nc[0]) * nc[1] * nc[2] > kMaxCells) {
+        err = "more than 2^20 cells: box too large for rc";
+        return RBSOG_EBOX;
+    }
+    return RBSOG_OK;
+}
+
+int64_t cells_for_box(const double box[3], double rc)
+{
+    int nc[3];
+    cell_grid(box, rc, nc);
+    return static_cast<int64_t>(nc[0]) * nc[1] * nc[2];
+}
+
+int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_q, const double box[3],
+                std::string &err)
+{
+    if (n <= 0 || n > (int64_t)1 << 30) {
+        err = "atom count must be in [1, 2^30]";
+        return RBSOG_EINVAL;
+    }
+    if (!host_q) {
+        err = "charges are NULL";
+        return RBSOG_EINVAL;
+    }
+    if (!(p.b > 1.0) || !(p.sigma > 0.0) || !std::isfinite(p.b) || !std::isfinite(p.sigma) ||
+        !std::isfinite(p.omega)) {
+        err = "bad SOG parameters";
+        return RBSOG_EINVAL;
+    }
+    if (p.M < 1 || p.M > RBSOG_MAX_M || p.P < 1 || p.P > kMaxP) {
+        err = "M or P out of range";
+        return RBSOG_EINVAL;
+    }
+    if (!(p.rc > 0.0) || !std::isfinite(p.rc) || !std::isfinite(p.coulomb_k)) {
+        err = "bad cutoff or prefactor";
+        return RBSOG_EINVAL;
+    }
+    if (p.precision != RBSOG_PREC_FP64 && p.precision != RBSOG_PREC_FP32C) {
+        err = "unknown precision";
+        return RBSOG_EINVAL;
+    }
+    if (p.recalibration != RBSOG_RECAL_PRINTED && p.recalibration != RBSOG_RECAL_EXCHANGE) {
+        err = "unknown recalibration";
+        return RBSOG_EINVAL;
+    }
+    if (p.system_id >> 32) {
+        err = "system_id must be < 2^32";
+        return RBSOG_EINVAL;
+    }
+    double qs = 0.0, qa = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(host_q[i])) {
+            err = "charges have NaN/Inf";
+            return RBSOG_EINVAL;
+        }
+        qs += host_q[i];
+        qa += std::fabs(host_q[i]);
+    }
+    if (std::fabs(qs) > 1e-10 * qa) {
+        err = "charges are not neutral";
+        return RBSOG_ENEUTRAL;
+    }
+    int rc = check_box(box, p.rc, err);
+    if (rc) return rc;
+
+    s.prm = p;
+    s.n = n;
+    if (s.prm.omega <= 0.0) s.prm.omega = omega_c0(p.b, p.sigma, p.rc, p.M);
+    sog_tables(s.prm, s.w, s.wt, s.s);
+    double wsum = 0.0;
+    for (int l = 0; l < p.M; ++l) wsum += s.w[l];
+    s.q2sum = 0.0;
+    for (int64_t i = 0; i < n; ++i) s.q2sum += host_q[i] * host_q[i];
+    // U_self = (1/2) F(0) sum q^2 (App. A)
+    s.Uself = p.coulomb_k * 0.5 * wsum * s.q2sum;
+
+    SogTables &tab = s.tab;
+    tab = SogTables{};
+    tab.M = p.M;
+    tab.rc2 = p.rc * p.rc;
+    tab.rc2_32 = static_cast<float>(p.rc * p.rc);
+    const double log2e = 1.4426950408889634073599246810018921;
+    for (int l = 0; l < p.M; ++l) {
+        tab.w[l] = s.w[l];
+        tab.wt[l] = s.wt[l];
+        tab.s[l] = s.s[l];
+        tab.inv_s2[l] = 1.0 / (s.s[l] * s.s[l]);
+        tab.s5[l] = std::pow(s.s[l], 5);
+        tab.s7[l] = std::pow(s.s[l], 7);
+        tab.w32[l] = static_cast<float>(s.w[l]);
+        tab.wt32[l] = static_cast<float>(s.wt[l]);
+        tab.c32[l] = static_cast<float>(-log2e / (s.s[l] * s.s[l]));
+    }
+
+    SysDesc &d = s.desc;
+    d = SysDesc{};
+    d.tab = tab;
+    d.n = n;
+    d.sk_blocks = (n + kSkChunk - 1) / kSkChunk;
+    d.P = p.P;
+    d.M = p.M;
+    d.variant = p.recalibration;
+    d.mcap = p.P + 1;
+    d.key0 = static_cast<uint32_t>(p.seed);
+    d.key1 = static_cast<uint32_t>(p.seed >> 32);
+    d.sys = static_cast<uint32_t>(p.system_id);
+    d.ck = p.coulomb_k;
+    d.Uself = s.Uself;
+    s.stp = SysStep{};
+    for (int k = 0; k < 3; ++k) s.stp.mu[k] = 1.0;
+    system_set_box(s, box);
+    return RBSOG_OK;
+}
+
+void system_set_box(System &s, const double box[3])
+{
+    for (int d = 0; d < 3; ++d) s.L[d] = box[d];
+    cell_grid(s.L, s.prm.rc, s.nc);
+    s.ncells = static_cast<int64_t>(s.nc[0]) * s.nc[1] * s.nc[2];
+    norm_consts(s.L, s.prm.M, s.wt, s.s, &s.Sr, &s.Snr);
+    SysStep &t = s.stp;
+    for (int d = 0; d < 3; ++d) {
+        t.L[d] = s.L[d];
+        t.iL[d] = 1.0 / s.L[d];
+        t.nc[d] = s.nc[d];
+    }
+    t.ncells = static_cast<int32_t>(s.ncells);
+    t.Sr = s.Sr;
+    t.Snr = s.Snr;
+}
+
+size_t system_atom_bytes(const rbsog_params &p, int64_t n) { return atom_layout(p, n).total(); }
+
+size_t system_cell_bytes(int64_t n, int64_t ncells_cap)
+{
+    const size_t pair_cap = static_cast<size_t>((n + kPairWave - 1) / kPairWave + ncells_cap);
+    return 5 * align_up((ncells_cap + 1) * 4) + align_up(pair_cap * sizeof(int2)) + align_up(pair_cap * 8 * 8);
+}
+
+void system_carve_atoms(System &s, void *mem)
+{
+    const AtomLayout a = atom_layout(s.prm, s.n);
+    char *p = static_cast<char *>(mem);
+    SysDesc &d = s.desc;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += bytes;
+        return static_cast<void *>(r);
+    };
+    d.q = take(a.q);
+    d.u = take(a.u);
+    d.cell = static_cast<int32_t *>(take(a.cell));
+    d.perm_tmp = static_cast<int32_t *>(take(a.perm_tmp));
+    d.perm = static_cast<int32_t *>(take(a.perm));
+    d.rec = take(a.rec);
+    d.fsr = take(a.fsr);
+    d.mraw = static_cast<int32_t *>(take(a.mraw));
+    d.modes = static_cast<int4 *>(take(a.modes));
+    d.cnt = static_cast<int32_t *>(take(a.cnt));
+    d.rho_part = static_cast<double *>(take(a.rho_part));
+    d.rho = static_cast<double *>(take(a.rho));
+    d.coef = take(a.coef);
+    d.scan_tmp = static_cast<int32_t *>(take(a.scan_tmp));
+    s.atom_mem = mem;
+    s.atom_bytes = a.total();
+}
+
+void system_carve_cells(System &s, void *mem, int64_t ncells_cap)
+{
+    char *p = static_cast<char *>(mem);
+    SysDesc &d = s.desc;
+    const size_t cb = align_up((ncells_cap + 1) * 4);
+    int32_t **arrs[] = {&d.count, &d.cursor, &d.start, &d.nblk, &d.bstart};
+    for (auto a : arrs) {
+        *a = reinterpret_cast<int32_t *>(p);
+        p += cb;
+    }
+    d.pair_cap = (s.n + kPairWave - 1) / kPairWave + ncells_cap;
+    d.blocks = reinterpret_cast<int2 *>(p);
+    p += align_up(d.pair_cap * sizeof(int2));
+    d.pair_part = reinterpret_cast<double *>(p);
+    d.ncells_cap = ncells_cap;
+    s.cell_mem = mem;
+    s.cell_bytes = system_cell_bytes(s.n, ncells_cap);
+    s.ncells_cap = ncells_cap;
+}
+
+int system_alloc(System &s, std::string &err)
+{
+    void *am = nullptr;
+    const size_t ab = system_atom_bytes(s.prm, s.n);
+    if (hipMalloc(&am, ab) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "device allocation failed";
+        return RBSOG_ENOMEM;
+    }
+    s.own_mem = true;
+    system_carve_atoms(s, am);
+    s.ncells_cap = 0;
+    return system_ensure_cells(s, err);
+}
+
+int system_ensure_cells(System &s, std::string &err)
+{
+    if (s.ncells <= s.ncells_cap) return RBSOG_OK;
+    if (!s.own_mem && s.cell_mem) {
+        err = "cell grid outgrew the memory reserved at admission";
+        return RBSOG_EBOX;
+    }
+    if (s.cell_mem) {
+        (void)hipFree(s.cell_mem);  // synchronises the device
+        s.cell_mem = nullptr;
+    }
+    void *cm = nullptr;
+    if (hipMalloc(&cm, system_cell_bytes(s.n, s.ncells)) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "device allocation failed";
+        return RBSOG_ENOMEM;
+    }
+    system_carve_cells(s, cm, s.ncells);
+    return RBSOG_OK;
+}
+
+void system_free(System &s)
+{
+    if (s.own_mem) {
+        if (s.atom_mem) (void)hipFree(s.atom_mem);
+        if (s.cell_mem) (void)hipFree(s.cell_mem);
+    }
+    s.atom_mem = s.cell_mem = nullptr;
+}
+
+int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err)
+{
+    const int64_t n = s.n;
+    hipError_t e;
+    if (is_fp64(s.prm)) {
+        e = hipMemcpyAsync(const_cast<void *>(s.desc.q), host_q, n * sizeof(double), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    } else {
+        std::vector<float> q32(n);
+        for (int64_t i = 0; i < n; ++i) q32[i] = static_cast<float>(host_q[i]);
+        e = hipMemcpyAsync(const_cast<void *>(s.desc.q), q32.data(), n * sizeof(float), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);  // q32 leaves scope
+    }
+    if (e != hipSuccess) {
+        err = std::string("charge upload: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    return RBSOG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+
+int batch_init(Batch &b, hipStream_t stream, int precision, std::string &err)
+{
+    b.stream = stream;
+    b.precision = precision;
+    if (hipGetDevice(&b.device) != hipSuccess) {
+        err = "no HIP device";
+        return RBSOG_EDEVICE;
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b.device) == hipSuccess && ncu > 0)
+        b.num_cu = ncu;
+    bool ok = hipMalloc(&b.d_ctrl, 64) == hipSuccess &&
+              hipEventCreateWithFlags(&b.up_done, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < Batch::kStepRing; ++k)
+        ok = hipEventCreateWithFlags(&b.step_ev[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        err = "device allocation failed";
+        return RBSOG_ENOMEM;
+    }
+    return RBSOG_OK;
+}
+
+static void free_timers(Batch &b)
+{
+    for (auto &t : b.timers) {
+        for (auto &e : t.pending) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        for (auto &e : t.pool) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+    b.timers.clear();
+}
+
+void batch_free(Batch &b)
+{
+    if (b.graph_exec) (void)hipGraphExecDestroy(b.graph_exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.graph_exec = nullptr;
+    b.graph = nullptr;
+    void *dev[] = {b.d_desc, b.d_step, b.d_res, b.d_plan, b.d_ctrl};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    void *host[] = {b.h_desc, b.h_res, b.h_plan};
+    for (void *p : host)
+        if (p) (void)hipHostFree(p);
+    for (int k = 0; k < Batch::kStepRing; ++k) {
+        if (b.h_step[k]) (void)hipHostFree(b.h_step[k]);
+        if (b.step_ev[k]) (void)hipEventDestroy(b.step_ev[k]);
+        b.h_step[k] = nullptr;
+        b.step_ev[k] = nullptr;
+    }
+    if (b.up_done) (void)hipEventDestroy(b.up_done);
+    b.d_desc = nullptr;
+    b.d_step = nullptr;
+    b.d_res = nullptr;
+    b.d_plan = nullptr;
+    b.d_ctrl = nullptr;
+    b.h_desc = nullptr;
+    b.h_res = nullptr;
+    b.h_plan = nullptr;
+    b.up_done = nullptr;
+    free_timers(b);
+}
+
+// the pinned mirrors may be rewritten only after the last upload has run
+static int wait_uploads(Batch &b, std::string &err)
+{
+    if (!b.up_pending) return RBSOG_OK;
+    const hipError_t e = hipEventSynchronize(b.up_done);
+    if (e != hipSuccess) {
+        err = std::string("upload wait: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    b.up_pending = false;
+    return RBSOG_OK;
+}
+
+int batch_set_systems(Batch &b, const std::vector<System *> &sys, std::string &err)
+{
+    int rc = wait_uploads(b, err);
+    if (rc) return rc;
+    const int64_t S = static_cast<int64_t>(sys.size());
+    if (S > b.cap_sys) {
+        // the old buffers may still be read by queued work
+        if (hipStreamSynchronize(b.stream) != hipSuccess) {
+            err = "stream synchronisation failed";
+            return RBSOG_EDEVICE;
+        }
+        const int64_t cap = std::max<int64_t>(S, 2 * b.cap_sys);
+        if (b.d_desc) (void)hipFree(b.d_desc);
+        if (b.d_step) (void)hipFree(b.d_step);
+        if (b.d_res) (void)hipFree(b.d_res);
+        if (b.h_desc) (void)hipHostFree(b.h_desc);
+        if (b.h_res) (void)hipHostFree(b.h_res);
+        for (int k = 0; k < Batch::kStepRing; ++k) {
+            if (b.h_step[k]) (void)hipHostFree(b.h_step[k]);
+            b.h_step[k] = nullptr;
+            b.step_ev_used[k] = false;
+        }
+        b.d_desc = nullptr;
+        b.d_step = nullptr;
+        b.d_res = nullptr;
+        b.h_desc = nullptr;
+        b.h_res = nullptr;
+        b.cap_sys = 0;
+        bool ok = hipMalloc(&b.d_desc, cap * sizeof(SysDesc)) == hipSuccess &&
+                  hipMalloc(&b.d_step, cap * sizeof(SysStep)) == hipSuccess &&
+                  hipMalloc(&b.d_res, cap * sizeof(StepResults)) == hipSuccess &&
+                  hipHostMalloc(reinterpret_cast<void **>(&b.h_desc), cap * sizeof(SysDesc)) == hipSuccess &&
+                  hipHostMalloc(reinterpret_cast<void **>(&b.h_res), cap * sizeof(StepResults)) == hipSuccess;
+        for (int k = 0; ok && k < Batch::kStepRing; ++k)
+            ok = hipHostMalloc(reinterpret_cast<void **>(&b.h_step[k]), cap * sizeof(SysStep)) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            err = "batch allocation failed";
+            return RBSOG_ENOMEM;
+        }
+        b.cap_sys = cap;
+    }
+    b.sys = sys;
+    b.desc_dirty = true;
+    b.plan_dirty = true;
+    return RBSOG_OK;
+}
+
+static std::vector<int64_t> plan_sizes(const Batch &b)
+{
+    std::vector<int64_t> k;
+    k.reserve(3 * b.sys.size());
+    for (const System *s : b.sys) {
+        k.push_back(s->n);
+        k.push_back(s->ncells);
+        k.push_back(s->prm.P);
+    }
+    return k;
+}
+
+static int build_plans(Batch &b, std::string &err)
+{
+    int64_t len[kNumPlans] = {};
+    for (const System *s : b.sys) {
+        len[kPlanAtoms] += (s->n + kAtomBlock - 1) / kAtomBlock;
+        len[kPlanCells] += (s->ncells + 1 + kCellBlock - 1) / kCellBlock;
+        len[kPlanScan] += (s->ncells + kScanBlock - 1) / kScanBlock;
+        len[kPlanPair] += (s->n + kPairWave - 1) / kPairWave + s->ncells;
+        len[kPlanSk] += (s->n + kSkChunk - 1) / kSkChunk;
+        len[kPlanReduce] += s->prm.P + 2;
+    }
+    int64_t total = 0;
+    for (int k = 0; k < kNumPlans; ++k) {
+        b.plan_off[k] = total;
+        b.plan_len[k] = len[k];
+        total += len[k];
+    }
+    if (total > INT32_MAX) {
+        err = "batch too large for one launch";
+        return RBSOG_EINVAL;
+    }
+    if (total > b.cap_plan) {
+        const int64_t cap = std::max<int64_t>(total, 2 * b.cap_plan);
+        if (b.d_plan) (void)hipFree(b.d_plan);
+        if (b.h_plan) (void)hipHostFree(b.h_plan);
+        b.d_plan = nullptr;
+        b.h_plan = nullptr;
+        b.cap_plan = 0;
+        if (hipMalloc(&b.d_plan, cap * sizeof(int2)) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&b.h_plan), cap * sizeof(int2)) != hipSuccess) {
+            (void)hipGetLastError();
+            err = "plan allocation failed";
+            return RBSOG_ENOMEM;
+        }
+        b.cap_plan = cap;
+    }
+    int64_t pos[kNumPlans];
+    for (int k = 0; k < kNumPlans; ++k) pos[k] = b.plan_off[k];
+    auto put = [&](PlanKind k, int s, int64_t nblocks) {
+        for (int64_t i = 0; i < nblocks; ++i) b.h_plan[pos[k]++] = make_int2(s, static_cast<int>(i));
+    };
+    const int S = static_cast<int>(b.sys.size());
+    for (int s = 0; s < S; ++s) {
+        const System *y = b.sys[s];
+        put(kPlanAtoms, s, (y->n + kAtomBlock - 1) / kAtomBlock);
+        put(kPlanCells, s, (y->ncells + 1 + kCellBlock - 1) / kCellBlock);
+        put(kPlanScan, s, (y->ncells + kScanBlock - 1) / kScanBlock);
+        put(kPlanSk, s, (y->n + kSkChunk - 1) / kSkChunk);
+        put(kPlanReduce, s, y->prm.P + 2);
+    }
+    // pair blocks of systems with M = 10 first (kernel with the weights in
+    // registers), then the others (runtime M)
+    for (int pass = 0; pass < 2; ++pass)
+        for (int s = 0; s < S; ++s) {
+            const System *y = b.sys[s];
+            if ((y->prm.M == 10) == (pass == 0)) put(kPlanPair, s, (y->n + kPairWave - 1) / kPairWave + y->ncells);
+            if (pass == 0 && s == S - 1) b.pair_m10 = pos[kPlanPair] - b.plan_off[kPlanPair];
+        }
+    return RBSOG_OK;
+}
+
+int batch_upload(Batch &b, std::string &err)
+{
+    if (b.sys.empty()) return RBSOG_OK;
+    int rc = wait_uploads(b, err);
+    if (rc) return rc;
+    const int64_t S = static_cast<int64_t>(b.sys.size());
+    hipError_t e = hipSuccess;
+    if (b.desc_dirty) {
+        for (int64_t s = 0; s < S; ++s) {
+            b.h_desc[s] = b.sys[s]->desc;
+            b.h_desc[s].res = b.d_res + s;
+        }
+        e = hipMemcpyAsync(b.d_desc, b.h_desc, S * sizeof(SysDesc), hipMemcpyHostToDevice, b.stream);
+        b.desc_dirty = false;
+    }
+    const std::vector<int64_t> key = plan_sizes(b);
+    if (e == hipSuccess && (b.plan_dirty || key != b.plan_key)) {
+        rc = build_plans(b, err);
+        if (rc) return rc;
+        int64_t total = 0;
+        for (int k = 0; k < kNumPlans; ++k) total += b.plan_len[k];
+        e = hipMemcpyAsync(b.d_plan, b.h_plan, total * sizeof(int2), hipMemcpyHostToDevice, b.stream);
+        b.plan_key = key;
+        b.plan_dirty = false;
+    }
+    if (e == hipSuccess) e = hipEventRecord(b.up_done, b.stream);
+    b.up_pending = true;
+    // per-step data: the next pinned buffer of the ring, reused once the copy
+    // that last read it has run
+    if (e == hipSuccess) {
+        const int k = b.step_slot;
+        b.step_slot = (k + 1) % Batch::kStepRing;
+        if (b.step_ev_used[k]) e = hipEventSynchronize(b.step_ev[k]);
+        if (e == hipSuccess) {
+            for (int64_t s = 0; s < S; ++s) b.h_step[k][s] = b.sys[s]->stp;
+            e = hipMemcpyAsync(b.d_step, b.h_step[k], S * sizeof(SysStep), hipMemcpyHostToDevice, b.stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(b.step_ev[k], b.stream);
+        b.step_ev_used[k] = true;
+    }
+    if (e != hipSuccess) {
+        err = std::string("batch upload: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    return RBSOG_OK;
+}
+
+int batch_fetch_results(Batch &b, std::string &err)
+{
+    if (b.sys.empty()) return RBSOG_OK;
+    hipError_t e = hipMemcpyAsync(b.h_res, b.d_res, b.sys.size() * sizeof(StepResults), hipMemcpyDeviceToHost,
+                                  b.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) {
+        err = std::string("result copy: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    b.up_pending = false;
+    return RBSOG_OK;
+}
+
+void timer_begin(Batch &b, const char *name)
+{
+    if (!b.timing) return;
+    Timer *t = nullptr;
+    for (auto &x : b.timers)
+        if (x.name == name) t = &x;
+    if (!t) {
+        if (b.timers.size() >= static_cast<size_t>(kMaxTimed)) return;
+        b.timers.push_back(Timer{});
+        t = &b.timers.back();
+        t->name = name;
+    }
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!t->pool.empty()) {
+        ev = t->pool.back();
+        t->pool.pop_back();
+    } else {
+        (void)hipEventCreate(&ev.first);
+        (void)hipEventCreate(&ev.second);
+    }
+    (void)hipEventRecord(ev.first, b.stream);
+    t->pending.push_back(ev);
+}
+
+void timer_end(Batch &b, const char *name)
+{
+    if (!b.timing) return;
+    for (auto &x : b.timers)
+        if (x.name == name && !x.pending.empty()) {
+            (void)hipEventRecord(x.pending.back().second, b.stream);
+            return;
+        }
+}
+
+void batch_set_timing(Batch &b, bool on)
+{
+    (void)hipStreamSynchronize(b.stream);
+    free_timers(b);
+    b.timing = on;
+}
+
+int batch_get_timing(Batch &b, int32_t cap, int32_t *host_nk, char *host_names, double *host_ms,
+                     int64_t *host_count, std::string &err)
+{
+    const hipError_t e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) {
+        err = std::string("timing: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    for (auto &t : b.timers) {
+        for (auto &ev : t.pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+                t.ms += ms;
+                t.count += 1;
+            }
+            t.pool.push_back(ev);
+        }
+        t.pending.clear();
+    }
+    const int nk = static_cast<int>(b.timers.size());
+    if (host_nk) *host_nk = nk;
+    for (int k = 0; k < std::min(nk, static_cast<int>(cap)); ++k) {
+        if (host_names) {
+            std::memset(host_names + 32 * k, 0, 32);
+            std::strncpy(host_names + 32 * k, b.timers[k].name.c_str(), 31);
+        }
+        if (host_ms) host_ms[k] = b.timers[k].ms;
+        if (host_count) host_count[k] = b.timers[k].count;
+    }
+    return RBSOG_OK;
+}
+
+}  // namespace rbsog

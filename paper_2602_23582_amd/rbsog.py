@@ -26,9 +26,17 @@ MAX_MODES = MAX_P + 1
 ERRORS = {0: "RBSOG_OK", -1: "RBSOG_EINVAL", -2: "RBSOG_ENEUTRAL", -3: "RBSOG_EBOX", -4: "RBSOG_ENOMEM",
           -5: "RBSOG_EDEVICE", -6: "RBSOG_ESTATE", -7: "RBSOG_EAGAIN"}
 
+SCHED_STATIC = 0
+SCHED_PERSISTENT = 1
+AUTOTUNE_CANDIDATES = [("static", 1), ("persistent", 4), ("persistent", 8), ("persistent", 16), ("persistent", 32)]
+
 EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_force_virial", "rbsog_pressure",
            "rbsog_rescale", "rbsog_destroy", "rbsog_strerror", "rbsog_last_error", "rbsog_debug_cells",
-           "rbsog_debug_modes", "rbsog_step_info", "rbsog_set_timing", "rbsog_get_timing", "rbsog_version"]
+           "rbsog_debug_modes", "rbsog_step_info", "rbsog_set_timing", "rbsog_get_timing", "rbsog_version",
+           "rbsog_batch_setup", "rbsog_batch_step", "rbsog_batch_rescale", "rbsog_batch_set_options",
+           "rbsog_batch_autotune", "rbsog_batch_set_timing", "rbsog_batch_get_timing", "rbsog_batch_destroy",
+           "rbsog_batch_last_error", "rbsog_server_create", "rbsog_server_submit", "rbsog_server_wait",
+           "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_last_error"]
 
 
 class rbsog_params(C.Structure):
@@ -74,6 +82,21 @@ def load(path: str | None = None):
         "rbsog_set_timing": (C.c_int, [vp, C.c_int]),
         "rbsog_get_timing": (C.c_int, [vp, i32, pi32, C.c_char_p, pd, pi64]),
         "rbsog_version": (C.c_int, []),
+        "rbsog_batch_setup": (C.c_int, [C.POINTER(rbsog_params), i32, pi64, pd, pd, vp, C.POINTER(vp)]),
+        "rbsog_batch_step": (C.c_int, [vp, pi64, pd, vp, vp, vp, vp, vp, vp, pd, pd, pi64]),
+        "rbsog_batch_rescale": (C.c_int, [vp, pd, vp, vp, vp, pd]),
+        "rbsog_batch_set_options": (C.c_int, [vp, i32, i32, i32]),
+        "rbsog_batch_autotune": (C.c_int, [vp, pi64, pd, vp, vp, vp, vp, vp, vp, i32, pd, pi32]),
+        "rbsog_batch_set_timing": (C.c_int, [vp, C.c_int]),
+        "rbsog_batch_get_timing": (C.c_int, [vp, i32, pi32, C.c_char_p, pd, pi64]),
+        "rbsog_batch_destroy": (C.c_int, [vp]),
+        "rbsog_batch_last_error": (C.c_char_p, [vp]),
+        "rbsog_server_create": (C.c_int, [i32, i64, i32, vp, C.POINTER(vp)]),
+        "rbsog_server_submit": (C.c_int, [vp, C.POINTER(rbsog_params), i64, pd, pd, pd, pd, pd, i32, d, pi64]),
+        "rbsog_server_wait": (C.c_int, [vp, i64, d, pd, pd, pd, pd, pd, pd]),
+        "rbsog_server_stats": (C.c_int, [vp, pd]),
+        "rbsog_server_destroy": (C.c_int, [vp]),
+        "rbsog_server_last_error": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -211,23 +234,228 @@ class Context:
         self._check(load().rbsog_set_timing(self._h, 1 if on else 0), "rbsog_set_timing")
 
     def get_timing(self):
-        cap = 32
-        nk = np.zeros(1, dtype=np.int32)
-        names = C.create_string_buffer(32 * cap)
-        ms = np.zeros(cap)
-        cnt = np.zeros(cap, dtype=np.int64)
-        self._check(load().rbsog_get_timing(self._h, cap, _pi32(nk), names, _pd(ms),
-                                            cnt.ctypes.data_as(C.POINTER(C.c_int64))), "rbsog_get_timing")
-        out = {}
-        raw = names.raw
-        for k in range(int(nk[0])):
-            nm = raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode()
-            out[nm] = (float(ms[k]), int(cnt[k]))
+        rc_, out = _timing_table(load().rbsog_get_timing, self._h)
+        self._check(rc_, "rbsog_get_timing")
         return out
 
     def close(self):
         if getattr(self, "_h", None):
             load().rbsog_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _pi64(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _timing_table(getter, handle):
+    cap = 32
+    nk = np.zeros(1, dtype=np.int32)
+    names = C.create_string_buffer(32 * cap)
+    ms = np.zeros(cap)
+    cnt = np.zeros(cap, dtype=np.int64)
+    rc = getter(handle, cap, _pi32(nk), names, _pd(ms), _pi64(cnt))
+    out = {}
+    raw = names.raw
+    for k in range(int(nk[0])):
+        nm = raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode()
+        out[nm] = (float(ms[k]), int(cnt[k]))
+    return rc, out
+
+
+def make_params(rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_PRINTED, M=10,
+                coulomb_k=1.0):
+    p = default_params(rc)
+    p.P, p.seed, p.system_id, p.M = int(P), int(seed), int(system_id), int(M)
+    p.precision, p.recalibration, p.coulomb_k = int(precision), int(recalibration), float(coulomb_k)
+    return p
+
+
+def _stream_or_default(stream):
+    if stream is not None:
+        return stream
+    try:
+        import torch
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+    except ImportError:
+        return None
+
+
+class Batch:
+    """Many systems per launch: wraps rbsog_batch_setup .. rbsog_batch_destroy.
+
+    systems: list of dicts with keys q, box, rc and optionally P, seed,
+    system_id, M, recalibration.  Positions and forces are device tensors of
+    sum(n) float64 entries, system after system."""
+
+    def __init__(self, systems, precision=PREC_FP32C, stream=None):
+        L = load()
+        S = len(systems)
+        arr = (rbsog_params * S)()
+        n = np.zeros(S, dtype=np.int64)
+        qs, boxes = [], np.zeros((S, 3))
+        for s, spec in enumerate(systems):
+            arr[s] = make_params(spec["rc"], P=spec.get("P", 100), seed=spec.get("seed", 0),
+                                 system_id=spec.get("system_id", 0), precision=precision,
+                                 recalibration=spec.get("recalibration", RECAL_PRINTED), M=spec.get("M", 10))
+            n[s] = len(spec["q"])
+            qs.append(np.asarray(spec["q"], dtype=np.float64))
+            boxes[s] = spec["box"]
+        q = np.ascontiguousarray(np.concatenate(qs))
+        self.n = n
+        self.offsets = np.concatenate([[0], np.cumsum(n)])
+        self.nsys = S
+        self.boxes = np.ascontiguousarray(boxes)
+        stream = _stream_or_default(stream)
+        h = C.c_void_p()
+        rc_ = L.rbsog_batch_setup(arr, S, _pi64(n), _pd(q), _pd(self.boxes), C.c_void_p(stream) if stream else None,
+                                  C.byref(h))
+        if rc_ != 0:
+            raise RBSOGError(rc_, "rbsog_batch_setup")
+        self._h = h
+
+    def _check(self, rc_, what):
+        if rc_ != 0:
+            msg = load().rbsog_batch_last_error(self._h)
+            raise RBSOGError(rc_, f"{what}: {msg.decode() if msg else ''}")
+
+    def step(self, steps, boxes, x, y, z, fx, fy, fz, results=True):
+        steps = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.int64), (self.nsys,)))
+        boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(self.nsys, 3)
+        if not results:
+            self._check(load().rbsog_batch_step(self._h, _pi64(steps), _pd(boxes), _ptr(x), _ptr(y), _ptr(z),
+                                                _ptr(fx), _ptr(fy), _ptr(fz), None, None, None), "rbsog_batch_step")
+            return None
+        P = np.zeros((self.nsys, 9))
+        U = np.zeros((self.nsys, 3))
+        info = np.zeros((self.nsys, 4), dtype=np.int64)
+        self._check(load().rbsog_batch_step(self._h, _pi64(steps), _pd(boxes), _ptr(x), _ptr(y), _ptr(z), _ptr(fx),
+                                            _ptr(fy), _ptr(fz), _pd(P), _pd(U), _pi64(info)), "rbsog_batch_step")
+        return P.reshape(self.nsys, 3, 3), U, info
+
+    def rescale(self, mu, x, y, z):
+        mu = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), (self.nsys, 3)))
+        self._check(load().rbsog_batch_rescale(self._h, _pd(mu), _ptr(x), _ptr(y), _ptr(z), _pd(self.boxes)),
+                    "rbsog_batch_rescale")
+        return self.boxes
+
+    def set_options(self, schedule=SCHED_STATIC, wg_per_cu=16, graph=False):
+        self._check(load().rbsog_batch_set_options(self._h, int(schedule), int(wg_per_cu), 1 if graph else 0),
+                    "rbsog_batch_set_options")
+
+    def autotune(self, steps, boxes, x, y, z, fx, fy, fz, reps=3):
+        steps = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.int64), (self.nsys,)))
+        boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(self.nsys, 3)
+        ms = np.zeros(len(AUTOTUNE_CANDIDATES))
+        choice = np.zeros(1, dtype=np.int32)
+        self._check(load().rbsog_batch_autotune(self._h, _pi64(steps), _pd(boxes), _ptr(x), _ptr(y), _ptr(z),
+                                                _ptr(fx), _ptr(fy), _ptr(fz), int(reps), _pd(ms), _pi32(choice)),
+                    "rbsog_batch_autotune")
+        return int(choice[0]), ms
+
+    def set_timing(self, on=True):
+        self._check(load().rbsog_batch_set_timing(self._h, 1 if on else 0), "rbsog_batch_set_timing")
+
+    def get_timing(self):
+        rc_, out = _timing_table(load().rbsog_batch_get_timing, self._h)
+        self._check(rc_, "rbsog_batch_get_timing")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rbsog_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """The served form: wraps rbsog_server_create .. rbsog_server_destroy."""
+
+    def __init__(self, precision=PREC_FP32C, pool_bytes=1 << 30, max_active=4096, stream=None):
+        L = load()
+        stream = _stream_or_default(stream)
+        h = C.c_void_p()
+        rc_ = L.rbsog_server_create(int(precision), int(pool_bytes), int(max_active),
+                                    C.c_void_p(stream) if stream else None, C.byref(h))
+        if rc_ != 0:
+            raise RBSOGError(rc_, "rbsog_server_create")
+        self._h = h
+        self.precision = precision
+        self._n = {}
+        self._steps = {}
+
+    def _check(self, rc_, what):
+        if rc_ != 0:
+            msg = load().rbsog_server_last_error(self._h)
+            raise RBSOGError(rc_, f"{what}: {msg.decode() if msg else ''}")
+
+    def submit(self, q, pos, box, rc, nsteps=10, growth=0.001, P=100, seed=0, system_id=0, M=10,
+               recalibration=RECAL_PRINTED):
+        """Queue one request; pos is (n, 3).  Returns its ticket."""
+        p = make_params(rc, P=P, seed=seed, system_id=system_id, precision=self.precision, M=M,
+                        recalibration=recalibration)
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        pos = np.asarray(pos, dtype=np.float64)
+        x, y, z = (np.ascontiguousarray(pos[:, k]) for k in range(3))
+        box = np.ascontiguousarray(box, dtype=np.float64)
+        t = np.zeros(1, dtype=np.int64)
+        self._check(load().rbsog_server_submit(self._h, C.byref(p), len(q), _pd(q), _pd(x), _pd(y), _pd(z), _pd(box),
+                                               int(nsteps), float(growth), _pi64(t)), "rbsog_server_submit")
+        ticket = int(t[0])
+        self._n[ticket] = len(q)
+        self._steps[ticket] = int(nsteps)
+        return ticket
+
+    def wait(self, ticket, timeout=-1.0):
+        """Block until the request completes; returns dict(forces (n, 3), P (nsteps, 3, 3),
+        U (nsteps, 3), queue_s, latency_s, shared_ticks), or None on timeout."""
+        n, ns = self._n[ticket], self._steps[ticket]
+        fx, fy, fz = np.zeros(n), np.zeros(n), np.zeros(n)
+        P = np.zeros((ns, 9))
+        U = np.zeros((ns, 3))
+        tm = np.zeros(3)
+        rc_ = load().rbsog_server_wait(self._h, int(ticket), float(timeout), _pd(fx), _pd(fy), _pd(fz), _pd(P), _pd(U),
+                                       _pd(tm))
+        if rc_ == -7:
+            return None
+        del self._n[ticket], self._steps[ticket]
+        self._check(rc_, "rbsog_server_wait")
+        return dict(forces=np.stack([fx, fy, fz], axis=1), P=P.reshape(ns, 3, 3), U=U, queue_s=float(tm[0]),
+                    latency_s=float(tm[1]), shared_ticks=int(tm[2]))
+
+    def stats(self):
+        st = np.zeros(8)
+        self._check(load().rbsog_server_stats(self._h, _pd(st)), "rbsog_server_stats")
+        keys = ["submitted", "completed", "ticks", "atom_steps", "busy_s", "peak_active", "peak_pool_bytes",
+                "waiting"]
+        return dict(zip(keys, st.tolist()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rbsog_server_destroy(self._h)
             self._h = None
 
     def __del__(self):
