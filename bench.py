@@ -26,27 +26,40 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RBSOG force+pressure atom-steps/s at 1e6 atoms, P=100; served p50/p99 latency"
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = VALU issue slots per second
-# (one non-packed FP32 lane-op per slot; transcendentals take 4 slots).
-VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-TRANS_SLOTS = 4
+# MI355X FP32 vector peak: 157.3 TFLOP/s = 256 CUs x 4 SIMDs x 32 FMA lanes per
+# clock x 2.4 GHz x 2 flops, i.e. 78.6e12 FP32 lane-ops (FMA, add, mul) per second.
+VALU_LANE_OPS_PER_S = 256 * 4 * 32 * 2.4e9
+# A transcendental (v_exp/v_rsq/v_sin/v_cos) occupies the issue of this many
+# FP32 lane-ops; measured by the probe in every run (this value only when the
+# probe is skipped).
+TRANS_WEIGHT_DEFAULT = 3.4
 
 
-def pair_slots(M):
-    """VALU slots of one unordered in-cutoff pair in the paper's M-exp form:
-    displacement 3, r^2 3, cutoff test 1, r^-3 from r^-1 2, exponent scaling M,
-    two weighted Gaussian sums 2M, N~ and N 2, q_i q_j and f 2, force on both
-    atoms 9, virial 6, energy 1; transcendentals: r^-1 and M exponentials."""
-    ops = 29 + 3 * M
-    trans = 1 + M
-    return ops + TRANS_SLOTS * trans
+def pair_work(trans_weight, M=10):
+    """Algorithmic work of one unordered in-cutoff pair, in FP32 lane-op
+    equivalents, for the paper's form of the SOG kernels: about 42 FMA-class
+    operations (2M for the two weighted Gaussian sums, about 22 for distance,
+    cutoff, N~, force on both atoms, 6 virial components and energy) and M + 1
+    transcendentals (M exponentials and r^-1)."""
+    return 42 + trans_weight * (M + 1)
 
 
-def mode_slots():
-    """VALU slots per (atom, distinct mode) of the structure factor (3 integer
-    multiply-adds, convert, 2 FMA + sin, cos) and of the force scatter (3
+def pair_work_implemented(trans_weight):
+    """The FP32C polynomial form as implemented: displacement 9, r^2 3, cutoff
+    1, r^-3 2, t 1, degree-10 Horner 10, N~ 1, q_i q_j and f 2, f r 3, force on
+    both atoms 6, virial 6 (no energy in the timed step), one transcendental."""
+    return 44 + trans_weight * 1
+
+
+def mode_work(trans_weight):
+    """Work per (atom, distinct mode): structure factor (3 integer
+    multiply-adds, convert, 2 FMA + sin, cos) and force scatter (3
     multiply-adds, convert, 2 + 3 FMA + sin, cos)."""
-    return (6 + 2 * TRANS_SLOTS), (9 + 2 * TRANS_SLOTS)
+    return 6 + 2 * trans_weight, 9 + 2 * trans_weight
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def make_workload(name):
@@ -129,6 +142,52 @@ def valu_probe(iters=32768, blocks=2048):
     return res
 
 
+def served_bench(n_req, seed, pool_bytes, lam_frac=0.8, nsteps=10, growth=0.001):
+    """The served stream: n_req independent systems (sizes log-uniform in
+    [500, 50,000] atoms, +-1e on jittered lattices at 0.1 A^-3, P from
+    {50, 100, 200}), each a request of nsteps steps under L_k = L_0 (1 + g k).
+    Capacity is measured with every request submitted at once; then requests
+    arrive as a Poisson stream at lam_frac x that capacity.  Each is run with
+    continuous batching (all admitted requests per tick) and one request at a
+    time (the same server with one slot), on the same GPU and at the same
+    accuracy.  Latency = completion - submission."""
+    from paper_2602_23582_amd import rbsog
+    from paper_2602_23582_amd import workloads as W
+    sizes, seeds = W.served_stream(n_req, seed=seed)
+    reqs = [W.ionic_system(int(n), int(sd)) for n, sd in zip(sizes, seeds)]
+    atom_steps = float(sum(len(r["q"]) for r in reqs)) * nsteps
+
+    def run(max_active, arrivals):
+        with rbsog.Server(max_active=max_active, pool_bytes=pool_bytes) as sv:
+            t0 = time.perf_counter()
+            tickets = []
+            for i, (r, ta) in enumerate(zip(reqs, arrivals)):
+                dt = ta - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(sv.submit(r["q"], r["pos"], r["L"], r["rc"], nsteps=nsteps, growth=growth, P=r["P"],
+                                         seed=int(seeds[i]), system_id=i))
+            res = [sv.wait(t) for t in tickets]
+            wall = time.perf_counter() - t0
+            st = sv.stats()
+        lat = np.array([x["latency_s"] for x in res])
+        return {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "atom_steps_per_s": atom_steps / wall, "requests_per_s": n_req / wall, "wall_s": wall,
+                "ticks": st["ticks"], "peak_active": st["peak_active"], "peak_pool_mib": st["peak_pool_bytes"] / 2**20}
+
+    burst = np.zeros(n_req)
+    sat = run(65536, burst)
+    lam = lam_frac * sat["requests_per_s"]
+    arrivals = np.cumsum(np.random.default_rng(seed).exponential(1.0 / lam, n_req))
+    batched = run(65536, arrivals)
+    solo_sat = run(1, burst)
+    solo = run(1, arrivals)
+    return {"requests": n_req, "steps_per_request": nsteps, "pool_mib": pool_bytes / 2**20,
+            "arrival_rate_per_s": lam, "arrival_rate_frac_of_capacity": lam_frac,
+            "continuous_batching": batched, "one_at_a_time": solo,
+            "capacity": {"continuous_batching": sat, "one_at_a_time": solo_sat}}
+
+
 def cpu_baseline(d, P, seed, sample_atoms):
     """The oracle as it stands on a bounded sample: long-range structure factors
     of all atoms for every sampled mode (2P evaluations), short-range and
@@ -168,6 +227,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-valu-probe", action="store_true")
+    ap.add_argument("--served", type=int, default=256, help="requests of the served-stream run (0: skip)")
+    ap.add_argument("--served-pool-mib", type=int, default=1024)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -181,6 +242,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     d, desc = make_workload(args.config)
+    log(f"workload {args.config} ready: {len(d['q'])} atoms")
     n = len(d["q"])
     P = int(d["P"])
     dev = "cuda"
@@ -215,23 +277,31 @@ def main():
     ms_step = 1e3 * T / args.steps
     value = n * args.steps / T
 
+    log(f"{args.steps} timed steps: {ms_step:.3f} ms/step")
+    probe = None if args.no_valu_probe else valu_probe()
+    tw = TRANS_WEIGHT_DEFAULT
+    if probe:
+        tw = probe["fma"]["valu_per_simd_cycle"] / probe["exp"]["trans_per_simd_cycle"]
     pair_ms, pair_cnt = timing.get("pair", (0.0, 1))
     t_pair = pair_ms / max(pair_cnt, 1) * 1e-3
-    slots = info["npairs"] * pair_slots(10)
-    achieved = slots / t_pair if t_pair > 0 else 0.0
+    work = info["npairs"] * pair_work(tw)
+    achieved = work / t_pair if t_pair > 0 else 0.0
+    work_impl = info["npairs"] * pair_work_implemented(tw)
     traffic = read_traffic(args.config)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12,
-                "unit": "T VALU-slot/s", "frac": achieved / VALU_SLOTS_PER_S, "traffic": traffic,
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PER_S / 1e12,
+                "unit": "T FP32 lane-op/s", "frac": achieved / VALU_LANE_OPS_PER_S, "traffic": traffic,
                 "kernel": "k_pair", "unordered_pairs_per_launch": info["npairs"],
-                "slots_per_pair": pair_slots(10), "avg_launch_ms": 1e3 * t_pair}
-    sk_slots, fo_slots = mode_slots()
+                "work_per_pair": pair_work(tw), "trans_weight": tw, "avg_launch_ms": 1e3 * t_pair,
+                "implemented_form": {"work_per_pair": pair_work_implemented(tw),
+                                     "frac": work_impl / t_pair / VALU_LANE_OPS_PER_S if t_pair > 0 else 0.0}}
+    sk_w, fo_w = mode_work(tw)
     kernels = {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in timing.items()}
-    for k, per in (("sk", sk_slots), ("force", fo_slots)):
+    for k, per in (("sk", sk_w), ("force", fo_w)):
         if k in kernels and kernels[k]["avg_ms"] > 0:
-            kernels[k]["frac_valu"] = n * info["nd"] * per / (kernels[k]["avg_ms"] * 1e-3) / VALU_SLOTS_PER_S
-    probe = None if args.no_valu_probe else valu_probe()
+            kernels[k]["frac_valu"] = n * info["nd"] * per / (kernels[k]["avg_ms"] * 1e-3) / VALU_LANE_OPS_PER_S
     cpu = None
     if not args.no_cpu_baseline:
+        log("oracle on the host cores")
         cpu = cpu_baseline(d, P, args.seed, args.cpu_sample)
     out = {
         "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -243,6 +313,9 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
         "distinct_modes": info["nd"], "valu_probe": probe,
     }
+    if args.served > 0:
+        log(f"served stream: {args.served} requests")
+        out["served"] = served_bench(args.served, 5, args.served_pool_mib << 20)
     ctx.close()
     if args.calibration_copy_mib > 0:
         src = torch.ones(args.calibration_copy_mib * 262144, dtype=torch.float32, device=dev)

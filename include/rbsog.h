@@ -62,6 +62,8 @@ extern "C" {
 
 #define RBSOG_MAX_M 64
 
+#define RBSOG_FLAG_EXP_FORM 1 /* FP32C: evaluate the M exponentials, not the polynomial form */
+
 typedef struct rbsog_ctx rbsog_ctx;
 
 /*
@@ -79,6 +81,13 @@ typedef struct rbsog_ctx rbsog_ctx;
  *  coulomb_k        prefactor applied to every energy, force and pressure.
  *  precision        RBSOG_PREC_FP64 or RBSOG_PREC_FP32C.
  *  recalibration    RBSOG_RECAL_PRINTED or RBSOG_RECAL_EXCHANGE.
+ *  flags            0, or RBSOG_FLAG_EXP_FORM.  In FP32C the short-range
+ *                   sums sum_l wt_l exp(-r^2/s_l^2) and sum_l w_l exp(-r^2/s_l^2)
+ *                   are evaluated as degree-10 polynomials in r^2 on
+ *                   [0, rc^2] (Chebyshev interpolants fitted in FP64 at set-up,
+ *                   used when their truncation error is below 5e-8 of the sum
+ *                   at r = 0, else the exponentials); RBSOG_FLAG_EXP_FORM asks
+ *                   for the M exponentials of eqs. force_SOG and U_short.
  */
 typedef struct rbsog_params {
     double b;
@@ -92,7 +101,8 @@ typedef struct rbsog_params {
     double coulomb_k;
     int32_t precision;
     int32_t recalibration;
-    int32_t reserved[6];
+    int32_t flags;
+    int32_t reserved[5];
 } rbsog_params;
 
 /*
@@ -100,7 +110,7 @@ typedef struct rbsog_params {
  * 3.270345668108471, omega~ = 1.007806979343806 at r_c = 9 A; the row the
  * paper uses in all runs) rescaled to the cutoff rc by sigma = sigma9 * rc / 9
  * (the split is scale covariant), M = 10 (the pressure column's M~), P = 100,
- * seed 0, system 0, coulomb_k 1, FP32C, printed recalibration.
+ * seed 0, system 0, coulomb_k 1, FP32C, printed recalibration, flags 0.
  * Returns RBSOG_EINVAL if p is NULL or rc <= 0.
  */
 int rbsog_params_init(rbsog_params *p, double rc);

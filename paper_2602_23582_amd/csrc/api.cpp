@@ -214,6 +214,7 @@ int rbsog_force_virial(rbsog_ctx *c, const double *x, const double *y, const dou
     t.fx = gx;
     t.fy = gy;
     t.fz = gz;
+    c->batch.want_energy = host_energy != nullptr;
     RB_TRY(rbsog::batch_upload(c->batch, c->err));
     HIP_TRY(c, rbsog::launch_bin_and_sort(c->batch));
     HIP_TRY(c, rbsog::launch_pair(c->batch));

@@ -90,7 +90,8 @@ std::vector<int64_t> graph_key(const Batch &bt)
     k.push_back(reinterpret_cast<intptr_t>(bt.d_step));
     k.push_back(reinterpret_cast<intptr_t>(bt.d_plan));
     k.push_back(static_cast<int64_t>(bt.sys.size()));
-    k.push_back(bt.pair_m10);
+    for (int f = 0; f <= rbsog::kNumForms; ++f) k.push_back(bt.pair_split[f]);
+    k.push_back(bt.want_energy);
     return k;
 }
 
@@ -152,6 +153,7 @@ int step_impl(rbsog_batch *b, const int64_t *host_steps, const double *host_boxe
         t.fy = fy + b->off[s];
         t.fz = fz + b->off[s];
     }
+    bt.want_energy = host_energy != nullptr;
     RB_TRY(rbsog::batch_upload(bt, b->err));
     if (b->use_graph && !bt.timing) {
         RB_TRY(run_graph(b));

@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kCellBlock) void k_zero(const SysDesc *__restrict__
         D.count[c] = 0;
         D.cursor[c] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x < 2) ctrl[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kNumForms) ctrl[threadIdx.x] = 0;
 }
 
 // s = x (1/L) wrapped into [0,1) by subtracting floor(s); u = s 2^bits; the
@@ -647,7 +647,9 @@ struct PairAcc {
     int n = 0;  // pairs inside rc
 };
 
-// Splitting weights held in registers for the whole kernel.
+// Splitting weights held in registers for the whole kernel.  M > 0: M
+// exponentials with compile-time M; M = 0: runtime M read from the table;
+// M = -1: the FP32C polynomial form (coefficients of both sums in t).
 template <class T, int M>
 struct Weights {
     using real = typename T::real;
@@ -659,11 +661,23 @@ struct Weights<T, 0> {  // runtime M: read from the table
     const SogTables *tab;
     int m;
 };
+template <class T>
+struct Weights<T, -1> {
+    float pa;
+    float pg[kPolyDeg + 1], pf[kPolyDeg + 1];
+};
 
 template <class T, int M>
 __device__ inline void load_weights(Weights<T, M> &W, const SogTables *__restrict__ tab)
 {
-    if constexpr (M == 0) {
+    if constexpr (M == -1) {
+        W.pa = tab->pa;
+#pragma unroll
+        for (int k = 0; k <= kPolyDeg; ++k) {
+            W.pg[k] = tab->pg[k];
+            W.pf[k] = tab->pf[k];
+        }
+    } else if constexpr (M == 0) {
         W.tab = tab;
         W.m = tab->M;
     } else {
@@ -682,7 +696,7 @@ __device__ inline void load_weights(Weights<T, M> &W, const SogTables *__restric
     }
 }
 
-template <class T, int M>
+template <class T, int M, bool E>
 __device__ inline typename T::real gauss(const Weights<T, M> &W, int l, typename T::real r2, typename T::real &wl)
 {
     using real = typename T::real;
@@ -705,8 +719,17 @@ __device__ inline typename T::real gauss(const Weights<T, M> &W, int l, typename
     real e;
     if constexpr (sizeof(real) == 4) e = __builtin_amdgcn_exp2f(r2 * c);
     else e = exp(r2 * c);
-    wl *= e;
+    if constexpr (E) wl *= e;
     return wtl * e;
+}
+
+// Horner evaluation of sum_k p[k] t^k
+__device__ __forceinline__ float horner(const float *p, float t)
+{
+    float v = p[kPolyDeg];
+#pragma unroll
+    for (int k = kPolyDeg - 1; k >= 0; --k) v = v * t + p[k];
+    return v;
 }
 
 template <class T>
@@ -722,10 +745,10 @@ __device__ inline void displacement(const typename T::Rec &ri, const typename T:
 
 // The SOG short-range kernels of one pair: N~(r) = 1/r^3 - sum wt_l e_l for
 // the force and the virial (eqs. force_SOG, P_short; 2 w_l/s_l^2 = wt_l) and
-// N(r) = 1/r - sum w_l e_l for the energy (eq. U_short), e_l = exp(-r^2/s_l^2).
-// A listed pair farther than rc (possible only through the padded fast
-// filter) contributes nothing.
-template <class T, int M>
+// N(r) = 1/r - sum w_l e_l for the energy (eq. U_short), e_l = exp(-r^2/s_l^2),
+// the energy only when E.  A listed pair farther than rc (possible only
+// through the padded fast filter) contributes nothing.
+template <class T, int M, bool E>
 __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Rec &rj, typename T::real sx,
                                  typename T::real sy, typename T::real sz, typename T::real rc2,
                                  const Weights<T, M> &W, PairAcc<T> &acc)
@@ -738,18 +761,22 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
     real swt = 0, sw = 0, rinv;
     if constexpr (sizeof(real) == 4) rinv = __builtin_amdgcn_rsqf(r2);
     else rinv = 1.0 / sqrt(r2);
-    if constexpr (M == 0) {
+    if constexpr (M == -1) {
+        const float t = r2 * W.pa - 1.0f;
+        swt = horner(W.pg, t);
+        if constexpr (E) sw = horner(W.pf, t);
+    } else if constexpr (M == 0) {
         for (int l = 0; l < W.m; ++l) {
             real wl;
-            swt += gauss<T, M>(W, l, r2, wl);
-            sw += wl;
+            swt += gauss<T, M, E>(W, l, r2, wl);
+            if constexpr (E) sw += wl;
         }
     } else {
 #pragma unroll
         for (int l = 0; l < M; ++l) {
             real wl;
-            swt += gauss<T, M>(W, l, r2, wl);
-            sw += wl;
+            swt += gauss<T, M, E>(W, l, r2, wl);
+            if constexpr (E) sw += wl;
         }
     }
     const real qq = inside ? ri.q * rj.q : static_cast<real>(0);
@@ -765,7 +792,7 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
     acc.vxy += fdx * dy;
     acc.vxz += fdx * dz;
     acc.vyz += fdy * dz;
-    acc.u += qq * (rinv - sw);
+    if constexpr (E) acc.u += qq * (rinv - sw);
 }
 
 template <class T>
@@ -778,7 +805,7 @@ struct PairShared {
 };
 
 // One pair block b of system D (one wavefront).
-template <class T, int M>
+template <class T, int M, bool E>
 __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, const SysStep &St, int b)
 {
     using real = typename T::real;
@@ -891,10 +918,10 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         for (; e + 2 <= kmax; e += 2) {
             const int j0 = sh.list[e * 64 + lane], j1 = sh.list[(e + 1) * 64 + lane];
             const Rec r0 = sh.tile[j0], r1 = sh.tile[j1];
-            if (e < cnt) pair_eval<T, M>(ri, r0, sx, sy, sz, rc2, W, acc);
-            if (e + 1 < cnt) pair_eval<T, M>(ri, r1, sx, sy, sz, rc2, W, acc);
+            if (e < cnt) pair_eval<T, M, E>(ri, r0, sx, sy, sz, rc2, W, acc);
+            if (e + 1 < cnt) pair_eval<T, M, E>(ri, r1, sx, sy, sz, rc2, W, acc);
         }
-        if (e < kmax && e < cnt) pair_eval<T, M>(ri, sh.tile[sh.list[e * 64 + lane]], sx, sy, sz, rc2, W, acc);
+        if (e < kmax && e < cnt) pair_eval<T, M, E>(ri, sh.tile[sh.list[e * 64 + lane]], sx, sy, sz, rc2, W, acc);
         hits += acc.n;
         cnt = 0;
         fx += acc.fx;
@@ -982,19 +1009,19 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
 }
 
 // Static schedule: workgroup g runs plan entry g.
-template <class T, int M>
+template <class T, int M, bool E>
 __global__ __launch_bounds__(64) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                              const int2 *__restrict__ plan)
 {
     __shared__ PairShared<T> sh;
     const int2 e = plan[blockIdx.x];
-    pair_block<T, M>(sh, desc[e.x], stp[e.x], e.y);
+    pair_block<T, M, E>(sh, desc[e.x], stp[e.x], e.y);
 }
 
 // Persistent schedule: a fixed number of workgroups take plan entries from a
 // global counter (zeroed by k_zero) until all nitems are taken; every
 // workgroup leaves once the counter has passed nitems.
-template <class T, int M>
+template <class T, int M, bool E>
 __global__ __launch_bounds__(64) void k_pair_queue(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                                    const int2 *__restrict__ plan, int nitems, int32_t *ctrl)
 {
@@ -1005,7 +1032,7 @@ __global__ __launch_bounds__(64) void k_pair_queue(const SysDesc *__restrict__ d
         idx = __shfl(idx, 0, 64);
         if (idx >= nitems) break;
         const int2 e = plan[idx];
-        pair_block<T, M>(sh, desc[e.x], stp[e.x], e.y);
+        pair_block<T, M, E>(sh, desc[e.x], stp[e.x], e.y);
         __syncthreads();
     }
 }
@@ -1379,29 +1406,38 @@ hipError_t launch_bin_and_sort(Batch &b)
     return b.precision == RBSOG_PREC_FP64 ? bin_and_sort_t<F64>(b) : bin_and_sort_t<F32>(b);
 }
 
-template <class T, int M>
-static void pair_launch(Batch &b, int64_t first, int64_t items, int queue)
+template <class T, int M, bool E>
+static void pair_launch(Batch &b, int form)
 {
+    const int64_t first = b.pair_split[form], items = b.pair_split[form + 1] - first;
     if (items <= 0) return;
     const int2 *plan = plan_ptr(b, kPlanPair) + first;
     if (b.pair_schedule == kPairPersistent) {
         const int64_t wgs = std::min<int64_t>(items, static_cast<int64_t>(b.num_cu) * b.pair_wg_per_cu);
-        hipLaunchKernelGGL((k_pair_queue<T, M>), dim3(static_cast<unsigned>(wgs)), dim3(64), 0, b.stream, b.d_desc,
-                           b.d_step, plan, static_cast<int>(items), b.d_ctrl + queue);
+        hipLaunchKernelGGL((k_pair_queue<T, M, E>), dim3(static_cast<unsigned>(wgs)), dim3(64), 0, b.stream,
+                           b.d_desc, b.d_step, plan, static_cast<int>(items), b.d_ctrl + form);
     } else {
-        hipLaunchKernelGGL((k_pair<T, M>), dim3(static_cast<unsigned>(items)), dim3(64), 0, b.stream, b.d_desc,
+        hipLaunchKernelGGL((k_pair<T, M, E>), dim3(static_cast<unsigned>(items)), dim3(64), 0, b.stream, b.d_desc,
                            b.d_step, plan);
     }
+}
+
+template <class T, bool E>
+static void pair_forms(Batch &b)
+{
+    // one launch per form of the SOG kernels: the FP32C polynomial form, the
+    // M = 10 exponentials with the weights in registers, runtime M
+    if constexpr (sizeof(typename T::real) == 4) pair_launch<T, -1, E>(b, kFormPoly);
+    pair_launch<T, 10, E>(b, kFormExp10);
+    pair_launch<T, 0, E>(b, kFormExpM);
 }
 
 template <class T>
 static hipError_t pair_t(Batch &b)
 {
-    // systems with M = 10 (the pressure column of Table 1) run the
-    // instantiation with the weights in registers, the others the runtime-M one
     timer_begin(b, "pair");
-    pair_launch<T, 10>(b, 0, b.pair_m10, 0);
-    pair_launch<T, 0>(b, b.pair_m10, b.plan_len[kPlanPair] - b.pair_m10, 1);
+    if (b.want_energy) pair_forms<T, true>(b);
+    else pair_forms<T, false>(b);
     timer_end(b, "pair");
     return hipGetLastError();
 }

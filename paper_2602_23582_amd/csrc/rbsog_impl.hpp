@@ -30,6 +30,7 @@ constexpr int kCellBlock = 256;    // cells per workgroup of the per-cell kernel
 constexpr int kScanBlock = 1024;   // cells per workgroup of the local scan
 constexpr int64_t kMaxCells = int64_t(1024) * kScanBlock;  // cells per system (two-level scan)
 constexpr int kMaxTimed = 24;
+constexpr int kPolyDeg = 10;       // degree of the FP32C polynomial form of the SOG sums
 
 // SOG tables read by the kernels (device memory, uniform loads).
 struct SogTables {
@@ -41,7 +42,13 @@ struct SogTables {
     // exp(-r^2/s^2) = exp2(r^2 * c_l) with c_l = -log2(e)/s_l^2 (FP32 kernel)
     float w32[RBSOG_MAX_M], wt32[RBSOG_MAX_M], c32[RBSOG_MAX_M];
     float rc2_32;
-    float pad32;
+    // FP32C polynomial form on r^2 in [0, rc^2]: with t = pa r^2 - 1,
+    // sum_l wt_l e_l = sum_k pg[k] t^k and sum_l w_l e_l = sum_k pf[k] t^k
+    // (Chebyshev interpolants, truncation error checked at set-up)
+    float pa;
+    float pg[kPolyDeg + 1], pf[kPolyDeg + 1];
+    int poly;             // 1: the polynomial form is used (FP32C only)
+    float poly_err;       // max |p - sum| / sum(0) of the fit, both sums
     // sampler: s_l, and wt_l s_l^5, wt_l s_l^7 are formed from s5, s7
     double s[RBSOG_MAX_M], s5[RBSOG_MAX_M], s7[RBSOG_MAX_M];
 };
@@ -112,6 +119,14 @@ struct Timer {
     int64_t count = 0;
 };
 
+// Pair-kernel forms of the SOG kernels, chosen per system.
+enum PairForm {
+    kFormPoly = 0,   // FP32C: degree-kPolyDeg polynomials in r^2
+    kFormExp10 = 1,  // M = 10 exponentials, weights in registers
+    kFormExpM = 2,   // runtime M exponentials
+    kNumForms = 3,
+};
+
 // Pair-kernel schedules (none changes any result).
 enum PairSchedule {
     kPairStatic = 0,      // one workgroup per pair-block slot
@@ -137,6 +152,7 @@ struct System {
     size_t cell_bytes = 0;
     int64_t ncells_cap = 0;
     bool own_mem = true;  // false: the memory belongs to a pool
+    int pair_form = kFormExpM;
     SysDesc desc{};       // host copy of the device descriptor
     SysStep stp{};        // host copy of the per-step data
 };
@@ -157,10 +173,11 @@ struct Batch {
     int step_slot = 0;
     StepResults *d_res = nullptr, *h_res = nullptr;
     int2 *d_plan = nullptr, *h_plan = nullptr;
-    int32_t *d_ctrl = nullptr;  // [0], [1]: work-queue counters of the two pair launches
+    int32_t *d_ctrl = nullptr;  // [0..2]: work-queue counters of the pair launches (one per form)
     int64_t cap_sys = 0, cap_plan = 0;
     int64_t plan_off[kNumPlans]{}, plan_len[kNumPlans]{};
-    int64_t pair_m10 = 0;  // leading pair-plan entries that belong to systems with M = 10
+    int64_t pair_split[kNumForms + 1]{};  // pair-plan entries of each form: [split[f], split[f+1])
+    bool want_energy = true;              // the pair kernel sums U^N
     bool desc_dirty = true, plan_dirty = true;
     std::vector<int64_t> plan_key;  // sizes the plans were built for
     // event that guards the pinned descriptor and plan mirrors

@@ -202,6 +202,7 @@ int tick(rbsog_server *sv, std::string &err)
         t.fy = r->d_frc + r->n;
         t.fz = r->d_frc + 2 * r->n;
     }
+    bt.want_energy = true;  // every request reports its energies
     rc = rbsog::batch_upload(bt, err);
     if (rc) return rc;
     e = rbsog::launch_sample(bt);

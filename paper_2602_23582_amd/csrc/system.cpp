@@ -52,6 +52,49 @@ AtomLayout atom_layout(const rbsog_params &p, int64_t n)
     return a;
 }
 
+// Chebyshev interpolant of degree kPolyDeg of g(x) = sum_l c_l exp(-x/s_l^2)
+// on x in [0, X], returned as monomial coefficients in t = 2x/X - 1; *err is
+// the largest |p - g| on a fine grid divided by g(0).
+void poly_fit(const double *c, const double *s, int M, double X, double mono[kPolyDeg + 1], double *err)
+{
+    constexpr int N = kPolyDeg + 1;
+    constexpr double pi = 3.141592653589793238462643383279502884;
+    auto g = [&](double x) {
+        double v = 0.0;
+        for (int l = 0; l < M; ++l) v += c[l] * std::exp(-x / (s[l] * s[l]));
+        return v;
+    };
+    double f[N], cheb[N];
+    for (int k = 0; k < N; ++k) f[k] = g(0.5 * X * (1.0 + std::cos(pi * (k + 0.5) / N)));
+    for (int j = 0; j < N; ++j) {
+        double a = 0.0;
+        for (int k = 0; k < N; ++k) a += f[k] * std::cos(pi * j * (k + 0.5) / N);
+        cheb[j] = (j == 0 ? 1.0 : 2.0) * a / N;
+    }
+    // T_j in monomials: T_0 = 1, T_1 = t, T_{j+1} = 2 t T_j - T_{j-1}
+    double Tm[N][N] = {};
+    Tm[0][0] = 1.0;
+    if (N > 1) Tm[1][1] = 1.0;
+    for (int j = 1; j + 1 < N; ++j)
+        for (int k = 0; k < N; ++k) Tm[j + 1][k] = (k > 0 ? 2.0 * Tm[j][k - 1] : 0.0) - Tm[j - 1][k];
+    for (int k = 0; k < N; ++k) {
+        mono[k] = 0.0;
+        for (int j = 0; j < N; ++j) mono[k] += cheb[j] * Tm[j][k];
+    }
+    double e = 0.0;
+    const int grid = 8192;
+    for (int q = 0; q <= grid; ++q) {
+        const double x = X * q / grid, t = 2.0 * x / X - 1.0;
+        double p = 0.0;
+        for (int k = kPolyDeg; k >= 0; --k) p = p * t + mono[k];
+        e = std::max(e, std::fabs(p - g(x)));
+    }
+    *err = e / g(0.0);
+}
+
+// largest accepted truncation error of the polynomial form (FP32 rounding is ~1e-7)
+constexpr double kPolyTol = 5e-8;
+
 }  // namespace
 
 int check_box(const double *box, double rc, std::string &err)
@@ -125,6 +168,10 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
         err = "system_id must be < 2^32";
         return RBSOG_EINVAL;
     }
+    if (p.flags & ~RBSOG_FLAG_EXP_FORM) {
+        err = "unknown flags";
+        return RBSOG_EINVAL;
+    }
     double qs = 0.0, qa = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         if (!std::isfinite(host_q[i])) {
@@ -168,6 +215,25 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
         tab.w32[l] = static_cast<float>(s.w[l]);
         tab.wt32[l] = static_cast<float>(s.wt[l]);
         tab.c32[l] = static_cast<float>(-log2e / (s.s[l] * s.s[l]));
+    }
+    // FP32C: the SOG sums as polynomials in r^2 when the fit is within
+    // kPolyTol of the exponential form; otherwise the M exponentials
+    s.pair_form = p.M == 10 ? kFormExp10 : kFormExpM;
+    if (p.precision == RBSOG_PREC_FP32C) {
+        const double X = p.rc * p.rc;
+        double mg[kPolyDeg + 1], mf[kPolyDeg + 1], eg = 1.0, ef = 1.0;
+        poly_fit(s.wt, s.s, p.M, X, mg, &eg);
+        poly_fit(s.w, s.s, p.M, X, mf, &ef);
+        tab.poly_err = static_cast<float>(std::max(eg, ef));
+        if (eg <= kPolyTol && ef <= kPolyTol && !(p.flags & RBSOG_FLAG_EXP_FORM)) {
+            tab.poly = 1;
+            tab.pa = static_cast<float>(2.0 / X);
+            for (int k = 0; k <= kPolyDeg; ++k) {
+                tab.pg[k] = static_cast<float>(mg[k]);
+                tab.pf[k] = static_cast<float>(mf[k]);
+            }
+            s.pair_form = kFormPoly;
+        }
     }
 
     SysDesc &d = s.desc;
@@ -469,6 +535,7 @@ static std::vector<int64_t> plan_sizes(const Batch &b)
         k.push_back(s->n);
         k.push_back(s->ncells);
         k.push_back(s->prm.P);
+        k.push_back(s->pair_form);
     }
     return k;
 }
@@ -523,14 +590,15 @@ static int build_plans(Batch &b, std::string &err)
         put(kPlanSk, s, (y->n + kSkChunk - 1) / kSkChunk);
         put(kPlanReduce, s, y->prm.P + 2);
     }
-    // pair blocks of systems with M = 10 first (kernel with the weights in
-    // registers), then the others (runtime M)
-    for (int pass = 0; pass < 2; ++pass)
+    // pair blocks grouped by the form of the SOG kernels (one launch per form)
+    for (int f = 0; f < kNumForms; ++f) {
+        b.pair_split[f] = pos[kPlanPair] - b.plan_off[kPlanPair];
         for (int s = 0; s < S; ++s) {
             const System *y = b.sys[s];
-            if ((y->prm.M == 10) == (pass == 0)) put(kPlanPair, s, (y->n + kPairWave - 1) / kPairWave + y->ncells);
-            if (pass == 0 && s == S - 1) b.pair_m10 = pos[kPlanPair] - b.plan_off[kPlanPair];
+            if (y->pair_form == f) put(kPlanPair, s, (y->n + kPairWave - 1) / kPairWave + y->ncells);
         }
+    }
+    b.pair_split[kNumForms] = pos[kPlanPair] - b.plan_off[kPlanPair];
     return RBSOG_OK;
 }
 

@@ -20,6 +20,7 @@ PREC_FP64 = 0
 PREC_FP32C = 1
 RECAL_PRINTED = 0
 RECAL_EXCHANGE = 1
+FLAG_EXP_FORM = 1
 MAX_P = 1024
 MAX_MODES = MAX_P + 1
 
@@ -43,7 +44,7 @@ class rbsog_params(C.Structure):
     _fields_ = [("b", C.c_double), ("sigma", C.c_double), ("omega", C.c_double), ("M", C.c_int32),
                 ("rc", C.c_double), ("P", C.c_int32), ("seed", C.c_uint64), ("system_id", C.c_uint64),
                 ("coulomb_k", C.c_double), ("precision", C.c_int32), ("recalibration", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("flags", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class RBSOGError(RuntimeError):
@@ -138,11 +139,12 @@ class Context:
     """One system: wraps rbsog_setup .. rbsog_destroy."""
 
     def __init__(self, q, box, rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_PRINTED,
-                 M=10, b=None, sigma=None, omega=None, coulomb_k=1.0, stream=None):
+                 M=10, b=None, sigma=None, omega=None, coulomb_k=1.0, stream=None, flags=0):
         L = load()
         p = default_params(rc)
         p.P, p.seed, p.system_id, p.M = int(P), int(seed), int(system_id), int(M)
         p.precision, p.recalibration, p.coulomb_k = int(precision), int(recalibration), float(coulomb_k)
+        p.flags = int(flags)
         if b is not None:
             p.b = b
         if sigma is not None:
@@ -276,10 +278,11 @@ def _timing_table(getter, handle):
 
 
 def make_params(rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_PRINTED, M=10,
-                coulomb_k=1.0):
+                coulomb_k=1.0, flags=0):
     p = default_params(rc)
     p.P, p.seed, p.system_id, p.M = int(P), int(seed), int(system_id), int(M)
     p.precision, p.recalibration, p.coulomb_k = int(precision), int(recalibration), float(coulomb_k)
+    p.flags = int(flags)
     return p
 
 
@@ -309,7 +312,8 @@ class Batch:
         for s, spec in enumerate(systems):
             arr[s] = make_params(spec["rc"], P=spec.get("P", 100), seed=spec.get("seed", 0),
                                  system_id=spec.get("system_id", 0), precision=precision,
-                                 recalibration=spec.get("recalibration", RECAL_PRINTED), M=spec.get("M", 10))
+                                 recalibration=spec.get("recalibration", RECAL_PRINTED), M=spec.get("M", 10),
+                                 flags=spec.get("flags", 0))
             n[s] = len(spec["q"])
             qs.append(np.asarray(spec["q"], dtype=np.float64))
             boxes[s] = spec["box"]

@@ -48,6 +48,7 @@ def test_params_struct_layout_matches_header(lib):
     assert offs["b"] == 0 and offs["sigma"] == 8 and offs["omega"] == 16 and offs["M"] == 24
     assert offs["rc"] == 32 and offs["P"] == 40 and offs["seed"] == 48 and offs["system_id"] == 56
     assert offs["coulomb_k"] == 64 and offs["precision"] == 72 and offs["recalibration"] == 76
+    assert offs["flags"] == 80
     assert C.sizeof(rbsog.rbsog_params) == 104
 
 

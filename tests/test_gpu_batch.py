@@ -50,7 +50,7 @@ def _systems():
 def _alone(torch, rb, spec, step, box):
     """One step of one system through the single-system calls."""
     with rb.Context(spec["q"], spec["box"], spec["rc"], P=spec["P"], seed=spec["seed"],
-                    system_id=spec["system_id"], M=spec.get("M", 10)) as ctx:
+                    system_id=spec["system_id"], M=spec.get("M", 10), flags=spec.get("flags", 0)) as ctx:
         x, y, z = (_dev(torch, spec["pos"][:, k]) for k in range(3))
         fx, fy, fz = (torch.empty_like(x) for _ in range(3))
         ctx.sample_modes(step, box)
@@ -160,6 +160,34 @@ def test_autotune_keeps_results(torch, rb):
         assert np.array_equal(P0, P1) and np.array_equal(U0, U1)
 
 
+def test_energy_request_does_not_change_forces_or_pressure(torch, rb):
+    spec = _systems()[3]
+    with rb.Context(spec["q"], spec["box"], spec["rc"], P=spec["P"], seed=spec["seed"]) as ctx:
+        x, y, z = (_dev(torch, spec["pos"][:, k]) for k in range(3))
+        out = []
+        for energy in (True, False, True):
+            fx, fy, fz = (torch.empty_like(x) for _ in range(3))
+            ctx.sample_modes(5, spec["box"])
+            ctx.force_virial(x, y, z, fx, fy, fz, energy=energy)
+            out.append((torch.stack([fx, fy, fz], 1).cpu().numpy(), ctx.pressure()[0]))
+    for F, P in out[1:]:
+        assert np.array_equal(F, out[0][0]) and np.array_equal(P, out[0][1])
+
+
+def test_mixed_forms_keep_each_system_exact(torch, rb):
+    """Polynomial and exponential FP32C forms in one batch."""
+    systems = _systems()[:4]
+    systems[2] = dict(systems[2], flags=rb.FLAG_EXP_FORM)
+    boxes = np.array([s["box"] for s in systems])
+    with rb.Batch(systems) as b:
+        (x, y, z), f = _concat(torch, systems)
+        P, U, _ = b.step([6] * 4, boxes, x, y, z, *f)
+        Fs = _split(torch, f, b.offsets)
+    for s, spec in enumerate(systems):
+        F1, P1, e1 = _alone(torch, rb, spec, 6, spec["box"])
+        assert np.array_equal(Fs[s], F1) and np.array_equal(P[s], P1) and np.array_equal(U[s], e1), f"system {s}"
+
+
 def test_mixed_term_counts_keep_each_system_exact(torch, rb):
     systems = _systems()[:3]
     systems[1] = dict(systems[1], M=12)
@@ -199,7 +227,7 @@ def _alone_steps(torch, rb, spec, nsteps, growth):
                 mu = (1.0 + growth * k) / (1.0 + growth * (k - 1))
                 ctx.rescale([mu, mu, mu], x, y, z)
             ctx.sample_modes(k, ctx.box)
-            ctx.force_virial(x, y, z, fx, fy, fz, energy=False)
+            ctx.force_virial(x, y, z, fx, fy, fz, energy=True)
             Ps.append(ctx.pressure()[0])
         return torch.stack([fx, fy, fz], 1).cpu().numpy(), np.array(Ps)
 

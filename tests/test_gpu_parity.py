@@ -153,33 +153,41 @@ def test_device_rescale_matches_host_rescale(torch, rb):
     np.testing.assert_array_equal(z.cpu().numpy(), d["pos"][:, 2] * mu[2])
 
 
+# FP32C evaluates the SOG sums either as polynomials in r^2 (default) or as
+# the M exponentials (flag); both are checked against the oracle
+FORMS = [0, 1]
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("variant", [0, 1])
-def test_fp32c_lattice(torch, rb, orc, variant):
+def test_fp32c_lattice(torch, rb, orc, variant, form):
     d = W.c1_lattice(jitter=0.2)
-    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=9, recalibration=variant) as ctx:
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=9, recalibration=variant, flags=form) as ctx:
         for step in (0, 3):
             g = gpu_step(torch, ctx, d["pos"], step, d["L"])
             o = oracle_step(orc, d, d["L"], d["pos"], 100, 9, 0, step, variant=variant)
-            check(g, o, TOL_FP32C, f"fp32c lattice v{variant} step {step}")
+            check(g, o, TOL_FP32C, f"fp32c lattice v{variant} form {form} step {step}")
 
 
-def test_fp32c_water_30k(torch, rb, orc):
+@pytest.mark.parametrize("form", FORMS)
+def test_fp32c_water_30k(torch, rb, orc, form):
     """10,000 three-site molecules at 1 g/cm^3 (L = 66.9 A), rc 10, P 100."""
     d = W.water_box()
-    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=2) as ctx:
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=2, flags=form) as ctx:
         for step in range(3):
             box = W.rescale_schedule(d["L"], step)
             pos = d["pos"] * (box / d["L"])
             g = gpu_step(torch, ctx, pos, step, box)
             o = oracle_step(orc, d, box, pos, 100, 2, 0, step)
-            check(g, o, TOL_FP32C, f"water step {step}")
+            check(g, o, TOL_FP32C, f"water form {form} step {step}")
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("P", [100, 400])
-def test_fp32c_small_slab(torch, rb, orc, P):
+def test_fp32c_small_slab(torch, rb, orc, P, form):
     """Anisotropic slab (60 x 60 x 150 A) with dipole layers, rc 12."""
     d = W.slab(Lx=60.0, n_water=8000, layer_grid=15, seed=6)
-    with rb.Context(d["q"], d["L"], d["rc"], P=P, seed=31) as ctx:
+    with rb.Context(d["q"], d["L"], d["rc"], P=P, seed=31, flags=form) as ctx:
         g = gpu_step(torch, ctx, d["pos"], 4, d["L"])
     o = oracle_step(orc, d, d["L"], d["pos"], P, 31, 0, 4)
     check(g, o, TOL_FP32C, f"slab P={P}")
