@@ -408,6 +408,34 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
 // Fixed point, binning and the stable cell sort
 // ----------------------------------------------------------------------------
 
+// Wave-aggregated counter increment: every active lane adds 1 to
+// counter[key]; lanes with equal keys are served by one atomic of their
+// leader, and each lane receives the counter's old value plus its rank among
+// those lanes (by lane order).  One atomic per distinct key in the wavefront.
+template <bool kReturn>
+__device__ inline int aggregated_increment(int32_t *counter, int key, bool active)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(active);
+    int result = 0;
+    while (todo) {
+        const int leader = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+        const int lkey = __shfl(key, leader, 64);
+        const uint64_t peers = __ballot(active && key == lkey) & todo;
+        int base = 0;
+        if (lane == leader) {
+            if constexpr (kReturn) base = atomicAdd(&counter[lkey], __popcll(peers));
+            else atomicAdd(&counter[lkey], __popcll(peers));
+        }
+        if constexpr (kReturn) {
+            base = __shfl(base, leader, 64);
+            if ((peers >> lane) & 1ull) result = base + __popcll(peers & ((1ull << lane) - 1ull));
+        }
+        todo &= ~peers;
+    }
+    return result;
+}
+
 // per-cell counters to zero; block 0 also resets the pair work-queue counters
 __global__ __launch_bounds__(kCellBlock) void k_zero(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                                      const int2 *__restrict__ plan, int32_t *__restrict__ ctrl)
@@ -434,8 +462,10 @@ __global__ __launch_bounds__(kAtomBlock) void k_fix(const SysDesc *__restrict__ 
     const SysStep &St = stp[e.x];
     const int64_t n = D.n;
     const int64_t i = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
-    if (i >= n) return;
-    const double p[3] = {gp(St.x)[i], gp(St.y)[i], gp(St.z)[i]};
+    const bool active = i < n;
+    if (!__any(active)) return;
+    const int64_t ii = active ? i : 0;
+    const double p[3] = {gp(St.x)[ii], gp(St.y)[ii], gp(St.z)[ii]};
     const int nc[3] = {St.nc[0], St.nc[1], St.nc[2]};
     RB_GLOBAL typename T::fix *u = gp(static_cast<typename T::fix *>(D.u));
     uint32_t c[3];
@@ -445,18 +475,18 @@ __global__ __launch_bounds__(kAtomBlock) void k_fix(const SysDesc *__restrict__ 
         uint32_t top;
         if constexpr (sizeof(typename T::fix) == 4) {
             top = static_cast<uint32_t>(static_cast<uint64_t>(s * 4294967296.0) & 0xFFFFFFFFull);
-            u[d * n + i] = top;
+            if (active) u[d * n + i] = top;
         } else {
             if (s >= 1.0) s -= 1.0;
             const uint64_t v = static_cast<uint64_t>(s * 18446744073709551616.0);
-            u[d * n + i] = v;
+            if (active) u[d * n + i] = v;
             top = static_cast<uint32_t>(v >> 32);
         }
         c[d] = static_cast<uint32_t>((static_cast<uint64_t>(top) * static_cast<uint32_t>(nc[d])) >> 32);
     }
     const int32_t id = static_cast<int32_t>(c[0] + static_cast<uint32_t>(nc[0]) * (c[1] + static_cast<uint32_t>(nc[1]) * c[2]));
-    gp(D.cell)[i] = id;
-    atomicAdd(&D.count[id], 1);
+    if (active) gp(D.cell)[i] = id;
+    aggregated_increment<false>(D.count, id, active);
 }
 
 // Two-level exclusive scan of the per-cell counts (and of the per-cell number
@@ -579,9 +609,11 @@ __global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restric
     const int2 e = plan[blockIdx.x];
     const SysDesc &D = desc[e.x];
     const int64_t i = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
-    if (i >= D.n) return;
-    const int c = gp(D.cell)[i];
-    gp(D.perm_tmp)[gp(D.start)[c] + atomicAdd(&D.cursor[c], 1)] = static_cast<int32_t>(i);
+    const bool active = i < D.n;
+    if (!__any(active)) return;
+    const int c = active ? gp(D.cell)[i] : 0;
+    const int slot = aggregated_increment<true>(D.cursor, c, active);
+    if (active) gp(D.perm_tmp)[gp(D.start)[c] + slot] = static_cast<int32_t>(i);
 }
 
 // Within each cell, atoms keep the caller's order: the slot of atom i is the
@@ -637,6 +669,7 @@ __global__ __launch_bounds__(kAtomBlock) void k_order(const SysDesc *__restrict_
 #endif
 constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round (byte indices, <= 256)
 constexpr int kListCap = RBSOG_PAIR_LISTCAP; // per-lane list capacity between flushes (>= 64)
+constexpr int kListStride = kListCap + 1;    // lane-major lists; an odd stride spreads the lanes over the banks
 constexpr int kMaxRanges = 18;
 static_assert(kChunk <= 256 && kChunk % 64 == 0 && kListCap >= 64, "pair tiling");
 
@@ -756,8 +789,9 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
     using real = typename T::real;
     real dx, dy, dz;
     displacement<T>(ri, rj, sx, sy, sz, dx, dy, dz);
-    const real r2 = dx * dx + dy * dy + dz * dz;
-    const bool inside = r2 < rc2;
+    // one fixed evaluation order, so a pair is inside from both of its atoms
+    const real r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const bool inside = (r2 < rc2) & (r2 > static_cast<real>(0));  // the atom itself is listed by the fast filter
     real swt = 0, sw = 0, rinv;
     if constexpr (sizeof(real) == 4) rinv = __builtin_amdgcn_rsqf(r2);
     else rinv = 1.0 / sqrt(r2);
@@ -779,9 +813,10 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
             if constexpr (E) sw += wl;
         }
     }
-    const real qq = inside ? ri.q * rj.q : static_cast<real>(0);
+    // the mask selects the products (r = 0 gives rinv = inf for the atom itself)
+    const real qq = ri.q * rj.q;
     acc.n += inside;
-    const real f = qq * (rinv * rinv * rinv - swt);
+    const real f = inside ? qq * (rinv * rinv * rinv - swt) : static_cast<real>(0);
     const real fdx = f * dx, fdy = f * dy, fdz = f * dz;
     acc.fx += fdx;
     acc.fy += fdy;
@@ -792,14 +827,14 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
     acc.vxy += fdx * dy;
     acc.vxz += fdx * dz;
     acc.vyz += fdy * dz;
-    if constexpr (E) acc.u += qq * (rinv - sw);
+    if constexpr (E) acc.u += inside ? qq * (rinv - sw) : static_cast<real>(0);
 }
 
 template <class T>
 struct PairShared {
     typename T::Rec tile[kChunk];
-    __attribute__((aligned(16))) float rel[3][kChunk];  // filter coordinates (fast filter)
-    uint8_t list[kListCap * 64];
+    float4 rel[kChunk];  // fast filter: coordinates relative to the block origin and their squared norm
+    uint8_t list[kListStride * 64];
     int pre[kMaxRanges + 1];  // flattened-neighbourhood offset of each range
     int beg[kMaxRanges];
 };
@@ -846,8 +881,11 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     // float coordinates relative to the first atom of the block, o.  With five
     // or more cells per edge, i and every candidate lie within two cells of o,
     // well inside half a box, so differences of relative coordinates are
-    // minimum-image displacements.  The filter radius is padded by 1e-3 A for
-    // float rounding; the pair evaluation applies the exact test on fixed-point
+    // minimum-image displacements.  The test is |r_j|^2 - 2 r_i.r_j <
+    // rcf^2 - |r_i|^2 (three FMAs); with |r| below 45 A its rounding error
+    // stays under 1e-3 A^2, far inside the 2 rc 1e-3 A^2 that padding the
+    // radius by 1e-3 A adds.  The atom itself passes this test; the pair
+    // evaluation applies the exact test (0 < r^2 < rc^2) on fixed-point
     // differences.
     constexpr bool kIsF32 = sizeof(real) == 4;
     const bool fast = RBSOG_FAST_FILTER && kIsF32 && nx >= 5 && ny >= 5 && nz >= 5;
@@ -855,10 +893,12 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const fix oy_ = static_cast<fix>(__shfl(static_cast<long long>(ri.y), 0, 64));
     const fix oz_ = static_cast<fix>(__shfl(static_cast<long long>(ri.z), 0, 64));
     const float rcf = static_cast<float>(sqrt(static_cast<double>(rc2))) + 1e-3f;
-    const float rcf2_lane = valid ? rcf * rcf : -1.0f;
     const float xi = static_cast<float>(static_cast<sfix>(ri.x - ox)) * static_cast<float>(sx);
     const float yi = static_cast<float>(static_cast<sfix>(ri.y - oy_)) * static_cast<float>(sy);
     const float zi = static_cast<float>(static_cast<sfix>(ri.z - oz_)) * static_cast<float>(sz);
+    const float ax = -2.0f * xi, ay = -2.0f * yi, az = -2.0f * zi;
+    const float thr = valid ? rcf * rcf - (xi * xi + yi * yi + zi * zi) : -INFINITY;
+    uint8_t *const mylist = sh.list + lane * kListStride;
     const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
     const int oy = ny >= 3 ? 1 : 0, oz = nz >= 3 ? 1 : 0;
 
@@ -916,12 +956,12 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         PairAcc<T> acc;
         int e = 0;
         for (; e + 2 <= kmax; e += 2) {
-            const int j0 = sh.list[e * 64 + lane], j1 = sh.list[(e + 1) * 64 + lane];
+            const int j0 = mylist[e], j1 = mylist[e + 1];
             const Rec r0 = sh.tile[j0], r1 = sh.tile[j1];
             if (e < cnt) pair_eval<T, M, E>(ri, r0, sx, sy, sz, rc2, W, acc);
             if (e + 1 < cnt) pair_eval<T, M, E>(ri, r1, sx, sy, sz, rc2, W, acc);
         }
-        if (e < kmax && e < cnt) pair_eval<T, M, E>(ri, sh.tile[sh.list[e * 64 + lane]], sx, sy, sz, rc2, W, acc);
+        if (e < kmax && e < cnt) pair_eval<T, M, E>(ri, sh.tile[mylist[e]], sx, sy, sz, rc2, W, acc);
         hits += acc.n;
         cnt = 0;
         fx += acc.fx;
@@ -949,9 +989,10 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
             const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
             sh.tile[k] = rj;
             if (fast) {
-                sh.rel[0][k] = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
-                sh.rel[1][k] = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
-                sh.rel[2][k] = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
+                const float xj = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
+                const float yj = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
+                const float zj = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
+                sh.rel[k] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
             }
         }
         __syncthreads();
@@ -961,32 +1002,21 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
             const int s1 = min(filled, s0 + 64);
             int s = s0;
             if (fast) {
-                for (; s + 4 <= s1; s += 4) {
-                    const float4 X = *reinterpret_cast<const float4 *>(&sh.rel[0][s]);
-                    const float4 Y = *reinterpret_cast<const float4 *>(&sh.rel[1][s]);
-                    const float4 Z = *reinterpret_cast<const float4 *>(&sh.rel[2][s]);
-                    const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w},
-                                zs[4] = {Z.x, Z.y, Z.z, Z.w};
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float dx = xi - xs[k], dy = yi - ys[k], dz = zi - zs[k];
-                        const float d2 = dx * dx + dy * dy + dz * dz;
-                        sh.list[cnt * 64 + lane] = static_cast<uint8_t>(s + k);
-                        cnt += (d2 < rcf2_lane) & (d2 > 0.0f);
-                    }
-                }
+                uint8_t *p = mylist + cnt;
+#pragma unroll 4
                 for (; s < s1; ++s) {
-                    const float dx = xi - sh.rel[0][s], dy = yi - sh.rel[1][s], dz = zi - sh.rel[2][s];
-                    const float d2 = dx * dx + dy * dy + dz * dz;
-                    sh.list[cnt * 64 + lane] = static_cast<uint8_t>(s);
-                    cnt += (d2 < rcf2_lane) & (d2 > 0.0f);
+                    const float4 c = sh.rel[s];
+                    const float t = fmaf(c.x, ax, fmaf(c.y, ay, fmaf(c.z, az, c.w)));
+                    *p = static_cast<uint8_t>(s);
+                    p += t < thr;
                 }
+                cnt = static_cast<int>(p - mylist);
             } else {
                 for (; s < s1; ++s) {
                     real dx, dy, dz;
                     displacement<T>(ri, sh.tile[s], sx, sy, sz, dx, dy, dz);
                     const real d2 = dx * dx + dy * dy + dz * dz;
-                    sh.list[cnt * 64 + lane] = static_cast<uint8_t>(s);
+                    mylist[cnt] = static_cast<uint8_t>(s);
                     cnt += (d2 < rc2_lane) & (d2 > 0);
                 }
             }
