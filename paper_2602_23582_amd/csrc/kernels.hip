@@ -662,16 +662,23 @@ __global__ __launch_bounds__(kAtomBlock) void k_order(const SysDesc *__restrict_
 #define RBSOG_PAIR_CHUNK 128
 #endif
 #ifndef RBSOG_PAIR_LISTCAP
-#define RBSOG_PAIR_LISTCAP 96
+#define RBSOG_PAIR_LISTCAP 48
+#endif
+#ifndef RBSOG_PAIR_STEP
+#define RBSOG_PAIR_STEP 16
+#endif
+#ifndef RBSOG_PAIR_OCC
+#define RBSOG_PAIR_OCC 5
 #endif
 #ifndef RBSOG_FAST_FILTER
 #define RBSOG_FAST_FILTER 1
 #endif
 constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round (byte indices, <= 256)
-constexpr int kListCap = RBSOG_PAIR_LISTCAP; // per-lane list capacity between flushes (>= 64)
+constexpr int kListCap = RBSOG_PAIR_LISTCAP; // per-lane list capacity between flushes
 constexpr int kListStride = kListCap + 1;    // lane-major lists; an odd stride spreads the lanes over the banks
+constexpr int kStep = RBSOG_PAIR_STEP;       // candidates tested between list-capacity checks
 constexpr int kMaxRanges = 18;
-static_assert(kChunk <= 256 && kChunk % 64 == 0 && kListCap >= 64, "pair tiling");
+static_assert(kChunk <= 256 && kChunk % kStep == 0 && kStep % 4 == 0 && kListCap >= 2 * kStep, "pair tiling");
 
 template <class T>
 struct PairAcc {
@@ -976,39 +983,62 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         uu += acc.u;
     };
 
-    for (int ch = 0; ch < nch; ++ch) {
-        // this chunk's groups: ch, ch + nch, ...; slots k of the chunk map to
-        // flattened indices 4 (ch + nch (k/4)) + k%4, a prefix of them valid
+    // this chunk's groups: ch, ch + nch, ...; slots k of the chunk map to
+    // flattened indices 4 (ch + nch (k/4)) + k%4, a prefix of them valid
+    auto chunk_filled = [&](int ch) {
         const int ng = ch < ngroups ? (ngroups - ch + nch - 1) / nch : 0;
         const int glast = ch + nch * (ng - 1);
-        const int filled = ng > 0 ? 4 * (ng - 1) + min(4, total - 4 * glast) : 0;
+        return ng > 0 ? 4 * (ng - 1) + min(4, total - 4 * glast) : 0;
+    };
+    for (int ch = 0; ch < nch; ++ch) {
+        const int filled = chunk_filled(ch);
         for (int k = lane; k < filled; k += 64) {
-            const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
-            int r = 0;
-            while (r + 1 < kMaxRanges && sh.pre[r + 1] <= f) ++r;
-            const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
-            sh.tile[k] = rj;
-            if (fast) {
-                const float xj = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
-                const float yj = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
-                const float zj = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
-                sh.rel[k] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
+            {
+                const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
+                int r = 0;
+                while (r + 1 < kMaxRanges && sh.pre[r + 1] <= f) ++r;
+                const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
+                sh.tile[k] = rj;
+                if (fast) {
+                    const float xj = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
+                    const float yj = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
+                    const float zj = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
+                    sh.rel[k] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
+                }
             }
         }
+        // the fast filter reads whole groups of four: padding candidates never pass
+        const int filled4 = (filled + 3) & ~3;
+        if (fast && lane < filled4 - filled) sh.rel[filled + lane] = make_float4(0.f, 0.f, 0.f, INFINITY);
         __syncthreads();
-        // test every staged candidate; the append is branch-free (the byte at
-        // the list head is overwritten when the test fails)
-        for (int s0 = 0; s0 < filled; s0 += 64) {
-            const int s1 = min(filled, s0 + 64);
+        // test every staged candidate, kStep at a time; the append is
+        // branch-free (the byte at the list head is written for every
+        // candidate and kept when the candidate hits)
+        for (int s0 = 0; s0 < filled; s0 += kStep) {
+            const int s1 = min(filled, s0 + kStep);
             int s = s0;
             if (fast) {
+                // groups of four, the next group's loads issued before this
+                // group's tests so that the LDS latency overlaps the arithmetic
+                const int e1 = min(filled4, s0 + kStep);
                 uint8_t *p = mylist + cnt;
-#pragma unroll 4
-                for (; s < s1; ++s) {
-                    const float4 c = sh.rel[s];
-                    const float t = fmaf(c.x, ax, fmaf(c.y, ay, fmaf(c.z, az, c.w)));
-                    *p = static_cast<uint8_t>(s);
-                    p += t < thr;
+                float4 nb[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nb[k] = sh.rel[s0 + k];
+                for (; s < e1; s += 4) {
+                    float4 c[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) c[k] = nb[k];
+                    if (s + 4 < e1) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) nb[k] = sh.rel[s + 4 + k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float t = fmaf(c[k].x, ax, fmaf(c[k].y, ay, fmaf(c[k].z, az, c[k].w)));
+                        *p = static_cast<uint8_t>(s + k);
+                        p += t < thr;
+                    }
                 }
                 cnt = static_cast<int>(p - mylist);
             } else {
@@ -1020,7 +1050,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                     cnt += (d2 < rc2_lane) & (d2 > 0);
                 }
             }
-            if (wave_max(cnt) > kListCap - 64) flush();
+            if (__any(cnt > kListCap - kStep)) flush();
         }
         flush();
         __syncthreads();
@@ -1039,8 +1069,14 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
 }
 
 // Static schedule: workgroup g runs plan entry g.
+// Register budget of the FP32 pair kernel: RBSOG_PAIR_OCC waves per SIMD (the
+// kernel waits on LDS and memory more than it computes, so occupancy pays;
+// 5 fits its 92 registers without spilling).  FP64 keeps the default.
+template <class T>
+constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? RBSOG_PAIR_OCC : 1; }
+
 template <class T, int M, bool E>
-__global__ __launch_bounds__(64) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_min_waves<T>()))) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                              const int2 *__restrict__ plan)
 {
     __shared__ PairShared<T> sh;
