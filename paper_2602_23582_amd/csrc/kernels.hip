@@ -604,6 +604,21 @@ __global__ __launch_bounds__(kCellBlock) void k_scan_add(const SysDesc *__restri
     }
 }
 
+// The sort key of an atom inside its cell: its z fixed-point coordinate (top
+// 32 bits), then its index.  Sorting each cell by z makes every 64-atom pair
+// block a thin z-slab, which the pair kernel uses to skip neighbours out of
+// reach in z.
+template <class T>
+__device__ inline uint64_t cell_key(const SysDesc &D, int64_t i)
+{
+    const typename T::fix uz = gp(static_cast<const typename T::fix *>(D.u))[2 * D.n + i];
+    uint32_t top;
+    if constexpr (sizeof(typename T::fix) == 4) top = uz;
+    else top = static_cast<uint32_t>(uz >> 32);
+    return (static_cast<uint64_t>(top) << 32) | static_cast<uint64_t>(i);
+}
+
+template <class T>
 __global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restrict__ desc, const int2 *__restrict__ plan)
 {
     const int2 e = plan[blockIdx.x];
@@ -613,11 +628,12 @@ __global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restric
     if (!__any(active)) return;
     const int c = active ? gp(D.cell)[i] : 0;
     const int slot = aggregated_increment<true>(D.cursor, c, active);
-    if (active) gp(D.perm_tmp)[gp(D.start)[c] + slot] = static_cast<int32_t>(i);
+    if (active) gp(D.keys)[gp(D.start)[c] + slot] = cell_key<T>(D, i);
 }
 
-// Within each cell, atoms keep the caller's order: the slot of atom i is the
-// cell start plus the number of atoms of its cell with a smaller index.
+// Within each cell, atoms are ordered by their key (z, then index): the slot
+// of an atom is the cell start plus the number of keys of its cell below its
+// own.  Keys are unique, so the order does not depend on the scatter's.
 template <class T>
 __global__ __launch_bounds__(kAtomBlock) void k_order(const SysDesc *__restrict__ desc, const int2 *__restrict__ plan)
 {
@@ -626,12 +642,13 @@ __global__ __launch_bounds__(kAtomBlock) void k_order(const SysDesc *__restrict_
     const int64_t n = D.n;
     const int64_t t = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
     if (t >= n) return;
-    const RB_GLOBAL int32_t *perm_tmp = gp(D.perm_tmp);
-    const int i = perm_tmp[t];
+    const RB_GLOBAL uint64_t *keys = gp(D.keys);
+    const uint64_t key = keys[t];
+    const int i = static_cast<int>(key & 0xFFFFFFFFull);
     const int c = gp(D.cell)[i];
     const int s0 = gp(D.start)[c], s1 = gp(D.start)[c + 1];
     int rank = 0;
-    for (int j = s0; j < s1; ++j) rank += perm_tmp[j] < i;
+    for (int j = s0; j < s1; ++j) rank += keys[j] < key;
     const int slot = s0 + rank;
     gp(D.perm)[slot] = i;
     const RB_GLOBAL typename T::fix *u = gp(static_cast<const typename T::fix *>(D.u));
@@ -677,7 +694,7 @@ constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round (byt
 constexpr int kListCap = RBSOG_PAIR_LISTCAP; // per-lane list capacity between flushes
 constexpr int kListStride = kListCap + 1;    // lane-major lists; an odd stride spreads the lanes over the banks
 constexpr int kStep = RBSOG_PAIR_STEP;       // candidates tested between list-capacity checks
-constexpr int kMaxRanges = 18;
+constexpr int kMaxRanges = 27;  // one per neighbour cell (fast path) or per row run (exact path)
 static_assert(kChunk <= 256 && kChunk % kStep == 0 && kStep % 4 == 0 && kListCap >= 2 * kStep, "pair tiling");
 
 template <class T>
@@ -909,9 +926,53 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
     const int oy = ny >= 3 ? 1 : 0, oz = nz >= 3 ? 1 : 0;
 
-    // neighbour ranges: one per row (dy, dz), split where the x-run wraps;
-    // they are concatenated into one flattened candidate index
-    if (lane == 0) {
+    if (kIsF32 && fast) {
+        // The block's atoms are a slab of their cell, sorted by z, spanning
+        // [0, zext] in fixed point relative to o.  Each of the 27 neighbour
+        // cells (distinct: at least 5 per edge) is cut to the atoms whose z
+        // lies within the padded cutoff of that slab; inside a cell the
+        // relative z is monotonic (no cell straddles the periodic seam and
+        // neighbours are within two cells of o), so the cut is a binary search.
+        const int nvalid = min(kPairWave, ce - cs - cb.y * kPairWave);
+        const sfix rzi = static_cast<sfix>(ri.z - oz_);
+        const sfix zext = __shfl(rzi, nvalid - 1, 64);
+        const int64_t reach = static_cast<int64_t>(ceil(static_cast<double>(rcf) / St.L[2] * 4294967296.0)) + 2;
+        const int64_t zlo = -reach, zhi = static_cast<int64_t>(zext) + reach;
+        if (lane < 27) {
+            const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+            const int jx = (cx + dx + nx) % nx, jy = (cy + dy + ny) % ny, jz = (cz + dz + nz) % nz;
+            const int c2 = jx + nx * (jy + ny * jz);
+            int lo = start[c2], hi = start[c2 + 1];
+            const RB_GLOBAL uint32_t *zw = reinterpret_cast<const RB_GLOBAL uint32_t *>(gp(rec));
+            auto zrel = [&](int j) {
+                return static_cast<int64_t>(static_cast<int32_t>(static_cast<uint32_t>(zw[4 * j + 2] - static_cast<uint32_t>(oz_))));
+            };
+            // first atom at or above zlo, then first atom above zhi
+            int a = lo, b = hi;
+            while (a < b) {
+                const int m = (a + b) >> 1;
+                if (zrel(m) < zlo) a = m + 1;
+                else b = m;
+            }
+            lo = a;
+            b = hi;
+            while (a < b) {
+                const int m = (a + b) >> 1;
+                if (zrel(m) <= zhi) a = m + 1;
+                else b = m;
+            }
+            hi = a;
+            sh.beg[lane] = lo;
+            sh.pre[lane + 1] = hi - lo;  // length for now
+        }
+        __syncthreads();
+        if (lane == 0) {
+            sh.pre[0] = 0;
+            for (int k = 0; k < kMaxRanges; ++k) sh.pre[k + 1] += sh.pre[k];
+        }
+    } else if (lane == 0) {
+        // exact path: one range per row (dy, dz), split where the x-run
+        // wraps; rows of a dimension with fewer than three cells are whole
         int nr = 0;
         auto put = [&](int lo, int hi) {
             sh.beg[nr] = lo;
@@ -995,8 +1056,11 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         for (int k = lane; k < filled; k += 64) {
             {
                 const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
+                // the range holding flattened index f: the last r with pre[r] <= f
                 int r = 0;
-                while (r + 1 < kMaxRanges && sh.pre[r + 1] <= f) ++r;
+#pragma unroll
+                for (int step = 16; step >= 1; step >>= 1)
+                    if (r + step < kMaxRanges && sh.pre[r + step] <= f) r += step;
                 const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
                 sh.tile[k] = rj;
                 if (fast) {
@@ -1458,7 +1522,7 @@ static hipError_t bin_and_sort_t(Batch &b)
     hipLaunchKernelGGL(k_scan_top, dim3(nsys(b)), dim3(256), 0, b.stream, b.d_desc, b.d_step);
     hipLaunchKernelGGL(k_scan_add, dim3(plan_grid(b, kPlanCells)), dim3(kCellBlock), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanCells));
-    hipLaunchKernelGGL(k_scatter, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
+    hipLaunchKernelGGL(k_scatter<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
                        plan_ptr(b, kPlanAtoms));
     hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
                        plan_ptr(b, kPlanAtoms));

@@ -81,7 +81,8 @@ struct SysDesc {
     int32_t *count, *cursor, *start, *nblk, *bstart;  // per cell [ncells_cap + 1]
     int32_t *scan_tmp;    // [2 * 1024 + 2] block sums of the two-level scan
     int2 *blocks;         // pair-block table (cell, sub-block) [pair_cap]
-    int32_t *perm_tmp, *perm;  // cell-sorted slot -> system atom index
+    uint64_t *keys;       // binned slot -> (z sort key << 32) | system atom index
+    int32_t *perm;        // sorted slot -> system atom index
     void *rec;            // sorted records (fixed-point position + charge)
     void *fsr;            // short-range force, sorted order (3 SoA planes)
     double *pair_part;    // 8 doubles per pair block

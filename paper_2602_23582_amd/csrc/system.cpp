@@ -21,10 +21,10 @@ bool is_fp64(const rbsog_params &p) { return p.precision == RBSOG_PREC_FP64; }
 
 // byte sizes of the per-atom and per-mode buffers, in carving order
 struct AtomLayout {
-    size_t q, u, cell, perm_tmp, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, coef, scan_tmp;
+    size_t q, u, cell, keys, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, coef, scan_tmp;
     size_t total() const
     {
-        return q + u + cell + perm_tmp + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + coef + scan_tmp;
+        return q + u + cell + keys + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + coef + scan_tmp;
     }
 };
 
@@ -38,7 +38,7 @@ AtomLayout atom_layout(const rbsog_params &p, int64_t n)
     a.q = align_up(n * rsz);
     a.u = align_up(3 * n * fsz);
     a.cell = align_up(n * 4);
-    a.perm_tmp = align_up(n * 4);
+    a.keys = align_up(n * 8);
     a.perm = align_up(n * 4);
     a.rec = align_up(n * recsz);
     a.fsr = align_up(3 * n * rsz);
@@ -294,7 +294,7 @@ void system_carve_atoms(System &s, void *mem)
     d.q = take(a.q);
     d.u = take(a.u);
     d.cell = static_cast<int32_t *>(take(a.cell));
-    d.perm_tmp = static_cast<int32_t *>(take(a.perm_tmp));
+    d.keys = static_cast<uint64_t *>(take(a.keys));
     d.perm = static_cast<int32_t *>(take(a.perm));
     d.rec = take(a.rec);
     d.fsr = take(a.fsr);
