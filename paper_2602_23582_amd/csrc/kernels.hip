@@ -107,11 +107,6 @@ __device__ inline T wave_sum(T v)
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-__device__ inline int wave_max(int v)
-{
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
 
 // ----------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11) and the sampler's draws
@@ -664,38 +659,30 @@ __global__ __launch_bounds__(kAtomBlock) void k_order(const SysDesc *__restrict_
 // Short-range pair kernel
 // ----------------------------------------------------------------------------
 //
-// One wavefront owns up to 64 atoms of one cell (a "pair block") and walks the
-// atoms of the 27 neighbouring cells (full shell: every pair is evaluated from
-// both sides, so no atomics and a fixed summation order).  The neighbours are
-// up to 18 contiguous ranges of the sorted arrays (the three cells of a row are
-// adjacent in memory unless the row wraps).  They are staged kChunk at a time
-// in LDS; every lane tests every staged candidate against r_c and appends the
-// LDS index of each partner inside r_c to its own byte list; then all lanes
-// walk their lists, reading partner records from LDS, so the expensive SOG
-// kernel runs on wavefronts whose lanes all hold a real pair until the
-// shortest list ends.
+// One wavefront owns up to 64 atoms of one cell (a "pair block"; cells are
+// sorted by z, so a block is a z-slab of its cell) and walks the atoms of the
+// 27 neighbouring cells (full shell: every pair is evaluated from both sides,
+// so no atomics and a fixed summation order).  The neighbours are contiguous
+// ranges of the sorted arrays: with at least five cells per edge, one per
+// neighbour cell cut to the block's z-window; otherwise one per row.  They are
+// staged kChunk at a time in LDS; every lane tests every staged candidate
+// against r_c and keeps one hit bit per candidate; then every lane walks its
+// hit bits, reading partner records from LDS, so the expensive SOG kernel runs
+// on wavefronts whose lanes all hold a real pair until the lane with the
+// fewest partners in the chunk is done.
 
 #ifndef RBSOG_PAIR_CHUNK
 #define RBSOG_PAIR_CHUNK 128
 #endif
-#ifndef RBSOG_PAIR_LISTCAP
-#define RBSOG_PAIR_LISTCAP 48
-#endif
-#ifndef RBSOG_PAIR_STEP
-#define RBSOG_PAIR_STEP 16
-#endif
 #ifndef RBSOG_PAIR_OCC
-#define RBSOG_PAIR_OCC 5
+#define RBSOG_PAIR_OCC 6
 #endif
 #ifndef RBSOG_FAST_FILTER
 #define RBSOG_FAST_FILTER 1
 #endif
-constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round (byte indices, <= 256)
-constexpr int kListCap = RBSOG_PAIR_LISTCAP; // per-lane list capacity between flushes
-constexpr int kListStride = kListCap + 1;    // lane-major lists; an odd stride spreads the lanes over the banks
-constexpr int kStep = RBSOG_PAIR_STEP;       // candidates tested between list-capacity checks
+constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round
 constexpr int kMaxRanges = 27;  // one per neighbour cell (fast path) or per row run (exact path)
-static_assert(kChunk <= 256 && kChunk % kStep == 0 && kStep % 4 == 0 && kListCap >= 2 * kStep, "pair tiling");
+static_assert(kChunk % 32 == 0 && kChunk % 4 == 0, "pair tiling");
 
 template <class T>
 struct PairAcc {
@@ -858,7 +845,7 @@ template <class T>
 struct PairShared {
     typename T::Rec tile[kChunk];
     float4 rel[kChunk];  // fast filter: coordinates relative to the block origin and their squared norm
-    uint8_t list[kListStride * 64];
+    uint32_t mask[kChunk / 32][64];  // hit bits of each lane, one word per 32 candidates
     int pre[kMaxRanges + 1];  // flattened-neighbourhood offset of each range
     int beg[kMaxRanges];
 };
@@ -922,7 +909,6 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const float zi = static_cast<float>(static_cast<sfix>(ri.z - oz_)) * static_cast<float>(sz);
     const float ax = -2.0f * xi, ay = -2.0f * yi, az = -2.0f * zi;
     const float thr = valid ? rcf * rcf - (xi * xi + yi * yi + zi * zi) : -INFINITY;
-    uint8_t *const mylist = sh.list + lane * kListStride;
     const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
     const int oy = ny >= 3 ? 1 : 0, oz = nz >= 3 ? 1 : 0;
 
@@ -1008,41 +994,14 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const int total = sh.pre[kMaxRanges];
     // Candidates go to the chunks in groups of 4 consecutive records, group g to
     // chunk g mod nch: every chunk samples the whole neighbourhood, so each
-    // lane's share of partners is about the same in every chunk and the lists
-    // of a wavefront end together.
+    // lane's share of partners is about the same in every chunk and the lanes
+    // of a wavefront run out of partners together.
     const int ngroups = (total + 3) / 4;
     const int gpc = kChunk / 4;
     const int nch = (ngroups + gpc - 1) / gpc;
 
     double fx = 0, fy = 0, fz = 0, v[6] = {0, 0, 0, 0, 0, 0}, uu = 0;
-    int cnt = 0;     // entries in this lane's list
     int hits = 0;    // in-cutoff partners of this lane's atom
-
-    // every lane evaluates its listed partners; lanes drop out as their lists end
-    auto flush = [&]() {
-        const int kmax = wave_max(cnt);
-        PairAcc<T> acc;
-        int e = 0;
-        for (; e + 2 <= kmax; e += 2) {
-            const int j0 = mylist[e], j1 = mylist[e + 1];
-            const Rec r0 = sh.tile[j0], r1 = sh.tile[j1];
-            if (e < cnt) pair_eval<T, M, E>(ri, r0, sx, sy, sz, rc2, W, acc);
-            if (e + 1 < cnt) pair_eval<T, M, E>(ri, r1, sx, sy, sz, rc2, W, acc);
-        }
-        if (e < kmax && e < cnt) pair_eval<T, M, E>(ri, sh.tile[mylist[e]], sx, sy, sz, rc2, W, acc);
-        hits += acc.n;
-        cnt = 0;
-        fx += acc.fx;
-        fy += acc.fy;
-        fz += acc.fz;
-        v[0] += acc.vxx;
-        v[1] += acc.vyy;
-        v[2] += acc.vzz;
-        v[3] += acc.vxy;
-        v[4] += acc.vxz;
-        v[5] += acc.vyz;
-        uu += acc.u;
-    };
 
     // this chunk's groups: ch, ch + nch, ...; slots k of the chunk map to
     // flattened indices 4 (ch + nch (k/4)) + k%4, a prefix of them valid
@@ -1054,69 +1013,106 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     for (int ch = 0; ch < nch; ++ch) {
         const int filled = chunk_filled(ch);
         for (int k = lane; k < filled; k += 64) {
-            {
-                const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
-                // the range holding flattened index f: the last r with pre[r] <= f
-                int r = 0;
+            const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
+            // the range holding flattened index f: the last r with pre[r] <= f
+            int r = 0;
 #pragma unroll
-                for (int step = 16; step >= 1; step >>= 1)
-                    if (r + step < kMaxRanges && sh.pre[r + step] <= f) r += step;
-                const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
-                sh.tile[k] = rj;
-                if (fast) {
-                    const float xj = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
-                    const float yj = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
-                    const float zj = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
-                    sh.rel[k] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
-                }
+            for (int step = 16; step >= 1; step >>= 1)
+                if (r + step < kMaxRanges && sh.pre[r + step] <= f) r += step;
+            const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
+            sh.tile[k] = rj;
+            if (fast) {
+                const float xj = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
+                const float yj = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
+                const float zj = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
+                sh.rel[k] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
             }
         }
-        // the fast filter reads whole groups of four: padding candidates never pass
-        const int filled4 = (filled + 3) & ~3;
-        if (fast && lane < filled4 - filled) sh.rel[filled + lane] = make_float4(0.f, 0.f, 0.f, INFINITY);
+        // the filter reads whole 32-candidate words: padding candidates never pass
+        const int words = (filled + 31) >> 5;
+        if (fast)
+            for (int k = filled + lane; k < 32 * words; k += 64) sh.rel[k] = make_float4(0.f, 0.f, 0.f, INFINITY);
         __syncthreads();
-        // test every staged candidate, kStep at a time; the append is
-        // branch-free (the byte at the list head is written for every
-        // candidate and kept when the candidate hits)
-        for (int s0 = 0; s0 < filled; s0 += kStep) {
-            const int s1 = min(filled, s0 + kStep);
-            int s = s0;
+
+        // Filter: one hit bit per candidate, shifted in so that the first
+        // candidate of a word ends up in its top bit.  Nothing is written
+        // per candidate; each lane stores its words, then walks their set bits.
+        for (int w = 0; w < words; ++w) {
+            uint32_t m = 0;
             if (fast) {
                 // groups of four, the next group's loads issued before this
                 // group's tests so that the LDS latency overlaps the arithmetic
-                const int e1 = min(filled4, s0 + kStep);
-                uint8_t *p = mylist + cnt;
                 float4 nb[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) nb[k] = sh.rel[s0 + k];
-                for (; s < e1; s += 4) {
+                for (int k = 0; k < 4; ++k) nb[k] = sh.rel[32 * w + k];
+#pragma unroll
+                for (int g = 0; g < 8; ++g) {
                     float4 c[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) c[k] = nb[k];
-                    if (s + 4 < e1) {
+                    if (g < 7) {
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) nb[k] = sh.rel[s + 4 + k];
+                        for (int k = 0; k < 4; ++k) nb[k] = sh.rel[32 * w + 4 * (g + 1) + k];
                     }
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const float t = fmaf(c[k].x, ax, fmaf(c[k].y, ay, fmaf(c[k].z, az, c[k].w)));
-                        *p = static_cast<uint8_t>(s + k);
-                        p += t < thr;
+                        m = m + m + static_cast<uint32_t>(t < thr);
                     }
                 }
-                cnt = static_cast<int>(p - mylist);
             } else {
-                for (; s < s1; ++s) {
-                    real dx, dy, dz;
-                    displacement<T>(ri, sh.tile[s], sx, sy, sz, dx, dy, dz);
-                    const real d2 = dx * dx + dy * dy + dz * dz;
-                    mylist[cnt] = static_cast<uint8_t>(s);
-                    cnt += (d2 < rc2_lane) & (d2 > 0);
+                const int s_end = min(filled, 32 * w + 32);
+                for (int s = 32 * w; s < 32 * w + 32; ++s) {
+                    bool hit = false;
+                    if (s < s_end) {
+                        real dx, dy, dz;
+                        displacement<T>(ri, sh.tile[s], sx, sy, sz, dx, dy, dz);
+                        const real d2 = dx * dx + dy * dy + dz * dz;
+                        hit = (d2 < rc2_lane) & (d2 > 0);
+                    }
+                    m = m + m + static_cast<uint32_t>(hit);
                 }
             }
-            if (__any(cnt > kListCap - kStep)) flush();
+            sh.mask[w][lane] = m;
         }
-        flush();
+
+        // Evaluation: every lane takes its hits in increasing candidate order,
+        // two per round from its current word; lanes whose word is spent move
+        // to their next word (their own LDS entries, no barrier needed).
+        PairAcc<T> acc;
+        int w = 0;
+        uint32_t cur = words > 0 ? sh.mask[0][lane] : 0u;
+        for (;;) {
+            for (;;) {
+                const bool need = cur == 0u && w + 1 < words;
+                if (!__any(need)) break;
+                if (need) {
+                    ++w;
+                    cur = sh.mask[w][lane];
+                }
+            }
+            if (!__any(cur != 0u)) break;
+            const bool a0 = cur != 0u;
+            const int k0 = a0 ? __builtin_clz(cur) : 0;
+            cur = a0 ? (cur & ~(0x80000000u >> k0)) : 0u;
+            const bool a1 = cur != 0u;
+            const int k1 = a1 ? __builtin_clz(cur) : 0;
+            cur = a1 ? (cur & ~(0x80000000u >> k1)) : 0u;
+            const Rec r0 = sh.tile[32 * w + k0], r1 = sh.tile[32 * w + k1];
+            if (a0) pair_eval<T, M, E>(ri, r0, sx, sy, sz, rc2, W, acc);
+            if (a1) pair_eval<T, M, E>(ri, r1, sx, sy, sz, rc2, W, acc);
+        }
+        hits += acc.n;
+        fx += acc.fx;
+        fy += acc.fy;
+        fz += acc.fz;
+        v[0] += acc.vxx;
+        v[1] += acc.vyy;
+        v[2] += acc.vzz;
+        v[3] += acc.vxy;
+        v[4] += acc.vxz;
+        v[5] += acc.vyz;
+        uu += acc.u;
         __syncthreads();
     }
     if (valid) {
@@ -1133,14 +1129,15 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
 }
 
 // Static schedule: workgroup g runs plan entry g.
-// Register budget of the FP32 pair kernel: RBSOG_PAIR_OCC waves per SIMD (the
-// kernel waits on LDS and memory more than it computes, so occupancy pays;
-// 5 fits its 92 registers without spilling).  FP64 keeps the default.
-template <class T>
-constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? RBSOG_PAIR_OCC : 1; }
+// Register budget of the FP32 pair kernel: RBSOG_PAIR_OCC waves per SIMD
+// without the energy sum, one fewer with it (the kernel waits on LDS more
+// than it computes, so occupancy pays; both budgets fit without spilling).
+// FP64 keeps the default.
+template <class T, bool E>
+constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? (E ? RBSOG_PAIR_OCC - 1 : RBSOG_PAIR_OCC) : 1; }
 
 template <class T, int M, bool E>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_min_waves<T>()))) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_min_waves<T, E>()))) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                              const int2 *__restrict__ plan)
 {
     __shared__ PairShared<T> sh;
