@@ -1500,16 +1500,20 @@ inline unsigned nsys(const Batch &b) { return static_cast<unsigned>(b.sys.size()
 hipError_t launch_sample(Batch &b)
 {
     if (b.sys.empty()) return hipSuccess;
-    timer_begin(b, "sampler");
-    hipLaunchKernelGGL(k_sampler, dim3(nsys(b)), dim3(256), 0, b.stream, b.d_desc, b.d_step);
-    timer_end(b, "sampler");
+    // on the second stream, after everything queued so far on the first
+    hipError_t e = hipEventRecord(b.ev_up, b.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b.aux, b.ev_up, 0);
+    if (e != hipSuccess) return e;
+    timer_begin(b, "sampler", b.aux);
+    hipLaunchKernelGGL(k_sampler, dim3(nsys(b)), dim3(256), 0, b.aux, b.d_desc, b.d_step);
+    timer_end(b, "sampler", b.aux);
     return hipGetLastError();
 }
 
 template <class T>
 static hipError_t bin_and_sort_t(Batch &b)
 {
-    timer_begin(b, "bin");
+    timer_begin(b, "bin", b.stream);
     hipLaunchKernelGGL(k_zero, dim3(plan_grid(b, kPlanCells)), dim3(kCellBlock), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanCells), b.d_ctrl);
     hipLaunchKernelGGL(k_fix<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc, b.d_step,
@@ -1523,8 +1527,9 @@ static hipError_t bin_and_sort_t(Batch &b)
                        plan_ptr(b, kPlanAtoms));
     hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
                        plan_ptr(b, kPlanAtoms));
-    timer_end(b, "bin");
-    return hipGetLastError();
+    timer_end(b, "bin", b.stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? hipEventRecord(b.ev_bin, b.stream) : e;
 }
 
 hipError_t launch_bin_and_sort(Batch &b)
@@ -1562,10 +1567,10 @@ static void pair_forms(Batch &b)
 template <class T>
 static hipError_t pair_t(Batch &b)
 {
-    timer_begin(b, "pair");
+    timer_begin(b, "pair", b.stream);
     if (b.want_energy) pair_forms<T, true>(b);
     else pair_forms<T, false>(b);
-    timer_end(b, "pair");
+    timer_end(b, "pair", b.stream);
     return hipGetLastError();
 }
 
@@ -1578,18 +1583,26 @@ hipError_t launch_pair(Batch &b)
 template <class T>
 static hipError_t kspace_t(Batch &b)
 {
-    timer_begin(b, "sk");
-    hipLaunchKernelGGL(k_sk<T>, dim3(plan_grid(b, kPlanSk)), dim3(256), 0, b.stream, b.d_desc, plan_ptr(b, kPlanSk));
-    timer_end(b, "sk");
-    timer_begin(b, "reduce");
+    // structure factors on the second stream once the records are sorted,
+    // beside the pair kernel; the first stream joins before the reductions
+    hipError_t e = hipStreamWaitEvent(b.aux, b.ev_bin, 0);
+    if (e != hipSuccess) return e;
+    timer_begin(b, "sk", b.aux);
+    hipLaunchKernelGGL(k_sk<T>, dim3(plan_grid(b, kPlanSk)), dim3(256), 0, b.aux, b.d_desc, plan_ptr(b, kPlanSk));
+    timer_end(b, "sk", b.aux);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(b.ev_sk, b.aux);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.ev_sk, 0);
+    if (e != hipSuccess) return e;
+    timer_begin(b, "reduce", b.stream);
     hipLaunchKernelGGL(k_rho_reduce, dim3(plan_grid(b, kPlanReduce)), dim3(256), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanReduce));
     hipLaunchKernelGGL(k_estimators<T>, dim3(nsys(b)), dim3(256), 0, b.stream, b.d_desc, b.d_step);
-    timer_end(b, "reduce");
-    timer_begin(b, "force");
+    timer_end(b, "reduce", b.stream);
+    timer_begin(b, "force", b.stream);
     hipLaunchKernelGGL(k_force<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanAtoms));
-    timer_end(b, "force");
+    timer_end(b, "force", b.stream);
     return hipGetLastError();
 }
 

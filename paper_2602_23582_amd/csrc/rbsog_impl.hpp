@@ -161,6 +161,13 @@ struct System {
 // A batch of systems sharing one stream and one set of launches.
 struct Batch {
     hipStream_t stream = nullptr;
+    // The sampler and the structure factors run on a second stream, beside
+    // binning and the pair kernel (default priority, joined by events):
+    //   stream: upload -+-> bin -+-> pair ----------+-> reduce, estimators, force
+    //                   |        |                  |
+    //   aux:            +-> sampler -> (bin done) sk -+
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_up = nullptr, ev_bin = nullptr, ev_sk = nullptr;
     int device = 0;
     int precision = RBSOG_PREC_FP32C;
     std::vector<System *> sys;
@@ -251,7 +258,7 @@ hipError_t launch_kspace(Batch &b);
 hipError_t launch_rescale(Batch &b);
 
 // timing hooks used by the launchers (system.cpp)
-void timer_begin(Batch &b, const char *name);
-void timer_end(Batch &b, const char *name);
+void timer_begin(Batch &b, const char *name, hipStream_t s);
+void timer_end(Batch &b, const char *name, hipStream_t s);
 
 }  // namespace rbsog

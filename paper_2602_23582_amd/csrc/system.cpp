@@ -409,7 +409,11 @@ int batch_init(Batch &b, hipStream_t stream, int precision, std::string &err)
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b.device) == hipSuccess && ncu > 0)
         b.num_cu = ncu;
     bool ok = hipMalloc(&b.d_ctrl, 64) == hipSuccess &&
-              hipEventCreateWithFlags(&b.up_done, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&b.up_done, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&b.aux, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&b.ev_up, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b.ev_bin, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b.ev_sk, hipEventDisableTiming) == hipSuccess;
     for (int k = 0; ok && k < Batch::kStepRing; ++k)
         ok = hipEventCreateWithFlags(&b.step_ev[k], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
@@ -454,6 +458,15 @@ void batch_free(Batch &b)
         b.step_ev[k] = nullptr;
     }
     if (b.up_done) (void)hipEventDestroy(b.up_done);
+    if (b.aux) {
+        (void)hipStreamSynchronize(b.aux);
+        (void)hipStreamDestroy(b.aux);
+    }
+    hipEvent_t evs[] = {b.ev_up, b.ev_bin, b.ev_sk};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
+    b.aux = nullptr;
+    b.ev_up = b.ev_bin = b.ev_sk = nullptr;
     b.d_desc = nullptr;
     b.d_step = nullptr;
     b.d_res = nullptr;
@@ -652,8 +665,10 @@ int batch_upload(Batch &b, std::string &err)
 int batch_fetch_results(Batch &b, std::string &err)
 {
     if (b.sys.empty()) return RBSOG_OK;
-    hipError_t e = hipMemcpyAsync(b.h_res, b.d_res, b.sys.size() * sizeof(StepResults), hipMemcpyDeviceToHost,
-                                  b.stream);
+    // work on the second stream (a sampler not yet joined) finishes first
+    hipError_t e = hipStreamSynchronize(b.aux);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b.h_res, b.d_res, b.sys.size() * sizeof(StepResults), hipMemcpyDeviceToHost, b.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
     if (e != hipSuccess) {
         err = std::string("result copy: ") + hipGetErrorString(e);
@@ -663,7 +678,7 @@ int batch_fetch_results(Batch &b, std::string &err)
     return RBSOG_OK;
 }
 
-void timer_begin(Batch &b, const char *name)
+void timer_begin(Batch &b, const char *name, hipStream_t stream)
 {
     if (!b.timing) return;
     Timer *t = nullptr;
@@ -683,22 +698,23 @@ void timer_begin(Batch &b, const char *name)
         (void)hipEventCreate(&ev.first);
         (void)hipEventCreate(&ev.second);
     }
-    (void)hipEventRecord(ev.first, b.stream);
+    (void)hipEventRecord(ev.first, stream);
     t->pending.push_back(ev);
 }
 
-void timer_end(Batch &b, const char *name)
+void timer_end(Batch &b, const char *name, hipStream_t stream)
 {
     if (!b.timing) return;
     for (auto &x : b.timers)
         if (x.name == name && !x.pending.empty()) {
-            (void)hipEventRecord(x.pending.back().second, b.stream);
+            (void)hipEventRecord(x.pending.back().second, stream);
             return;
         }
 }
 
 void batch_set_timing(Batch &b, bool on)
 {
+    (void)hipStreamSynchronize(b.aux);
     (void)hipStreamSynchronize(b.stream);
     free_timers(b);
     b.timing = on;
@@ -707,7 +723,8 @@ void batch_set_timing(Batch &b, bool on)
 int batch_get_timing(Batch &b, int32_t cap, int32_t *host_nk, char *host_names, double *host_ms,
                      int64_t *host_count, std::string &err)
 {
-    const hipError_t e = hipStreamSynchronize(b.stream);
+    hipError_t e = hipStreamSynchronize(b.aux);
+    if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
     if (e != hipSuccess) {
         err = std::string("timing: ") + hipGetErrorString(e);
         return RBSOG_EDEVICE;
