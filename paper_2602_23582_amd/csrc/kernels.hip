@@ -626,25 +626,16 @@ __global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restric
     if (active) gp(D.keys)[gp(D.start)[c] + slot] = cell_key<T>(D, i);
 }
 
-// Within each cell, atoms are ordered by their key (z, then index): the slot
-// of an atom is the cell start plus the number of keys of its cell below its
-// own.  Keys are unique, so the order does not depend on the scatter's.
+// Within each cell, atoms are ordered by their key (z, then index); keys are
+// unique, so the order does not depend on the scatter's.  One workgroup per
+// cell: a cell of up to 256 atoms is sorted in LDS (bitonic network over the
+// next power of two); a larger cell ranks each atom against all keys of the
+// cell.  The sorted slot receives the atom's index and its record.
 template <class T>
-__global__ __launch_bounds__(kAtomBlock) void k_order(const SysDesc *__restrict__ desc, const int2 *__restrict__ plan)
+__device__ inline void write_sorted(const SysDesc &D, int slot, uint64_t key)
 {
-    const int2 e = plan[blockIdx.x];
-    const SysDesc &D = desc[e.x];
     const int64_t n = D.n;
-    const int64_t t = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
-    if (t >= n) return;
-    const RB_GLOBAL uint64_t *keys = gp(D.keys);
-    const uint64_t key = keys[t];
     const int i = static_cast<int>(key & 0xFFFFFFFFull);
-    const int c = gp(D.cell)[i];
-    const int s0 = gp(D.start)[c], s1 = gp(D.start)[c + 1];
-    int rank = 0;
-    for (int j = s0; j < s1; ++j) rank += keys[j] < key;
-    const int slot = s0 + rank;
     gp(D.perm)[slot] = i;
     const RB_GLOBAL typename T::fix *u = gp(static_cast<const typename T::fix *>(D.u));
     typename T::Rec r;
@@ -653,6 +644,48 @@ __global__ __launch_bounds__(kAtomBlock) void k_order(const SysDesc *__restrict_
     r.z = u[2 * n + i];
     r.q = gp(static_cast<const typename T::real *>(D.q))[i];
     gstore(static_cast<typename T::Rec *>(D.rec) + slot, r);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc, const int2 *__restrict__ plan)
+{
+    __shared__ uint64_t s_key[256];
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const int c = e.y;
+    const int tid = threadIdx.x;
+    const int s0 = gp(D.start)[c], s1 = gp(D.start)[c + 1];
+    const int cnt = s1 - s0;
+    if (cnt == 0) return;
+    const RB_GLOBAL uint64_t *keys = gp(D.keys);
+    if (cnt <= 256) {
+        int N = 1;
+        while (N < cnt) N <<= 1;
+        s_key[tid] = tid < cnt ? keys[s0 + tid] : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= N; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int p = tid ^ j;
+                if (tid < N && p > tid) {
+                    const uint64_t a = s_key[tid], b = s_key[p];
+                    const bool up = (tid & k) == 0;
+                    if ((a > b) == up) {
+                        s_key[tid] = b;
+                        s_key[p] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (tid < cnt) write_sorted<T>(D, s0 + tid, s_key[tid]);
+    } else {
+        for (int t = tid; t < cnt; t += 256) {
+            const uint64_t key = keys[s0 + t];
+            int rank = 0;
+            for (int j = 0; j < cnt; ++j) rank += keys[s0 + j] < key;
+            write_sorted<T>(D, s0 + rank, key);
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1525,8 +1558,8 @@ static hipError_t bin_and_sort_t(Batch &b)
                        plan_ptr(b, kPlanCells));
     hipLaunchKernelGGL(k_scatter<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
                        plan_ptr(b, kPlanAtoms));
-    hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
-                       plan_ptr(b, kPlanAtoms));
+    hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanCell1)), dim3(256), 0, b.stream, b.d_desc,
+                       plan_ptr(b, kPlanCell1));
     timer_end(b, "bin", b.stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? hipEventRecord(b.ev_bin, b.stream) : e;

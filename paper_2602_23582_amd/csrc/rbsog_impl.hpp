@@ -110,7 +110,7 @@ struct SysStep {
 };
 
 // Plans: one entry (system index, block index within the system) per workgroup.
-enum PlanKind { kPlanAtoms, kPlanCells, kPlanScan, kPlanPair, kPlanSk, kPlanReduce, kNumPlans };
+enum PlanKind { kPlanAtoms, kPlanCells, kPlanScan, kPlanPair, kPlanSk, kPlanReduce, kPlanCell1, kNumPlans };
 
 struct Timer {
     std::string name;

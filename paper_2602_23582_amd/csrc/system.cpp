@@ -563,6 +563,7 @@ static int build_plans(Batch &b, std::string &err)
         len[kPlanPair] += (s->n + kPairWave - 1) / kPairWave + s->ncells;
         len[kPlanSk] += (s->n + kSkChunk - 1) / kSkChunk;
         len[kPlanReduce] += s->prm.P + 2;
+        len[kPlanCell1] += s->ncells;
     }
     int64_t total = 0;
     for (int k = 0; k < kNumPlans; ++k) {
@@ -602,6 +603,7 @@ static int build_plans(Batch &b, std::string &err)
         put(kPlanScan, s, (y->ncells + kScanBlock - 1) / kScanBlock);
         put(kPlanSk, s, (y->n + kSkChunk - 1) / kSkChunk);
         put(kPlanReduce, s, y->prm.P + 2);
+        put(kPlanCell1, s, y->ncells);
     }
     // pair blocks grouped by the form of the SOG kernels (one launch per form)
     for (int f = 0; f < kNumForms; ++f) {
