@@ -227,6 +227,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-valu-probe", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="run the step as a batch of one replaying a captured HIP graph")
     ap.add_argument("--served", type=int, default=256, help="requests of the served-stream run (0: skip)")
     ap.add_argument("--served-pool-mib", type=int, default=1024)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -250,29 +252,56 @@ def main():
                for k in range(3))
     fx, fy, fz = (torch.empty_like(x) for _ in range(3))
     L0 = np.asarray(d["L"], dtype=np.float64)
-    ctx = rbsog.Context(d["q"], L0, d["rc"], P=P, seed=args.seed, precision=rbsog.PREC_FP32C)
+    if args.graph:
+        # one system as a batch of one; the step's launches replay a captured graph
+        ctx = rbsog.Batch([dict(q=d["q"], box=L0, rc=d["rc"], P=P, seed=args.seed)])
+        ctx.set_options(schedule=rbsog.SCHED_STATIC, graph=True)
+        last = {}
 
-    def step(s):
-        target = L0 * (1.0 + 0.001 * (s % 10))
-        mu = target / ctx.box
-        ctx.rescale(mu, x, y, z)
-        ctx.sample_modes(s, ctx.box)
-        ctx.force_virial(x, y, z, fx, fy, fz, energy=False)
-        return ctx.pressure()
+        def step(s):
+            target = L0 * (1.0 + 0.001 * (s % 10))
+            mu = target / ctx.boxes[0]
+            ctx.rescale(mu[None, :], x, y, z)
+            Pb, _, inf = ctx.step(s, ctx.boxes, x, y, z, fx, fy, fz, energy=False)
+            last["info"] = inf[0]
+            return Pb[0]
+    else:
+        ctx = rbsog.Context(d["q"], L0, d["rc"], P=P, seed=args.seed, precision=rbsog.PREC_FP32C)
+
+        def step(s):
+            target = L0 * (1.0 + 0.001 * (s % 10))
+            mu = target / ctx.box
+            ctx.rescale(mu, x, y, z)
+            ctx.sample_modes(s, ctx.box)
+            ctx.force_virial(x, y, z, fx, fy, fz, energy=False)
+            return ctx.pressure()
 
     for s in range(args.warmup):
         step(s)
     torch.cuda.synchronize()
-    ctx.set_timing(True)
+    if not args.graph:
+        ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.warmup, args.warmup + args.steps):
         step(s)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    timing = ctx.get_timing()
-    info = ctx.step_info()
-    ctx.set_timing(False)
+    if args.graph:
+        # per-kernel times from a few eager steps of the same launches (events
+        # cannot be recorded inside the replayed graph)
+        ctx.set_timing(True)
+        for s in range(args.warmup + args.steps, args.warmup + args.steps + 3):
+            step(s)
+        torch.cuda.synchronize()
+        timing = ctx.get_timing()
+        ctx.set_timing(False)
+        inf = last["info"]
+        info = dict(nd=int(inf[0]), acc_r=int(inf[1]), acc_nr=int(inf[2]), npairs=int(inf[3]))
+    else:
+        timing = ctx.get_timing()
+        info = ctx.step_info()
+        ctx.set_timing(False)
     T = t1 - t0
     ms_step = 1e3 * T / args.steps
     value = n * args.steps / T
@@ -309,7 +338,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "n_atoms": n, "box": L0.tolist(), "rc": d["rc"], "P": P,
                    "precision": "FP32C (FP32 arithmetic, FP64 partial sums and reductions)",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "api": "batch of one, HIP graph" if args.graph else "context"},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
         "distinct_modes": info["nd"], "valu_probe": probe,
     }

@@ -78,9 +78,9 @@ void destroy(rbsog_ctx *c)
 // grid for the current box: more cells than allocated re-carve the cell part
 int refresh_cells(rbsog_ctx *c)
 {
-    void *before = c->sys.cell_mem;
-    RB_TRY(rbsog::system_ensure_cells(c->sys, c->err));
-    if (c->sys.cell_mem != before) c->batch.desc_dirty = true;
+    bool recarved = false;
+    RB_TRY(rbsog::system_ensure_cells(c->sys, c->err, &recarved));
+    if (recarved) c->batch.desc_dirty = true;
     return RBSOG_OK;
 }
 

@@ -141,9 +141,9 @@ int step_impl(rbsog_batch *b, const int64_t *host_steps, const double *host_boxe
     for (size_t s = 0; s < S; ++s) {
         System &y_ = *b->systems[s];
         rbsog::system_set_box(y_, host_boxes + 3 * s);
-        void *before = y_.cell_mem;
-        RB_TRY(rbsog::system_ensure_cells(y_, b->err));
-        if (y_.cell_mem != before) bt.desc_dirty = true;
+        bool recarved = false;
+        RB_TRY(rbsog::system_ensure_cells(y_, b->err, &recarved));
+        if (recarved) bt.desc_dirty = true;
         rbsog::SysStep &t = y_.stp;
         t.step = static_cast<uint32_t>(host_steps[s]);
         t.x = x + b->off[s];

@@ -227,7 +227,10 @@ void system_carve_atoms(System &s, void *mem);
 void system_carve_cells(System &s, void *mem, int64_t ncells_cap);
 // Allocate (own_mem) or re-carve the buffers; grows the cell part to the grid.
 int system_alloc(System &s, std::string &err);
-int system_ensure_cells(System &s, std::string &err);
+// Grows the cell part when the grid outgrows it; *recarved tells whether the
+// cell arrays moved (the device descriptor must then be uploaded again: the
+// allocator may hand back the old address, so comparing addresses is not enough).
+int system_ensure_cells(System &s, std::string &err, bool *recarved = nullptr);
 void system_free(System &s);
 // Upload the charges (FP32 or FP64 copy) on the stream.
 int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err);

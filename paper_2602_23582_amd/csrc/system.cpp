@@ -344,8 +344,9 @@ int system_alloc(System &s, std::string &err)
     return system_ensure_cells(s, err);
 }
 
-int system_ensure_cells(System &s, std::string &err)
+int system_ensure_cells(System &s, std::string &err, bool *recarved)
 {
+    if (recarved) *recarved = false;
     if (s.ncells <= s.ncells_cap) return RBSOG_OK;
     if (!s.own_mem && s.cell_mem) {
         err = "cell grid outgrew the memory reserved at admission";
@@ -362,6 +363,7 @@ int system_ensure_cells(System &s, std::string &err)
         return RBSOG_ENOMEM;
     }
     system_carve_cells(s, cm, s.ncells);
+    if (recarved) *recarved = true;
     return RBSOG_OK;
 }
 

@@ -335,7 +335,10 @@ class Batch:
             msg = load().rbsog_batch_last_error(self._h)
             raise RBSOGError(rc_, f"{what}: {msg.decode() if msg else ''}")
 
-    def step(self, steps, boxes, x, y, z, fx, fy, fz, results=True):
+    def step(self, steps, boxes, x, y, z, fx, fy, fz, results=True, energy=True):
+        """One step of every system.  With results, returns the pressure
+        tensors, the energies (zeros unless energy) and the counters of
+        rbsog_step_info per system; the energy sum runs only when asked for."""
         steps = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.int64), (self.nsys,)))
         boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(self.nsys, 3)
         if not results:
@@ -346,7 +349,8 @@ class Batch:
         U = np.zeros((self.nsys, 3))
         info = np.zeros((self.nsys, 4), dtype=np.int64)
         self._check(load().rbsog_batch_step(self._h, _pi64(steps), _pd(boxes), _ptr(x), _ptr(y), _ptr(z), _ptr(fx),
-                                            _ptr(fy), _ptr(fz), _pd(P), _pd(U), _pi64(info)), "rbsog_batch_step")
+                                            _ptr(fy), _ptr(fz), _pd(P), _pd(U) if energy else None, _pi64(info)),
+                    "rbsog_batch_step")
         return P.reshape(self.nsys, 3, 3), U, info
 
     def rescale(self, mu, x, y, z):

@@ -205,6 +205,28 @@ def test_mixed_term_counts_keep_each_system_exact(torch, rb):
 # served form
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_grid_growth_matches_fresh_batches(torch, rb, graph):
+    """Boxes that grow past cell boundaries re-carve the cell arrays inside a
+    batch (eager and graph replay); each step equals a fresh batch at that box."""
+    d = W.water_box(n_mol=8000, seed=21)
+    spec = dict(q=d["q"], box=d["L"], rc=d["rc"], P=100, seed=9)
+    b = rb.Batch([spec])
+    b.set_options(graph=graph)
+    for k, g in enumerate([1.0, 1.15, 1.30, 1.0, 1.45, 1.15]):
+        box = d["L"] * g
+        print(f"graph {graph} growth {g}", flush=True)
+        (x, y, z), f = _concat(torch, [dict(pos=d["pos"] * g)])
+        P, _, _ = b.step(k, box[None, :], x, y, z, *f)
+        fresh = rb.Batch([dict(spec, box=box)])
+        (x2, y2, z2), f2 = _concat(torch, [dict(pos=d["pos"] * g)])
+        P2, _, _ = fresh.step(k, box[None, :], x2, y2, z2, *f2)
+        fresh.close()
+        assert np.array_equal(_split(torch, f, [0, len(d["q"])])[0], _split(torch, f2, [0, len(d["q"])])[0])
+        assert np.array_equal(P, P2)
+    b.close()
+
+
 def _requests(k=6, seed=3):
     sizes, seeds = W.served_stream(k, seed=seed, n_max=12_000)
     out = []

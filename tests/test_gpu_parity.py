@@ -240,6 +240,25 @@ def test_bitwise_reproducible(torch, rb):
     assert out[0]["U"] == out[1]["U"]
 
 
+GROWTH = [1.0, 1.15, 1.30, 1.0, 1.45, 1.15]  # 6, 7, 8, 6, 9, 7 cells per edge at rc 10
+
+
+def test_grid_growth_reuploads_cell_arrays(torch, rb):
+    """A box that grows past a cell boundary re-carves the cell arrays; every
+    step must equal a fresh context built at that box (bit for bit)."""
+    d = W.water_box(n_mol=8000, seed=21)
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=9) as ctx:
+        for k, g in enumerate(GROWTH):
+            box = d["L"] * g
+            pos = d["pos"] * g
+            print(f"growth {g}: box {box[0]:.2f}", flush=True)
+            a = gpu_step(torch, ctx, pos, k, box)
+            with rb.Context(d["q"], box, d["rc"], P=100, seed=9) as fresh:
+                b = gpu_step(torch, fresh, pos, k, box)
+            assert np.array_equal(a["F"], b["F"]), f"growth {g}: forces differ from a fresh context"
+            assert np.array_equal(a["P"], b["P"]), f"growth {g}: pressure differs from a fresh context"
+
+
 def test_state_errors(torch, rb):
     d = W.c1_lattice()
     x, y, z = (_dev(torch, d["pos"][:, k]) for k in range(3))
