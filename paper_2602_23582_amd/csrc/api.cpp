@@ -291,8 +291,16 @@ int rbsog_debug_cells(rbsog_ctx *c, int32_t *host_cell, int32_t host_ncell[3])
     if (!c) return RBSOG_EINVAL;
     if (c->state < 2) return fail(c, RBSOG_ESTATE, "no evaluation yet");
     HIP_TRY(c, hipStreamSynchronize(c->batch.stream));
-    if (host_cell)
+    if (host_cell) {
         HIP_TRY(c, hipMemcpy(host_cell, c->sys.desc.cell, c->sys.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        // the device numbers cells z fastest; the interface reports x fastest
+        const int nx = c->sys.nc[0], ny = c->sys.nc[1], nz = c->sys.nc[2];
+        for (int64_t i = 0; i < c->sys.n; ++i) {
+            const int id = host_cell[i];
+            const int cz = id % nz, cy = (id / nz) % ny, cx = id / (nz * ny);
+            host_cell[i] = cx + nx * (cy + ny * cz);
+        }
+    }
     if (host_ncell)
         for (int d = 0; d < 3; ++d) host_ncell[d] = c->sys.nc[d];
     return RBSOG_OK;

@@ -479,14 +479,18 @@ __global__ __launch_bounds__(kAtomBlock) void k_fix(const SysDesc *__restrict__ 
         }
         c[d] = static_cast<uint32_t>((static_cast<uint64_t>(top) * static_cast<uint32_t>(nc[d])) >> 32);
     }
-    const int32_t id = static_cast<int32_t>(c[0] + static_cast<uint32_t>(nc[0]) * (c[1] + static_cast<uint32_t>(nc[1]) * c[2]));
+    // z fastest: the cells of one column (cx, cy) are consecutive, so a column's
+    // atoms are one range of the sorted arrays, ordered by z
+    const int32_t id = static_cast<int32_t>(c[2] + static_cast<uint32_t>(nc[2]) * (c[1] + static_cast<uint32_t>(nc[1]) * c[0]));
     if (active) gp(D.cell)[i] = id;
     aggregated_increment<false>(D.count, id, active);
 }
 
 // Two-level exclusive scan of the per-cell counts (and of the per-cell number
 // of 64-atom pair blocks) of each system: kScanBlock cells per workgroup, at
-// most 1024 workgroups per system.
+// most 1024 workgroups per system.  Pair blocks tile segments of g cells of a
+// column (the cells cz = 0, g, 2g, ... own the blocks of their segment), so a
+// segment's last block is the only one with idle lanes.
 __device__ inline void block_scan_256(int *s_a, int tid)
 {
     // Hillis-Steele inclusive scan over 256 ints in shared memory
@@ -504,7 +508,9 @@ __global__ __launch_bounds__(256) void k_scan_local(const SysDesc *__restrict__ 
     __shared__ int s_a[256], s_b[256];
     const int2 e = plan[blockIdx.x];
     const SysDesc &D = desc[e.x];
-    const int64_t m = stp[e.x].ncells;
+    const SysStep &St = stp[e.x];
+    const int64_t m = St.ncells;
+    const int nz = St.nc[2], g = St.g;
     const int tid = threadIdx.x;
     const int64_t base = e.y * static_cast<int64_t>(kScanBlock) + 4 * tid;
     int va[4], vb[4], ta = 0, tb = 0;
@@ -512,8 +518,16 @@ __global__ __launch_bounds__(256) void k_scan_local(const SysDesc *__restrict__ 
         const int64_t i = base + k;
         const int c = i < m ? D.count[i] : 0;
         va[k] = c;
-        vb[k] = (c + kPairWave - 1) / kPairWave;
-        if (i < m) D.nblk[i] = vb[k];
+        vb[k] = 0;
+        if (i < m) {
+            const int cz = static_cast<int>(i % nz);
+            if (cz % g == 0) {
+                int seg = c;
+                for (int t = 1; t < g && cz + t < nz; ++t) seg += D.count[i + t];
+                vb[k] = (seg + kPairWave - 1) / kPairWave;
+            }
+            D.nblk[i] = vb[k];
+        }
         ta += va[k];
         tb += vb[k];
     }
@@ -692,17 +706,20 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
 // Short-range pair kernel
 // ----------------------------------------------------------------------------
 //
-// One wavefront owns up to 64 atoms of one cell (a "pair block"; cells are
-// sorted by z, so a block is a z-slab of its cell) and walks the atoms of the
-// 27 neighbouring cells (full shell: every pair is evaluated from both sides,
-// so no atomics and a fixed summation order).  The neighbours are contiguous
-// ranges of the sorted arrays: with at least five cells per edge, one per
-// neighbour cell cut to the block's z-window; otherwise one per row.  They are
-// staged kChunk at a time in LDS; every lane tests every staged candidate
-// against r_c and keeps one hit bit per candidate; then every lane walks its
-// hit bits, reading partner records from LDS, so the expensive SOG kernel runs
-// on wavefronts whose lanes all hold a real pair until the lane with the
-// fewest partners in the chunk is done.
+// One wavefront owns up to 64 atoms of one pair block: a z-slab of a segment
+// of g cells of one column (cells are numbered z fastest and sorted by z, so
+// a segment is a z-sorted range of the sorted arrays and only its last block
+// has idle lanes).  It walks the atoms of the neighbouring cells (full shell:
+// every pair is evaluated from both sides, so no atomics and a fixed
+// summation order).  The neighbours are contiguous ranges of the sorted
+// arrays: with at least five cells per edge (FP32), each of the 9 neighbour
+// columns cut to the block's z-window; otherwise a run of cells per
+// neighbour column.  They are staged kChunk at a time in LDS; every lane
+// tests every staged candidate against r_c and keeps one hit bit per
+// candidate; then every lane walks its hit bits, reading partner records
+// from LDS, so the expensive SOG kernel runs on wavefronts whose lanes all
+// hold a real pair until the lane with the fewest partners in the chunk is
+// done.
 
 #ifndef RBSOG_PAIR_CHUNK
 #define RBSOG_PAIR_CHUNK 128
@@ -714,12 +731,13 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
 #define RBSOG_FAST_FILTER 1
 #endif
 constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round
-constexpr int kMaxRanges = 27;  // one per neighbour cell (fast path) or per row run (exact path)
+constexpr int kMaxRanges = 27;  // at most two per neighbour column (a run split at the periodic seam)
 static_assert(kChunk % 32 == 0 && kChunk % 4 == 0, "pair tiling");
 
 template <class T>
 struct PairAcc {
     using real = typename T::real;
+    // sums over partners j of q_j-weighted terms (the common q_i is applied once per chunk)
     real fx = 0, fy = 0, fz = 0, vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0, u = 0;
     int n = 0;  // pairs inside rc
 };
@@ -823,19 +841,21 @@ __device__ inline void displacement(const typename T::Rec &ri, const typename T:
 // The SOG short-range kernels of one pair: N~(r) = 1/r^3 - sum wt_l e_l for
 // the force and the virial (eqs. force_SOG, P_short; 2 w_l/s_l^2 = wt_l) and
 // N(r) = 1/r - sum w_l e_l for the energy (eq. U_short), e_l = exp(-r^2/s_l^2),
-// the energy only when E.  A listed pair farther than rc (possible only
-// through the padded fast filter) contributes nothing.
+// the energy only when E.  Every lane of the wavefront runs it; a lane with no
+// pair this round (active false) and a listed pair farther than rc (possible
+// only through the padded fast filter) contribute nothing.  The terms carry
+// q_j only; the caller multiplies the sums by q_i.
 template <class T, int M, bool E>
-__device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Rec &rj, typename T::real sx,
-                                 typename T::real sy, typename T::real sz, typename T::real rc2,
-                                 const Weights<T, M> &W, PairAcc<T> &acc)
+__device__ __forceinline__ void pair_eval(const typename T::Rec &ri, const typename T::Rec &rj, bool active,
+                                          typename T::real sx, typename T::real sy, typename T::real sz,
+                                          typename T::real rc2, const Weights<T, M> &W, PairAcc<T> &acc)
 {
     using real = typename T::real;
     real dx, dy, dz;
     displacement<T>(ri, rj, sx, sy, sz, dx, dy, dz);
     // one fixed evaluation order, so a pair is inside from both of its atoms
     const real r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    const bool inside = (r2 < rc2) & (r2 > static_cast<real>(0));  // the atom itself is listed by the fast filter
+    const bool inside = active & (r2 < rc2) & (r2 > static_cast<real>(0));  // the atom itself is listed too
     real swt = 0, sw = 0, rinv;
     if constexpr (sizeof(real) == 4) rinv = __builtin_amdgcn_rsqf(r2);
     else rinv = 1.0 / sqrt(r2);
@@ -858,9 +878,8 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
         }
     }
     // the mask selects the products (r = 0 gives rinv = inf for the atom itself)
-    const real qq = ri.q * rj.q;
     acc.n += inside;
-    const real f = inside ? qq * (rinv * rinv * rinv - swt) : static_cast<real>(0);
+    const real f = inside ? rj.q * (rinv * rinv * rinv - swt) : static_cast<real>(0);
     const real fdx = f * dx, fdy = f * dy, fdz = f * dz;
     acc.fx += fdx;
     acc.fy += fdy;
@@ -871,7 +890,19 @@ __device__ inline void pair_eval(const typename T::Rec &ri, const typename T::Re
     acc.vxy += fdx * dy;
     acc.vxz += fdx * dz;
     acc.vyz += fdy * dz;
-    if constexpr (E) acc.u += inside ? qq * (rinv - sw) : static_cast<real>(0);
+    if constexpr (E) acc.u += inside ? rj.q * (rinv - sw) : static_cast<real>(0);
+}
+
+// m <- 2 m + (t < thr): one compare into VCC and one add with carry (the
+// compiler's own form of this step takes three instructions)
+__device__ __forceinline__ uint32_t push_hit(uint32_t m, float t, float thr)
+{
+    uint32_t r;
+    asm("v_cmp_lt_f32_e32 vcc, %1, %2\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
+        : "=v"(r)
+        : "v"(t), "v"(thr), "v"(m)
+        : "vcc");
+    return r;
 }
 
 template <class T>
@@ -914,25 +945,29 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     }
     const RB_GLOBAL int32_t *start = gp(D.start);
     const int2 cb = gload(D.blocks + b);
+    // the block's segment: cells c .. c + gs - 1 of one column
     const int c = cb.x;
-    const int cs = start[c], ce = start[c + 1];
+    const int cz = c % nz, cy = (c / nz) % ny, cx = c / (nz * ny);
+    const int gs = min(St.g, nz - cz);
+    const int cs = start[c], ce = start[c + gs];
     const int i = cs + cb.y * kPairWave + lane;
     const bool valid = i < ce;
     Rec ri{};
     if (valid) ri = gload(rec + i);
     const real rc2_lane = valid ? rc2 : static_cast<real>(-1);  // padding lanes find no partner
     // Fast filter (FP32, at least 5 cells per edge): candidates are tested in
-    // float coordinates relative to the first atom of the block, o.  With five
-    // or more cells per edge, i and every candidate lie within two cells of o,
-    // well inside half a box, so differences of relative coordinates are
-    // minimum-image displacements.  The test is |r_j|^2 - 2 r_i.r_j <
-    // rcf^2 - |r_i|^2 (three FMAs); with |r| below 45 A its rounding error
-    // stays under 1e-3 A^2, far inside the 2 rc 1e-3 A^2 that padding the
-    // radius by 1e-3 A adds.  The atom itself passes this test; the pair
-    // evaluation applies the exact test (0 < r^2 < rc^2) on fixed-point
-    // differences.
+    // float coordinates relative to the first atom of the block, o.  The
+    // block lies in one column and spans at most g cells in z, candidates lie
+    // within the cutoff of it, and the grid has nz >= 2 g + 3 and at least 5
+    // cells along x and y, so every candidate is within half a box of o and
+    // differences of relative coordinates are minimum-image displacements.
+    // The test is |r_j|^2 - 2 r_i.r_j < rcf^2 - |r_i|^2 (three FMAs); with
+    // |r| below 45 A its rounding error stays under 1e-3 A^2, far inside the
+    // 2 rc 1e-3 A^2 that padding the radius by 1e-3 A adds.  The atom itself
+    // passes this test; the pair evaluation applies the exact test
+    // (0 < r^2 < rc^2) on fixed-point differences.
     constexpr bool kIsF32 = sizeof(real) == 4;
-    const bool fast = RBSOG_FAST_FILTER && kIsF32 && nx >= 5 && ny >= 5 && nz >= 5;
+    const bool fast = RBSOG_FAST_FILTER && kIsF32 && St.fast;
     const fix ox = static_cast<fix>(__shfl(static_cast<long long>(ri.x), 0, 64));
     const fix oy_ = static_cast<fix>(__shfl(static_cast<long long>(ri.y), 0, 64));
     const fix oz_ = static_cast<fix>(__shfl(static_cast<long long>(ri.z), 0, 64));
@@ -942,47 +977,55 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const float zi = static_cast<float>(static_cast<sfix>(ri.z - oz_)) * static_cast<float>(sz);
     const float ax = -2.0f * xi, ay = -2.0f * yi, az = -2.0f * zi;
     const float thr = valid ? rcf * rcf - (xi * xi + yi * yi + zi * zi) : -INFINITY;
-    const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
-    const int oy = ny >= 3 ? 1 : 0, oz = nz >= 3 ? 1 : 0;
 
     if (kIsF32 && fast) {
-        // The block's atoms are a slab of their cell, sorted by z, spanning
-        // [0, zext] in fixed point relative to o.  Each of the 27 neighbour
-        // cells (distinct: at least 5 per edge) is cut to the atoms whose z
-        // lies within the padded cutoff of that slab; inside a cell the
-        // relative z is monotonic (no cell straddles the periodic seam and
-        // neighbours are within two cells of o), so the cut is a binary search.
+        // The block's atoms are sorted by z and span [0, zext] in fixed point
+        // relative to o.  Each of the 9 neighbour columns (distinct: at least
+        // 5 cells per edge) is a z-sorted range of the sorted arrays; it is
+        // cut by binary search to the atoms whose z lies in the padded
+        // cutoff window [oz - reach, oz + zext + reach], one range, or two
+        // where the window wraps around the periodic seam.
         const int nvalid = min(kPairWave, ce - cs - cb.y * kPairWave);
         const sfix rzi = static_cast<sfix>(ri.z - oz_);
         const sfix zext = __shfl(rzi, nvalid - 1, 64);
-        const int64_t reach = static_cast<int64_t>(ceil(static_cast<double>(rcf) / St.L[2] * 4294967296.0)) + 2;
-        const int64_t zlo = -reach, zhi = static_cast<int64_t>(zext) + reach;
-        if (lane < 27) {
-            const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
-            const int jx = (cx + dx + nx) % nx, jy = (cy + dy + ny) % ny, jz = (cz + dz + nz) % nz;
-            const int c2 = jx + nx * (jy + ny * jz);
-            int lo = start[c2], hi = start[c2 + 1];
+        const uint32_t reach =
+            static_cast<uint32_t>(ceil(static_cast<double>(rcf) / St.L[2] * 4294967296.0)) + 2u;
+        const uint32_t za = static_cast<uint32_t>(oz_) - reach;
+        const uint32_t zb = static_cast<uint32_t>(oz_) + static_cast<uint32_t>(zext) + reach;
+        if (lane < 9) {
+            const int dx = lane % 3 - 1, dy = lane / 3 - 1;
+            const int jx = (cx + dx + nx) % nx, jy = (cy + dy + ny) % ny;
+            const int col = nz * (jy + ny * jx);
+            const int lo = start[col], hi = start[col + nz];
             const RB_GLOBAL uint32_t *zw = reinterpret_cast<const RB_GLOBAL uint32_t *>(gp(rec));
-            auto zrel = [&](int j) {
-                return static_cast<int64_t>(static_cast<int32_t>(static_cast<uint32_t>(zw[4 * j + 2] - static_cast<uint32_t>(oz_))));
+            // first atom of [l, h) with z >= v (above) or z > v (!above)
+            auto search = [&](int l, int h, uint32_t v, bool above) {
+                while (l < h) {
+                    const int m = (l + h) >> 1;
+                    const uint32_t zm = zw[4 * m + 2];
+                    if (above ? zm < v : zm <= v) l = m + 1;
+                    else h = m;
+                }
+                return l;
             };
-            // first atom at or above zlo, then first atom above zhi
-            int a = lo, b = hi;
-            while (a < b) {
-                const int m = (a + b) >> 1;
-                if (zrel(m) < zlo) a = m + 1;
-                else b = m;
+            int b0, e0, b1, e1;
+            if (za <= zb) {
+                b0 = search(lo, hi, za, true);
+                e0 = search(b0, hi, zb, false);
+                b1 = e1 = lo;
+            } else {
+                b0 = search(lo, hi, za, true);
+                e0 = hi;
+                b1 = lo;
+                e1 = search(lo, b0, zb, false);
             }
-            lo = a;
-            b = hi;
-            while (a < b) {
-                const int m = (a + b) >> 1;
-                if (zrel(m) <= zhi) a = m + 1;
-                else b = m;
-            }
-            hi = a;
-            sh.beg[lane] = lo;
-            sh.pre[lane + 1] = hi - lo;  // length for now
+            sh.beg[2 * lane] = b0;
+            sh.pre[2 * lane + 1] = e0 - b0;  // lengths for now
+            sh.beg[2 * lane + 1] = b1;
+            sh.pre[2 * lane + 2] = e1 - b1;
+        } else if (lane >= 18 && lane < kMaxRanges) {
+            sh.beg[lane] = 0;
+            sh.pre[lane + 1] = 0;
         }
         __syncthreads();
         if (lane == 0) {
@@ -990,29 +1033,32 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
             for (int k = 0; k < kMaxRanges; ++k) sh.pre[k + 1] += sh.pre[k];
         }
     } else if (lane == 0) {
-        // exact path: one range per row (dy, dz), split where the x-run
-        // wraps; rows of a dimension with fewer than three cells are whole
+        // exact path: per neighbour column, the run of cells cz - 1 .. cz + gs
+        // (split where it wraps); a dimension with fewer than three cells is
+        // taken whole
+        const int ox = nx >= 3 ? 1 : 0, oy = ny >= 3 ? 1 : 0;
         int nr = 0;
         auto put = [&](int lo, int hi) {
             sh.beg[nr] = lo;
             sh.pre[nr + 1] = hi - lo;  // length for now, prefix sums below
             ++nr;
         };
-        for (int dz = -oz; dz <= oz; ++dz) {
-            const int jz = (cz + dz + nz) % nz;
+        for (int dx = -ox; dx <= ox; ++dx) {
+            const int jx = (cx + dx + nx) % nx;
             for (int dy = -oy; dy <= oy; ++dy) {
                 const int jy = (cy + dy + ny) % ny;
-                const int row = nx * (jy + ny * jz);
-                if (nx < 3) {
-                    put(start[row], start[row + nx]);
-                } else if (cx == 0) {
-                    put(start[row + nx - 1], start[row + nx]);
-                    put(start[row], start[row + 2]);
-                } else if (cx == nx - 1) {
-                    put(start[row + cx - 1], start[row + nx]);
-                    put(start[row], start[row + 1]);
+                const int col = nz * (jy + ny * jx);
+                const int z0 = cz - 1, z1 = cz + gs;  // inclusive
+                if (nz < 3 || z1 - z0 + 1 >= nz) {
+                    put(start[col], start[col + nz]);
+                } else if (z0 < 0) {
+                    put(start[col + nz - 1], start[col + nz]);
+                    put(start[col], start[col + z1 + 1]);
+                } else if (z1 >= nz) {
+                    put(start[col + z0], start[col + nz]);
+                    put(start[col], start[col + z1 - nz + 1]);
                 } else {
-                    put(start[row + cx - 1], start[row + cx + 2]);
+                    put(start[col + z0], start[col + z1 + 1]);
                 }
             }
         }
@@ -1090,7 +1136,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const float t = fmaf(c[k].x, ax, fmaf(c[k].y, ay, fmaf(c[k].z, az, c[k].w)));
-                        m = m + m + static_cast<uint32_t>(t < thr);
+                        m = push_hit(m, t, thr);
                     }
                 }
             } else {
@@ -1109,43 +1155,47 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
             sh.mask[w][lane] = m;
         }
 
-        // Evaluation: every lane takes its hits in increasing candidate order,
-        // two per round from its current word; lanes whose word is spent move
-        // to their next word (their own LDS entries, no barrier needed).
+        // Evaluation: every lane takes its hits from its current word in
+        // candidate order (the first candidate sits in the top bit), two per round; lanes whose word is spent move to their
+        // next word (their own LDS entries, no barrier needed).  Every lane
+        // runs both evaluations of a round (a wavefront issues them anyway),
+        // a lane without a hit masked off, so no branch splits the round.
         PairAcc<T> acc;
         int w = 0;
         uint32_t cur = words > 0 ? sh.mask[0][lane] : 0u;
         for (;;) {
-            for (;;) {
-                const bool need = cur == 0u && w + 1 < words;
-                if (!__any(need)) break;
-                if (need) {
+            bool adv = (cur == 0u) & (w + 1 < words);
+            while (__any(adv)) {
+                if (adv) {
                     ++w;
                     cur = sh.mask[w][lane];
                 }
+                adv = (cur == 0u) & (w + 1 < words);
             }
             if (!__any(cur != 0u)) break;
+            // a spent word gives slot 31, a valid record, masked off by active
             const bool a0 = cur != 0u;
-            const int k0 = a0 ? __builtin_clz(cur) : 0;
-            cur = a0 ? (cur & ~(0x80000000u >> k0)) : 0u;
+            const int k0 = __builtin_clz(cur | 1u);
+            cur &= ~(0x80000000u >> k0);
             const bool a1 = cur != 0u;
-            const int k1 = a1 ? __builtin_clz(cur) : 0;
-            cur = a1 ? (cur & ~(0x80000000u >> k1)) : 0u;
+            const int k1 = __builtin_clz(cur | 1u);
+            cur &= ~(0x80000000u >> k1);
             const Rec r0 = sh.tile[32 * w + k0], r1 = sh.tile[32 * w + k1];
-            if (a0) pair_eval<T, M, E>(ri, r0, sx, sy, sz, rc2, W, acc);
-            if (a1) pair_eval<T, M, E>(ri, r1, sx, sy, sz, rc2, W, acc);
+            pair_eval<T, M, E>(ri, r0, a0, sx, sy, sz, rc2, W, acc);
+            pair_eval<T, M, E>(ri, r1, a1, sx, sy, sz, rc2, W, acc);
         }
+        const double qi = ri.q;
         hits += acc.n;
-        fx += acc.fx;
-        fy += acc.fy;
-        fz += acc.fz;
-        v[0] += acc.vxx;
-        v[1] += acc.vyy;
-        v[2] += acc.vzz;
-        v[3] += acc.vxy;
-        v[4] += acc.vxz;
-        v[5] += acc.vyz;
-        uu += acc.u;
+        fx += qi * acc.fx;
+        fy += qi * acc.fy;
+        fz += qi * acc.fz;
+        v[0] += qi * acc.vxx;
+        v[1] += qi * acc.vyy;
+        v[2] += qi * acc.vzz;
+        v[3] += qi * acc.vxy;
+        v[4] += qi * acc.vxz;
+        v[5] += qi * acc.vyz;
+        uu += qi * acc.u;
         __syncthreads();
     }
     if (valid) {

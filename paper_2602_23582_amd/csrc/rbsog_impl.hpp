@@ -31,6 +31,7 @@ constexpr int kScanBlock = 1024;   // cells per workgroup of the local scan
 constexpr int64_t kMaxCells = int64_t(1024) * kScanBlock;  // cells per system (two-level scan)
 constexpr int kMaxTimed = 24;
 constexpr int kPolyDeg = 10;       // degree of the FP32C polynomial form of the SOG sums
+constexpr int kSuperCells = 4;     // most cells stacked in z into one pair-block segment
 
 // SOG tables read by the kernels (device memory, uniform loads).
 struct SogTables {
@@ -101,10 +102,12 @@ struct SysStep {
     double iL[3];         // 1/L, rounded once on the host
     double mu[3];         // scale factors of the next rescale
     double Sr, Snr;
-    int32_t nc[3];
+    int32_t nc[3];        // cells per edge; cell id = cz + nc[2] (cy + nc[1] cx), z fastest
     int32_t ncells;
     uint32_t step;
-    int32_t pad[3];
+    int32_t g;            // cells per pair-block segment along z (a column's cells cz = 0, g, 2g, ... start one)
+    int32_t fast;         // FP32 relative-coordinate filter over whole neighbour columns (needs 5+ cells per edge)
+    int32_t pad;
     const double *x, *y, *z;  // positions (device, system order)
     double *fx, *fy, *fz;     // forces (device, system order)
 };
