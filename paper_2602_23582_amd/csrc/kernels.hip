@@ -730,6 +730,9 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
 #ifndef RBSOG_FAST_FILTER
 #define RBSOG_FAST_FILTER 1
 #endif
+#ifndef RBSOG_REL_EVAL
+#define RBSOG_REL_EVAL 1
+#endif
 constexpr int kChunk = RBSOG_PAIR_CHUNK;     // candidates staged per round
 constexpr int kMaxRanges = 27;  // at most two per neighbour column (a run split at the periodic seam)
 static_assert(kChunk % 32 == 0 && kChunk % 4 == 0, "pair tiling");
@@ -772,6 +775,7 @@ __device__ inline void load_weights(Weights<T, M> &W, const SogTables *__restric
             W.pg[k] = tab->pg[k];
             W.pf[k] = tab->pf[k];
         }
+
     } else if constexpr (M == 0) {
         W.tab = tab;
         W.m = tab->M;
@@ -838,22 +842,20 @@ __device__ inline void displacement(const typename T::Rec &ri, const typename T:
     dz = fix_to_real(static_cast<sfix>(ri.z - rj.z), sz);
 }
 
-// The SOG short-range kernels of one pair: N~(r) = 1/r^3 - sum wt_l e_l for
-// the force and the virial (eqs. force_SOG, P_short; 2 w_l/s_l^2 = wt_l) and
-// N(r) = 1/r - sum w_l e_l for the energy (eq. U_short), e_l = exp(-r^2/s_l^2),
-// the energy only when E.  Every lane of the wavefront runs it; a lane with no
-// pair this round (active false) and a listed pair farther than rc (possible
-// only through the padded fast filter) contribute nothing.  The terms carry
-// q_j only; the caller multiplies the sums by q_i.
+// The SOG short-range kernels of one pair with displacement (dx, dy, dz) and
+// partner charge qj: N~(r) = 1/r^3 - sum wt_l e_l for the force and the virial
+// (eqs. force_SOG, P_short; 2 w_l/s_l^2 = wt_l) and N(r) = 1/r - sum w_l e_l
+// for the energy (eq. U_short), e_l = exp(-r^2/s_l^2), the energy only when E.
+// Every lane of the wavefront runs it; a lane with no pair this round (active
+// false) and a listed pair farther than rc (possible only through the padded
+// fast filter) contribute nothing.  The terms carry q_j only; the caller
+// multiplies the sums by q_i.
 template <class T, int M, bool E>
-__device__ __forceinline__ void pair_eval(const typename T::Rec &ri, const typename T::Rec &rj, bool active,
-                                          typename T::real sx, typename T::real sy, typename T::real sz,
-                                          typename T::real rc2, const Weights<T, M> &W, PairAcc<T> &acc)
+__device__ __forceinline__ void pair_eval_d(typename T::real dx, typename T::real dy, typename T::real dz,
+                                            typename T::real qj, bool active, typename T::real rc2,
+                                            const Weights<T, M> &W, PairAcc<T> &acc)
 {
     using real = typename T::real;
-    real dx, dy, dz;
-    displacement<T>(ri, rj, sx, sy, sz, dx, dy, dz);
-    // one fixed evaluation order, so a pair is inside from both of its atoms
     const real r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     const bool inside = active & (r2 < rc2) & (r2 > static_cast<real>(0));  // the atom itself is listed too
     real swt = 0, sw = 0, rinv;
@@ -879,7 +881,7 @@ __device__ __forceinline__ void pair_eval(const typename T::Rec &ri, const typen
     }
     // the mask selects the products (r = 0 gives rinv = inf for the atom itself)
     acc.n += inside;
-    const real f = inside ? rj.q * (rinv * rinv * rinv - swt) : static_cast<real>(0);
+    const real f = inside ? qj * (rinv * rinv * rinv - swt) : static_cast<real>(0);
     const real fdx = f * dx, fdy = f * dy, fdz = f * dz;
     acc.fx += fdx;
     acc.fy += fdy;
@@ -890,24 +892,48 @@ __device__ __forceinline__ void pair_eval(const typename T::Rec &ri, const typen
     acc.vxy += fdx * dy;
     acc.vxz += fdx * dz;
     acc.vyz += fdy * dz;
-    if constexpr (E) acc.u += inside ? rj.q * (rinv - sw) : static_cast<real>(0);
+    if constexpr (E) acc.u += inside ? qj * (rinv - sw) : static_cast<real>(0);
 }
 
-// m <- 2 m + (t < thr): one compare into VCC and one add with carry (the
-// compiler's own form of this step takes three instructions)
-__device__ __forceinline__ uint32_t push_hit(uint32_t m, float t, float thr)
+// A pair from fixed-point records: exact minimum-image displacement (integer
+// difference, then scaled), r^2 in one fixed evaluation order, so a pair is
+// inside from both of its atoms.
+template <class T, int M, bool E>
+__device__ __forceinline__ void pair_eval(const typename T::Rec &ri, const typename T::Rec &rj, bool active,
+                                          typename T::real sx, typename T::real sy, typename T::real sz,
+                                          typename T::real rc2, const Weights<T, M> &W, PairAcc<T> &acc)
 {
-    uint32_t r;
-    asm("v_cmp_lt_f32_e32 vcc, %1, %2\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
-        : "=v"(r)
-        : "v"(t), "v"(thr), "v"(m)
+    typename T::real dx, dy, dz;
+    displacement<T>(ri, rj, sx, sy, sz, dx, dy, dz);
+    pair_eval_d<T, M, E>(dx, dy, dz, rj.q, active, rc2, W, acc);
+}
+
+// m <- 16 m + the four bits (t_k < thr), t0 first: per candidate one compare
+// into VCC and one add with carry (the compiler's own form of this step takes
+// three instructions).  The t_k come from FMAs, whose results a following VALU
+// instruction may read at once.
+__device__ __forceinline__ uint32_t push_hits4(uint32_t m, float t0, float t1, float t2, float t3, float thr)
+{
+    asm("v_cmp_lt_f32_e32 vcc, %1, %5\n\t"
+        "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc\n\t"
+        "v_cmp_lt_f32_e32 vcc, %2, %5\n\t"
+        "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc\n\t"
+        "v_cmp_lt_f32_e32 vcc, %3, %5\n\t"
+        "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc\n\t"
+        "v_cmp_lt_f32_e32 vcc, %4, %5\n\t"
+        "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc"
+        : "+v"(m)
+        : "v"(t0), "v"(t1), "v"(t2), "v"(t3), "v"(thr)
         : "vcc");
-    return r;
+    return m;
 }
 
 template <class T>
 struct PairShared {
-    typename T::Rec tile[kChunk];
+    union {
+        typename T::Rec tile[kChunk];  // exact path: fixed-point records
+        float4 rtile[kChunk];          // fast path: (x, y, z) relative to the block origin, q
+    };
     float4 rel[kChunk];  // fast filter: coordinates relative to the block origin and their squared norm
     uint32_t mask[kChunk / 32][64];  // hit bits of each lane, one word per 32 candidates
     int pre[kMaxRanges + 1];  // flattened-neighbourhood offset of each range
@@ -930,6 +956,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const Rec *__restrict__ rec = static_cast<const Rec *>(D.rec);
     Weights<T, M> W;
     load_weights<T, M>(W, &D.tab);
+
     const int nx = St.nc[0], ny = St.nc[1], nz = St.nc[2];
     real sx, sy, sz, rc2;
     if constexpr (sizeof(real) == 4) {
@@ -963,11 +990,16 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     // differences of relative coordinates are minimum-image displacements.
     // The test is |r_j|^2 - 2 r_i.r_j < rcf^2 - |r_i|^2 (three FMAs); with
     // |r| below 45 A its rounding error stays under 1e-3 A^2, far inside the
-    // 2 rc 1e-3 A^2 that padding the radius by 1e-3 A adds.  The atom itself
-    // passes this test; the pair evaluation applies the exact test
-    // (0 < r^2 < rc^2) on fixed-point differences.
+    // 2 rc 1e-3 A^2 that padding the radius by 1e-3 A adds, so it never drops
+    // a pair inside rc.  The atom itself passes it; the pair evaluation
+    // applies the exact test 0 < r^2 < rc^2.
     constexpr bool kIsF32 = sizeof(real) == 4;
     const bool fast = RBSOG_FAST_FILTER && kIsF32 && St.fast;
+    // Fast-path pairs without the energy sum take their displacement from
+    // FP32 block-relative coordinates (two roundings of exact fixed-point
+    // offsets, about 1e-6 A); with the energy, whose close pairs (1/r) need
+    // it, from exact fixed-point differences.
+    constexpr bool kRelEval = kIsF32 && RBSOG_REL_EVAL && !E;
     const fix ox = static_cast<fix>(__shfl(static_cast<long long>(ri.x), 0, 64));
     const fix oy_ = static_cast<fix>(__shfl(static_cast<long long>(ri.y), 0, 64));
     const fix oz_ = static_cast<fix>(__shfl(static_cast<long long>(ri.z), 0, 64));
@@ -1099,18 +1131,25 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
             for (int step = 16; step >= 1; step >>= 1)
                 if (r + step < kMaxRanges && sh.pre[r + step] <= f) r += step;
             const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
-            sh.tile[k] = rj;
             if (fast) {
                 const float xj = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
                 const float yj = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
                 const float zj = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
                 sh.rel[k] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
+                if constexpr (kRelEval) sh.rtile[k] = make_float4(xj, yj, zj, static_cast<float>(rj.q));
+                else sh.tile[k] = rj;
+            } else {
+                sh.tile[k] = rj;
             }
         }
         // the filter reads whole 32-candidate words: padding candidates never pass
         const int words = (filled + 31) >> 5;
         if (fast)
-            for (int k = filled + lane; k < 32 * words; k += 64) sh.rel[k] = make_float4(0.f, 0.f, 0.f, INFINITY);
+            for (int k = filled + lane; k < 32 * words; k += 64) {
+                sh.rel[k] = make_float4(0.f, 0.f, 0.f, INFINITY);
+                // read (masked off) by lanes whose word is spent: keep it finite
+                sh.rtile[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         __syncthreads();
 
         // Filter: one hit bit per candidate, shifted in so that the first
@@ -1133,11 +1172,12 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
 #pragma unroll
                         for (int k = 0; k < 4; ++k) nb[k] = sh.rel[32 * w + 4 * (g + 1) + k];
                     }
+                    float t[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const float t = fmaf(c[k].x, ax, fmaf(c[k].y, ay, fmaf(c[k].z, az, c[k].w)));
-                        m = push_hit(m, t, thr);
+                        t[k] = fmaf(c[k].x, ax, fmaf(c[k].y, ay, fmaf(c[k].z, az, c[k].w)));
                     }
+                    m = push_hits4(m, t[0], t[1], t[2], t[3], thr);
                 }
             } else {
                 const int s_end = min(filled, 32 * w + 32);
@@ -1161,29 +1201,42 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         // runs both evaluations of a round (a wavefront issues them anyway),
         // a lane without a hit masked off, so no branch splits the round.
         PairAcc<T> acc;
-        int w = 0;
-        uint32_t cur = words > 0 ? sh.mask[0][lane] : 0u;
-        for (;;) {
-            bool adv = (cur == 0u) & (w + 1 < words);
-            while (__any(adv)) {
-                if (adv) {
-                    ++w;
-                    cur = sh.mask[w][lane];
+        auto walk = [&](auto rel_tag) {
+            constexpr bool kRel = decltype(rel_tag)::value;
+            int w = 0;
+            uint32_t cur = words > 0 ? sh.mask[0][lane] : 0u;
+            for (;;) {
+                bool adv = (cur == 0u) & (w + 1 < words);
+                while (__any(adv)) {
+                    if (adv) {
+                        ++w;
+                        cur = sh.mask[w][lane];
+                    }
+                    adv = (cur == 0u) & (w + 1 < words);
                 }
-                adv = (cur == 0u) & (w + 1 < words);
+                if (!__any(cur != 0u)) break;
+                // a spent word gives slot 31, a valid record, masked off by active
+                const bool a0 = cur != 0u;
+                const int k0 = __builtin_clz(cur | 1u);
+                cur &= ~(0x80000000u >> k0);
+                const bool a1 = cur != 0u;
+                const int k1 = __builtin_clz(cur | 1u);
+                cur &= ~(0x80000000u >> k1);
+                if constexpr (kRel) {
+                    // FP32 block-relative coordinates: the difference of two exact
+                    // minimum-image offsets from o, each rounded once to FP32
+                    const float4 t0 = sh.rtile[32 * w + k0], t1 = sh.rtile[32 * w + k1];
+                    pair_eval_d<T, M, E>(xi - t0.x, yi - t0.y, zi - t0.z, t0.w, a0, rc2, W, acc);
+                    pair_eval_d<T, M, E>(xi - t1.x, yi - t1.y, zi - t1.z, t1.w, a1, rc2, W, acc);
+                } else {
+                    const Rec r0 = sh.tile[32 * w + k0], r1 = sh.tile[32 * w + k1];
+                    pair_eval<T, M, E>(ri, r0, a0, sx, sy, sz, rc2, W, acc);
+                    pair_eval<T, M, E>(ri, r1, a1, sx, sy, sz, rc2, W, acc);
+                }
             }
-            if (!__any(cur != 0u)) break;
-            // a spent word gives slot 31, a valid record, masked off by active
-            const bool a0 = cur != 0u;
-            const int k0 = __builtin_clz(cur | 1u);
-            cur &= ~(0x80000000u >> k0);
-            const bool a1 = cur != 0u;
-            const int k1 = __builtin_clz(cur | 1u);
-            cur &= ~(0x80000000u >> k1);
-            const Rec r0 = sh.tile[32 * w + k0], r1 = sh.tile[32 * w + k1];
-            pair_eval<T, M, E>(ri, r0, a0, sx, sy, sz, rc2, W, acc);
-            pair_eval<T, M, E>(ri, r1, a1, sx, sy, sz, rc2, W, acc);
-        }
+        };
+        if (kIsF32 && fast) walk(std::integral_constant<bool, kRelEval>{});
+        else walk(std::false_type{});
         const double qi = ri.q;
         hits += acc.n;
         fx += qi * acc.fx;
