@@ -38,15 +38,20 @@ def _dev(torch, a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def gpu_step(torch, ctx, pos, step, box):
+def gpu_step(torch, ctx, pos, step, box, energy=True):
+    """One step; energy=False is the force + pressure call the benchmark times
+    (the FP32 fast path then takes pair displacements from block-relative
+    coordinates)."""
     x, y, z = (_dev(torch, pos[:, k]) for k in range(3))
     fx, fy, fz = (torch.empty_like(x) for _ in range(3))
     m_r, m_nr, S = ctx.sample_modes(step, box, return_modes=True)
-    e, v = ctx.force_virial(x, y, z, fx, fy, fz)
+    e, v = ctx.force_virial(x, y, z, fx, fy, fz, energy=energy)
     P, parts = ctx.pressure()
     F = torch.stack([fx, fy, fz], 1).cpu().numpy()
-    return dict(F=F, UN=e[0], UF=e[1], Uself=e[2], U=e[0] + e[1] - e[2], vir=v, P=P, PN=parts[0],
-                Pr=parts[1], Pnr=parts[2], m_r=m_r, m_nr=m_nr, Sr=S[0], Snr=S[1])
+    out = dict(F=F, P=P, PN=parts[0], Pr=parts[1], Pnr=parts[2], m_r=m_r, m_nr=m_nr, Sr=S[0], Snr=S[1], U=None)
+    if energy:
+        out.update(UN=e[0], UF=e[1], Uself=e[2], U=e[0] + e[1] - e[2], vir=v)
+    return out
 
 
 def oracle_step(orc, d, box, pos, P, seed, sys, step, variant=0, sample=None):
@@ -62,6 +67,11 @@ def check(g, o, tol, what=""):
     pn = np.linalg.norm(o["P"])
     pr = np.linalg.norm(g["P"] - o["P"]) / pn
     parts = {k: np.linalg.norm(g[k] - o[k]) / pn for k in ("PN", "Pr", "Pnr")}
+    if g["U"] is None:  # forces and pressure only
+        msg = f"{what}: F {fr:.2e} P {pr:.2e} parts {parts}"
+        print(msg, flush=True)
+        assert fr <= tol and pr <= tol and all(v <= tol for v in parts.values()), msg
+        return
     ur = abs(g["U"] - o["U"]) / abs(o["U"])
     un = abs(g["UN"] - o["UN"]) / abs(o["U"])
     uf = abs(g["UF"] - o["UF"]) / abs(o["U"])
@@ -169,28 +179,30 @@ def test_fp32c_lattice(torch, rb, orc, variant, form):
             check(g, o, TOL_FP32C, f"fp32c lattice v{variant} form {form} step {step}")
 
 
+@pytest.mark.parametrize("energy", [True, False])
 @pytest.mark.parametrize("form", FORMS)
-def test_fp32c_water_30k(torch, rb, orc, form):
+def test_fp32c_water_30k(torch, rb, orc, form, energy):
     """10,000 three-site molecules at 1 g/cm^3 (L = 66.9 A), rc 10, P 100."""
     d = W.water_box()
     with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=2, flags=form) as ctx:
         for step in range(3):
             box = W.rescale_schedule(d["L"], step)
             pos = d["pos"] * (box / d["L"])
-            g = gpu_step(torch, ctx, pos, step, box)
+            g = gpu_step(torch, ctx, pos, step, box, energy=energy)
             o = oracle_step(orc, d, box, pos, 100, 2, 0, step)
-            check(g, o, TOL_FP32C, f"water form {form} step {step}")
+            check(g, o, TOL_FP32C, f"water form {form} energy {energy} step {step}")
 
 
+@pytest.mark.parametrize("energy", [True, False])
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("P", [100, 400])
-def test_fp32c_small_slab(torch, rb, orc, P, form):
+def test_fp32c_small_slab(torch, rb, orc, P, form, energy):
     """Anisotropic slab (60 x 60 x 150 A) with dipole layers, rc 12."""
     d = W.slab(Lx=60.0, n_water=8000, layer_grid=15, seed=6)
     with rb.Context(d["q"], d["L"], d["rc"], P=P, seed=31, flags=form) as ctx:
-        g = gpu_step(torch, ctx, d["pos"], 4, d["L"])
+        g = gpu_step(torch, ctx, d["pos"], 4, d["L"], energy=energy)
     o = oracle_step(orc, d, d["L"], d["pos"], P, 31, 0, 4)
-    check(g, o, TOL_FP32C, f"slab P={P}")
+    check(g, o, TOL_FP32C, f"slab P={P} form {form} energy {energy}")
 
 
 @pytest.mark.parametrize("n", [500, 2000, 6000])
@@ -293,8 +305,9 @@ def test_full_size_slab_sampled(torch, rb, orc, slab_1m):
     smp = np.sort(rng.choice(len(d["q"]), 400, replace=False))
     smp = np.concatenate([smp, np.arange(990000, 990040)])  # layer atoms
     with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=11) as ctx:
-        g = gpu_step(torch, ctx, d["pos"], 0, d["L"])
+        g = gpu_step(torch, ctx, d["pos"], 0, d["L"], energy=False)  # the benchmark's call
         modes, counts, rho = ctx.debug_modes()
+        ge = gpu_step(torch, ctx, d["pos"], 0, d["L"])
     p = orc.sog(d["rc"], row=2, M=10)
     m_r, m_nr, _ = orc.sample_modes(d["L"], p, 100, 11, 0, 0)
     assert np.array_equal(g["m_r"], m_r) and np.array_equal(g["m_nr"], m_nr)
@@ -312,7 +325,10 @@ def test_full_size_slab_sampled(torch, rb, orc, slab_1m):
     pn = np.linalg.norm(g["P"])
     assert np.linalg.norm(g["Pr"] - o["Pr"]) / pn < TOL_FP32C
     assert np.linalg.norm(g["Pnr"] - o["Pnr"]) / pn < TOL_FP32C
-    assert abs(g["UF"] - o["UF"]) / abs(o["UF"]) < TOL_FP32C
+    assert abs(ge["UF"] - o["UF"]) / abs(o["UF"]) < TOL_FP32C
+    fre = np.sqrt(((ge["F"][smp] - Fo) ** 2).sum() / (Fo ** 2).sum())
+    print("1M slab sampled force rel RMS with the energy sum", fre)
+    assert fre < TOL_FP32C
 
 
 @pytest.mark.slow
@@ -321,5 +337,7 @@ def test_full_size_slab_pressure(torch, rb, orc, slab_1m):
     d = slab_1m
     with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=11) as ctx:
         g = gpu_step(torch, ctx, d["pos"], 0, d["L"])
+        gf = gpu_step(torch, ctx, d["pos"], 0, d["L"], energy=False)
     o = oracle_step(orc, d, d["L"], d["pos"], 100, 11, 0, 0)
     check(g, o, TOL_FP32C, "1M slab full")
+    check(gf, o, TOL_FP32C, "1M slab full, no energy")
