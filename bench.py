@@ -217,6 +217,37 @@ def cpu_baseline(d, P, seed, sample_atoms):
             "seconds": t3 - t0}
 
 
+def npt_bench(torch, ctx, d, x, y, z, nsteps, force_ms):
+    """Langevin NPT steps (rbsog_npt_run, semi-isotropic for a box with Lx = Ly)
+    from the benchmark's final positions and box with thermal momenta; synthetic masses (16 for
+    negative sites, 1 for positive).  Reports time per NPT step and what it adds
+    to the force + pressure evaluation."""
+    from paper_2602_23582_amd import rbsog
+    q = d["q"]
+    m = np.where(q < 0, 16.0, 1.0)
+    rng = np.random.default_rng(7)
+    kT = 0.6
+    mom = rng.normal(size=(len(q), 3)) * np.sqrt(m * kT)[:, None]
+    xs, ys, zs = (t.clone() for t in (x, y, z))
+    px, py, pz = (torch.tensor(np.ascontiguousarray(mom[:, k]), dtype=torch.float64, device="cuda") for k in range(3))
+    L = np.asarray(ctx.box, dtype=np.float64)   # the box the positions were last rescaled to
+    coupling = rbsog.COUPLE_SEMI if L[0] == L[1] else rbsog.COUPLE_ANISO
+    ctx.npt_init(m, dt=0.002, kT=kT, gamma=1.0, gamma_box=0.5, box_mass=1e4, p_ext=0.0, coupling=coupling)
+    pbox = np.zeros(3)
+    box, pbox, _, _ = ctx.npt_run(xs, ys, zs, px, py, pz, 1000, 2, pbox)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    box, pbox, Pi, Pk = ctx.npt_run(xs, ys, zs, px, py, pz, 1002, nsteps, pbox)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # one call evaluates the starting state first: nsteps + 1 evaluations
+    ms = 1e3 * (t1 - t0) / nsteps
+    return {"steps": nsteps, "ms_per_npt_step": ms, "atom_steps_per_s": len(q) * nsteps / (t1 - t0),
+            "force_pressure_ms_per_step": force_ms, "coupling": "semi-isotropic" if coupling else "anisotropic",
+            "final_box": box.tolist(), "P_ins_diag": np.diag(Pi).tolist(), "P_kin_diag": np.diag(Pk).tolist(),
+            "note": "per call the starting state is evaluated once more (nsteps + 1 evaluations)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +261,7 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="run the step as a batch of one replaying a captured HIP graph")
     ap.add_argument("--served", type=int, default=256, help="requests of the served-stream run (0: skip)")
+    ap.add_argument("--npt-steps", type=int, default=20, help="Langevin NPT steps timed after the main run (0: skip)")
     ap.add_argument("--served-pool-mib", type=int, default=1024)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB (counter calibration)")
@@ -342,6 +374,9 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
         "distinct_modes": info["nd"], "valu_probe": probe,
     }
+    if args.npt_steps > 0 and not args.graph:
+        log(f"NPT integration: {args.npt_steps} steps")
+        out["npt"] = npt_bench(torch, ctx, d, x, y, z, args.npt_steps, ms_step)
     if args.served > 0:
         log(f"served stream: {args.served} requests")
         out["served"] = served_bench(args.served, 5, args.served_pool_mib << 20)

@@ -220,6 +220,72 @@ int rbsog_get_timing(rbsog_ctx *ctx, int32_t cap, int32_t *host_nk, char *host_n
 int rbsog_version(void);
 
 /* ========================================================================
+ * NPT integration around the evaluation (Algorithm 1 step 7): the Langevin
+ * equations of motion of eq. Langevin_NPT for a diagonal h, with the
+ * random-batch force and the instantaneous pressure
+ * P_ins = P_coul (this library) + sum_i p_i (x) p_i / (m_i V) (eq.
+ * K_U_Pins_re; the caller's other interactions are not included).
+ *
+ * One step of length dt is the symmetric splitting
+ *   B_h(dt/2) B(dt/2) A(dt/2) O(dt) A(dt/2) [evaluate F, P] B(dt/2) B_h(dt/2)
+ *   B_h: p^h_g += t G_g,  G_g = (V / L_g) sum_{mu in g} (P_ins,mumu - p_ext)
+ *                               - n_g kT / L_g
+ *   B:   p_i += t F_i
+ *   A:   L_g += t p^h_g / (n_g M); per axis a = L_new/L_old,
+ *        r_i <- a r_i + t p_i/m_i,  p_i <- p_i / a
+ *        (the exact flow of r' = p/m + (L'/L) r, p' = -(L'/L) p, L' = p^h/M
+ *        with p^h held fixed)
+ *   O:   p_i <- c p_i + sqrt((1 - c^2) kT m_i) xi_i,  c = exp(-gamma dt);
+ *        p^h_g <- c_h p^h_g + sqrt((1 - c_h^2) kT n_g M) xi_g,
+ *        c_h = exp(-gamma_box dt)
+ * where the box degrees of freedom g are the axes (RBSOG_COUPLE_ANISO), x+y
+ * and z (RBSOG_COUPLE_SEMI, needs Lx = Ly) or all three (RBSOG_COUPLE_ISO,
+ * needs a cube); coupled axes share one momentum and keep equal lengths.  The
+ * normals xi are Philox4x32-10 draws keyed by (seed, system_id) of the
+ * context with counter (atom, 16|17, step, system_id) for atoms and
+ * (0|1, 18, step, system_id) for the box.  Units are the caller's: F and P
+ * carry coulomb_k, kT is in the same energy unit, masses and dt consistent.
+ * ======================================================================== */
+
+#define RBSOG_COUPLE_ANISO 0 /* each axis its own box momentum               */
+#define RBSOG_COUPLE_SEMI 1  /* x and y share one (Lx = Ly), z its own        */
+#define RBSOG_COUPLE_ISO 2   /* one for all three axes (cubic box)            */
+
+typedef struct {
+    double dt;          /* time step                                              */
+    double kT;          /* thermal energy                                         */
+    double gamma;       /* particle friction (1 / time)                           */
+    double gamma_box;   /* box friction (1 / time)                                */
+    double box_mass;    /* M per box axis                                         */
+    double p_ext;       /* external pressure (energy / length^3)                  */
+    int32_t coupling;   /* RBSOG_COUPLE_*                                         */
+    int32_t reserved[7];
+} rbsog_npt_params;
+
+/*
+ * Attach the integrator to a context: parameters and the n masses
+ * (host_mass, caller order, all > 0).  Device memory: 56 B per atom.
+ * Errors: EINVAL for bad parameters or masses.
+ */
+int rbsog_npt_init(rbsog_ctx *ctx, const rbsog_npt_params *params, const double *host_mass);
+
+/*
+ * Advance nsteps steps from the state (x, y, z, px, py, pz; device arrays,
+ * caller order, updated in place; host_box[3], host_pbox[3] box lengths and
+ * momenta per axis, updated in place).  The forces and pressure are
+ * evaluated at the starting state first; the evaluation after step k samples
+ * its modes with step index first_step + k, and step k draws its noise with
+ * step index first_step + k.  host_P_ins[9] (optional) receives the
+ * instantaneous pressure tensor at the end (row-major), host_P_kin[9]
+ * (optional) its kinetic part.  Synchronises twice per step.
+ * Errors: ESTATE before rbsog_npt_init; EINVAL for host arrays or a coupled
+ * group with unequal lengths; EBOX if the box shrinks below the cutoff rule.
+ */
+int rbsog_npt_run(rbsog_ctx *ctx, double *x, double *y, double *z, double *px, double *py, double *pz,
+                  int64_t first_step, int32_t nsteps, double host_box[3], double host_pbox[3],
+                  double host_P_ins[9], double host_P_kin[9]);
+
+/* ========================================================================
  * Batched form: many independent systems of uneven size evaluated by one set
  * of launches per step.  Each launch covers every system; workgroups find
  * their (system, block) in a launch plan, and every reduction runs over one

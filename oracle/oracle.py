@@ -54,6 +54,7 @@ def lib():
             "orc_norm_consts": (None, [pd, C.c_int, pd, pd, C.c_int, pd, pd]),
             "orc_philox4x32_10": (None, [pu32, pu32, pu32]),
             "orc_draw_proposal": (None, [u64, u64, u64, u32, u32, u32, pd, pd]),
+            "orc_npt_normals": (None, [u64, u64, u64, i64, pd, pd]),
             "orc_target_r": (d, [pi32, pd, C.c_int, pd, pd]),
             "orc_ratio_nr": (d, [pi32, pd, C.c_int, pd, pd]),
             "orc_proposal_pmf": (d, [pi32, pd, d]),
@@ -347,3 +348,92 @@ def rbsog_step(q, pos, L, p: SOG, P, seed, system_id, step, modes=None, sample=N
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------------------
+# NPT integration (Algorithm 1 step 7; eq. Langevin_NPT for a diagonal h)
+# ---------------------------------------------------------------------------
+
+def npt_normals(seed, system_id, step, n):
+    """Standard normals of one step's Langevin noise: (n, 3) for the atoms, 3 for the box."""
+    z = np.zeros((n, 3)); zb = np.zeros(3)
+    lib().orc_npt_normals(seed, system_id, step, n, _pd(z), _pd(zb))
+    return z, zb
+
+
+COUPLINGS = {0: [[0], [1], [2]], 1: [[0, 1], [2]], 2: [[0, 1, 2]]}   # box degrees of freedom per coupling
+
+
+def npt_kinetic(mom, mass, L):
+    """Kinetic pressure sum_i p_i p_i^T / (m_i V) (eq. K_U_Pins_re), 3x3."""
+    return (mom[:, :, None] * mom[:, None, :] / mass[:, None, None]).sum(axis=0) / np.prod(L)
+
+
+def npt_kick_box(ph, L, Pi, groups, p_ext, kT, t):
+    """B_h over t: dp^h/dt = det(h) [(P_ins - p_ext - kT/det h) h^-T]_mumu (eq.
+    Langevin_NPT, diagonal h); a coupled group of n_g axes sharing p^h and L_g
+    takes the sum over its axes, (V/L_g) sum_mu (P_mumu - p_ext) - n_g kT/L_g."""
+    V = np.prod(L)
+    for k, g in enumerate(groups):
+        Lg = L[g[0]]
+        ph[k] += t * ((V / Lg) * sum(Pi[d, d] - p_ext for d in g) - len(g) * kT / Lg)
+
+
+def npt_drift(pos, mom, mass, L, ph, groups, M, t):
+    """A over t, in place: dL_g/dt = p^h_g/(n_g M) with p^h fixed (L linear in
+    t), and for each atom dr/dt = p/m + (dL/dt / L) r, dp/dt = -(dL/dt / L) p.
+    The exact flow: p(t) = p0 L0/L(t), and d(r/L)/dt = p0 L0/(m L^2) integrates
+    to r(t) = (L(t)/L0) r0 + t p0/m."""
+    a = np.ones(3)
+    for k, g in enumerate(groups):
+        Lnew = L[g[0]] + t * ph[k] / (len(g) * M)
+        for d in g:
+            a[d] = Lnew / L[d]
+            L[d] = Lnew
+    pos[:] = a * pos + t * mom / mass[:, None]
+    mom[:] = mom / a
+
+
+def npt_ou(mom, mass, ph, groups, M, kT, c1, ch, z, zb):
+    """O over dt, in place: the exact Ornstein-Uhlenbeck update of dp = -gamma p
+    dt + sqrt(2 gamma kT m) dW, p <- c p + sqrt((1 - c^2) kT m) xi with
+    c = exp(-gamma dt); the box with its own friction and mass n_g M."""
+    mom[:] = c1 * mom + np.sqrt((1.0 - c1 * c1) * kT * mass)[:, None] * z
+    for k, g in enumerate(groups):
+        ph[k] = ch * ph[k] + np.sqrt((1.0 - ch * ch) * kT * len(g) * M) * zb[k]
+
+
+def npt_run(q, pos, mom, mass, L, pbox, prm, p: SOG, P, seed, system_id, first_step, nsteps, evaluate=None):
+    """Langevin NPT steps of eq. Langevin_NPT for h = diag(L), advanced by the
+    splitting B_h B A O A [evaluate] B B_h (prm: dt, kT, gamma, gamma_box,
+    box_mass, p_ext, coupling); B is dp_i/dt = F_i.  P_ins = P_coul + the
+    kinetic pressure.  evaluate(pos, L, step) -> (F, P_coul); default: the
+    random-batch step of this oracle with modes sampled at that step.  The
+    evaluation after step k and the noise of step k use step index
+    first_step + k.  Returns (pos, mom, L, pbox, P_ins, P_kin)."""
+    pos = _f64(pos).copy(); mom = _f64(mom).copy(); mass = _f64(mass)
+    L = _f64(L).copy(); groups = COUPLINGS[prm["coupling"]]
+    ph = np.array([pbox[g[0]] for g in groups], dtype=np.float64)
+    dt = prm["dt"]; kT = prm["kT"]; M = prm["box_mass"]; tau = 0.5 * dt
+    n = len(mass)
+    if evaluate is None:
+        def evaluate(x, box, step):
+            o = rbsog_step(q, x, box, p, P, seed, system_id, step)
+            return o["F"], o["P"]
+    F, PC = evaluate(pos, L.copy(), first_step)
+    Pk = npt_kinetic(mom, mass, L); Pi = PC + Pk
+    c1 = np.exp(-prm["gamma"] * dt); ch = np.exp(-prm["gamma_box"] * dt)
+    for s in range(1, nsteps + 1):
+        step = first_step + s
+        npt_kick_box(ph, L, Pi, groups, prm["p_ext"], kT, tau)
+        mom += tau * F
+        npt_drift(pos, mom, mass, L, ph, groups, M, tau)
+        z, zb = npt_normals(seed, system_id, step, n)
+        npt_ou(mom, mass, ph, groups, M, kT, c1, ch, z, zb)
+        npt_drift(pos, mom, mass, L, ph, groups, M, tau)
+        F, PC = evaluate(pos, L.copy(), step)
+        mom += tau * F
+        Pk = npt_kinetic(mom, mass, L); Pi = PC + Pk
+        npt_kick_box(ph, L, Pi, groups, prm["p_ext"], kT, tau)
+    pbox_out = np.array([ph[next(k for k, g in enumerate(groups) if d in g)] for d in range(3)])
+    return pos, mom, L, pbox_out, Pi, Pk

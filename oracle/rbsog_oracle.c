@@ -272,6 +272,24 @@ void orc_draw_proposal(uint64_t seed, uint64_t sys, uint64_t step, uint32_t t,
     if (uacc) orc_draw(seed, sys, step, t, 2u, &uacc[0], &uacc[1]);
 }
 
+/*
+ * Standard normals of the Langevin noise of one integration step (eq.
+ * Langevin_NPT): atom i gets three from the draws with counter (i, 16, step,
+ * sys) and (i, 17, step, sys) (Box-Muller, as for a proposal); the box gets
+ * three from (0, 18, step, sys) and (1, 18, step, sys).  A reading: the paper
+ * leaves the noise generator open.
+ */
+void orc_npt_normals(uint64_t seed, uint64_t sys, uint64_t step, int64_t n, double *z_atoms, double z_box[3])
+{
+    for (int64_t i = 0; i < n; ++i) orc_draw_proposal(seed, sys, step, (uint32_t)i, 16u, 17u, z_atoms + 3 * i, NULL);
+    double u1, u2, u3, u4;
+    orc_draw(seed, sys, step, 0u, 18u, &u1, &u2);
+    orc_draw(seed, sys, step, 1u, 18u, &u3, &u4);
+    z_box[0] = sqrt(-2.0 * log(u1)) * cos(2.0 * ORC_PI * u2);
+    z_box[1] = sqrt(-2.0 * log(u1)) * sin(2.0 * ORC_PI * u2);
+    z_box[2] = sqrt(-2.0 * log(u3)) * cos(2.0 * ORC_PI * u4);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Mode sampling: App. D (r-chain) and Sec. 3.2 (measure recalibration)       */
 /* ------------------------------------------------------------------------- */

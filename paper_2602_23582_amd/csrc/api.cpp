@@ -14,14 +14,6 @@
 using rbsog::Batch;
 using rbsog::System;
 
-struct rbsog_ctx {
-    System sys;
-    Batch batch;
-    int state = 0;  // 0: set up, 1: modes sampled, 2: forces computed
-    double *d_stage = nullptr;  // host-array staging (6 n doubles), allocated on first use
-    std::string err;
-};
-
 namespace {
 
 // Table 1, row 2 (r_c = 9 A): the parameter set used in all of the paper's runs.
@@ -72,6 +64,8 @@ void destroy(rbsog_ctx *c)
     rbsog::system_free(c->sys);
     rbsog::batch_free(c->batch);
     if (c->d_stage) (void)hipFree(c->d_stage);
+    for (double *p : {c->npt.d_mass, c->npt.d_F, c->npt.d_part, c->npt.d_kin})
+        if (p) (void)hipFree(p);
     delete c;
 }
 

@@ -1623,6 +1623,115 @@ __global__ __launch_bounds__(kAtomBlock) void k_rescale(const SysDesc *__restric
     z[i] *= St.mu[2];
 }
 
+// ----------------------------------------------------------------------------
+// NPT integration (the splitting of eq. Langevin_NPT; host side in npt.cpp).
+// One system, caller order, FP64.
+// ----------------------------------------------------------------------------
+
+// B: p += c F
+__global__ __launch_bounds__(kNptBlock) void k_npt_kick(int64_t n, double c, const double *__restrict__ F,
+                                                        double *__restrict__ px, double *__restrict__ py,
+                                                        double *__restrict__ pz)
+{
+    const int64_t i = blockIdx.x * static_cast<int64_t>(kNptBlock) + threadIdx.x;
+    if (i >= n) return;
+    px[i] += c * F[i];
+    py[i] += c * F[n + i];
+    pz[i] += c * F[2 * n + i];
+}
+
+// A: exact flow over one substep with the box moving linearly, per axis
+// r <- a r + b p/m, p <- p/a (a = L_new/L_old, b = the substep)
+__global__ __launch_bounds__(kNptBlock) void k_npt_drift(int64_t n, double ax, double ay, double az, double bx,
+                                                         double by, double bz, const double *__restrict__ mass,
+                                                         double *__restrict__ x, double *__restrict__ y,
+                                                         double *__restrict__ z, double *__restrict__ px,
+                                                         double *__restrict__ py, double *__restrict__ pz)
+{
+    const int64_t i = blockIdx.x * static_cast<int64_t>(kNptBlock) + threadIdx.x;
+    if (i >= n) return;
+    const double m = mass[i];
+    x[i] = ax * x[i] + bx * px[i] / m;
+    y[i] = ay * y[i] + by * py[i] / m;
+    z[i] = az * z[i] + bz * pz[i] / m;
+    px[i] = px[i] / ax;
+    py[i] = py[i] / ay;
+    pz[i] = pz[i] / az;
+}
+
+// O: Ornstein-Uhlenbeck update p <- c p + sc sqrt(m) xi with three standard
+// normals per atom, Box-Muller of the Philox draws (atom, 16, step, sys) and
+// (atom, 17, step, sys)
+__global__ __launch_bounds__(kNptBlock) void k_npt_ou(int64_t n, double c, double sc,
+                                                      const double *__restrict__ mass, double *__restrict__ px,
+                                                      double *__restrict__ py, double *__restrict__ pz,
+                                                      uint32_t key0, uint32_t key1, uint32_t step, uint32_t sys)
+{
+#pragma clang fp contract(off)
+    const int64_t i = blockIdx.x * static_cast<int64_t>(kNptBlock) + threadIdx.x;
+    if (i >= n) return;
+    const uint2 key = make_uint2(key0, key1);
+    const uint4 o1 = philox4x32_10(make_uint4(static_cast<uint32_t>(i), 16u, step, sys), key);
+    const uint4 o2 = philox4x32_10(make_uint4(static_cast<uint32_t>(i), 17u, step, sys), key);
+    const double u1 = unit_open(o1.x, o1.y), u2 = unit_open(o1.z, o1.w);
+    const double u3 = unit_open(o2.x, o2.y), u4 = unit_open(o2.z, o2.w);
+    const double r1 = sqrt(-2.0 * log(u1));
+    const double r2 = sqrt(-2.0 * log(u3));
+    const double s = sc * sqrt(mass[i]);
+    px[i] = c * px[i] + s * (r1 * cos(2.0 * kPi * u2));
+    py[i] = c * py[i] + s * (r1 * sin(2.0 * kPi * u2));
+    pz[i] = c * pz[i] + s * (r2 * cos(2.0 * kPi * u4));
+}
+
+// sum_i p_i p_i^T / m_i: per-block partials (xx, yy, zz, xy, xz, yz)
+__global__ __launch_bounds__(kNptBlock) void k_npt_kinetic_part(int64_t n, const double *__restrict__ mass,
+                                                                const double *__restrict__ px,
+                                                                const double *__restrict__ py,
+                                                                const double *__restrict__ pz,
+                                                                double *__restrict__ part)
+{
+    __shared__ double s_w[kNptBlock / 64][6];
+    const int64_t i = blockIdx.x * static_cast<int64_t>(kNptBlock) + threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (i < n) {
+        const double im = 1.0 / mass[i], a = px[i], b = py[i], c = pz[i];
+        v[0] = a * a * im;
+        v[1] = b * b * im;
+        v[2] = c * c * im;
+        v[3] = a * b * im;
+        v[4] = a * c * im;
+        v[5] = b * c * im;
+    }
+    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) s_w[wv][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double t = 0;
+        for (int w = 0; w < kNptBlock / 64; ++w) t += s_w[w][threadIdx.x];
+        part[6 * static_cast<int64_t>(blockIdx.x) + threadIdx.x] = t;
+    }
+}
+
+// one workgroup: the partials in a fixed order
+__global__ __launch_bounds__(256) void k_npt_kinetic_sum(int64_t nblocks, const double *__restrict__ part,
+                                                         double *__restrict__ kin)
+{
+    __shared__ double s_v[256][6];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nblocks; b += 256)
+        for (int k = 0; k < 6; ++k) v[k] += part[6 * b + k];
+    for (int k = 0; k < 6; ++k) s_v[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int k = 0; k < 6; ++k) s_v[threadIdx.x][k] += s_v[threadIdx.x + o][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) kin[threadIdx.x] = s_v[0][threadIdx.x];
+}
+
 inline const int2 *plan_ptr(const Batch &b, PlanKind k) { return b.d_plan + b.plan_off[k]; }
 inline unsigned plan_grid(const Batch &b, PlanKind k) { return static_cast<unsigned>(b.plan_len[k]); }
 inline unsigned nsys(const Batch &b) { return static_cast<unsigned>(b.sys.size()); }
@@ -1753,6 +1862,39 @@ hipError_t launch_rescale(Batch &b)
     if (b.sys.empty()) return hipSuccess;
     hipLaunchKernelGGL(k_rescale, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanAtoms));
+    return hipGetLastError();
+}
+
+static unsigned npt_grid(int64_t n) { return static_cast<unsigned>((n + kNptBlock - 1) / kNptBlock); }
+
+hipError_t launch_npt_kick(hipStream_t s, int64_t n, double c, const double *F, double *px, double *py, double *pz)
+{
+    hipLaunchKernelGGL(k_npt_kick, dim3(npt_grid(n)), dim3(kNptBlock), 0, s, n, c, F, px, py, pz);
+    return hipGetLastError();
+}
+
+hipError_t launch_npt_drift(hipStream_t s, int64_t n, const double a[3], const double b[3], const double *mass,
+                            double *x, double *y, double *z, double *px, double *py, double *pz)
+{
+    hipLaunchKernelGGL(k_npt_drift, dim3(npt_grid(n)), dim3(kNptBlock), 0, s, n, a[0], a[1], a[2], b[0], b[1], b[2],
+                       mass, x, y, z, px, py, pz);
+    return hipGetLastError();
+}
+
+hipError_t launch_npt_ou(hipStream_t s, int64_t n, double c, double sc, const double *mass, double *px, double *py,
+                         double *pz, uint64_t seed, uint32_t step, uint32_t sys)
+{
+    hipLaunchKernelGGL(k_npt_ou, dim3(npt_grid(n)), dim3(kNptBlock), 0, s, n, c, sc, mass, px, py, pz,
+                       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), step, sys);
+    return hipGetLastError();
+}
+
+hipError_t launch_npt_kinetic(hipStream_t s, int64_t n, const double *mass, const double *px, const double *py,
+                              const double *pz, double *part, int64_t nblocks, double *kin)
+{
+    if (nblocks != static_cast<int64_t>(npt_grid(n))) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_npt_kinetic_part, dim3(npt_grid(n)), dim3(kNptBlock), 0, s, n, mass, px, py, pz, part);
+    hipLaunchKernelGGL(k_npt_kinetic_sum, dim3(1), dim3(256), 0, s, nblocks, part, kin);
     return hipGetLastError();
 }
 

@@ -267,4 +267,38 @@ hipError_t launch_rescale(Batch &b);
 void timer_begin(Batch &b, const char *name, hipStream_t s);
 void timer_end(Batch &b, const char *name, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// NPT integration (npt.cpp, kernels in kernels.hip)
+struct NptState {
+    bool ready = false;
+    rbsog_npt_params prm{};
+    double *d_mass = nullptr;  // [n] masses, caller order
+    double *d_F = nullptr;     // [3n] force of the last evaluation (SoA)
+    double *d_part = nullptr;  // [6 * kinetic blocks] partial sums of p p^T / m
+    double *d_kin = nullptr;   // [6] their fixed-order total
+    int64_t kin_blocks = 0;
+};
+constexpr int kNptBlock = 256;
+// p += c F (three planes)
+hipError_t launch_npt_kick(hipStream_t s, int64_t n, double c, const double *F, double *px, double *py, double *pz);
+// per axis: r <- a r + b p/m, p <- p / a
+hipError_t launch_npt_drift(hipStream_t s, int64_t n, const double a[3], const double b[3], const double *mass,
+                            double *x, double *y, double *z, double *px, double *py, double *pz);
+// p <- c p + sqrt(m) sc xi, xi standard normals from Philox (atom, 16|17, step, sys) keyed by seed
+hipError_t launch_npt_ou(hipStream_t s, int64_t n, double c, double sc, const double *mass, double *px, double *py,
+                         double *pz, uint64_t seed, uint32_t step, uint32_t sys);
+// sum_i p_i p_i^T / m_i (xx, yy, zz, xy, xz, yz) into kin[6], fixed order
+hipError_t launch_npt_kinetic(hipStream_t s, int64_t n, const double *mass, const double *px, const double *py,
+                              const double *pz, double *part, int64_t nblocks, double *kin);
+
 }  // namespace rbsog
+
+// A single-system context: one system evaluated as a batch of one.
+struct rbsog_ctx {
+    rbsog::System sys;
+    rbsog::Batch batch;
+    int state = 0;  // 0: set up, 1: modes sampled, 2: forces computed
+    double *d_stage = nullptr;  // host-array staging (6 n doubles), allocated on first use
+    rbsog::NptState npt;
+    std::string err;
+};

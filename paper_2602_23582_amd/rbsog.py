@@ -37,7 +37,18 @@ EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_forc
            "rbsog_batch_setup", "rbsog_batch_step", "rbsog_batch_rescale", "rbsog_batch_set_options",
            "rbsog_batch_autotune", "rbsog_batch_set_timing", "rbsog_batch_get_timing", "rbsog_batch_destroy",
            "rbsog_batch_last_error", "rbsog_server_create", "rbsog_server_submit", "rbsog_server_wait",
-           "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_last_error"]
+           "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_last_error", "rbsog_npt_init",
+           "rbsog_npt_run"]
+
+COUPLE_ANISO = 0
+COUPLE_SEMI = 1
+COUPLE_ISO = 2
+
+
+class rbsog_npt_params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("kT", C.c_double), ("gamma", C.c_double), ("gamma_box", C.c_double),
+                ("box_mass", C.c_double), ("p_ext", C.c_double), ("coupling", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 class rbsog_params(C.Structure):
@@ -98,6 +109,8 @@ def load(path: str | None = None):
         "rbsog_server_stats": (C.c_int, [vp, pd]),
         "rbsog_server_destroy": (C.c_int, [vp]),
         "rbsog_server_last_error": (C.c_char_p, [vp]),
+        "rbsog_npt_init": (C.c_int, [vp, C.POINTER(rbsog_npt_params), pd]),
+        "rbsog_npt_run": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, i64, i32, pd, pd, pd, pd]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -239,6 +252,27 @@ class Context:
         rc_, out = _timing_table(load().rbsog_get_timing, self._h)
         self._check(rc_, "rbsog_get_timing")
         return out
+
+    def npt_init(self, mass, dt, kT, gamma, gamma_box, box_mass, p_ext, coupling=COUPLE_ANISO):
+        """Attach the Langevin NPT integrator (rbsog_npt_init)."""
+        p = rbsog_npt_params(dt=dt, kT=kT, gamma=gamma, gamma_box=gamma_box, box_mass=box_mass, p_ext=p_ext,
+                             coupling=coupling)
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        if mass.shape != (self.n,):
+            raise ValueError("one mass per atom")
+        self._check(load().rbsog_npt_init(self._h, C.byref(p), _pd(mass)), "rbsog_npt_init")
+
+    def npt_run(self, x, y, z, px, py, pz, first_step, nsteps, pbox):
+        """Advance nsteps NPT steps in place (device tensors); returns (box, pbox, P_ins, P_kin)."""
+        box = np.ascontiguousarray(self.box, dtype=np.float64).copy()
+        pbox = np.ascontiguousarray(pbox, dtype=np.float64).copy()
+        Pi = np.zeros(9)
+        Pk = np.zeros(9)
+        self._check(load().rbsog_npt_run(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(px), _ptr(py), _ptr(pz),
+                                         int(first_step), int(nsteps), _pd(box), _pd(pbox), _pd(Pi), _pd(Pk)),
+                    "rbsog_npt_run")
+        self.box = box.copy()
+        return box, pbox, Pi.reshape(3, 3), Pk.reshape(3, 3)
 
     def close(self):
         if getattr(self, "_h", None):
