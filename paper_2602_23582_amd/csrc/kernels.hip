@@ -1461,18 +1461,18 @@ __global__ __launch_bounds__(256) void k_rho_reduce(const SysDesc *__restrict__ 
             D.rho[2 * d + 1] = im;
         }
     } else {
+        // slice of the pair-block partials: blocks [k c, (k + 1) c), c = ceil(npair / kPairRed)
+        const int k = d - D.mcap;
         const int64_t npair = gp(D.bstart)[stp[e.x].ncells];
+        const int64_t c = (npair + kPairRed - 1) / kPairRed;
+        const int64_t b0 = k * c, b1 = min(npair, b0 + c);
         const RB_GLOBAL double *pp = gp(D.pair_part);
         double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int64_t b = tid; b < npair; b += 256)
-            for (int k = 0; k < 8; ++k) acc[k] += pp[8 * b + k];
-        for (int k = 0; k < 8; ++k) {
-            const double s = block_sum_256(acc[k], s_tmp);
-            if (tid == 0) {
-                if (k < 6) res->vir[k] = s;
-                else if (k == 6) res->UN = s;
-                else res->npairs = s;
-            }
+        for (int64_t b = b0 + tid; b < b1; b += 256)
+            for (int j = 0; j < 8; ++j) acc[j] += pp[8 * b + j];
+        for (int j = 0; j < 8; ++j) {
+            const double s = block_sum_256(acc[j], s_tmp);
+            if (tid == 0) D.pair_red[8 * k + j] = s;
         }
     }
 }
@@ -1495,6 +1495,16 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
     const double V = L[0] * L[1] * L[2];
     const double S = 0.5 * St.Sr;
     const int P = D.P;
+    // short-range virial, energy and pair count: the slices in order
+    if (tid < 8) {
+        double s = 0.0;
+        for (int k = 0; k < kPairRed; ++k) s += D.pair_red[8 * k + tid];
+        StepResults *r = D.res;
+        if (tid < 6) r->vir[tid] = s;
+        else if (tid == 6) r->UN = s;
+        else r->npairs = s;
+    }
+    __syncthreads();
     double sr = 0.0, snr[6] = {0, 0, 0, 0, 0, 0};
     for (int d = tid; d < nd; d += 256) {
         const int4 m = D.modes[d];

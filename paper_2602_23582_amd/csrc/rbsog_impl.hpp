@@ -25,6 +25,7 @@ constexpr int kMaxP = 1024;        // samples per chain handled by the one-workg
 constexpr int kMaxModes = kMaxP + 1; // distinct modes: accepted proposals plus the initial state
 constexpr int kPairWave = 64;      // i-atoms per pair-kernel wavefront
 constexpr int kSkChunk = 1024;     // atoms per structure-factor workgroup
+constexpr int kPairRed = 64;       // workgroups reducing a system's pair-block partials (then summed in order)
 constexpr int kAtomBlock = 256;    // atoms per workgroup of the per-atom kernels
 constexpr int kCellBlock = 256;    // cells per workgroup of the per-cell kernels
 constexpr int kScanBlock = 1024;   // cells per workgroup of the local scan
@@ -92,6 +93,7 @@ struct SysDesc {
     int32_t *cnt;         // multiplicities: r-chain [mcap], nr-chain [mcap]
     double *rho_part;     // [sk_blocks][mcap] x (re, im)
     double *rho;          // [mcap] x (re, im)
+    double *pair_red;     // [kPairRed][8] slice sums of the pair-block partials
     void *coef;           // per-mode force coefficients [mcap]
     StepResults *res;     // this system's slot of the batch results
 };

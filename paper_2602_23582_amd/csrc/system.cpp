@@ -21,10 +21,11 @@ bool is_fp64(const rbsog_params &p) { return p.precision == RBSOG_PREC_FP64; }
 
 // byte sizes of the per-atom and per-mode buffers, in carving order
 struct AtomLayout {
-    size_t q, u, cell, keys, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, coef, scan_tmp;
+    size_t q, u, cell, keys, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, pair_red, coef, scan_tmp;
     size_t total() const
     {
-        return q + u + cell + keys + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + coef + scan_tmp;
+        return q + u + cell + keys + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + pair_red + coef +
+               scan_tmp;
     }
 };
 
@@ -47,6 +48,7 @@ AtomLayout atom_layout(const rbsog_params &p, int64_t n)
     a.cnt = align_up(2 * mcap * 4);
     a.rho_part = align_up(skb * mcap * 16);
     a.rho = align_up(mcap * 16);
+    a.pair_red = align_up(kPairRed * 8 * sizeof(double));
     a.coef = align_up(mcap * 64);
     a.scan_tmp = align_up((2 * 1024 + 2) * 4);
     return a;
@@ -311,6 +313,7 @@ void system_carve_atoms(System &s, void *mem)
     d.cnt = static_cast<int32_t *>(take(a.cnt));
     d.rho_part = static_cast<double *>(take(a.rho_part));
     d.rho = static_cast<double *>(take(a.rho));
+    d.pair_red = static_cast<double *>(take(a.pair_red));
     d.coef = take(a.coef);
     d.scan_tmp = static_cast<int32_t *>(take(a.scan_tmp));
     s.atom_mem = mem;
@@ -572,7 +575,7 @@ static int build_plans(Batch &b, std::string &err)
         len[kPlanScan] += (s->ncells + kScanBlock - 1) / kScanBlock;
         len[kPlanPair] += (s->n + kPairWave - 1) / kPairWave + s->ncells;
         len[kPlanSk] += (s->n + kSkChunk - 1) / kSkChunk;
-        len[kPlanReduce] += s->prm.P + 2;
+        len[kPlanReduce] += s->prm.P + 1 + kPairRed;
         len[kPlanCell1] += s->ncells;
     }
     int64_t total = 0;
@@ -612,7 +615,7 @@ static int build_plans(Batch &b, std::string &err)
         put(kPlanCells, s, (y->ncells + 1 + kCellBlock - 1) / kCellBlock);
         put(kPlanScan, s, (y->ncells + kScanBlock - 1) / kScanBlock);
         put(kPlanSk, s, (y->n + kSkChunk - 1) / kSkChunk);
-        put(kPlanReduce, s, y->prm.P + 2);
+        put(kPlanReduce, s, y->prm.P + 1 + kPairRed);
         put(kPlanCell1, s, y->ncells);
     }
     // pair blocks grouped by the form of the SOG kernels (one launch per form)
