@@ -1319,7 +1319,11 @@ struct alignas(16) SkAtom32 {
 
 __device__ inline void phase_sincos32(const int4 &m, const SkAtom32 &at, float &s, float &c)
 {
-    const uint32_t hi = static_cast<uint32_t>(__mul24(m.x, at.hx) + __mul24(m.y, at.hy) + __mul24(m.z, at.hz));
+    // 24-bit multiplies (full rate; |m| < 2^23, halves < 2^16).  The empty asm
+    // keeps the compiler from moving the shift into the products, which would
+    // turn them into 32-bit (quarter-rate) multiplies by (u & 0xffff0000).
+    uint32_t hi = static_cast<uint32_t>(__mul24(m.x, at.hx) + __mul24(m.y, at.hy) + __mul24(m.z, at.hz));
+    asm("" : "+v"(hi));
     const uint32_t lo = static_cast<uint32_t>(__mul24(m.x, at.lx) + __mul24(m.y, at.ly) + __mul24(m.z, at.lz));
     const uint32_t ph = (hi << 16) + lo;
     const float rev = static_cast<float>(static_cast<int32_t>(ph)) * 0x1.0p-32f;
@@ -1584,15 +1588,25 @@ __global__ __launch_bounds__(kAtomBlock) void k_force(const SysDesc *__restrict_
         for (int d0 = 0; d0 < nd; d0 += 32) {
             float hx = 0.f, hy = 0.f, hz = 0.f;
             const int d1 = min(nd, d0 + 32);
-            for (int d = d0; d < d1; ++d) {
-                const Coef<float> c = gload(cf + d);
+            auto term = [&](const Coef<float> &c) {
                 float sn, cs;
                 phase_sincos32(make_int4(c.mx, c.my, c.mz, 0), at, sn, cs);
                 const float g = c.A * cs - c.B * sn;
                 hx += g * c.kx;
                 hy += g * c.ky;
                 hz += g * c.kz;
+            };
+            // four modes' coefficients loaded together (scalar loads, one wait),
+            // terms added in mode order
+            int d = d0;
+            for (; d + 4 <= d1; d += 4) {
+                Coef<float> c[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) c[k] = gload(cf + d + k);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) term(c[k]);
             }
+            for (; d < d1; ++d) term(gload(cf + d));
             gx += hx;
             gy += hy;
             gz += hz;
