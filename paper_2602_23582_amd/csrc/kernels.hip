@@ -712,7 +712,7 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
 // has idle lanes).  It walks the atoms of the neighbouring cells (full shell:
 // every pair is evaluated from both sides, so no atomics and a fixed
 // summation order).  The neighbours are contiguous ranges of the sorted
-// arrays: with at least five cells per edge (FP32), each of the 9 neighbour
+// arrays: with at least four cells per edge (FP32), each of the 9 neighbour
 // columns cut to the block's z-window; otherwise a run of cells per
 // neighbour column.  They are staged kChunk at a time in LDS; every lane
 // tests every staged candidate against r_c and keeps one hit bit per
@@ -982,12 +982,14 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     Rec ri{};
     if (valid) ri = gload(rec + i);
     const real rc2_lane = valid ? rc2 : static_cast<real>(-1);  // padding lanes find no partner
-    // Fast filter (FP32, at least 5 cells per edge): candidates are tested in
+    // Fast filter (FP32, at least 4 cells per edge): candidates are tested in
     // float coordinates relative to the first atom of the block, o.  The
-    // block lies in one column and spans at most g cells in z, candidates lie
-    // within the cutoff of it, and the grid has nz >= 2 g + 3 and at least 5
-    // cells along x and y, so every candidate is within half a box of o and
-    // differences of relative coordinates are minimum-image displacements.
+    // block lies in one column and spans at most g cells in z; a partner
+    // within rc of a block atom lies less than two cells from o along x and
+    // y and less than g + 1 along z, under half the box (nx, ny >= 4,
+    // nz >= 2 g + 2), so relative coordinates of every pair inside rc are
+    // minimum-image offsets and their difference is the displacement.  (A
+    // candidate beyond rc that wraps lands half a box away and fails.)
     // The test is |r_j|^2 - 2 r_i.r_j < rcf^2 - |r_i|^2 (three FMAs); with
     // |r| below 45 A its rounding error stays under 1e-3 A^2, far inside the
     // 2 rc 1e-3 A^2 that padding the radius by 1e-3 A adds, so it never drops
@@ -1013,7 +1015,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     if (kIsF32 && fast) {
         // The block's atoms are sorted by z and span [0, zext] in fixed point
         // relative to o.  Each of the 9 neighbour columns (distinct: at least
-        // 5 cells per edge) is a z-sorted range of the sorted arrays; it is
+        // 4 cells per edge) is a z-sorted range of the sorted arrays; it is
         // cut by binary search to the atoms whose z lies in the padded
         // cutoff window [oz - reach, oz + zext + reach], one range, or two
         // where the window wraps around the periodic seam.

@@ -272,11 +272,13 @@ void system_set_box(System &s, const double box[3])
     }
     t.ncells = static_cast<int32_t>(s.ncells);
     // Pair blocks are 64-atom z-slabs of segments of g cells of one column.
-    // The FP32 filter takes coordinates relative to a block's first atom; they
-    // are minimum-image displacements while the block's z-extent (at most g
-    // cells) plus the cutoff (at most one cell) stays under half the box:
-    // nz >= 2 g + 3.  The other paths use single cells.
-    const bool fast = !is_fp64(s.prm) && s.nc[0] >= 5 && s.nc[1] >= 5 && s.nc[2] >= 5;
+    // The FP32 filter takes coordinates relative to a block's first atom o.
+    // A neighbour of a block atom lies less than two cells from o along x and
+    // y, and less than g + 1 cells along z; that is under half the box when
+    // nx, ny >= 4 and nz >= 2 g + 2 (g = 1 for nz < 7), so the relative
+    // coordinates of every pair inside rc are minimum-image offsets and their
+    // difference is the displacement.  The other paths use single cells.
+    const bool fast = !is_fp64(s.prm) && s.nc[0] >= 4 && s.nc[1] >= 4 && s.nc[2] >= 4;
     t.fast = fast ? 1 : 0;
     t.g = fast ? std::max(1, std::min(kSuperCells, (s.nc[2] - 3) / 2)) : 1;
     t.Sr = s.Sr;

@@ -205,15 +205,17 @@ def test_fp32c_small_slab(torch, rb, orc, P, form, energy):
     check(g, o, TOL_FP32C, f"slab P={P} form {form} energy {energy}")
 
 
-@pytest.mark.parametrize("n", [500, 2000, 6000])
-def test_fp32c_small_boxes_collapsed_cells(torch, rb, orc, n):
+@pytest.mark.parametrize("energy", [True, False])
+@pytest.mark.parametrize("n", [500, 2000, 6000, 9000])
+def test_fp32c_small_boxes_collapsed_cells(torch, rb, orc, n, energy):
     """Served-stream systems: 500 atoms gives L = 17.1 A, rc = L/2, every
-    dimension searched whole; 2,000 and 6,000 give 2 and 3 cells per edge."""
+    dimension searched whole; 2,000 and 6,000 give 2 and 3 cells per edge;
+    9,000 gives 4, the fewest the FP32 relative-coordinate filter takes."""
     d = W.ionic_system(n, seed=n)
     with rb.Context(d["q"], d["L"], d["rc"], P=d["P"], seed=n, system_id=3) as ctx:
-        g = gpu_step(torch, ctx, d["pos"], 1, d["L"])
+        g = gpu_step(torch, ctx, d["pos"], 1, d["L"], energy=energy)
     o = oracle_step(orc, d, d["L"], d["pos"], d["P"], n, 3, 1)
-    check(g, o, TOL_FP32C, f"ionic n={n}")
+    check(g, o, TOL_FP32C, f"ionic n={n} energy {energy}")
 
 
 def test_rho_of_distinct_modes(torch, rb, orc):
