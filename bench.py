@@ -150,7 +150,8 @@ def served_bench(n_req, seed, pool_bytes, lam_frac=0.8, nsteps=10, growth=0.001)
     arrive as a Poisson stream at lam_frac x that capacity.  Each is run with
     continuous batching (all admitted requests per tick) and one request at a
     time (the same server with one slot), on the same GPU and at the same
-    accuracy.  Latency = completion - submission."""
+    accuracy; every request is a force + pressure solve (no energy sum).
+    Latency = completion - submission."""
     from paper_2602_23582_amd import rbsog
     from paper_2602_23582_amd import workloads as W
     sizes, seeds = W.served_stream(n_req, seed=seed)
@@ -158,7 +159,7 @@ def served_bench(n_req, seed, pool_bytes, lam_frac=0.8, nsteps=10, growth=0.001)
     atom_steps = float(sum(len(r["q"]) for r in reqs)) * nsteps
 
     def run(max_active, arrivals):
-        with rbsog.Server(max_active=max_active, pool_bytes=pool_bytes) as sv:
+        with rbsog.Server(max_active=max_active, pool_bytes=pool_bytes, energy=False) as sv:
             t0 = time.perf_counter()
             tickets = []
             for i, (r, ta) in enumerate(zip(reqs, arrivals)):
@@ -173,7 +174,8 @@ def served_bench(n_req, seed, pool_bytes, lam_frac=0.8, nsteps=10, growth=0.001)
         lat = np.array([x["latency_s"] for x in res])
         return {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
                 "atom_steps_per_s": atom_steps / wall, "requests_per_s": n_req / wall, "wall_s": wall,
-                "ticks": st["ticks"], "peak_active": st["peak_active"], "peak_pool_mib": st["peak_pool_bytes"] / 2**20}
+                "ticks": st["ticks"], "peak_active": st["peak_active"], "peak_pool_mib": st["peak_pool_bytes"] / 2**20,
+                "tick_ms": {k: 1e3 * st[k + "_s"] / max(st["ticks"], 1) for k in ("admit", "launch", "wait")}}
 
     burst = np.zeros(n_req)
     sat = run(65536, burst)
@@ -182,7 +184,7 @@ def served_bench(n_req, seed, pool_bytes, lam_frac=0.8, nsteps=10, growth=0.001)
     batched = run(65536, arrivals)
     solo_sat = run(1, burst)
     solo = run(1, arrivals)
-    return {"requests": n_req, "steps_per_request": nsteps, "pool_mib": pool_bytes / 2**20,
+    return {"requests": n_req, "steps_per_request": nsteps, "pool_mib": pool_bytes / 2**20, "energy": False,
             "arrival_rate_per_s": lam, "arrival_rate_frac_of_capacity": lam_frac,
             "continuous_batching": batched, "one_at_a_time": solo,
             "capacity": {"continuous_batching": sat, "one_at_a_time": solo_sat}}
@@ -260,9 +262,9 @@ def main():
     ap.add_argument("--no-valu-probe", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="run the step as a batch of one replaying a captured HIP graph")
-    ap.add_argument("--served", type=int, default=256, help="requests of the served-stream run (0: skip)")
+    ap.add_argument("--served", type=int, default=4096, help="requests of the served-stream run (0: skip)")
     ap.add_argument("--npt-steps", type=int, default=20, help="Langevin NPT steps timed after the main run (0: skip)")
-    ap.add_argument("--served-pool-mib", type=int, default=1024)
+    ap.add_argument("--served-pool-mib", type=int, default=4096)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

@@ -388,6 +388,16 @@ int rbsog_server_create(int32_t precision, int64_t pool_bytes, int32_t max_activ
                         rbsog_server **out);
 
 /*
+ * Whether the server's steps sum the energies (on: the default).  Off, the
+ * pair kernel skips the energy sum and rbsog_server_wait returns zeros for
+ * them; the forces then take the relative-coordinate displacements of the
+ * call without energy (they differ from the energy-on forces by rounding).
+ * One setting holds for every request, so a request's results never depend
+ * on its neighbours in a tick: RBSOG_ESTATE once a request was submitted.
+ */
+int rbsog_server_set_energy(rbsog_server *s, int32_t on);
+
+/*
  * Queue a request (copies every input; returns at once).
  *  params         parameters of the system (params->precision must match).
  *  n, host_q[n]   charges; host_x, host_y, host_z[n] initial positions.
@@ -414,9 +424,11 @@ int rbsog_server_wait(rbsog_server *s, int64_t ticket, double timeout_s, double 
                       double *host_fz, double *host_P, double *host_energy, double *host_times);
 
 /*
- * host_stats[8]: requests submitted, completed, ticks run, atom-steps done,
+ * host_stats[11]: requests submitted, completed, ticks run, atom-steps done,
  * seconds the worker spent in ticks, peak active requests, peak pool bytes
- * in use, requests waiting now.
+ * in use, requests waiting now, and the ticks' seconds split three ways:
+ * uploading admitted requests, setting up and launching the batched steps,
+ * waiting for their results and the completed requests' forces.
  */
 int rbsog_server_stats(rbsog_server *s, double *host_stats);
 

@@ -644,7 +644,12 @@ __global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restric
 // unique, so the order does not depend on the scatter's.  One workgroup per
 // cell: a cell of up to 256 atoms is sorted in LDS (bitonic network over the
 // next power of two); a larger cell ranks each atom against all keys of the
-// cell.  The sorted slot receives the atom's index and its record.
+// cell, which pass through LDS 256 at a time while every thread holds
+// kRankKeys of the keys it ranks in registers.  A single-cell system has one
+// workgroup per kOrderPart of its keys instead.  The sorted slot receives the
+// atom's index and its record.
+constexpr int kRankKeys = 4;
+static_assert(256 * kRankKeys == kOrderPart, "one rank pass per part of a single cell");
 template <class T>
 __device__ inline void write_sorted(const SysDesc &D, int slot, uint64_t key)
 {
@@ -661,18 +666,20 @@ __device__ inline void write_sorted(const SysDesc &D, int slot, uint64_t key)
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc, const int2 *__restrict__ plan)
+__global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                               const int2 *__restrict__ plan)
 {
     __shared__ uint64_t s_key[256];
     const int2 e = plan[blockIdx.x];
     const SysDesc &D = desc[e.x];
-    const int c = e.y;
+    const bool single = stp[e.x].ncells == 1;
+    const int c = single ? 0 : e.y;
     const int tid = threadIdx.x;
     const int s0 = gp(D.start)[c], s1 = gp(D.start)[c + 1];
     const int cnt = s1 - s0;
     if (cnt == 0) return;
     const RB_GLOBAL uint64_t *keys = gp(D.keys);
-    if (cnt <= 256) {
+    if (cnt <= 256) {  // a single cell this small has one part
         int N = 1;
         while (N < cnt) N <<= 1;
         s_key[tid] = tid < cnt ? keys[s0 + tid] : ~0ull;
@@ -693,11 +700,30 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
         }
         if (tid < cnt) write_sorted<T>(D, s0 + tid, s_key[tid]);
     } else {
-        for (int t = tid; t < cnt; t += 256) {
-            const uint64_t key = keys[s0 + t];
-            int rank = 0;
-            for (int j = 0; j < cnt; ++j) rank += keys[s0 + j] < key;
-            write_sorted<T>(D, s0 + rank, key);
+        const int lo = single ? e.y * kOrderPart : 0;
+        const int hi = single ? min(cnt, lo + kOrderPart) : cnt;
+        for (int base = lo; base < hi; base += kOrderPart) {
+            uint64_t mine[kRankKeys];
+            int rank[kRankKeys];
+            for (int r = 0; r < kRankKeys; ++r) {
+                const int t = base + 256 * r + tid;
+                mine[r] = t < hi ? keys[s0 + t] : 0ull;
+                rank[r] = 0;
+            }
+            for (int j0 = 0; j0 < cnt; j0 += 256) {
+                __syncthreads();  // the previous tile is no longer read
+                s_key[tid] = j0 + tid < cnt ? keys[s0 + j0 + tid] : 0ull;
+                __syncthreads();
+                const int m = min(256, cnt - j0);
+                for (int j = 0; j < m; ++j) {
+                    const uint64_t k = s_key[j];
+                    for (int r = 0; r < kRankKeys; ++r) rank[r] += k < mine[r];
+                }
+            }
+            for (int r = 0; r < kRankKeys; ++r) {
+                const int t = base + 256 * r + tid;
+                if (t < hi) write_sorted<T>(D, s0 + rank[r], mine[r]);
+            }
         }
     }
 }
@@ -1796,7 +1822,7 @@ static hipError_t bin_and_sort_t(Batch &b)
                        plan_ptr(b, kPlanCells));
     hipLaunchKernelGGL(k_scatter<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
                        plan_ptr(b, kPlanAtoms));
-    hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanCell1)), dim3(256), 0, b.stream, b.d_desc,
+    hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanCell1)), dim3(256), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanCell1));
     timer_end(b, "bin", b.stream);
     const hipError_t e = hipGetLastError();

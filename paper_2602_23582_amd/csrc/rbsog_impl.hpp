@@ -33,6 +33,7 @@ constexpr int64_t kMaxCells = int64_t(1024) * kScanBlock;  // cells per system (
 constexpr int kMaxTimed = 24;
 constexpr int kPolyDeg = 10;       // degree of the FP32C polynomial form of the SOG sums
 constexpr int kSuperCells = 4;     // most cells stacked in z into one pair-block segment
+constexpr int kOrderPart = 1024;   // keys one ordering workgroup ranks in a single-cell system
 
 // SOG tables read by the kernels (device memory, uniform loads).
 struct SogTables {
@@ -238,7 +239,10 @@ int system_alloc(System &s, std::string &err);
 int system_ensure_cells(System &s, std::string &err, bool *recarved = nullptr);
 void system_free(System &s);
 // Upload the charges (FP32 or FP64 copy) on the stream.
-int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err);
+// Charges to the device (FP32C: rounded to float).  With a stage, the copy is
+// left in flight: the caller keeps host_q and *stage until the stream is synchronised.
+int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err,
+                    std::vector<float> *stage = nullptr);
 // New box: grid, S^r, S^nr.
 void system_set_box(System &s, const double box[3]);
 // Cells needed by a box.

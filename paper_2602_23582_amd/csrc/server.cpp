@@ -89,6 +89,7 @@ struct Request {
     int nsteps = 1;
     double growth = 0.0;
     std::vector<double> q, x, y, z;  // inputs, freed once uploaded
+    std::vector<float> q32;          // FP32C charges in flight to the device
     std::vector<double> boxes;       // box of every step (3 nsteps)
     std::vector<double> mus;         // scale factor before every step (1 at k = 0)
     int64_t max_cells = 0;
@@ -109,6 +110,7 @@ struct rbsog_server {
     int precision = RBSOG_PREC_FP32C;
     size_t pool_bytes = 0;
     int max_active = 1;
+    bool energy = true;  // every tick sums the energies
     int device = 0;
     hipStream_t stream = nullptr;
     char *pool_mem = nullptr;
@@ -125,6 +127,7 @@ struct rbsog_server {
     // statistics
     int64_t submitted = 0, completed = 0, ticks = 0, peak_active = 0;
     double atom_steps = 0.0, busy_s = 0.0;
+    double phase_s[3] = {};  // admission; set-up and launch; results and forces back
     std::string err, worker_err;
 };
 
@@ -136,7 +139,8 @@ size_t request_bytes(const rbsog_params &p, int64_t n, int64_t max_cells)
            2 * align_up(3 * n * sizeof(double));
 }
 
-// Upload an admitted request's state into its pool memory.
+// Queue the upload of an admitted request's state into its pool memory; the
+// host copies stay alive until admit_finish has synchronised the stream.
 int admit(rbsog_server *sv, Request *r, std::string &err)
 {
     char *base = sv->pool_mem + r->off;
@@ -149,7 +153,7 @@ int admit(rbsog_server *sv, Request *r, std::string &err)
     r->d_pos = reinterpret_cast<double *>(base);
     base += align_up(3 * r->n * sizeof(double));
     r->d_frc = reinterpret_cast<double *>(base);
-    int rc = rbsog::system_upload_q(s, r->q.data(), sv->stream, err);
+    int rc = rbsog::system_upload_q(s, r->q.data(), sv->stream, err, &r->q32);
     if (rc) return rc;
     const int64_t n = r->n;
     hipError_t e = hipMemcpyAsync(r->d_pos, r->x.data(), n * sizeof(double), hipMemcpyHostToDevice, sv->stream);
@@ -157,21 +161,37 @@ int admit(rbsog_server *sv, Request *r, std::string &err)
         e = hipMemcpyAsync(r->d_pos + n, r->y.data(), n * sizeof(double), hipMemcpyHostToDevice, sv->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(r->d_pos + 2 * n, r->z.data(), n * sizeof(double), hipMemcpyHostToDevice, sv->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
     if (e != hipSuccess) {
         err = std::string("request upload: ") + hipGetErrorString(e);
         return RBSOG_EDEVICE;
     }
-    std::vector<double>().swap(r->q);
-    std::vector<double>().swap(r->x);
-    std::vector<double>().swap(r->y);
-    std::vector<double>().swap(r->z);
-    r->t_admit = Clock::now();
     return RBSOG_OK;
 }
 
-// One batched step over every active request.
-int tick(rbsog_server *sv, std::string &err)
+// One synchronisation for every upload queued this tick; the host copies go.
+int admit_finish(rbsog_server *sv, const std::vector<Request *> &admitted, std::string &err)
+{
+    if (admitted.empty()) return RBSOG_OK;
+    const hipError_t e = hipStreamSynchronize(sv->stream);
+    if (e != hipSuccess) {
+        err = std::string("request upload: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    const Clock::time_point t = Clock::now();
+    for (Request *r : admitted) {
+        std::vector<double>().swap(r->q);
+        std::vector<double>().swap(r->x);
+        std::vector<double>().swap(r->y);
+        std::vector<double>().swap(r->z);
+        std::vector<float>().swap(r->q32);
+        r->t_admit = t;
+    }
+    return RBSOG_OK;
+}
+
+// One batched step over every active request; the forces of the requests it
+// completes are copied out behind the step, before its results are fetched.
+int tick(rbsog_server *sv, std::vector<Request *> &finished, double &wait_s, std::string &err)
 {
     Batch &bt = sv->batch;
     // rescale before step k >= 1 (mu = 1 at k = 0 leaves positions unchanged)
@@ -202,7 +222,7 @@ int tick(rbsog_server *sv, std::string &err)
         t.fy = r->d_frc + r->n;
         t.fz = r->d_frc + 2 * r->n;
     }
-    bt.want_energy = true;  // every request reports its energies
+    bt.want_energy = sv->energy;
     rc = rbsog::batch_upload(bt, err);
     if (rc) return rc;
     e = rbsog::launch_sample(bt);
@@ -213,8 +233,28 @@ int tick(rbsog_server *sv, std::string &err)
         err = std::string("step launch: ") + hipGetErrorString(e);
         return RBSOG_EDEVICE;
     }
+    const Clock::time_point t_launched = Clock::now();
+    for (Request *r : sv->active) {
+        if (r->k + 1 < r->nsteps) continue;
+        const int64_t n = r->n;
+        r->fx.resize(n);
+        r->fy.resize(n);
+        r->fz.resize(n);
+        e = hipMemcpyAsync(r->fx.data(), r->d_frc, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->fy.data(), r->d_frc + n, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->fz.data(), r->d_frc + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost,
+                               sv->stream);
+        if (e != hipSuccess) {
+            err = std::string("force copy: ") + hipGetErrorString(e);
+            return RBSOG_EDEVICE;
+        }
+        finished.push_back(r);
+    }
     rc = rbsog::batch_fetch_results(bt, err);
     if (rc) return rc;
+    wait_s = std::chrono::duration<double>(Clock::now() - t_launched).count();
     const bool shared = sv->active.size() > 1;
     for (size_t i = 0; i < sv->active.size(); ++i) {
         Request *r = sv->active[i];
@@ -224,37 +264,14 @@ int tick(rbsog_server *sv, std::string &err)
             return RBSOG_EDEVICE;
         }
         for (int k = 0; k < 9; ++k) r->P[9 * r->k + k] = res.Ptot[k];
-        r->U[3 * r->k] = res.UN;
-        r->U[3 * r->k + 1] = res.UF;
-        r->U[3 * r->k + 2] = res.Uself;
+        if (sv->energy) {
+            r->U[3 * r->k] = res.UN;
+            r->U[3 * r->k + 1] = res.UF;
+            r->U[3 * r->k + 2] = res.Uself;
+        }
         r->shared_ticks += shared;
         sv->atom_steps += static_cast<double>(r->n);
         r->k += 1;
-    }
-    return RBSOG_OK;
-}
-
-// Copy the forces of finished requests out and release their memory.
-int retire(rbsog_server *sv, std::vector<Request *> &finished, std::string &err)
-{
-    for (Request *r : sv->active) {
-        if (r->k < r->nsteps) continue;
-        const int64_t n = r->n;
-        r->fx.resize(n);
-        r->fy.resize(n);
-        r->fz.resize(n);
-        hipError_t e = hipMemcpyAsync(r->fx.data(), r->d_frc, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(r->fy.data(), r->d_frc + n, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(r->fz.data(), r->d_frc + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost,
-                               sv->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
-        if (e != hipSuccess) {
-            err = std::string("force copy: ") + hipGetErrorString(e);
-            return RBSOG_EDEVICE;
-        }
-        finished.push_back(r);
     }
     return RBSOG_OK;
 }
@@ -284,22 +301,29 @@ void worker_main(rbsog_server *sv)
         for (Request *r : admitted) {
             if (rc == RBSOG_OK) rc = admit(sv, r, err);
         }
+        if (rc == RBSOG_OK) rc = admit_finish(sv, admitted, err);
+        const Clock::time_point ta = Clock::now();
+        double wait_s = 0.0;
         std::vector<Request *> finished;
         if (rc == RBSOG_OK) {
             sv->active.insert(sv->active.end(), admitted.begin(), admitted.end());
             std::vector<System *> sys;
             for (Request *r : sv->active) sys.push_back(&r->sys);
             if (!admitted.empty() || sv->batch.sys.size() != sys.size()) rc = rbsog::batch_set_systems(sv->batch, sys, err);
-            if (rc == RBSOG_OK) rc = tick(sv, err);
-            if (rc == RBSOG_OK) rc = retire(sv, finished, err);
+            if (rc == RBSOG_OK) rc = tick(sv, finished, wait_s, err);
         }
         const Clock::time_point t1 = Clock::now();
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->busy_s += std::chrono::duration<double>(t1 - t0).count();
+        sv->phase_s[0] += std::chrono::duration<double>(ta - t0).count();
+        sv->phase_s[1] += std::chrono::duration<double>(t1 - ta).count() - wait_s;
+        sv->phase_s[2] += wait_s;
         sv->ticks += 1;
         sv->peak_active = std::max<int64_t>(sv->peak_active, static_cast<int64_t>(sv->active.size()));
         if (rc != RBSOG_OK) {
             // a failed tick fails every request it held; the worker stops
+            // once nothing queued still reads their host copies
+            (void)hipStreamSynchronize(sv->stream);
             sv->worker_err = err;
             for (Request *r : sv->active) {
                 r->status = rc;
@@ -367,6 +391,18 @@ int rbsog_server_create(int32_t precision, int64_t pool_bytes, int32_t max_activ
     sv->pool.reset(sv->pool_bytes);
     sv->worker = std::thread(worker_main, sv);
     *out = sv;
+    return RBSOG_OK;
+}
+
+int rbsog_server_set_energy(rbsog_server *sv, int32_t on)
+{
+    if (!sv) return RBSOG_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->submitted > 0) {
+        sv->err = "the energy setting is fixed once a request was submitted";
+        return RBSOG_ESTATE;
+    }
+    sv->energy = on != 0;
     return RBSOG_OK;
 }
 
@@ -505,6 +541,9 @@ int rbsog_server_stats(rbsog_server *sv, double *host_stats)
     host_stats[5] = static_cast<double>(sv->peak_active);
     host_stats[6] = static_cast<double>(sv->pool.peak());
     host_stats[7] = static_cast<double>(sv->pending.size());
+    host_stats[8] = sv->phase_s[0];
+    host_stats[9] = sv->phase_s[1];
+    host_stats[10] = sv->phase_s[2];
     return RBSOG_OK;
 }
 

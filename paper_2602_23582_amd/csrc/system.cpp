@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "rbsog_impl.hpp"
@@ -96,6 +98,41 @@ void poly_fit(const double *c, const double *s, int M, double X, double mono[kPo
 
 // largest accepted truncation error of the polynomial form (FP32 rounding is ~1e-7)
 constexpr double kPolyTol = 5e-8;
+
+// The fit and its error check cost about a millisecond; systems set up with
+// the same weights, widths and cutoff (a served stream's, a batch's) share
+// one.  A cached fit is the fit the same inputs give, bit for bit.
+void poly_fit_cached(const double *c, const double *s, int M, double X, double mono[kPolyDeg + 1], double *err)
+{
+    struct Fit {
+        double mono[kPolyDeg + 1];
+        double err;
+    };
+    static std::mutex mu;
+    static std::map<std::vector<double>, Fit> cache;
+    std::vector<double> key;
+    key.reserve(2 * M + 2);
+    key.push_back(M);
+    key.push_back(X);
+    key.insert(key.end(), c, c + M);
+    key.insert(key.end(), s, s + M);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            std::memcpy(mono, it->second.mono, sizeof(it->second.mono));
+            *err = it->second.err;
+            return;
+        }
+    }
+    Fit f;
+    poly_fit(c, s, M, X, f.mono, &f.err);
+    std::memcpy(mono, f.mono, sizeof(f.mono));
+    *err = f.err;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache.size() >= 1024) cache.clear();
+    cache.emplace(std::move(key), f);
+}
 
 }  // namespace
 
@@ -224,8 +261,8 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
     if (p.precision == RBSOG_PREC_FP32C) {
         const double X = p.rc * p.rc;
         double mg[kPolyDeg + 1], mf[kPolyDeg + 1], eg = 1.0, ef = 1.0;
-        poly_fit(s.wt, s.s, p.M, X, mg, &eg);
-        poly_fit(s.w, s.s, p.M, X, mf, &ef);
+        poly_fit_cached(s.wt, s.s, p.M, X, mg, &eg);
+        poly_fit_cached(s.w, s.s, p.M, X, mf, &ef);
         tab.poly_err = static_cast<float>(std::max(eg, ef));
         if (eg <= kPolyTol && ef <= kPolyTol && !(p.flags & RBSOG_FLAG_EXP_FORM)) {
             tab.poly = 1;
@@ -389,18 +426,21 @@ void system_free(System &s)
     s.atom_mem = s.cell_mem = nullptr;
 }
 
-int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err)
+int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err,
+                    std::vector<float> *stage)
 {
     const int64_t n = s.n;
     hipError_t e;
     if (is_fp64(s.prm)) {
         e = hipMemcpyAsync(const_cast<void *>(s.desc.q), host_q, n * sizeof(double), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess && !stage) e = hipStreamSynchronize(stream);
     } else {
-        std::vector<float> q32(n);
-        for (int64_t i = 0; i < n; ++i) q32[i] = static_cast<float>(host_q[i]);
-        e = hipMemcpyAsync(const_cast<void *>(s.desc.q), q32.data(), n * sizeof(float), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);  // q32 leaves scope
+        std::vector<float> q32;
+        std::vector<float> &buf = stage ? *stage : q32;
+        buf.resize(n);
+        for (int64_t i = 0; i < n; ++i) buf[i] = static_cast<float>(host_q[i]);
+        e = hipMemcpyAsync(const_cast<void *>(s.desc.q), buf.data(), n * sizeof(float), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && !stage) e = hipStreamSynchronize(stream);  // q32 leaves scope
     }
     if (e != hipSuccess) {
         err = std::string("charge upload: ") + hipGetErrorString(e);
@@ -568,6 +608,13 @@ static std::vector<int64_t> plan_sizes(const Batch &b)
     return k;
 }
 
+// Ordering workgroups of a system: one per cell; a single-cell system (the
+// whole box within reach) splits its one cell into parts of kOrderPart keys.
+static int64_t order_parts(const System &s)
+{
+    return s.ncells == 1 ? (s.n + kOrderPart - 1) / kOrderPart : s.ncells;
+}
+
 static int build_plans(Batch &b, std::string &err)
 {
     int64_t len[kNumPlans] = {};
@@ -578,7 +625,7 @@ static int build_plans(Batch &b, std::string &err)
         len[kPlanPair] += (s->n + kPairWave - 1) / kPairWave + s->ncells;
         len[kPlanSk] += (s->n + kSkChunk - 1) / kSkChunk;
         len[kPlanReduce] += s->prm.P + 1 + kPairRed;
-        len[kPlanCell1] += s->ncells;
+        len[kPlanCell1] += order_parts(*s);
     }
     int64_t total = 0;
     for (int k = 0; k < kNumPlans; ++k) {
@@ -618,7 +665,7 @@ static int build_plans(Batch &b, std::string &err)
         put(kPlanScan, s, (y->ncells + kScanBlock - 1) / kScanBlock);
         put(kPlanSk, s, (y->n + kSkChunk - 1) / kSkChunk);
         put(kPlanReduce, s, y->prm.P + 1 + kPairRed);
-        put(kPlanCell1, s, y->ncells);
+        put(kPlanCell1, s, order_parts(*y));
     }
     // pair blocks grouped by the form of the SOG kernels (one launch per form)
     for (int f = 0; f < kNumForms; ++f) {

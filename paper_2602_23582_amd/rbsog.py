@@ -37,8 +37,8 @@ EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_forc
            "rbsog_batch_setup", "rbsog_batch_step", "rbsog_batch_rescale", "rbsog_batch_set_options",
            "rbsog_batch_autotune", "rbsog_batch_set_timing", "rbsog_batch_get_timing", "rbsog_batch_destroy",
            "rbsog_batch_last_error", "rbsog_server_create", "rbsog_server_submit", "rbsog_server_wait",
-           "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_last_error", "rbsog_npt_init",
-           "rbsog_npt_run"]
+           "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_set_energy", "rbsog_server_last_error",
+           "rbsog_npt_init", "rbsog_npt_run"]
 
 COUPLE_ANISO = 0
 COUPLE_SEMI = 1
@@ -107,6 +107,7 @@ def load(path: str | None = None):
         "rbsog_server_submit": (C.c_int, [vp, C.POINTER(rbsog_params), i64, pd, pd, pd, pd, pd, i32, d, pi64]),
         "rbsog_server_wait": (C.c_int, [vp, i64, d, pd, pd, pd, pd, pd, pd]),
         "rbsog_server_stats": (C.c_int, [vp, pd]),
+        "rbsog_server_set_energy": (C.c_int, [vp, C.c_int32]),
         "rbsog_server_destroy": (C.c_int, [vp]),
         "rbsog_server_last_error": (C.c_char_p, [vp]),
         "rbsog_npt_init": (C.c_int, [vp, C.POINTER(rbsog_npt_params), pd]),
@@ -436,7 +437,7 @@ class Batch:
 class Server:
     """The served form: wraps rbsog_server_create .. rbsog_server_destroy."""
 
-    def __init__(self, precision=PREC_FP32C, pool_bytes=1 << 30, max_active=4096, stream=None):
+    def __init__(self, precision=PREC_FP32C, pool_bytes=1 << 30, max_active=4096, stream=None, energy=True):
         L = load()
         stream = _stream_or_default(stream)
         h = C.c_void_p()
@@ -448,6 +449,11 @@ class Server:
         self.precision = precision
         self._n = {}
         self._steps = {}
+        if not energy:
+            self.set_energy(False)
+
+    def set_energy(self, on):
+        self._check(load().rbsog_server_set_energy(self._h, 1 if on else 0), "rbsog_server_set_energy")
 
     def _check(self, rc_, what):
         if rc_ != 0:
@@ -489,10 +495,10 @@ class Server:
                     latency_s=float(tm[1]), shared_ticks=int(tm[2]))
 
     def stats(self):
-        st = np.zeros(8)
+        st = np.zeros(11)
         self._check(load().rbsog_server_stats(self._h, _pd(st)), "rbsog_server_stats")
         keys = ["submitted", "completed", "ticks", "atom_steps", "busy_s", "peak_active", "peak_pool_bytes",
-                "waiting"]
+                "waiting", "admit_s", "launch_s", "wait_s"]
         return dict(zip(keys, st.tolist()))
 
     def close(self):

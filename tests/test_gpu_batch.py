@@ -247,7 +247,7 @@ def _requests(k=6, seed=3):
     return out
 
 
-def _alone_steps(torch, rb, spec, nsteps, growth):
+def _alone_steps(torch, rb, spec, nsteps, growth, energy=True):
     """The request's box law run through the single-system calls."""
     box = np.array(spec["box"], dtype=np.float64)
     with rb.Context(spec["q"], box, spec["rc"], P=spec["P"], seed=spec["seed"], system_id=spec["system_id"]) as ctx:
@@ -259,15 +259,16 @@ def _alone_steps(torch, rb, spec, nsteps, growth):
                 mu = (1.0 + growth * k) / (1.0 + growth * (k - 1))
                 ctx.rescale([mu, mu, mu], x, y, z)
             ctx.sample_modes(k, ctx.box)
-            ctx.force_virial(x, y, z, fx, fy, fz, energy=True)
+            ctx.force_virial(x, y, z, fx, fy, fz, energy=energy)
             Ps.append(ctx.pressure()[0])
         return torch.stack([fx, fy, fz], 1).cpu().numpy(), np.array(Ps)
 
 
-def test_server_results_alone_equal_results_in_the_mix(torch, rb):
+@pytest.mark.parametrize("energy", [True, False])
+def test_server_results_alone_equal_results_in_the_mix(torch, rb, energy):
     reqs = _requests()
     nsteps, growth = 3, 0.001
-    with rb.Server(max_active=64) as sv:
+    with rb.Server(max_active=64, energy=energy) as sv:
         tickets = [sv.submit(r["q"], r["pos"], r["box"], r["rc"], nsteps=nsteps, growth=growth, P=r["P"],
                              seed=r["seed"], system_id=r["system_id"]) for r in reqs]
         mix = [sv.wait(t, timeout=120.0) for t in tickets]
@@ -277,11 +278,12 @@ def test_server_results_alone_equal_results_in_the_mix(torch, rb):
     assert st["completed"] == len(reqs) and st["peak_active"] >= 2
     assert sum(m["shared_ticks"] for m in mix) > 0
     for r, m in zip(reqs, mix):
-        F1, P1 = _alone_steps(torch, rb, r, nsteps, growth)
+        F1, P1 = _alone_steps(torch, rb, r, nsteps, growth, energy)
         assert np.array_equal(m["forces"], F1), "forces in the mix differ from the request alone"
         assert np.array_equal(m["P"], P1), "pressures in the mix differ from the request alone"
+        assert energy or not np.any(m["U"]), "energies reported although the server skips them"
     # one request at a time gives the same bits too
-    with rb.Server(max_active=1) as sv:
+    with rb.Server(max_active=1, energy=energy) as sv:
         t = sv.submit(reqs[0]["q"], reqs[0]["pos"], reqs[0]["box"], reqs[0]["rc"], nsteps=nsteps, growth=growth,
                       P=reqs[0]["P"], seed=reqs[0]["seed"], system_id=reqs[0]["system_id"])
         solo = sv.wait(t, timeout=60.0)
@@ -302,6 +304,18 @@ def test_server_admission_is_bounded_by_the_memory_pool(torch, rb):
     assert all(r is not None for r in res)
     assert st["peak_pool_bytes"] <= pool
     assert st["completed"] == len(reqs)
+
+
+def test_server_energy_setting_is_fixed_after_the_first_request(torch, rb):
+    r = _requests(1, seed=4)[0]
+    with rb.Server(max_active=4) as sv:
+        sv.set_energy(False)
+        sv.set_energy(True)
+        t = sv.submit(r["q"], r["pos"], r["box"], r["rc"], nsteps=1, P=r["P"], seed=r["seed"])
+        with pytest.raises(rb.RBSOGError) as ei:
+            sv.set_energy(False)
+        assert ei.value.code == -6
+        assert sv.wait(t, timeout=60.0) is not None
 
 
 def test_server_rejects_a_request_larger_than_the_pool(torch, rb):

@@ -206,16 +206,33 @@ def test_fp32c_small_slab(torch, rb, orc, P, form, energy):
 
 
 @pytest.mark.parametrize("energy", [True, False])
-@pytest.mark.parametrize("n", [500, 2000, 6000, 9000])
+@pytest.mark.parametrize("n", [500, 2000, 2600, 6000, 9000])
 def test_fp32c_small_boxes_collapsed_cells(torch, rb, orc, n, energy):
-    """Served-stream systems: 500 atoms gives L = 17.1 A, rc = L/2, every
-    dimension searched whole; 2,000 and 6,000 give 2 and 3 cells per edge;
-    9,000 gives 4, the fewest the FP32 relative-coordinate filter takes."""
+    """Served-stream systems.  Fewer than three cells of rc per edge make the
+    whole box one cell: 500 atoms (L = 17.1 A, rc = L/2), 2,000 and 2,600
+    (L < 3 rc; 2,600 keys are ordered by three workgroups of 1,024).  6,000
+    gives 3 cells per edge; 9,000 gives 4, the fewest the FP32
+    relative-coordinate filter takes."""
     d = W.ionic_system(n, seed=n)
     with rb.Context(d["q"], d["L"], d["rc"], P=d["P"], seed=n, system_id=3) as ctx:
         g = gpu_step(torch, ctx, d["pos"], 1, d["L"], energy=energy)
     o = oracle_step(orc, d, d["L"], d["pos"], d["P"], n, 3, 1)
     check(g, o, TOL_FP32C, f"ionic n={n} energy {energy}")
+
+
+@pytest.mark.parametrize("n,precision", [(9000, "fp32c"), (9000, "fp64"), (30000, "fp32c")])
+def test_dense_cells_ordered_in_passes(torch, rb, orc, n, precision):
+    """Charges at 1 per cubic angstrom, rc 10.  9,000 (L = 20.8 A): one cell
+    of 9,000 atoms, its keys ranked by nine workgroups over LDS tiles of all
+    9,000.  30,000 (L = 31.1 A): 27 cells of about 1,110 atoms, each ranked by
+    one workgroup in two passes."""
+    d = W.ionic_system(n, seed=n, density=1.0, P=50)
+    assert d["L"][0] < (3 if n == 9000 else 4) * d["rc"]
+    prec = rb.PREC_FP32C if precision == "fp32c" else rb.PREC_FP64
+    with rb.Context(d["q"], d["L"], d["rc"], P=50, seed=n, system_id=1, precision=prec) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 2, d["L"])
+    o = oracle_step(orc, d, d["L"], d["pos"], 50, n, 1, 2)
+    check(g, o, TOL_FP32C if precision == "fp32c" else TOL_FP64, f"dense cells n={n} {precision}")
 
 
 def test_rho_of_distinct_modes(torch, rb, orc):
