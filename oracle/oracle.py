@@ -190,11 +190,14 @@ def proposal_pmf(m, L, s0):
 
 RECAL_PRINTED = 0
 RECAL_EXCHANGE = 1
+RECAL_SHARED = 2        # no recalibration: the r-chain's modes, weighted by P^nr/P^r
+RECAL_INDEPENDENT = 3   # a second MH chain with target P^nr (2P structure factors)
 
 
 def sample_modes(L, p: SOG, P, seed, system_id, step, variant=RECAL_PRINTED):
     """r-chain and nr-chain modes (P x 3 int32 each) and accepted-move counts.
-    variant 0: recalibration chain as printed; 1: exchange form."""
+    variant 0: recalibration chain as printed; 1: exchange form; 2: shared
+    proposal (m_nr = m_r); 3: an independent chain for P^nr."""
     m_r = np.zeros((P, 3), dtype=np.int32)
     m_nr = np.zeros((P, 3), dtype=np.int32)
     acc = np.zeros(2, dtype=np.int64)
@@ -273,6 +276,25 @@ def long_range_rb(q, pos, L, m_r, m_nr, Sr, Snr, forces=True, sample=None):
     return F, Pr.reshape(3, 3), Pnr.reshape(3, 3), UF.value
 
 
+def nonradial_shared(q, pos, L, p: SOG, m_r, Sr):
+    """Non-radial pressure from the r-chain's modes without recalibration
+    (the shared-proposal estimator the recalibration of Sec. 3.2 replaces):
+    importance sampling of eq. P_approx_nr's sum under P^r instead of P^nr,
+        -S^r/(8 V^2 P) sum_p R(k_p) |rho_p|^2 k_p k_p^T / |k_p|^4,
+    R = P^nr S^nr / (P^r S^r) = |k|^2 sum_l wt_l s_l^7 e_l / sum_l wt_l s_l^5 e_l.
+    Each sample's rho is evaluated on its own."""
+    L = _f64(L); V = float(np.prod(L))
+    m = np.ascontiguousarray(m_r, dtype=np.int32).reshape(-1, 3)
+    P = m.shape[0]
+    r = rho(q, pos, L, m)
+    acc = np.zeros((3, 3))
+    for t in range(P):
+        k = 2.0 * np.pi * m[t] / L
+        k2 = float(k @ k)
+        acc += ratio_nr(m[t], L, p) * abs(r[t]) ** 2 * np.outer(k, k) / (k2 * k2)
+    return -Sr / (8.0 * V * V * P) * acc
+
+
 def sog_kspace_full(q, pos, L, p: SOG, forces=True):
     q = _f64(q); x, y, z = _xyz(pos); n = q.shape[0]
     f = [np.zeros(n) for _ in range(3)] if forces else [None, None, None]
@@ -339,6 +361,8 @@ def rbsog_step(q, pos, L, p: SOG, P, seed, system_id, step, modes=None, sample=N
     Sr, Snr = norm_consts(L, p)
     FN, vir, UN = short_range(q, pos, L, p, method="cells", sample=sample)
     FF, Pr, Pnr, UF = long_range_rb(q, pos, L, m_r, m_nr, Sr, Snr, forces=True, sample=sample)
+    if variant == RECAL_SHARED:
+        Pnr = nonradial_shared(q, pos, L, p, m_r, Sr)
     US = self_energy(p, q)
     PN = vir_to_tensor(vir) / V
     return dict(F=FN + FF, FN=FN, FF=FF, UN=UN, UF=UF, Uself=US, U=UN + UF - US,

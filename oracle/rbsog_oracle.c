@@ -376,6 +376,20 @@ static double orc_weight(const int32_t m[3], const double L[3], int M, const dou
 }
 
 /*
+ * Importance weight of the independent non-radial chain: unnormalised P^nr,
+ * |k|^2 g(m) R(m) = |k|^4 sum_l wt_l s_l^7 e_l, over the pmf of a rounded
+ * Gaussian proposal ORC_NR_WIDEN^-1 times wider than the radial one (width
+ * parameter s_0 ORC_NR_WIDEN), so that the weight stays bounded in the tail
+ * where P^nr decays like |k|^4 e^{-s_0^2 |k|^2/4}.  0 at m = 0.
+ */
+#define ORC_NR_WIDEN 0.70710678118654752440
+static double orc_weight_nr(const int32_t m[3], const double L[3], int M, const double *wt, const double *s)
+{
+    if (m[0] == 0 && m[1] == 0 && m[2] == 0) return 0.0;
+    return orc_target_r(m, L, M, wt, s) * orc_ratio_nr(m, L, M, wt, s) / orc_proposal_pmf(m, L, s[0] * ORC_NR_WIDEN);
+}
+
+/*
  * The recalibration chain of Sec. 3.2 on a given proposal sequence: target
  * P^nr, proposal k* = props[t], acceptance
  *   min{1, P^nr(k*) P^r(k_t) / (P^nr(k_t) P^r(k*))} = min{1, R(k*)/R(k_t)},
@@ -416,6 +430,16 @@ void orc_recalibrate(int P, const int32_t *props, const double *u, const double 
  *  P^r x P^nr invariant even though consecutive r-states are correlated.
  * Both variants only ever visit accepted r-chain proposals and the initial
  * state, so at most P + 1 distinct modes appear.
+ * The two samplers the recalibration is weighed against (Sec. 3.2):
+ *  variant 2 (shared proposal, no recalibration): m_nr = m_r; the non-radial
+ *  estimator then weighs each r-chain mode by P^nr/P^r (see the oracle's
+ *  nonradial_shared).
+ *  variant 3 (independent proposals): a second independence MH chain with
+ *  target P^nr and a rounded Gaussian proposal of width parameter
+ *  s_0 ORC_NR_WIDEN (orc_weight_nr), its normals from streams (5, 6) and its
+ *  acceptance uniform the second one of stream 2; accept m* iff
+ *  u < w_nr(m*)/w_nr(m); it starts at the r-chain's initial state.  Up to
+ *  2P + 1 distinct modes.
  * Returns 0, or -1 when no nonzero initial state was drawn in 64 tries.
  * n_acc[0], n_acc[1] receive the accepted-move counts of the two chains.
  * Pinned by: chi^2 of long chains against the enumerated targets.
@@ -433,6 +457,8 @@ int orc_sample_modes(const double L[3], int M, const double *wt, const double *s
         found = !(cur[0] == 0 && cur[1] == 0 && cur[2] == 0);
     }
     if (!found) return -1;
+    int32_t cur0[3];
+    memcpy(cur0, cur, sizeof cur0);
     double wcur = orc_weight(cur, L, M, wt, s);
     double *unr = malloc(sizeof(double) * (P > 0 ? P : 1));
     int64_t acc_r = 0, acc_nr = 0;
@@ -472,7 +498,26 @@ int orc_sample_modes(const double L[3], int M, const double *wt, const double *s
         }
         memcpy(&m_r[3 * t], cur, sizeof cur);
     }
-    if (variant != 1) orc_recalibrate(P, m_r, unr, L, M, wt, s, m_nr, &acc_nr);
+    if (variant == 0) orc_recalibrate(P, m_r, unr, L, M, wt, s, m_nr, &acc_nr);
+    if (variant == 2) memcpy(m_nr, m_r, sizeof(int32_t) * 3 * (size_t)(P > 0 ? P : 0));
+    if (variant == 3) {
+        int32_t zc[3];
+        memcpy(zc, cur0, sizeof zc);
+        double wzc = orc_weight_nr(zc, L, M, wt, s);
+        for (int t = 0; t < P; ++t) {
+            double z[3];
+            int32_t prop[3];
+            orc_draw_proposal(seed, sys, step, (uint32_t)t, 5u, 6u, z, NULL);
+            orc_round_proposal(z, L, s[0] * ORC_NR_WIDEN, prop);
+            const double wprop = orc_weight_nr(prop, L, M, wt, s);
+            if (unr[t] < wprop / wzc) {
+                memcpy(zc, prop, sizeof zc);
+                wzc = wprop;
+                ++acc_nr;
+            }
+            memcpy(&m_nr[3 * t], zc, sizeof zc);
+        }
+    }
     free(unr);
     if (n_acc) {
         n_acc[0] = acc_r;

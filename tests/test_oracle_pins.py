@@ -373,6 +373,24 @@ def test_estimators_are_exactly_unbiased(orc):
     assert abs(E_U / Ufull - 1) < 1e-12
 
 
+def test_shared_proposal_estimator_is_exactly_unbiased(orc):
+    """The non-radial sum of eq. P_approx_nr importance-sampled under P^r (no
+    recalibration): E over P^r of S^r R(k) |rho|^2 k k^T/|k|^4 weights, with
+    the radial estimator, equals the full k-space pressure (App. A)."""
+    q, pos, L = _small_ionic(n_side=4, spacing=3.0, jitter=0.3, seed=21)
+    p = orc.sog(6.0, row=2, M=10)
+    Sr, Snr = orc.norm_consts(L, p)
+    modes = _enumerate_modes(L, p)
+    modes = modes[np.any(modes != 0, axis=1)]
+    Pr_prob = np.pi ** 1.5 * np.array([orc.target_r(m, L, p) for m in modes]) / Sr
+    E_P = np.zeros((3, 3))
+    for m, a in zip(modes, Pr_prob):
+        _, Pr, _, _ = orc.long_range_rb(q, pos, L, m[None], m[None], Sr, Snr, forces=False)
+        E_P += a * (Pr + orc.nonradial_shared(q, pos, L, p, m[None], Sr))
+    _, Pfull, _ = orc.sog_kspace_full(q, pos, L, p, forces=False)
+    assert _rel(E_P, Pfull) < 1e-12
+
+
 def test_proposal_pmf_normalised_and_matches_rounded_normals(orc):
     L = np.array([30.0, 26.0, 41.0])
     p = orc.sog(10.0, row=2, M=10)
@@ -471,9 +489,26 @@ def test_recalibration_on_correlated_states_is_biased(orc):
     assert abs(np.mean(1.0 / k2c) / e_nr - 1) < 0.01
 
 
-def test_batch_mean_converges_to_full_sum(orc):
+def test_independent_chain_samples_the_nonradial_target(orc):
+    """The independent sampler of the non-radial modes (a second independence
+    MH chain with a widened rounded-Gaussian proposal) samples P^nr, while the
+    r-chain beside it still samples P^r; the shared sampler reuses the r-chain."""
+    L, p, modes, pr, pnr = _mh_setup(orc)
+    m_r, m_nr, acc = orc.sample_modes(L, p, 300_000, seed=99, system_id=0, step=1,
+                                      variant=orc.RECAL_INDEPENDENT)
+    assert _chi2_z(m_r[::8], modes, pr) < 5
+    assert _chi2_z(m_nr[::8], modes, pnr) < 5
+    assert 0.3 < acc[1] / 300_000 < 0.95
+    m_r2, m_nr2, acc2 = orc.sample_modes(L, p, 500, seed=99, system_id=0, step=1, variant=orc.RECAL_SHARED)
+    assert np.array_equal(m_r2, m_nr2) and acc2[1] == 0
+    assert np.array_equal(m_r2, m_r[:500])  # the r-chain does not depend on the non-radial sampler
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_batch_mean_converges_to_full_sum(orc, variant):
     """Batch means of the stochastic pressure over many independent steps
-    converge to the deterministic P^F of Theorem 1 (unbiasedness, Prop. 2)."""
+    converge to the deterministic P^F of Theorem 1 (unbiasedness, Prop. 2),
+    for every non-radial sampler."""
     q, pos, L = _small_ionic(n_side=4, spacing=3.0, jitter=0.3, seed=5)
     p = orc.sog(6.0, row=2, M=10)
     Sr, Snr = orc.norm_consts(L, p)
@@ -481,8 +516,10 @@ def test_batch_mean_converges_to_full_sum(orc):
     R, P = 1500, 50
     acc = []
     for step in range(R):
-        m_r, m_nr, _ = orc.sample_modes(L, p, P, seed=1234, system_id=7, step=step)
+        m_r, m_nr, _ = orc.sample_modes(L, p, P, seed=1234, system_id=7, step=step, variant=variant)
         _, Pr, Pnr, UF = orc.long_range_rb(q, pos, L, m_r, m_nr, Sr, Snr, forces=False)
+        if variant == orc.RECAL_SHARED:
+            Pnr = orc.nonradial_shared(q, pos, L, p, m_r, Sr)
         acc.append((Pr + Pnr).ravel())
     acc = np.array(acc)
     mean, sem = acc.mean(0), acc.std(0, ddof=1) / np.sqrt(R)
