@@ -250,6 +250,51 @@ def npt_bench(torch, ctx, d, x, y, z, nsteps, force_ms):
             "note": "per call the starting state is evaluated once more (nsteps + 1 evaluations)"}
 
 
+SAMPLERS = {0: "recalibrated (as printed)", 1: "recalibrated (exchange form)", 2: "shared proposal, no recalibration",
+            3: "independent chain (2P structure factors)"}
+
+
+def variance_study(torch, reps, Ps=(50, 100, 200), sizes=(2000, 16000)):
+    """Variance of the long-range pressure estimator P^{F,r*} + P^{F,nr*}
+    under the four samplers of the non-radial modes (Sec. 3.2), against P and
+    N: seeded ionic systems at 0.1 A^-3 (rc 10 A).  For each sampler, P and
+    system size, reps steps (the step index draws the modes) give the variance
+    of every tensor component about its mean; reported as the mean over the
+    diagonal and over the off-diagonal components, with the mean number of
+    distinct modes (structure factors) per step and their product
+    (variance x work).  The radial estimator and the force are the same under
+    every sampler."""
+    from paper_2602_23582_amd import rbsog
+    from paper_2602_23582_amd import workloads as W
+    rows = []
+    for n in sizes:
+        d = W.ionic_system(n, seed=11, P=100)
+        x, y, z = (torch.tensor(np.ascontiguousarray(d["pos"][:, k]), dtype=torch.float64, device="cuda")
+                   for k in range(3))
+        fx, fy, fz = (torch.empty_like(x) for _ in range(3))
+        for variant in SAMPLERS:
+            for P in Ps:
+                vals, nd = [], []
+                with rbsog.Context(d["q"], d["L"], d["rc"], P=P, seed=31, system_id=n,
+                                   recalibration=variant) as ctx:
+                    for step in range(reps):
+                        ctx.sample_modes(step, d["L"])
+                        ctx.force_virial(x, y, z, fx, fy, fz, energy=False)
+                        _, parts = ctx.pressure()
+                        vals.append((parts[1] + parts[2]).ravel())
+                        nd.append(ctx.step_info()["nd"])
+                a = np.array(vals)
+                v = np.var(a, axis=0, ddof=1)
+                # standard error of each component's variance from its fourth central moment
+                m4 = np.mean((a - a.mean(0)) ** 4, axis=0)
+                se = np.sqrt(np.maximum(m4 - v * v, 0.0) / len(a))
+                vd, vo = float(v[[0, 4, 8]].mean()), float(v[[1, 2, 5]].mean())
+                rows.append({"n": n, "sampler": SAMPLERS[variant], "P": P, "var_diag": vd, "var_offdiag": vo,
+                             "var_diag_rel_se": float(se[[0, 4, 8]].mean() / 3 ** 0.5 / vd),
+                             "modes_per_step": float(np.mean(nd)), "var_diag_x_modes": vd * float(np.mean(nd))})
+    return {"system": "ionic, 0.1 A^-3, rc 10 A, +-1e on a jittered lattice", "reps": reps, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +310,8 @@ def main():
     ap.add_argument("--served", type=int, default=4096, help="requests of the served-stream run (0: skip)")
     ap.add_argument("--npt-steps", type=int, default=20, help="Langevin NPT steps timed after the main run (0: skip)")
     ap.add_argument("--served-pool-mib", type=int, default=4096)
+    ap.add_argument("--variance-reps", type=int, default=1000,
+                    help="steps per sampler, P and size in the estimator-variance study (0: skip)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -379,6 +426,9 @@ def main():
     if args.npt_steps > 0 and not args.graph:
         log(f"NPT integration: {args.npt_steps} steps")
         out["npt"] = npt_bench(torch, ctx, d, x, y, z, args.npt_steps, ms_step)
+    if args.variance_reps > 0 and not args.graph:
+        log(f"estimator variance: {args.variance_reps} steps per sampler, P and size")
+        out["variance"] = variance_study(torch, args.variance_reps)
     if args.served > 0:
         log(f"served stream: {args.served} requests")
         out["served"] = served_bench(args.served, 5, args.served_pool_mib << 20)

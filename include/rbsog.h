@@ -59,6 +59,9 @@ extern "C" {
 
 #define RBSOG_RECAL_PRINTED 0  /* recalibration chain as printed in Sec. 3.2      */
 #define RBSOG_RECAL_EXCHANGE 1 /* swap of the two chain states on acceptance      */
+/* The samplers the recalibration is weighed against (Sec. 3.2): */
+#define RBSOG_RECAL_SHARED 2      /* no recalibration: the r-chain's modes, weighted by P^nr/P^r */
+#define RBSOG_RECAL_INDEPENDENT 3 /* a second MH chain for P^nr: up to 2P+1 modes, P <= 512      */
 
 #define RBSOG_MAX_M 64
 
@@ -80,7 +83,16 @@ typedef struct rbsog_ctx rbsog_ctx;
  *                   system_id and step must be < 2^32.
  *  coulomb_k        prefactor applied to every energy, force and pressure.
  *  precision        RBSOG_PREC_FP64 or RBSOG_PREC_FP32C.
- *  recalibration    RBSOG_RECAL_PRINTED or RBSOG_RECAL_EXCHANGE.
+ *  recalibration    how the non-radial modes of eq. P_approx_nr are drawn:
+ *                   RBSOG_RECAL_PRINTED (default) or RBSOG_RECAL_EXCHANGE
+ *                   recalibrate the r-chain's states (Sec. 3.2);
+ *                   RBSOG_RECAL_SHARED uses the r-chain's modes themselves,
+ *                   each weighted by P^nr/P^r (times S^r/S^nr);
+ *                   RBSOG_RECAL_INDEPENDENT draws a second independence MH
+ *                   chain for P^nr (Philox streams 5, 6; a rounded Gaussian
+ *                   proposal sqrt(2) times wider than the radial one), so
+ *                   up to 2P + 1 distinct modes and P <= 512.  The radial
+ *                   estimator, the force and the energy always use the r-chain.
  *  flags            0, or RBSOG_FLAG_EXP_FORM.  In FP32C the short-range
  *                   sums sum_l wt_l exp(-r^2/s_l^2) and sum_l w_l exp(-r^2/s_l^2)
  *                   are evaluated as degree-10 polynomials in r^2 on

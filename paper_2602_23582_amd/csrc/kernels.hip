@@ -157,11 +157,16 @@ __device__ void draw_normals(const SampArgs &a, uint32_t t, uint32_t sxy, uint32
     z[2] = r2 * cos(2.0 * kPi * u4);
 }
 
+// The independent non-radial chain's proposal is the radial one with s0
+// scaled by this factor (sqrt(2) wider): its weight P^nr/q then stays bounded
+// where P^nr decays like |k|^4 exp(-s0^2 |k|^2/4).
+constexpr double kNrWiden = 0.70710678118654752440;
+
 // App. D: m*_xi = round(h^T u) with u_xi ~ N(0, 1/(2 pi^2 s0^2)), i.e. round(sig_xi z_xi)
-__device__ void round_proposal(const SampArgs &a, const double z[3], int m[3])
+__device__ void round_proposal(const SampArgs &a, const double z[3], int m[3], double widen = 1.0)
 {
 #pragma clang fp contract(off)
-    const double s0 = a.tab->s[0];
+    const double s0 = a.tab->s[0] * widen;
     for (int d = 0; d < 3; ++d) {
         const double sig = a.L[d] / (sqrt(2.0) * kPi * s0);
         double v = round(sig * z[d]);
@@ -171,13 +176,15 @@ __device__ void round_proposal(const SampArgs &a, const double z[3], int m[3])
 }
 
 // importance weight w = P^r(m)/q(m) (unnormalised, 0 at m = 0) and the
-// recalibration ratio R = P^nr(m)/P^r(m) (unnormalised)
-__device__ void mode_weights(const SampArgs &a, const int m[3], double *w, double *R)
+// recalibration ratio R = P^nr(m)/P^r(m) (unnormalised); with wnr, also the
+// independent non-radial chain's weight P^nr(m)/q'(m), q' the widened proposal
+__device__ void mode_weights(const SampArgs &a, const int m[3], double *w, double *R, double *wnr = nullptr)
 {
 #pragma clang fp contract(off)
     if (m[0] == 0 && m[1] == 0 && m[2] == 0) {
         *w = 0.0;
         *R = 0.0;
+        if (wnr) *wnr = 0.0;
         return;
     }
     double k2 = 0.0;
@@ -193,25 +200,31 @@ __device__ void mode_weights(const SampArgs &a, const int m[3], double *w, doubl
         a7 += t->wt[l] * t->s7[l] * e;
     }
     const double target = k2 * a5;
-    double q = 1.0;
-    for (int d = 0; d < 3; ++d) {
-        const double sig = a.L[d] / (sqrt(2.0) * kPi * t->s[0]);
-        const double c = 1.0 / (sqrt(2.0) * sig);
-        double qd;
-        if (m[d] == 0) {
-            qd = erf(0.5 * c);
-        } else {
-            const double am = fabs(static_cast<double>(m[d]));
-            qd = 0.5 * (erfc((am - 0.5) * c) - erfc((am + 0.5) * c));
+    auto pmf = [&](double s0) {
+        double q = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            const double sig = a.L[d] / (sqrt(2.0) * kPi * s0);
+            const double c = 1.0 / (sqrt(2.0) * sig);
+            double qd;
+            if (m[d] == 0) {
+                qd = erf(0.5 * c);
+            } else {
+                const double am = fabs(static_cast<double>(m[d]));
+                qd = 0.5 * (erfc((am - 0.5) * c) - erfc((am + 0.5) * c));
+            }
+            q *= qd;
         }
-        q *= qd;
-    }
-    *w = target / q;
+        return q;
+    };
+    *w = target / pmf(t->s[0]);
     *R = k2 * a7 / a5;
+    if (wnr) *wnr = target * *R / pmf(t->s[0] * kNrWiden);
 }
 
 // Algorithm 1 steps 2-3 for one system per workgroup of 256 threads.
-// Slot 0 holds the chain's initial state, slot t+1 the t-th proposal.
+// Slot 0 holds the chain's initial state, slot t+1 the t-th proposal, and
+// with the independent non-radial chain slot P+1+t that chain's t-th proposal
+// (its weight in s_w).
 __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp)
 {
 #pragma clang fp contract(off)
@@ -223,6 +236,7 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
     __shared__ uint8_t s_used[kMaxP + 1];
     __shared__ int s_cnt_r[kMaxP + 1], s_cnt_nr[kMaxP + 1];
     __shared__ int s_init, s_nd;
+    __shared__ double s_wnr0;
     __shared__ long long s_acc[2];
 
     const SysDesc &D = desc[blockIdx.x];
@@ -245,6 +259,8 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
 
     const int tid = threadIdx.x;
     const int P = a.P;
+    const bool indep = a.variant == RBSOG_RECAL_INDEPENDENT;
+    const int nslots = indep ? 2 * P + 1 : P + 1;  // == mcap
     if (tid == 0) s_init = 64;
     __syncthreads();
     // initial state: first nonzero draw of the initial-state streams (3, 4)
@@ -258,7 +274,9 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
         const int first = ball ? __ffsll(ball) - 1 : 64;
         if (tid == first) {
             s_mode[0] = make_int3(m[0], m[1], m[2]);
-            mode_weights(a, m, &s_w[0], &s_R[0]);
+            double wnr0;
+            mode_weights(a, m, &s_w[0], &s_R[0], &wnr0);
+            s_wnr0 = wnr0;
             s_init = first;
         }
     }
@@ -273,8 +291,16 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
                                       make_uint2(a.key0, a.key1));
         s_ur[t] = unit_open(o.x, o.y);
         s_unr[t] = unit_open(o.z, o.w);
+        if (indep) {
+            draw_normals(a, static_cast<uint32_t>(t), 5u, 6u, z);
+            round_proposal(a, z, m, kNrWiden);
+            double w, R;
+            s_mode[P + 1 + t] = make_int3(m[0], m[1], m[2]);
+            mode_weights(a, m, &w, &R, &s_w[P + 1 + t]);
+            s_R[P + 1 + t] = R;
+        }
     }
-    for (int s = tid; s <= P; s += blockDim.x) {
+    for (int s = tid; s < nslots; s += blockDim.x) {
         s_used[s] = 0;
         s_cnt_r[s] = 0;
         s_cnt_nr[s] = 0;
@@ -317,6 +343,31 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
                 s_sr[t] = static_cast<int16_t>(cur);
                 s_snr[t] = static_cast<int16_t>(zs);
             }
+        } else if (a.variant == RBSOG_RECAL_SHARED || indep) {
+            for (int t = 0; t < P; ++t) {
+                if (s_ur[t] < s_w[t + 1] / wcur) {
+                    cur = t + 1;
+                    wcur = s_w[t + 1];
+                    ++acc_r;
+                }
+                s_sr[t] = static_cast<int16_t>(cur);
+            }
+            if (indep) {
+                // its own chain from the same initial state, target P^nr
+                int zs = 0;
+                double wz = s_wnr0;
+                for (int t = 0; t < P; ++t) {
+                    const int prop = P + 1 + t;
+                    if (s_unr[t] < s_w[prop] / wz) {
+                        zs = prop;
+                        wz = s_w[prop];
+                        ++acc_nr;
+                    }
+                    s_snr[t] = static_cast<int16_t>(zs);
+                }
+            } else {
+                for (int t = 0; t < P; ++t) s_snr[t] = s_sr[t];
+            }
         } else {
             for (int t = 0; t < P; ++t) {
                 if (s_ur[t] < s_w[t + 1] / wcur) {
@@ -348,7 +399,7 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
     }
     __syncthreads();
     // representative of each used slot: the first used slot with the same mode
-    for (int s = tid; s <= P; s += blockDim.x) {
+    for (int s = tid; s < nslots; s += blockDim.x) {
         int rep = s;
         if (s_used[s]) {
             const int3 ms = s_mode[s];
@@ -364,7 +415,7 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
     __syncthreads();
     if (tid == 0) {
         int nd = 0;
-        for (int s = 0; s <= P; ++s) {
+        for (int s = 0; s < nslots; ++s) {
             if (s_used[s] && s_rep[s] == s) {
                 s_didx[s] = static_cast<int16_t>(nd);
                 a.modes[nd] = make_int4(s_mode[s].x, s_mode[s].y, s_mode[s].z, 0);
@@ -1513,6 +1564,8 @@ __global__ __launch_bounds__(256) void k_rho_reduce(const SysDesc *__restrict__ 
 // multiplicities c^r_d, c^nr_d (one workgroup per system):
 //   P^{F,r*}  =  S^r/(4 V^2 P) sum_d c^r_d |rho_d|^2/|k_d|^2 I            (eq. P_approx_r)
 //   P^{F,nr*} = -S^nr/(8 V^2 P) sum_d c^nr_d |rho_d|^2 k_d k_d^T/|k_d|^4  (eq. P_approx_nr)
+//     (shared sampler: the r-chain's modes, -S^r/(8 V^2 P) sum_d c^r_d R_d |rho_d|^2 k_d k_d^T/|k_d|^4
+//      with R_d = |k_d|^2 sum_l wt_l s_l^7 e_l / sum_l wt_l s_l^5 e_l the ratio P^nr S^nr/(P^r S^r))
 //   U^{F*}    =  S/(2 V P) sum_d c^r_d |rho_d|^2/|k_d|^2, S = S^r/2
 //   force coefficients a_d = (S/(P V)) c^r_d/|k_d|^2                      (eq. f_approx)
 template <class T>
@@ -1527,6 +1580,7 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
     const double V = L[0] * L[1] * L[2];
     const double S = 0.5 * St.Sr;
     const int P = D.P;
+    const bool shared = D.variant == RBSOG_RECAL_SHARED;
     // short-range virial, energy and pair count: the slices in order
     if (tid < 8) {
         double s = 0.0;
@@ -1546,7 +1600,16 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
         const double r2 = re * re + im * im;
         const int cr = D.cnt[d], cnr = D.cnt[D.mcap + d];
         sr += cr * r2 / k2;
-        const double g = cnr * r2 / (k2 * k2);
+        double g = cnr * r2 / (k2 * k2);
+        if (shared) {
+            double a5 = 0.0, a7 = 0.0;
+            for (int l = 0; l < D.tab.M; ++l) {
+                const double e = exp(-D.tab.s[l] * D.tab.s[l] * k2 / 4.0);
+                a5 += D.tab.wt[l] * D.tab.s5[l] * e;
+                a7 += D.tab.wt[l] * D.tab.s7[l] * e;
+            }
+            g *= k2 * a7 / a5;
+        }
         snr[0] += g * k[0] * k[0];
         snr[1] += g * k[1] * k[1];
         snr[2] += g * k[2] * k[2];
@@ -1573,7 +1636,7 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
         StepResults *r = D.res;
         const double ck = D.ck;
         const double pr = ck * St.Sr / (4.0 * V * V * P) * sr;
-        const double cnr = -ck * St.Snr / (8.0 * V * V * P);
+        const double cnr = -ck * (shared ? St.Sr : St.Snr) / (8.0 * V * V * P);
         const int ix[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
         for (int al = 0; al < 3; ++al)
             for (int be = 0; be < 3; ++be) {

@@ -35,6 +35,13 @@ constexpr int kPolyDeg = 10;       // degree of the FP32C polynomial form of the
 constexpr int kSuperCells = 4;     // most cells stacked in z into one pair-block segment
 constexpr int kOrderPart = 1024;   // keys one ordering workgroup ranks in a single-cell system
 
+// Distinct modes a step can visit: the r-chain's initial state and proposals,
+// plus the independent non-radial chain's proposals when it is drawn.
+inline int mode_cap(const rbsog_params &p)
+{
+    return p.recalibration == RBSOG_RECAL_INDEPENDENT ? 2 * p.P + 1 : p.P + 1;
+}
+
 // SOG tables read by the kernels (device memory, uniform loads).
 struct SogTables {
     int M;
@@ -74,7 +81,7 @@ struct SysDesc {
     int64_t pair_cap;     // pair-block slots allocated: ceil(n/64) + ncells_cap
     int64_t sk_blocks;    // structure-factor workgroups: ceil(n/kSkChunk)
     int64_t ncells_cap;   // cells allocated
-    int32_t P, M, variant, mcap;  // mcap = P + 1: stride of the per-mode arrays
+    int32_t P, M, variant, mcap;  // mcap = mode_cap(params): stride of the per-mode arrays
     uint32_t key0, key1, sys, pad;
     double ck, Uself;
     // internal device buffers

@@ -35,7 +35,7 @@ AtomLayout atom_layout(const rbsog_params &p, int64_t n)
 {
     const bool f64 = is_fp64(p);
     const size_t rsz = f64 ? 8 : 4, fsz = f64 ? 8 : 4, recsz = f64 ? 32 : 16;
-    const size_t mcap = static_cast<size_t>(p.P) + 1;
+    const size_t mcap = static_cast<size_t>(mode_cap(p));
     const size_t skb = static_cast<size_t>((n + kSkChunk - 1) / kSkChunk);
     AtomLayout a{};
     a.q = align_up(n * rsz);
@@ -199,8 +199,12 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
         err = "unknown precision";
         return RBSOG_EINVAL;
     }
-    if (p.recalibration != RBSOG_RECAL_PRINTED && p.recalibration != RBSOG_RECAL_EXCHANGE) {
+    if (p.recalibration < RBSOG_RECAL_PRINTED || p.recalibration > RBSOG_RECAL_INDEPENDENT) {
         err = "unknown recalibration";
+        return RBSOG_EINVAL;
+    }
+    if (p.recalibration == RBSOG_RECAL_INDEPENDENT && 2 * p.P + 1 > kMaxModes) {
+        err = "the independent non-radial chain takes P <= 512";
         return RBSOG_EINVAL;
     }
     if (p.system_id >> 32) {
@@ -283,7 +287,7 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
     d.P = p.P;
     d.M = p.M;
     d.variant = p.recalibration;
-    d.mcap = p.P + 1;
+    d.mcap = mode_cap(p);
     d.key0 = static_cast<uint32_t>(p.seed);
     d.key1 = static_cast<uint32_t>(p.seed >> 32);
     d.sys = static_cast<uint32_t>(p.system_id);
@@ -624,7 +628,7 @@ static int build_plans(Batch &b, std::string &err)
         len[kPlanScan] += (s->ncells + kScanBlock - 1) / kScanBlock;
         len[kPlanPair] += (s->n + kPairWave - 1) / kPairWave + s->ncells;
         len[kPlanSk] += (s->n + kSkChunk - 1) / kSkChunk;
-        len[kPlanReduce] += s->prm.P + 1 + kPairRed;
+        len[kPlanReduce] += mode_cap(s->prm) + kPairRed;
         len[kPlanCell1] += order_parts(*s);
     }
     int64_t total = 0;
@@ -664,7 +668,7 @@ static int build_plans(Batch &b, std::string &err)
         put(kPlanCells, s, (y->ncells + 1 + kCellBlock - 1) / kCellBlock);
         put(kPlanScan, s, (y->ncells + kScanBlock - 1) / kScanBlock);
         put(kPlanSk, s, (y->n + kSkChunk - 1) / kSkChunk);
-        put(kPlanReduce, s, y->prm.P + 1 + kPairRed);
+        put(kPlanReduce, s, mode_cap(y->prm) + kPairRed);
         put(kPlanCell1, s, order_parts(*y));
     }
     // pair blocks grouped by the form of the SOG kernels (one launch per form)

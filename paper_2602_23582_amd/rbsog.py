@@ -20,6 +20,8 @@ PREC_FP64 = 0
 PREC_FP32C = 1
 RECAL_PRINTED = 0
 RECAL_EXCHANGE = 1
+RECAL_SHARED = 2
+RECAL_INDEPENDENT = 3
 FLAG_EXP_FORM = 1
 MAX_P = 1024
 MAX_MODES = MAX_P + 1

@@ -92,7 +92,9 @@ def test_setup_rejects_bad_input_before_touching_the_device(lib):
     assert _setup(lib, q, box, M=0)[0] == -1
     assert _setup(lib, q, box, M=65)[0] == -1
     assert _setup(lib, q, box, precision=7)[0] == -1
-    assert _setup(lib, q, box, recalibration=3)[0] == -1
+    assert _setup(lib, q, box, recalibration=4)[0] == -1
+    assert _setup(lib, q, box, recalibration=-1)[0] == -1
+    assert _setup(lib, q, box, P=513, recalibration=3)[0] == -1     # independent chain: 2P + 1 mode slots
     assert _setup(lib, q, box, system_id=1 << 33)[0] == -1
     assert _setup(lib, np.array([1.0, np.inf]), box)[0] == -1
     # zero atoms

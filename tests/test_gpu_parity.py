@@ -89,11 +89,17 @@ def check(g, o, tol, what=""):
 @pytest.mark.parametrize("box,rc,P", [((30.0, 30.0, 30.0), 10.0, 100), ((200.0, 200.0, 500.0), 12.0, 400),
                                       ((17.1, 17.1, 17.1), 8.55, 50), ((66.88, 66.88, 66.88), 10.0, 1024),
                                       ((41.0, 23.0, 60.0), 11.0, 200)])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_modes_bit_exact(torch, rb, orc, box, rc, P, variant):
     q = np.array([1.0, -1.0, 0.5, -0.5])
     box = np.array(box)
     p = orc.sog(rc, row=2, M=10)
+    if variant == 3 and P > 512:
+        # the independent chain's proposals need P more mode slots
+        with pytest.raises(rb.RBSOGError) as ei:
+            rb.Context(q, box, rc, P=P, recalibration=variant)
+        assert ei.value.code == -1
+        return
     for seed, sys in ((1, 0), (12345, 7), (2**40 + 3, 99)):
         with rb.Context(q, box, rc, P=P, seed=seed, system_id=sys, recalibration=variant) as ctx:
             for step in (0, 1, 17, 4_000_000_000):
@@ -168,8 +174,20 @@ def test_device_rescale_matches_host_rescale(torch, rb):
 FORMS = [0, 1]
 
 
+@pytest.mark.parametrize("variant", [2, 3])
+def test_fp64_lattice_comparison_samplers(torch, rb, orc, variant):
+    """The shared-proposal and independent-chain samplers of the non-radial
+    modes, FP64 path, two steps."""
+    d = W.c1_lattice(jitter=0.2)
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=5, precision=rb.PREC_FP64, recalibration=variant) as ctx:
+        for step in (0, 7):
+            g = gpu_step(torch, ctx, d["pos"], step, d["L"])
+            o = oracle_step(orc, d, d["L"], d["pos"], 100, 5, 0, step, variant=variant)
+            check(g, o, TOL_FP64, f"fp64 sampler {variant} step {step}")
+
+
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_fp32c_lattice(torch, rb, orc, variant, form):
     d = W.c1_lattice(jitter=0.2)
     with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=9, recalibration=variant, flags=form) as ctx:
