@@ -686,10 +686,16 @@ static int build_plans(Batch &b, std::string &err)
 int batch_upload(Batch &b, std::string &err)
 {
     if (b.sys.empty()) return RBSOG_OK;
-    int rc = wait_uploads(b, err);
-    if (rc) return rc;
     const int64_t S = static_cast<int64_t>(b.sys.size());
+    const std::vector<int64_t> key = plan_sizes(b);
+    const bool plans = b.plan_dirty || key != b.plan_key;
+    // the pinned descriptor and plan buffers are rewritten only once the copies
+    // that last read them have run; a step that rewrites neither does not wait
+    int rc = RBSOG_OK;
+    if (b.desc_dirty || plans) rc = wait_uploads(b, err);
+    if (rc) return rc;
     hipError_t e = hipSuccess;
+    bool queued = false;
     if (b.desc_dirty) {
         for (int64_t s = 0; s < S; ++s) {
             b.h_desc[s] = b.sys[s]->desc;
@@ -697,9 +703,9 @@ int batch_upload(Batch &b, std::string &err)
         }
         e = hipMemcpyAsync(b.d_desc, b.h_desc, S * sizeof(SysDesc), hipMemcpyHostToDevice, b.stream);
         b.desc_dirty = false;
+        queued = true;
     }
-    const std::vector<int64_t> key = plan_sizes(b);
-    if (e == hipSuccess && (b.plan_dirty || key != b.plan_key)) {
+    if (e == hipSuccess && plans) {
         rc = build_plans(b, err);
         if (rc) return rc;
         int64_t total = 0;
@@ -707,9 +713,12 @@ int batch_upload(Batch &b, std::string &err)
         e = hipMemcpyAsync(b.d_plan, b.h_plan, total * sizeof(int2), hipMemcpyHostToDevice, b.stream);
         b.plan_key = key;
         b.plan_dirty = false;
+        queued = true;
     }
-    if (e == hipSuccess) e = hipEventRecord(b.up_done, b.stream);
-    b.up_pending = true;
+    if (e == hipSuccess && queued) {
+        e = hipEventRecord(b.up_done, b.stream);
+        b.up_pending = true;
+    }
     // per-step data: the next pinned buffer of the ring, reused once the copy
     // that last read it has run
     if (e == hipSuccess) {
