@@ -34,6 +34,12 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Pinned staging for the uploads of admitted requests: copies from it run
+// behind a step in flight without holding the host, where copies from the
+// requests' pageable buffers would wait for the stream.  Refilled every tick;
+// a tick that admits more than it holds uploads the rest from pageable memory.
+constexpr size_t kStageBytes = size_t(64) << 20;
+
 // First-fit allocator over offsets of one device allocation.
 class Pool {
 public:
@@ -114,6 +120,8 @@ struct rbsog_server {
     int device = 0;
     hipStream_t stream = nullptr;
     char *pool_mem = nullptr;
+    char *stage = nullptr;  // pinned, kStageBytes (null if it could not be allocated)
+    size_t stage_used = 0;
     Pool pool;
     Batch batch;
     std::mutex mu;
@@ -140,7 +148,7 @@ size_t request_bytes(const rbsog_params &p, int64_t n, int64_t max_cells)
 }
 
 // Queue the upload of an admitted request's state into its pool memory; the
-// host copies stay alive until admit_finish has synchronised the stream.
+// host copies stay alive until a synchronisation of the stream has covered it.
 int admit(rbsog_server *sv, Request *r, std::string &err)
 {
     char *base = sv->pool_mem + r->off;
@@ -153,9 +161,33 @@ int admit(rbsog_server *sv, Request *r, std::string &err)
     r->d_pos = reinterpret_cast<double *>(base);
     base += align_up(3 * r->n * sizeof(double));
     r->d_frc = reinterpret_cast<double *>(base);
+    const int64_t n = r->n;
+    const bool f64 = s.prm.precision == RBSOG_PREC_FP64;
+    const size_t qb = align_up(n * (f64 ? sizeof(double) : sizeof(float))), pb = 3 * n * sizeof(double);
+    if (sv->stage && sv->stage_used + qb + pb <= kStageBytes) {
+        char *p = sv->stage + sv->stage_used;
+        sv->stage_used += align_up(qb + pb);
+        if (f64) {
+            std::memcpy(p, r->q.data(), n * sizeof(double));
+        } else {
+            float *q32 = reinterpret_cast<float *>(p);
+            for (int64_t i = 0; i < n; ++i) q32[i] = static_cast<float>(r->q[i]);
+        }
+        double *xyz = reinterpret_cast<double *>(p + qb);
+        std::memcpy(xyz, r->x.data(), n * sizeof(double));
+        std::memcpy(xyz + n, r->y.data(), n * sizeof(double));
+        std::memcpy(xyz + 2 * n, r->z.data(), n * sizeof(double));
+        hipError_t e = hipMemcpyAsync(const_cast<void *>(s.desc.q), p, n * (f64 ? sizeof(double) : sizeof(float)),
+                                      hipMemcpyHostToDevice, sv->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(r->d_pos, xyz, pb, hipMemcpyHostToDevice, sv->stream);
+        if (e != hipSuccess) {
+            err = std::string("request upload: ") + hipGetErrorString(e);
+            return RBSOG_EDEVICE;
+        }
+        return RBSOG_OK;
+    }
     int rc = rbsog::system_upload_q(s, r->q.data(), sv->stream, err, &r->q32);
     if (rc) return rc;
-    const int64_t n = r->n;
     hipError_t e = hipMemcpyAsync(r->d_pos, r->x.data(), n * sizeof(double), hipMemcpyHostToDevice, sv->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(r->d_pos + n, r->y.data(), n * sizeof(double), hipMemcpyHostToDevice, sv->stream);
@@ -168,16 +200,10 @@ int admit(rbsog_server *sv, Request *r, std::string &err)
     return RBSOG_OK;
 }
 
-// One synchronisation for every upload queued this tick; the host copies go.
-int admit_finish(rbsog_server *sv, const std::vector<Request *> &admitted, std::string &err)
+// The host copies of requests whose uploads a stream synchronisation has
+// covered are no longer needed.
+void uploads_done(const std::vector<Request *> &admitted, Clock::time_point t)
 {
-    if (admitted.empty()) return RBSOG_OK;
-    const hipError_t e = hipStreamSynchronize(sv->stream);
-    if (e != hipSuccess) {
-        err = std::string("request upload: ") + hipGetErrorString(e);
-        return RBSOG_EDEVICE;
-    }
-    const Clock::time_point t = Clock::now();
     for (Request *r : admitted) {
         std::vector<double>().swap(r->q);
         std::vector<double>().swap(r->x);
@@ -186,12 +212,24 @@ int admit_finish(rbsog_server *sv, const std::vector<Request *> &admitted, std::
         std::vector<float>().swap(r->q32);
         r->t_admit = t;
     }
-    return RBSOG_OK;
 }
 
-// One batched step over every active request; the forces of the requests it
-// completes are copied out behind the step, before its results are fetched.
-int tick(rbsog_server *sv, std::vector<Request *> &finished, double &wait_s, std::string &err)
+// Queued requests, first come first served, while slots (busy of them taken)
+// and pool memory allow.  The caller holds the lock.
+void take_admissions(rbsog_server *sv, size_t busy, std::vector<Request *> &out)
+{
+    while (!sv->pending.empty() && static_cast<int>(busy + out.size()) < sv->max_active) {
+        Request *r = sv->pending.front();
+        size_t off = 0;
+        if (!sv->pool.alloc(r->bytes, off)) break;
+        r->off = off;
+        sv->pending.pop_front();
+        out.push_back(r);
+    }
+}
+
+// Launch one batched step over every active request.
+int tick_launch(rbsog_server *sv, std::string &err)
 {
     Batch &bt = sv->batch;
     // rescale before step k >= 1 (mu = 1 at k = 0 leaves positions unchanged)
@@ -233,14 +271,21 @@ int tick(rbsog_server *sv, std::vector<Request *> &finished, double &wait_s, std
         err = std::string("step launch: ") + hipGetErrorString(e);
         return RBSOG_EDEVICE;
     }
-    const Clock::time_point t_launched = Clock::now();
+    return RBSOG_OK;
+}
+
+// Queue the copies of the forces of the requests this step completes (the
+// copies into pageable memory may hold the host until the step is done, so
+// they come after everything else the tick queues).
+int copy_forces(rbsog_server *sv, std::vector<Request *> &finished, std::string &err)
+{
     for (Request *r : sv->active) {
         if (r->k + 1 < r->nsteps) continue;
         const int64_t n = r->n;
         r->fx.resize(n);
         r->fy.resize(n);
         r->fz.resize(n);
-        e = hipMemcpyAsync(r->fx.data(), r->d_frc, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
+        hipError_t e = hipMemcpyAsync(r->fx.data(), r->d_frc, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(r->fy.data(), r->d_frc + n, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
         if (e == hipSuccess)
@@ -252,9 +297,15 @@ int tick(rbsog_server *sv, std::vector<Request *> &finished, double &wait_s, std
         }
         finished.push_back(r);
     }
-    rc = rbsog::batch_fetch_results(bt, err);
+    return RBSOG_OK;
+}
+
+// Wait for the step (and everything queued behind it) and record its results.
+int tick_finish(rbsog_server *sv, double &atom_steps, std::string &err)
+{
+    Batch &bt = sv->batch;
+    const int rc = rbsog::batch_fetch_results(bt, err);
     if (rc) return rc;
-    wait_s = std::chrono::duration<double>(Clock::now() - t_launched).count();
     const bool shared = sv->active.size() > 1;
     for (size_t i = 0; i < sv->active.size(); ++i) {
         Request *r = sv->active[i];
@@ -270,69 +321,90 @@ int tick(rbsog_server *sv, std::vector<Request *> &finished, double &wait_s, std
             r->U[3 * r->k + 2] = res.Uself;
         }
         r->shared_ticks += shared;
-        sv->atom_steps += static_cast<double>(r->n);
+        atom_steps += static_cast<double>(r->n);
         r->k += 1;
     }
     return RBSOG_OK;
 }
 
+// Every tick: the requests uploaded during the previous tick join, the step
+// is launched, and while it runs the requests that arrived meanwhile are
+// admitted and their uploads queued behind it; one synchronisation then
+// covers the step, its results, the completed requests' forces and those
+// uploads.  Only when nothing is active does admission wait for nothing else.
 void worker_main(rbsog_server *sv)
 {
     (void)hipSetDevice(sv->device);
     std::string err;
+    std::vector<Request *> ready;  // uploaded and synchronised, joining the next tick
     for (;;) {
-        std::vector<Request *> admitted;
+        std::vector<Request *> admitted, next, finished;
+        sv->stage_used = 0;  // every copy from the staging area ran before the last synchronisation
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty() || !sv->active.empty(); });
+            sv->cv_work.wait(lk, [&] {
+                return sv->stop || !sv->pending.empty() || !sv->active.empty() || !ready.empty();
+            });
             if (sv->stop) break;
-            while (!sv->pending.empty() &&
-                   static_cast<int>(sv->active.size() + admitted.size()) < sv->max_active) {
-                Request *r = sv->pending.front();
-                size_t off = 0;
-                if (!sv->pool.alloc(r->bytes, off)) break;
-                r->off = off;
-                sv->pending.pop_front();
-                admitted.push_back(r);
-            }
+            if (sv->active.empty() && ready.empty()) take_admissions(sv, 0, admitted);
         }
         const Clock::time_point t0 = Clock::now();
         int rc = RBSOG_OK;
-        for (Request *r : admitted) {
-            if (rc == RBSOG_OK) rc = admit(sv, r, err);
-        }
-        if (rc == RBSOG_OK) rc = admit_finish(sv, admitted, err);
+        for (Request *r : admitted)
+            if (rc == RBSOG_OK) rc = admit(sv, r, err);  // stream order puts the uploads before the step
         const Clock::time_point ta = Clock::now();
-        double wait_s = 0.0;
-        std::vector<Request *> finished;
+        double launch_s = 0.0, admit2_s = 0.0, wait_s = 0.0, atom_steps = 0.0;
         if (rc == RBSOG_OK) {
+            sv->active.insert(sv->active.end(), ready.begin(), ready.end());
             sv->active.insert(sv->active.end(), admitted.begin(), admitted.end());
             std::vector<System *> sys;
             for (Request *r : sv->active) sys.push_back(&r->sys);
-            if (!admitted.empty() || sv->batch.sys.size() != sys.size()) rc = rbsog::batch_set_systems(sv->batch, sys, err);
-            if (rc == RBSOG_OK) rc = tick(sv, finished, wait_s, err);
+            if (!ready.empty() || !admitted.empty() || sv->batch.sys.size() != sys.size())
+                rc = rbsog::batch_set_systems(sv->batch, sys, err);
+            ready.clear();
+            if (rc == RBSOG_OK) rc = tick_launch(sv, err);
+            const Clock::time_point tl = Clock::now();
+            launch_s = std::chrono::duration<double>(tl - ta).count();
+            if (rc == RBSOG_OK) {
+                size_t completing = 0;
+                for (Request *r : sv->active) completing += r->k + 1 >= r->nsteps;
+                {
+                    std::lock_guard<std::mutex> lk(sv->mu);
+                    take_admissions(sv, sv->active.size() - completing, next);
+                }
+                for (Request *r : next)
+                    if (rc == RBSOG_OK) rc = admit(sv, r, err);
+            }
+            const Clock::time_point tw = Clock::now();
+            admit2_s = std::chrono::duration<double>(tw - tl).count();
+            if (rc == RBSOG_OK) rc = copy_forces(sv, finished, err);
+            if (rc == RBSOG_OK) rc = tick_finish(sv, atom_steps, err);
+            wait_s = std::chrono::duration<double>(Clock::now() - tw).count();
         }
         const Clock::time_point t1 = Clock::now();
+        if (rc == RBSOG_OK) {
+            uploads_done(admitted, t1);
+            uploads_done(next, t1);
+            ready = next;
+        }
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->busy_s += std::chrono::duration<double>(t1 - t0).count();
-        sv->phase_s[0] += std::chrono::duration<double>(ta - t0).count();
-        sv->phase_s[1] += std::chrono::duration<double>(t1 - ta).count() - wait_s;
+        sv->phase_s[0] += std::chrono::duration<double>(ta - t0).count() + admit2_s;
+        sv->phase_s[1] += launch_s;
         sv->phase_s[2] += wait_s;
+        sv->atom_steps += atom_steps;
         sv->ticks += 1;
         sv->peak_active = std::max<int64_t>(sv->peak_active, static_cast<int64_t>(sv->active.size()));
         if (rc != RBSOG_OK) {
-            // a failed tick fails every request it held; the worker stops
-            // once nothing queued still reads their host copies
+            // a failed tick fails every request it held or had admitted; the
+            // worker stops once nothing queued still reads their host copies
             (void)hipStreamSynchronize(sv->stream);
             sv->worker_err = err;
-            for (Request *r : sv->active) {
-                r->status = rc;
-                r->done = true;
-            }
-            for (Request *r : admitted) {
-                r->status = rc;
-                r->done = true;
-            }
+            for (const std::vector<Request *> *v : {&sv->active, &ready, &admitted, &next})
+                for (Request *r : *v) {
+                    r->status = rc;
+                    r->done = true;
+                }
             sv->active.clear();
             sv->cv_done.notify_all();
             break;
@@ -351,6 +423,13 @@ void worker_main(rbsog_server *sv)
             std::string e2;
             if (rbsog::batch_set_systems(sv->batch, sys, e2) != RBSOG_OK) {
                 sv->worker_err = e2;
+                for (const std::vector<Request *> *v : {&sv->active, &ready})
+                    for (Request *r : *v) {
+                        r->status = RBSOG_EDEVICE;
+                        r->done = true;
+                    }
+                sv->active.clear();
+                sv->cv_done.notify_all();
                 break;
             }
             sv->cv_done.notify_all();
@@ -382,6 +461,10 @@ int rbsog_server_create(int32_t precision, int64_t pool_bytes, int32_t max_activ
     if (rc == RBSOG_OK && hipMalloc(reinterpret_cast<void **>(&sv->pool_mem), sv->pool_bytes) != hipSuccess) {
         (void)hipGetLastError();
         rc = RBSOG_ENOMEM;
+    }
+    if (rc == RBSOG_OK && hipHostMalloc(reinterpret_cast<void **>(&sv->stage), kStageBytes) != hipSuccess) {
+        (void)hipGetLastError();  // uploads then come from the requests' own buffers
+        sv->stage = nullptr;
     }
     if (rc != RBSOG_OK) {
         rbsog::batch_free(sv->batch);
@@ -559,6 +642,7 @@ int rbsog_server_destroy(rbsog_server *sv)
     (void)hipStreamSynchronize(sv->stream);
     rbsog::batch_free(sv->batch);
     if (sv->pool_mem) (void)hipFree(sv->pool_mem);
+    if (sv->stage) (void)hipHostFree(sv->stage);
     delete sv;
     return RBSOG_OK;
 }
