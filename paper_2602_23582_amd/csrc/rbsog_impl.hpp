@@ -116,7 +116,7 @@ struct SysStep {
     int32_t ncells;
     uint32_t step;
     int32_t g;            // cells per pair-block segment along z (a column's cells cz = 0, g, 2g, ... start one)
-    int32_t fast;         // FP32 relative-coordinate filter over whole neighbour columns (needs 5+ cells per edge)
+    int32_t fast;         // FP32 relative-coordinate filter over whole neighbour columns (4+ cells per edge, nz >= 2g + 2)
     int32_t pad;
     const double *x, *y, *z;  // positions (device, system order)
     double *fx, *fy, *fz;     // forces (device, system order)
@@ -189,6 +189,7 @@ struct Batch {
     SysStep *d_step = nullptr;
     static constexpr int kStepRing = 4;        // pinned per-step buffers used in turn
     SysStep *h_step[kStepRing] = {};
+    std::vector<SysStep> step_last;           // what d_step holds once the queued copies have run
     hipEvent_t step_ev[kStepRing] = {};
     bool step_ev_used[kStepRing] = {};
     int step_slot = 0;

@@ -528,6 +528,7 @@ void batch_free(Batch &b)
     b.ev_up = b.ev_bin = b.ev_sk = nullptr;
     b.d_desc = nullptr;
     b.d_step = nullptr;
+    b.step_last.clear();
     b.d_res = nullptr;
     b.d_plan = nullptr;
     b.d_ctrl = nullptr;
@@ -575,6 +576,7 @@ int batch_set_systems(Batch &b, const std::vector<System *> &sys, std::string &e
         }
         b.d_desc = nullptr;
         b.d_step = nullptr;
+        b.step_last.clear();
         b.d_res = nullptr;
         b.h_desc = nullptr;
         b.h_res = nullptr;
@@ -720,8 +722,11 @@ int batch_upload(Batch &b, std::string &err)
         b.up_pending = true;
     }
     // per-step data: the next pinned buffer of the ring, reused once the copy
-    // that last read it has run
-    if (e == hipSuccess) {
+    // that last read it has run; nothing when the device already holds it
+    bool step_same = e == hipSuccess && b.step_last.size() == static_cast<size_t>(S);
+    for (int64_t s = 0; step_same && s < S; ++s)
+        step_same = std::memcmp(&b.step_last[s], &b.sys[s]->stp, sizeof(SysStep)) == 0;
+    if (e == hipSuccess && !step_same) {
         const int k = b.step_slot;
         b.step_slot = (k + 1) % Batch::kStepRing;
         if (b.step_ev_used[k]) e = hipEventSynchronize(b.step_ev[k]);
@@ -731,6 +736,8 @@ int batch_upload(Batch &b, std::string &err)
         }
         if (e == hipSuccess) e = hipEventRecord(b.step_ev[k], b.stream);
         b.step_ev_used[k] = true;
+        b.step_last.resize(S);
+        for (int64_t s = 0; s < S; ++s) b.step_last[s] = b.sys[s]->stp;
     }
     if (e != hipSuccess) {
         err = std::string("batch upload: ") + hipGetErrorString(e);

@@ -50,7 +50,8 @@ def _systems():
 def _alone(torch, rb, spec, step, box):
     """One step of one system through the single-system calls."""
     with rb.Context(spec["q"], spec["box"], spec["rc"], P=spec["P"], seed=spec["seed"],
-                    system_id=spec["system_id"], M=spec.get("M", 10), flags=spec.get("flags", 0)) as ctx:
+                    system_id=spec["system_id"], M=spec.get("M", 10), flags=spec.get("flags", 0),
+                    recalibration=spec.get("recalibration", rb.RECAL_PRINTED)) as ctx:
         x, y, z = (_dev(torch, spec["pos"][:, k]) for k in range(3))
         fx, fy, fz = (torch.empty_like(x) for _ in range(3))
         ctx.sample_modes(step, box)
@@ -209,6 +210,23 @@ def test_mixed_term_counts_keep_each_system_exact(torch, rb):
     for s, spec in enumerate(systems):
         F1, P1, _ = _alone(torch, rb, spec, 2, spec["box"])
         assert np.array_equal(Fs[s], F1) and np.array_equal(P[s], P1), f"system {s}"
+
+
+def test_mixed_samplers_keep_each_system_exact(torch, rb):
+    """All four non-radial samplers in one batch: the independent chain's
+    systems hold 2P + 1 mode slots beside systems holding P + 1."""
+    systems = _systems()[:4]
+    for s, v in enumerate([rb.RECAL_INDEPENDENT, rb.RECAL_PRINTED, rb.RECAL_SHARED, rb.RECAL_EXCHANGE]):
+        systems[s] = dict(systems[s], recalibration=v)
+    boxes = np.array([s["box"] for s in systems])
+    with rb.Batch(systems) as b:
+        (x, y, z), f = _concat(torch, systems)
+        P, U, info = b.step([4] * 4, boxes, x, y, z, *f)
+        Fs = _split(torch, f, b.offsets)
+    assert info[0, 0] <= 2 * systems[0]["P"] + 1
+    for s, spec in enumerate(systems):
+        F1, P1, e1 = _alone(torch, rb, spec, 4, spec["box"])
+        assert np.array_equal(Fs[s], F1) and np.array_equal(P[s], P1) and np.array_equal(U[s], e1), f"system {s}"
 
 
 # --------------------------------------------------------------------------
