@@ -1143,41 +1143,84 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
             sh.pre[0] = 0;
             for (int k = 0; k < kMaxRanges; ++k) sh.pre[k + 1] += sh.pre[k];
         }
-    } else if (lane == 0) {
-        // exact path: per neighbour column, the run of cells cz - 1 .. cz + gs
-        // (split where it wraps); a dimension with fewer than three cells is
-        // taken whole
+    } else {
+        // exact path: lanes 0 .. ncol - 1 each take one neighbour column and
+        // its run of cells cz - 1 .. cz + gs (split where it wraps); a
+        // dimension with fewer than three cells is taken whole.  A column
+        // taken whole in z is cut (FP32) to the block's padded z-window as on
+        // the fast path, unless the window covers it: the column is z-sorted
+        // (cells in z order, each sorted by z), and displacements here are
+        // exact minimum images whatever the window.
         const int ox = nx >= 3 ? 1 : 0, oy = ny >= 3 ? 1 : 0;
-        int nr = 0;
-        auto put = [&](int lo, int hi) {
-            sh.beg[nr] = lo;
-            sh.pre[nr + 1] = hi - lo;  // length for now, prefix sums below
-            ++nr;
-        };
-        for (int dx = -ox; dx <= ox; ++dx) {
-            const int jx = (cx + dx + nx) % nx;
-            for (int dy = -oy; dy <= oy; ++dy) {
-                const int jy = (cy + dy + ny) % ny;
-                const int col = nz * (jy + ny * jx);
-                const int z0 = cz - 1, z1 = cz + gs;  // inclusive
-                if (nz < 3 || z1 - z0 + 1 >= nz) {
-                    put(start[col], start[col + nz]);
-                } else if (z0 < 0) {
-                    put(start[col + nz - 1], start[col + nz]);
-                    put(start[col], start[col + z1 + 1]);
-                } else if (z1 >= nz) {
-                    put(start[col + z0], start[col + nz]);
-                    put(start[col], start[col + z1 - nz + 1]);
-                } else {
-                    put(start[col + z0], start[col + z1 + 1]);
-                }
-            }
+        const int wy = 2 * oy + 1, ncol = (2 * ox + 1) * wy;
+        bool cut = false;
+        uint32_t za = 0, zb = 0;
+        if constexpr (kIsF32) {
+            const int nvalid = min(kPairWave, ce - cs - cb.y * kPairWave);
+            const uint32_t zext = __shfl(static_cast<uint32_t>(ri.z - oz_), nvalid - 1, 64);
+            const uint32_t reach =
+                static_cast<uint32_t>(ceil(static_cast<double>(rcf) / St.L[2] * 4294967296.0)) + 2u;
+            cut = static_cast<uint64_t>(zext) + 2ull * reach < (1ull << 32);
+            za = static_cast<uint32_t>(oz_) - reach;
+            zb = static_cast<uint32_t>(oz_) + zext + reach;
         }
-        sh.pre[0] = 0;
-        for (int k = 0; k < kMaxRanges; ++k) {
-            const int len = k < nr ? sh.pre[k + 1] : 0;
-            if (k >= nr) sh.beg[k] = 0;
-            sh.pre[k + 1] = sh.pre[k] + len;
+        if (lane < ncol) {
+            const int dx = lane / wy - ox, dy = lane % wy - oy;
+            const int jx = (cx + dx + nx) % nx, jy = (cy + dy + ny) % ny;
+            const int col = nz * (jy + ny * jx);
+            const int z0 = cz - 1, z1 = cz + gs;  // inclusive
+            int b0, e0, b1 = 0, e1 = 0;
+            if (nz < 3 || z1 - z0 + 1 >= nz) {
+                b0 = start[col];
+                e0 = start[col + nz];
+                if (cut) {
+                    const int lo = b0, hi = e0;
+                    const RB_GLOBAL uint32_t *zw = reinterpret_cast<const RB_GLOBAL uint32_t *>(gp(rec));
+                    auto search = [&](int l, int h, uint32_t v, bool above) {
+                        while (l < h) {
+                            const int m = (l + h) >> 1;
+                            const uint32_t zm = zw[4 * m + 2];
+                            if (above ? zm < v : zm <= v) l = m + 1;
+                            else h = m;
+                        }
+                        return l;
+                    };
+                    if (za <= zb) {
+                        b0 = search(lo, hi, za, true);
+                        e0 = search(b0, hi, zb, false);
+                    } else {
+                        b0 = search(lo, hi, za, true);
+                        e0 = hi;
+                        b1 = lo;
+                        e1 = search(lo, b0, zb, false);
+                    }
+                }
+            } else if (z0 < 0) {
+                b0 = start[col + nz - 1];
+                e0 = start[col + nz];
+                b1 = start[col];
+                e1 = start[col + z1 + 1];
+            } else if (z1 >= nz) {
+                b0 = start[col + z0];
+                e0 = start[col + nz];
+                b1 = start[col];
+                e1 = start[col + z1 - nz + 1];
+            } else {
+                b0 = start[col + z0];
+                e0 = start[col + z1 + 1];
+            }
+            sh.beg[2 * lane] = b0;
+            sh.pre[2 * lane + 1] = e0 - b0;  // lengths for now
+            sh.beg[2 * lane + 1] = b1;
+            sh.pre[2 * lane + 2] = e1 - b1;
+        } else if (lane >= 2 * ncol && lane < kMaxRanges) {
+            sh.beg[lane] = 0;
+            sh.pre[lane + 1] = 0;
+        }
+        __syncthreads();
+        if (lane == 0) {
+            sh.pre[0] = 0;
+            for (int k = 0; k < kMaxRanges; ++k) sh.pre[k + 1] += sh.pre[k];
         }
     }
     __syncthreads();
