@@ -90,7 +90,7 @@ std::vector<int64_t> graph_key(const Batch &bt)
     k.push_back(reinterpret_cast<intptr_t>(bt.d_step));
     k.push_back(reinterpret_cast<intptr_t>(bt.d_plan));
     k.push_back(static_cast<int64_t>(bt.sys.size()));
-    for (int f = 0; f <= rbsog::kNumForms; ++f) k.push_back(bt.pair_split[f]);
+    for (int g = 0; g <= rbsog::kNumPairGroups; ++g) k.push_back(bt.pair_split[g]);
     k.push_back(bt.want_energy);
     return k;
 }

@@ -493,7 +493,7 @@ __global__ __launch_bounds__(kCellBlock) void k_zero(const SysDesc *__restrict__
         D.count[c] = 0;
         D.cursor[c] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x < kNumForms) ctrl[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kNumPairGroups) ctrl[threadIdx.x] = 0;
 }
 
 // s = x (1/L) wrapped into [0,1) by subtracting floor(s); u = s 2^bits; the
@@ -1005,20 +1005,34 @@ __device__ __forceinline__ uint32_t push_hits4(uint32_t m, float t0, float t1, f
     return m;
 }
 
+typedef short short2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ short2v as_short2(uint32_t v) { return __builtin_bit_cast(short2v, v); }
+
+// top 16 bits of x and y (y in the high half), and of z
+template <class Rec>
+__device__ __forceinline__ uint2 pack16(const Rec &r)
+{
+    return make_uint2((static_cast<uint32_t>(r.x) >> 16) | (static_cast<uint32_t>(r.y) & 0xFFFF0000u),
+                      static_cast<uint32_t>(r.z) >> 16);
+}
+
 template <class T>
 struct PairShared {
     union {
         typename T::Rec tile[kChunk];  // exact path: fixed-point records
         float4 rtile[kChunk];          // fast path: (x, y, z) relative to the block origin, q
     };
-    float4 rel[kChunk];  // fast filter: coordinates relative to the block origin and their squared norm
+    union {
+        float4 rel[kChunk];  // fast filter: coordinates relative to the block origin and their squared norm
+        uint2 pk[kChunk];    // FP32 exact filter: top 16 bits of the fixed-point x | y << 16, and of z
+    };
     uint32_t mask[kChunk / 32][64];  // hit bits of each lane, one word per 32 candidates
     int pre[kMaxRanges + 1];  // flattened-neighbourhood offset of each range
     int beg[kMaxRanges];
 };
 
 // One pair block b of system D (one wavefront).
-template <class T, int M, bool E>
+template <class T, int M, bool E, bool FAST>
 __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, const SysStep &St, int b)
 {
     using real = typename T::real;
@@ -1262,6 +1276,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                 else sh.tile[k] = rj;
             } else {
                 sh.tile[k] = rj;
+                if constexpr (kIsF32 && !FAST) sh.pk[k] = pack16(rj);
             }
         }
         // the filter reads whole 32-candidate words: padding candidates never pass
@@ -1301,6 +1316,30 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                     }
                     m = push_hits4(m, t[0], t[1], t[2], t[3], thr);
                 }
+            } else if constexpr (kIsF32 && !FAST) {
+                // The top 16 bits of the fixed-point coordinates wrap like the
+                // box, so their 16-bit differences are minimum images in units
+                // u_d = L_d / 2^16; a pair inside rc has sum (d_d/u_d)^2 below
+                // St.thr16 (at most 2^30).  The two-term integer dot products
+                // add the squares exactly: their wrapped int32 sum is the true
+                // sum, below 2^32, read as unsigned.
+                const uint2 pi = pack16(ri);
+                const uint32_t thr16 = valid ? St.thr16 : 0u;
+#pragma unroll
+                for (int g = 0; g < 8; ++g) {
+                    uint2 c[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) c[k] = sh.pk[32 * w + 4 * g + k];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const short2v dxy = as_short2(pi.x) - as_short2(c[k].x);
+                        const short2v dz = as_short2(pi.y) - as_short2(c[k].y);
+                        const int r = __builtin_amdgcn_sdot2(dz, dz, __builtin_amdgcn_sdot2(dxy, dxy, 0, false), false);
+                        m = m + m + static_cast<uint32_t>(static_cast<uint32_t>(r) < thr16);
+                    }
+                }
+                const int nv = filled - 32 * w;  // candidates of this word; the rest are stale slots
+                if (nv < 32) m &= ~0u << (32 - nv);
             } else {
                 const int s_end = min(filled, 32 * w + 32);
                 for (int s = 32 * w; s < 32 * w + 32; ++s) {
@@ -1394,19 +1433,19 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
 template <class T, bool E>
 constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? (E ? RBSOG_PAIR_OCC - 1 : RBSOG_PAIR_OCC) : 1; }
 
-template <class T, int M, bool E>
+template <class T, int M, bool E, bool FAST>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_min_waves<T, E>()))) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                              const int2 *__restrict__ plan)
 {
     __shared__ PairShared<T> sh;
     const int2 e = plan[blockIdx.x];
-    pair_block<T, M, E>(sh, desc[e.x], stp[e.x], e.y);
+    pair_block<T, M, E, FAST>(sh, desc[e.x], stp[e.x], e.y);
 }
 
 // Persistent schedule: a fixed number of workgroups take plan entries from a
 // global counter (zeroed by k_zero) until all nitems are taken; every
 // workgroup leaves once the counter has passed nitems.
-template <class T, int M, bool E>
+template <class T, int M, bool E, bool FAST>
 __global__ __launch_bounds__(64) void k_pair_queue(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                                    const int2 *__restrict__ plan, int nitems, int32_t *ctrl)
 {
@@ -1417,7 +1456,7 @@ __global__ __launch_bounds__(64) void k_pair_queue(const SysDesc *__restrict__ d
         idx = __shfl(idx, 0, 64);
         if (idx >= nitems) break;
         const int2 e = plan[idx];
-        pair_block<T, M, E>(sh, desc[e.x], stp[e.x], e.y);
+        pair_block<T, M, E, FAST>(sh, desc[e.x], stp[e.x], e.y);
         __syncthreads();
     }
 }
@@ -1941,20 +1980,28 @@ hipError_t launch_bin_and_sort(Batch &b)
     return b.precision == RBSOG_PREC_FP64 ? bin_and_sort_t<F64>(b) : bin_and_sort_t<F32>(b);
 }
 
-template <class T, int M, bool E>
-static void pair_launch(Batch &b, int form)
+template <class T, int M, bool E, bool FAST>
+static void pair_launch_group(Batch &b, int group)
 {
-    const int64_t first = b.pair_split[form], items = b.pair_split[form + 1] - first;
+    const int64_t first = b.pair_split[group], items = b.pair_split[group + 1] - first;
     if (items <= 0) return;
     const int2 *plan = plan_ptr(b, kPlanPair) + first;
     if (b.pair_schedule == kPairPersistent) {
         const int64_t wgs = std::min<int64_t>(items, static_cast<int64_t>(b.num_cu) * b.pair_wg_per_cu);
-        hipLaunchKernelGGL((k_pair_queue<T, M, E>), dim3(static_cast<unsigned>(wgs)), dim3(64), 0, b.stream,
-                           b.d_desc, b.d_step, plan, static_cast<int>(items), b.d_ctrl + form);
+        hipLaunchKernelGGL((k_pair_queue<T, M, E, FAST>), dim3(static_cast<unsigned>(wgs)), dim3(64), 0, b.stream,
+                           b.d_desc, b.d_step, plan, static_cast<int>(items), b.d_ctrl + group);
     } else {
-        hipLaunchKernelGGL((k_pair<T, M, E>), dim3(static_cast<unsigned>(items)), dim3(64), 0, b.stream, b.d_desc,
-                           b.d_step, plan);
+        hipLaunchKernelGGL((k_pair<T, M, E, FAST>), dim3(static_cast<unsigned>(items)), dim3(64), 0, b.stream,
+                           b.d_desc, b.d_step, plan);
     }
+}
+
+// one launch per path: the FP32 relative-coordinate filter exists only in FP32
+template <class T, int M, bool E>
+static void pair_launch(Batch &b, int form)
+{
+    pair_launch_group<T, M, E, false>(b, 2 * form);
+    if constexpr (sizeof(typename T::real) == 4) pair_launch_group<T, M, E, true>(b, 2 * form + 1);
 }
 
 template <class T, bool E>

@@ -117,7 +117,7 @@ struct SysStep {
     uint32_t step;
     int32_t g;            // cells per pair-block segment along z (a column's cells cz = 0, g, 2g, ... start one)
     int32_t fast;         // FP32 relative-coordinate filter over whole neighbour columns (4+ cells per edge, nz >= 2g + 2)
-    int32_t pad;
+    uint32_t thr16;       // FP32 exact filter: bound on sum (d_d / u_d)^2 of a pair inside rc, u_d = L_d / 2^16
     const double *x, *y, *z;  // positions (device, system order)
     double *fx, *fy, *fz;     // forces (device, system order)
 };
@@ -140,6 +140,9 @@ enum PairForm {
     kFormExpM = 2,   // runtime M exponentials
     kNumForms = 3,
 };
+// Pair launches: one per (form, path); path 1 is the FP32 relative-coordinate
+// filter over whole neighbour columns (SysStep::fast), path 0 the exact one.
+constexpr int kNumPairGroups = 2 * kNumForms;
 
 // Pair-kernel schedules (none changes any result).
 enum PairSchedule {
@@ -195,10 +198,10 @@ struct Batch {
     int step_slot = 0;
     StepResults *d_res = nullptr, *h_res = nullptr;
     int2 *d_plan = nullptr, *h_plan = nullptr;
-    int32_t *d_ctrl = nullptr;  // [0..2]: work-queue counters of the pair launches (one per form)
+    int32_t *d_ctrl = nullptr;  // [0 .. kNumPairGroups): work-queue counters of the pair launches
     int64_t cap_sys = 0, cap_plan = 0;
     int64_t plan_off[kNumPlans]{}, plan_len[kNumPlans]{};
-    int64_t pair_split[kNumForms + 1]{};  // pair-plan entries of each form: [split[f], split[f+1])
+    int64_t pair_split[kNumPairGroups + 1]{};  // pair-plan entries of launch group g = 2 form + path: [split[g], split[g+1])
     bool want_energy = true;              // the pair kernel sums U^N
     bool desc_dirty = true, plan_dirty = true;
     std::vector<int64_t> plan_key;  // sizes the plans were built for

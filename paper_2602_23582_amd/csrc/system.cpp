@@ -322,6 +322,14 @@ void system_set_box(System &s, const double box[3])
     const bool fast = !is_fp64(s.prm) && s.nc[0] >= 4 && s.nc[1] >= 4 && s.nc[2] >= 4;
     t.fast = fast ? 1 : 0;
     t.g = fast ? std::max(1, std::min(kSuperCells, (s.nc[2] - 3) / 2)) : 1;
+    // The FP32 exact filter compares 16-bit wrapped differences of the
+    // fixed-point coordinates, in units u_d = L_d / 2^16 truncated (under one
+    // unit per axis): a pair inside rc has sum (d_d/u_d)^2 < (rc/u_min + sqrt 3)^2,
+    // at most (2^15 + 2)^2 since rc <= L/2.
+    const double umin = std::min(s.L[0], std::min(s.L[1], s.L[2])) * 0x1.0p-16;
+    const double tr = static_cast<double>(static_cast<float>(s.prm.rc * s.prm.rc));
+    const double tb = std::sqrt(tr) / umin + 2.0;
+    t.thr16 = static_cast<uint32_t>(tb * tb) + 1u;
     t.Sr = s.Sr;
     t.Snr = s.Snr;
 }
@@ -610,6 +618,7 @@ static std::vector<int64_t> plan_sizes(const Batch &b)
         k.push_back(s->ncells);
         k.push_back(s->prm.P);
         k.push_back(s->pair_form);
+        k.push_back(s->stp.fast);
     }
     return k;
 }
@@ -673,15 +682,17 @@ static int build_plans(Batch &b, std::string &err)
         put(kPlanReduce, s, mode_cap(y->prm) + kPairRed);
         put(kPlanCell1, s, order_parts(*y));
     }
-    // pair blocks grouped by the form of the SOG kernels (one launch per form)
-    for (int f = 0; f < kNumForms; ++f) {
-        b.pair_split[f] = pos[kPlanPair] - b.plan_off[kPlanPair];
+    // pair blocks grouped by the form of the SOG kernels and the filter path
+    // (one launch per group, each compiled for its path alone)
+    for (int g = 0; g < kNumPairGroups; ++g) {
+        b.pair_split[g] = pos[kPlanPair] - b.plan_off[kPlanPair];
         for (int s = 0; s < S; ++s) {
             const System *y = b.sys[s];
-            if (y->pair_form == f) put(kPlanPair, s, (y->n + kPairWave - 1) / kPairWave + y->ncells);
+            if (2 * y->pair_form + (y->stp.fast ? 1 : 0) == g)
+                put(kPlanPair, s, (y->n + kPairWave - 1) / kPairWave + y->ncells);
         }
     }
-    b.pair_split[kNumForms] = pos[kPlanPair] - b.plan_off[kPlanPair];
+    b.pair_split[kNumPairGroups] = pos[kPlanPair] - b.plan_off[kPlanPair];
     return RBSOG_OK;
 }
 
