@@ -238,6 +238,25 @@ def test_fp32c_small_boxes_collapsed_cells(torch, rb, orc, n, energy):
     check(g, o, TOL_FP32C, f"ionic n={n} energy {energy}")
 
 
+@pytest.mark.parametrize("box", [(45.0, 45.0, 25.0), (25.0, 45.0, 60.0), (33.0, 61.0, 47.0)])
+def test_fp32c_anisotropic_exact_path(torch, rb, orc, box):
+    """Orthorhombic boxes on the exact path: (45, 45, 25) has 4 x 4 x 1 cells
+    (nine columns, each whole in z and cut to the block's z-window);
+    (25, 45, 60) has 1 x 4 x 6 (three columns, runs of cells); (33, 61, 47)
+    has 3 x 6 x 4.  The 16-bit filter's units differ per axis in all three."""
+    rng = np.random.default_rng(int(sum(box)))
+    L = np.array(box)
+    n = 2 * int(0.05 * np.prod(L))
+    pos = rng.uniform(0, 1, (n, 3)) * L
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    d = dict(q=q, pos=pos, L=L, rc=10.0)
+    with rb.Context(q, L, 10.0, P=100, seed=8, system_id=2) as ctx:
+        for energy in (True, False):
+            g = gpu_step(torch, ctx, pos, 3, L, energy=energy)
+            o = oracle_step(orc, d, L, pos, 100, 8, 2, 3)
+            check(g, o, TOL_FP32C, f"anisotropic {box} energy {energy}")
+
+
 @pytest.mark.parametrize("n,precision", [(9000, "fp32c"), (9000, "fp64"), (30000, "fp32c")])
 def test_dense_cells_ordered_in_passes(torch, rb, orc, n, precision):
     """Charges at 1 per cubic angstrom, rc 10.  9,000 (L = 20.8 A): one cell
