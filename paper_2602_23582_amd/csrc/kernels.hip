@@ -1427,8 +1427,10 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
 
 // Static schedule: workgroup g runs plan entry g.
 // Register budget of the FP32 pair kernel: RBSOG_PAIR_OCC waves per SIMD
-// without the energy sum, one fewer with it (the kernel waits on LDS more
-// than it computes, so occupancy pays; both budgets fit without spilling).
+// without the energy sum, one fewer with it.  The kernel waits on LDS more
+// than it computes, so occupancy pays: at 6 waves the relative-coordinate
+// kernel spills 40 bytes per lane to scratch, and fewer waves without
+// spills measured slower.
 // FP64 keeps the default.
 template <class T, bool E>
 constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? (E ? RBSOG_PAIR_OCC - 1 : RBSOG_PAIR_OCC) : 1; }
