@@ -388,6 +388,34 @@ def test_full_size_slab_sampled(torch, rb, orc, slab_1m):
 
 
 @pytest.mark.slow
+def test_full_size_electrolyte_sampled(torch, rb, orc):
+    """The 10^7-atom electrolyte (467.5 A cube, rc 10, P 100) in the call the
+    benchmark times: modes bit-exact, rho of every distinct mode, forces of
+    sampled atoms and the long-range estimators against the oracle."""
+    d = W.electrolyte()
+    rng = np.random.default_rng(3)
+    smp = np.sort(rng.choice(len(d["q"]), 300, replace=False))
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=13) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 0, d["L"], energy=False)
+        modes, counts, rho = ctx.debug_modes()
+    p = orc.sog(d["rc"], row=2, M=10)
+    m_r, m_nr, _ = orc.sample_modes(d["L"], p, 100, 13, 0, 0)
+    assert np.array_equal(g["m_r"], m_r) and np.array_equal(g["m_nr"], m_nr)
+    ref = orc.rho(d["q"], d["pos"], d["L"], modes)
+    err = np.abs(rho - ref).max() / np.sqrt(np.sum(d["q"] ** 2))
+    print("10M electrolyte rho max err / sqrt(sum q^2):", err)
+    assert err < RHO_TOL
+    o = orc.rbsog_step(d["q"], d["pos"], d["L"], p, 100, 13, 0, 0, modes=(m_r, m_nr), sample=smp)
+    Fo = o["F"]
+    fr = np.sqrt(((g["F"][smp] - Fo) ** 2).sum() / (Fo ** 2).sum())
+    print("10M electrolyte sampled force rel RMS", fr)
+    assert fr < TOL_FP32C
+    pn = np.linalg.norm(g["P"])
+    assert np.linalg.norm(g["Pr"] - o["Pr"]) / pn < TOL_FP32C
+    assert np.linalg.norm(g["Pnr"] - o["Pnr"]) / pn < TOL_FP32C
+
+
+@pytest.mark.slow
 def test_full_size_slab_pressure(torch, rb, orc, slab_1m):
     """Short-range virial and energy of all 1,000,000 atoms against the oracle."""
     d = slab_1m
