@@ -211,6 +211,35 @@ def test_fp32c_water_30k(torch, rb, orc, form, energy):
             check(g, o, TOL_FP32C, f"water form {form} energy {energy} step {step}")
 
 
+def test_fp32c_water_100_steps_with_rescale(torch, rb, orc):
+    """The bulk-water workload for 100 steps under L_n = L_0 (1 + 0.001 n),
+    positions rescaled on the device each step (the grid grows from 6 to 7
+    cells per edge on the way); steps 0, 57 and 99 against the oracle."""
+    d = W.water_box()
+    x, y, z = (_dev(torch, d["pos"][:, k]) for k in range(3))
+    fx, fy, fz = (torch.empty_like(x) for _ in range(3))
+    grids = set()
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=4) as ctx:
+        for step in range(100):
+            if step:
+                mu = (1.0 + 0.001 * step) / (1.0 + 0.001 * (step - 1))
+                ctx.rescale([mu, mu, mu], x, y, z)
+            box = ctx.box.copy()
+            ctx.sample_modes(step, box)
+            ctx.force_virial(x, y, z, fx, fy, fz, energy=False)
+            P, parts = ctx.pressure()
+            grids.add(int(ctx.debug_cells()[1][0]))
+            if step in (0, 57, 99):
+                pos = torch.stack([x, y, z], 1).cpu().numpy()
+                o = oracle_step(orc, d, box, pos, 100, 4, 0, step)
+                F = torch.stack([fx, fy, fz], 1).cpu().numpy()
+                fr = np.sqrt(((F - o["F"]) ** 2).sum() / (o["F"] ** 2).sum())
+                pr = np.linalg.norm(P - o["P"]) / np.linalg.norm(o["P"])
+                print(f"water step {step} box {box[0]:.3f}: F {fr:.2e} P {pr:.2e}", flush=True)
+                assert fr < TOL_FP32C and pr < TOL_FP32C, (step, fr, pr)
+    assert grids == {6, 7}, grids
+
+
 @pytest.mark.parametrize("energy", [True, False])
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("P", [100, 400])
