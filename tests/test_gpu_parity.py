@@ -384,23 +384,24 @@ def slab_1m():
     return W.slab()
 
 
-def test_full_size_slab_sampled(torch, rb, orc, slab_1m):
+@pytest.mark.parametrize("P", [100, 400])
+def test_full_size_slab_sampled(torch, rb, orc, slab_1m, P):
     d = slab_1m
     rng = np.random.default_rng(0)
     smp = np.sort(rng.choice(len(d["q"]), 400, replace=False))
     smp = np.concatenate([smp, np.arange(990000, 990040)])  # layer atoms
-    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=11) as ctx:
+    with rb.Context(d["q"], d["L"], d["rc"], P=P, seed=11) as ctx:
         g = gpu_step(torch, ctx, d["pos"], 0, d["L"], energy=False)  # the benchmark's call
         modes, counts, rho = ctx.debug_modes()
         ge = gpu_step(torch, ctx, d["pos"], 0, d["L"])
     p = orc.sog(d["rc"], row=2, M=10)
-    m_r, m_nr, _ = orc.sample_modes(d["L"], p, 100, 11, 0, 0)
+    m_r, m_nr, _ = orc.sample_modes(d["L"], p, P, 11, 0, 0)
     assert np.array_equal(g["m_r"], m_r) and np.array_equal(g["m_nr"], m_nr)
     ref = orc.rho(d["q"], d["pos"], d["L"], modes)
     err = np.abs(rho - ref).max() / np.sqrt(np.sum(d["q"] ** 2))
     print("1M slab rho max err / sqrt(sum q^2):", err)
     assert err < RHO_TOL
-    o = orc.rbsog_step(d["q"], d["pos"], d["L"], p, 100, 11, 0, 0, modes=(m_r, m_nr), sample=smp)
+    o = orc.rbsog_step(d["q"], d["pos"], d["L"], p, P, 11, 0, 0, modes=(m_r, m_nr), sample=smp)
     Fo = o["F"]
     Fg = g["F"][smp]
     fr = np.sqrt(((Fg - Fo) ** 2).sum() / (Fo ** 2).sum())
