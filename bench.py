@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--served", type=int, default=4096, help="requests of the served-stream run (0: skip)")
     ap.add_argument("--npt-steps", type=int, default=20, help="Langevin NPT steps timed after the main run (0: skip)")
     ap.add_argument("--served-pool-mib", type=int, default=4096)
+    ap.add_argument("--other-p", type=int, default=400,
+                    help="also time the workload at this batch size P (0: skip)")
     ap.add_argument("--variance-reps", type=int, default=1000,
                     help="steps per sampler, P and size in the estimator-variance study (0: skip)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -423,6 +425,26 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
         "distinct_modes": info["nd"], "valu_probe": probe,
     }
+    if args.other_p > 0 and not args.graph:
+        # the same workload at another batch size (the slab config names P = 100 and 400)
+        log(f"P = {args.other_p}: {args.steps} steps")
+        with rbsog.Context(d["q"], ctx.box, d["rc"], P=args.other_p, seed=args.seed) as c2:
+            def step2(s):
+                c2.sample_modes(s, c2.box)
+                c2.force_virial(x, y, z, fx, fy, fz, energy=False)
+                return c2.pressure()
+            for s in range(args.warmup):
+                step2(s)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for s in range(args.warmup, args.warmup + args.steps):
+                step2(s)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            out["other_P"] = {"P": args.other_p, "ms_per_step": 1e3 * (tb - ta) / args.steps,
+                              "atom_steps_per_s": n * args.steps / (tb - ta),
+                              "distinct_modes": c2.step_info()["nd"],
+                              "note": "no box rescale between these steps"}
     if args.npt_steps > 0 and not args.graph:
         log(f"NPT integration: {args.npt_steps} steps")
         out["npt"] = npt_bench(torch, ctx, d, x, y, z, args.npt_steps, ms_step)
