@@ -1435,12 +1435,29 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
 template <class T, bool E>
 constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? (E ? RBSOG_PAIR_OCC - 1 : RBSOG_PAIR_OCC) : 1; }
 
+// Workgroups go to the eight XCDs in turn (workgroup w to XCD w mod 8), each
+// XCD with its own L2.  Consecutive plan entries are neighbouring blocks of one
+// column, which stage the same neighbour records; this permutation cuts the
+// plan into windows of 8 runs of kXcdRun entries and gives each XCD one run per
+// window, so those re-reads meet one L2 (HBM fetches per launch fall about
+// tenfold) while the idle entries at the end of an over-provisioned plan stay
+// spread over all XCDs.  A permutation of the workgroups: no result changes.
+constexpr int kXcd = 8, kXcdRun = 128;
+__device__ inline int xcd_grouped(int w, int G)
+{
+    const int base = w / (kXcd * kXcdRun) * (kXcd * kXcdRun);
+    const int n = min(kXcd * kXcdRun, G - base);  // entries in this window
+    const int q = n / kXcd, r = n % kXcd;         // XCDs below r take q + 1 of them, the others q
+    const int o = w - base, x = o % kXcd;
+    return base + x * q + min(x, r) + o / kXcd;
+}
+
 template <class T, int M, bool E, bool FAST>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_min_waves<T, E>()))) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                              const int2 *__restrict__ plan)
 {
     __shared__ PairShared<T> sh;
-    const int2 e = plan[blockIdx.x];
+    const int2 e = plan[xcd_grouped(blockIdx.x, gridDim.x)];
     pair_block<T, M, E, FAST>(sh, desc[e.x], stp[e.x], e.y);
 }
 
