@@ -301,6 +301,34 @@ def test_dense_cells_ordered_in_passes(torch, rb, orc, n, precision):
     check(g, o, TOL_FP32C if precision == "fp32c" else TOL_FP64, f"dense cells n={n} {precision}")
 
 
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_degenerate_systems(torch, rb, orc, precision):
+    """The smallest inputs the method takes.  An ion pair 3 A apart in a 25 A
+    cube (one collapsed cell, one pair block with 62 idle lanes) at P = 1: one
+    mode per chain.  A lattice with every charge zero: neutral, so accepted,
+    and every force, pressure part and energy term is exactly zero on both
+    sides."""
+    prec = rb.PREC_FP32C if precision == "fp32c" else rb.PREC_FP64
+    tol = TOL_FP32C if precision == "fp32c" else TOL_FP64
+    L = np.full(3, 25.0)
+    d = dict(q=np.array([1.0, -1.0]), pos=np.array([[11.0, 12.0, 12.5], [13.0, 14.0, 13.5]]), L=L, rc=10.0)
+    with rb.Context(d["q"], L, 10.0, P=1, seed=17, precision=prec) as ctx:
+        for step in (0, 1):
+            g = gpu_step(torch, ctx, d["pos"], step, L)
+            o = oracle_step(orc, d, L, d["pos"], 1, 17, 0, step)
+            assert len(g["m_r"]) == 1 and len(g["m_nr"]) == 1
+            check(g, o, tol, f"ion pair {precision} step {step}")
+    z = W.c1_lattice(jitter=0.2)
+    z["q"] = np.zeros_like(z["q"])
+    with rb.Context(z["q"], z["L"], z["rc"], P=50, seed=5, precision=prec) as ctx:
+        g = gpu_step(torch, ctx, z["pos"], 2, z["L"])
+    o = oracle_step(orc, z, z["L"], z["pos"], 50, 5, 0, 2)
+    assert np.array_equal(g["m_r"], o["m_r"]) and np.array_equal(g["m_nr"], o["m_nr"])
+    for k in ("F", "P", "PN", "Pr", "Pnr", "UN", "UF", "Uself"):
+        assert not np.any(np.asarray(g[k])), (k, g[k])
+        assert not np.any(np.asarray(o[k])), (k, o[k])
+
+
 def test_rho_of_distinct_modes(torch, rb, orc):
     d = W.water_box(n_mol=4000, seed=12)
     with rb.Context(d["q"], d["L"], d["rc"], P=200, seed=3) as ctx:
