@@ -309,6 +309,48 @@ def test_server_results_alone_equal_results_in_the_mix(torch, rb, energy):
     assert np.array_equal(solo["forces"], mix[0]["forces"]) and np.array_equal(solo["P"], mix[0]["P"])
 
 
+def test_full_served_stream_sampled(torch, rb, orc):
+    """The served workload at full size, in the configuration the benchmark
+    times at capacity: 4,096 requests of 500-50,000 atoms (stream seed 5), 10
+    steps each under L_k = L_(k-1) (1 + 0.001 k) / (1 + 0.001 (k - 1)), force +
+    pressure solves from a 4 GiB pool, all submitted at once.  Sampled
+    requests: the smallest, the largest and four more give the same bits alone
+    as in the mix; three of at most 6,000 atoms match the oracle at their last
+    step within 1e-5."""
+    nsteps, growth, nreq = 10, 0.001, 4096
+    sizes, seeds = W.served_stream(nreq, seed=5)
+    reqs = [W.ionic_system(int(n), int(sd)) for n, sd in zip(sizes, seeds)]
+    print(f"served stream: {nreq} requests, {int(sizes.sum())} atoms", flush=True)
+    with rb.Server(max_active=65536, pool_bytes=4 << 30, energy=False) as sv:
+        tickets = [sv.submit(r["q"], r["pos"], r["L"], r["rc"], nsteps=nsteps, growth=growth, P=r["P"],
+                             seed=int(seeds[i]), system_id=i) for i, r in enumerate(reqs)]
+        res = [sv.wait(t, timeout=300.0) for t in tickets]
+        st = sv.stats()
+    print("server stats", st, flush=True)
+    assert all(m is not None for m in res) and st["completed"] == nreq and st["peak_active"] > 1000
+    rng = np.random.default_rng(11)
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), *rng.choice(nreq, 4, replace=False).tolist()})
+    for i in pick:
+        r = reqs[i]
+        spec = dict(q=r["q"], pos=r["pos"], box=r["L"], rc=r["rc"], P=r["P"], seed=int(seeds[i]), system_id=i)
+        F1, P1 = _alone_steps(torch, rb, spec, nsteps, growth, energy=False)
+        print(f"request {i}: {len(r['q'])} atoms, alone vs mix", flush=True)
+        assert np.array_equal(res[i]["forces"], F1) and np.array_equal(res[i]["P"], P1), i
+    small = [int(i) for i in rng.permutation(nreq) if sizes[i] <= 6000][:3]
+    for i in small:
+        r = reqs[i]
+        L, pos = np.array(r["L"], dtype=np.float64), np.array(r["pos"], dtype=np.float64)
+        for k in range(1, nsteps):  # the server's box law and device rescale, both in FP64
+            m = (1.0 + growth * k) / (1.0 + growth * (k - 1))
+            L, pos = L * m, pos * m
+        o = orc.rbsog_step(r["q"], pos, L, orc.sog(r["rc"], row=2, M=10), r["P"], int(seeds[i]), i, nsteps - 1)
+        F, P = res[i]["forces"], res[i]["P"][-1]
+        fr = np.sqrt(((F - o["F"]) ** 2).sum() / (o["F"] ** 2).sum())
+        pr = np.linalg.norm(P - o["P"]) / np.linalg.norm(o["P"])
+        print(f"request {i}: {len(r['q'])} atoms vs oracle: F {fr:.2e} P {pr:.2e}", flush=True)
+        assert fr < TOL_FP32C and pr < TOL_FP32C, (i, fr, pr)
+
+
 def test_server_admission_is_bounded_by_the_memory_pool(torch, rb):
     reqs = _requests(8, seed=9)
     # a pool that holds only a few of these requests at once
