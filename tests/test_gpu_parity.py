@@ -197,6 +197,21 @@ def test_fp32c_lattice(torch, rb, orc, variant, form):
             check(g, o, TOL_FP32C, f"fp32c lattice v{variant} form {form} step {step}")
 
 
+@pytest.mark.parametrize("M,P,precision", [(4, 100, "fp64"), (25, 100, "fp32c"), (64, 100, "fp32c"),
+                                         (64, 1024, "fp64"), (10, 1024, "fp32c")])
+def test_term_counts_and_the_largest_batch(torch, rb, orc, M, P, precision):
+    """Term counts other than M = 10, up to the largest (64): the kernels
+    with M read at run time, or the FP32C polynomial where its fit holds.
+    And the largest batch, P = 1024 (1,025 mode slots).  Jittered lattice,
+    energy included, Table 1 row 2 with its printed omega at every M."""
+    d = W.c1_lattice(jitter=0.2)
+    prec = rb.PREC_FP32C if precision == "fp32c" else rb.PREC_FP64
+    with rb.Context(d["q"], d["L"], d["rc"], P=P, seed=13, M=M, precision=prec) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 1, d["L"])
+    o = orc.rbsog_step(d["q"], d["pos"], d["L"], orc.sog(d["rc"], row=2, M=M), P, 13, 0, 1)
+    check(g, o, TOL_FP32C if precision == "fp32c" else TOL_FP64, f"M={M} P={P} {precision}")
+
+
 @pytest.mark.parametrize("energy", [True, False])
 @pytest.mark.parametrize("form", FORMS)
 def test_fp32c_water_30k(torch, rb, orc, form, energy):
