@@ -212,6 +212,21 @@ def test_term_counts_and_the_largest_batch(torch, rb, orc, M, P, precision):
     check(g, o, TOL_FP32C if precision == "fp32c" else TOL_FP64, f"M={M} P={P} {precision}")
 
 
+@pytest.mark.parametrize("row,M,precision", [(1, 4, "fp32c"), (3, 27, "fp32c"), (3, 27, "fp64"), (4, 64, "fp32c")])
+def test_other_table1_rows(torch, rb, orc, row, M, precision):
+    """The other parameter sets of Table 1 (b, sigma scaled to rc, omega as
+    printed) at their pressure term counts M~ (row 4 asks 69; the largest
+    allowed, 64, is used): jittered lattice, energy included."""
+    b, s9, om = orc.TABLE1[row][:3]
+    d = W.c1_lattice(jitter=0.2)
+    prec = rb.PREC_FP32C if precision == "fp32c" else rb.PREC_FP64
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=14, M=M, b=b, sigma=s9 * d["rc"] / orc.TABLE1_RC, omega=om,
+                    precision=prec) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 2, d["L"])
+    o = orc.rbsog_step(d["q"], d["pos"], d["L"], orc.sog(d["rc"], row=row, M=M), 100, 14, 0, 2)
+    check(g, o, TOL_FP32C if precision == "fp32c" else TOL_FP64, f"Table 1 row {row} M={M} {precision}")
+
+
 @pytest.mark.parametrize("energy", [True, False])
 @pytest.mark.parametrize("form", FORMS)
 def test_fp32c_water_30k(torch, rb, orc, form, energy):
