@@ -227,6 +227,24 @@ def test_other_table1_rows(torch, rb, orc, row, M, precision):
     check(g, o, TOL_FP32C if precision == "fp32c" else TOL_FP64, f"Table 1 row {row} M={M} {precision}")
 
 
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_coulomb_prefactor_scales_every_result(torch, rb, orc, precision):
+    """With the prefactor k (here 332.0637, kcal/mol A per e^2) every force,
+    pressure part and energy term is k times the oracle's (which works in
+    units of k = 1); the sampled modes do not depend on it."""
+    k = 332.0637
+    d = W.c1_lattice(jitter=0.2)
+    prec = rb.PREC_FP32C if precision == "fp32c" else rb.PREC_FP64
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=15, coulomb_k=k, precision=prec) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 3, d["L"])
+    o = oracle_step(orc, d, d["L"], d["pos"], 100, 15, 0, 3)
+    for key in ("F", "P", "PN", "Pr", "Pnr"):
+        o[key] = k * o[key]
+    for key in ("UN", "UF", "Uself", "U"):
+        o[key] = k * o[key]
+    check(g, o, TOL_FP32C if precision == "fp32c" else TOL_FP64, f"coulomb_k {precision}")
+
+
 @pytest.mark.parametrize("energy", [True, False])
 @pytest.mark.parametrize("form", FORMS)
 def test_fp32c_water_30k(torch, rb, orc, form, energy):
