@@ -245,6 +245,20 @@ def test_coulomb_prefactor_scales_every_result(torch, rb, orc, precision):
     check(g, o, TOL_FP32C if precision == "fp32c" else TOL_FP64, f"coulomb_k {precision}")
 
 
+@pytest.mark.parametrize("M", [7, 10])
+def test_omega_solved_at_the_given_term_count(torch, rb, orc, M):
+    """omega <= 0 asks the library for the C0 root of the 1/r^3 split at rc
+    and the given M (eq. continuity); the oracle solves the same equation
+    with its own code, and the FP64 results agree to 1e-12."""
+    d = W.c1_lattice(jitter=0.2)
+    p2 = orc.sog(d["rc"], row=2, M=M)
+    om = orc.omega_c0(p2.b, p2.sigma, d["rc"], M)
+    with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=16, M=M, omega=0.0, precision=rb.PREC_FP64) as ctx:
+        g = gpu_step(torch, ctx, d["pos"], 1, d["L"])
+    o = orc.rbsog_step(d["q"], d["pos"], d["L"], orc.sog(d["rc"], row=2, M=M, omega=om), 100, 16, 0, 1)
+    check(g, o, TOL_FP64, f"omega solved, M={M}")
+
+
 @pytest.mark.parametrize("energy", [True, False])
 @pytest.mark.parametrize("form", FORMS)
 def test_fp32c_water_30k(torch, rb, orc, form, energy):
