@@ -7,6 +7,7 @@ import dataclasses
 import importlib.util
 import os
 
+import numpy as np
 import pytest
 
 _spec = importlib.util.spec_from_file_location("oracle_pins", os.path.join(os.path.dirname(__file__),
@@ -70,3 +71,14 @@ def test_a_wrong_sign_in_the_nonradial_estimator_is_caught(orc, monkeypatch):
     _wrap(monkeypatch, orc, "long_range_rb", flip)
     with pytest.raises(AssertionError):
         pins.test_batch_mean_converges_to_full_sum(orc, 0)
+
+
+def test_transposed_cell_axes_are_caught(orc, monkeypatch):
+    def swap_xy(cid):
+        # ids built with the x and y strides exchanged: cx n_y + cy instead of cx + n_x cy
+        nc = np.array([7, 5, 6])
+        cx, cy, cz = cid % nc[0], (cid // nc[0]) % nc[1], cid // (nc[0] * nc[1])
+        return cy + nc[1] * (cx + nc[0] * cz)
+    _wrap(monkeypatch, orc, "cell_ids", swap_xy)
+    with pytest.raises(AssertionError):
+        pins.test_cell_ids_contain_their_atoms(orc)
