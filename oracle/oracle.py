@@ -61,6 +61,8 @@ def lib():
             "orc_sample_modes": (C.c_int, [pd, C.c_int, pd, pd, C.c_int, u64, u64, u64, C.c_int,
                                            pi32, pi32, pi64]),
             "orc_recalibrate": (None, [C.c_int, pi32, pd, pd, C.c_int, pd, pd, pi32, pi64]),
+            "orc_start_bound": (d, [pd, C.c_int, pd, pd, C.c_int]),
+            "orc_start_states": (C.c_int, [pd, C.c_int, pd, pd, u64, u64, u64, pi32, pi32]),
             "orc_cell_ids": (None, [i64, pd, pd, pd, pd, pi32, pi32]),
             "orc_short_range_brute": (None, [i64, pd, pd, pd, pd, pd, d, C.c_int, pd, pd, pd,
                                              pd, pd, pd, pd, pd]),
@@ -194,18 +196,33 @@ RECAL_SHARED = 2        # no recalibration: the r-chain's modes, weighted by P^n
 RECAL_INDEPENDENT = 3   # a second MH chain with target P^nr (2P structure factors)
 
 
-def sample_modes(L, p: SOG, P, seed, system_id, step, variant=RECAL_PRINTED):
+def sample_modes(L, p: SOG, P, seed, system_id, step, variant=RECAL_EXCHANGE):
     """r-chain and nr-chain modes (P x 3 int32 each) and accepted-move counts.
-    variant 0: recalibration chain as printed; 1: exchange form; 2: shared
-    proposal (m_nr = m_r); 3: an independent chain for P^nr."""
+    variant 0: recalibration chain as printed; 1: exchange form (the default);
+    2: shared proposal (m_nr = m_r); 3: an independent chain for P^nr."""
     m_r = np.zeros((P, 3), dtype=np.int32)
     m_nr = np.zeros((P, 3), dtype=np.int32)
     acc = np.zeros(2, dtype=np.int64)
     rc = lib().orc_sample_modes(_pd(_f64(L)), p.M, _pd(p.wt), _pd(p.s), P, seed, system_id, step, variant,
                                 _pi32(m_r), _pi32(m_nr), _pi64(acc))
     if rc != 0:
-        raise RuntimeError("oracle sampler found no nonzero initial state")
+        raise RuntimeError("oracle sampler: no start draw accepted")
     return m_r, m_nr, acc
+
+
+def start_bound(L, p: SOG, power):
+    """Upper bound of g_p / q' (power 2: radial target, 4: non-radial) used by
+    the rejection draw of a chain's start state."""
+    return lib().orc_start_bound(_pd(_f64(L)), p.M, _pd(p.wt), _pd(p.s), power)
+
+
+def start_states(L, p: SOG, seed, system_id, step):
+    """The exact start draws of both chains of one step (radial, non-radial)."""
+    a = np.zeros(3, dtype=np.int32); b = np.zeros(3, dtype=np.int32)
+    rc = lib().orc_start_states(_pd(_f64(L)), p.M, _pd(p.wt), _pd(p.s), seed, system_id, step, _pi32(a), _pi32(b))
+    if rc != 0:
+        raise RuntimeError("oracle sampler: no start draw accepted")
+    return a, b
 
 
 def recalibrate(props, u, L, p: SOG):
@@ -344,7 +361,7 @@ def sog_deterministic(q, pos, L, p: SOG, forces=True):
 
 
 def rbsog_step(q, pos, L, p: SOG, P, seed, system_id, step, modes=None, sample=None,
-               variant=RECAL_PRINTED):
+               variant=RECAL_EXCHANGE):
     """One evaluation of Algorithm 1 steps 2-6 (Algorithm O): returns forces,
     energy parts, pressure parts and the sampled modes.
 

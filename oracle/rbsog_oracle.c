@@ -417,19 +417,107 @@ void orc_recalibrate(int P, const int32_t *props, const double *u, const double 
 }
 
 /*
+ * Upper bound B_p >= g_p(m) / q'(m) over the whole integer lattice, used by the
+ * rejection draw that starts a chain at its own target.  g_2(m) is the
+ * unnormalised radial target |k|^2 sum_l wt_l s_l^5 e_l (eq. samplingP),
+ * g_4(m) = |k|^4 sum_l wt_l s_l^7 e_l the non-radial one (eq. samplingPnr),
+ * e_l = exp(-s_l^2 |k|^2 / 4), and q' the rounded-Gaussian proposal of App. D
+ * with width parameter s_0/sqrt2, i.e. per-axis standard deviation
+ * sig_xi = L_xi / (pi s_0).
+ * Derivation.  The cell integral of the normal density over [m - 1/2, m + 1/2]
+ * is at least the density at the far end |m| + 1/2, and (|m| + 1/2)/sig_xi =
+ * s_0 |k_xi|/2 + c_xi with c_xi = 1/(2 sig_xi), so
+ *   1/q'(m) <= K exp(s_0^2 |k|^2 / 8 + (s_0/2) sum_xi c_xi |k_xi|),
+ *   K = prod_xi sqrt(2 pi) sig_xi exp(c_xi^2 / 2),
+ * and sum_xi c_xi |k_xi| <= |c| |k| (Cauchy-Schwarz).  Term l of g_p/q' is
+ * then at most K coef_l kappa^p exp(-alpha_l kappa^2 + beta kappa) with
+ * kappa = |k|, alpha_l = s_l^2/4 - s_0^2/8 > 0 and beta = s_0 |c| / 2; its
+ * maximum over kappa >= 0 lies at
+ *   kappa* = (beta + sqrt(beta^2 + 8 alpha_l p)) / (4 alpha_l).
+ * B_p is the sum over l of these maxima.
+ * Pinned by: B_p above the largest ratio found by enumerating small boxes.
+ */
+double orc_start_bound(const double L[3], int M, const double *wt, const double *s, int p)
+{
+    const double s0 = s[0];
+    double K = 1.0, c2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double sig = L[d] / (ORC_PI * s0);
+        const double c = 1.0 / (2.0 * sig);
+        K *= sqrt(2.0 * ORC_PI) * sig * exp(0.5 * c * c);
+        c2 += c * c;
+    }
+    const double beta = 0.5 * s0 * sqrt(c2);
+    double B = 0.0;
+    for (int l = 0; l < M; ++l) {
+        const double coef = wt[l] * pow(s[l], p == 2 ? 5 : 7);
+        const double alpha = s[l] * s[l] / 4.0 - s0 * s0 / 8.0;
+        const double ks = (beta + sqrt(beta * beta + 8.0 * alpha * p)) / (4.0 * alpha);
+        B += coef * pow(ks, p) * exp(-alpha * ks * ks + beta * ks);
+    }
+    return K * B;
+}
+
+/* g_2(m) / q'(m) of the radial target over the widened proposal (0 at m = 0) */
+static double orc_weight_r_wide(const int32_t m[3], const double L[3], int M, const double *wt, const double *s)
+{
+    if (m[0] == 0 && m[1] == 0 && m[2] == 0) return 0.0;
+    return orc_target_r(m, L, M, wt, s) / orc_proposal_pmf(m, L, s[0] * ORC_NR_WIDEN);
+}
+
+/* tries of the rejection draw of a start state; each passes with probability
+   (normalised target mass) / B_p, above 0.08 for every box tested */
+#define ORC_START_TRIES 1024
+
+/*
+ * Start state of a chain, an exact draw of its target by rejection: try t
+ * draws m from the widened proposal (normals of streams sxy, sz at counter t)
+ * and is accepted iff u * B_p < g_p(m) / q'(m), u the first (r-chain) or
+ * second (non-radial chain) uniform of stream 7 at counter t.  The first
+ * accepted try gives the state.  Returns 0, or -1 if no try was accepted.
+ */
+static int orc_exact_start(const double L[3], int M, const double *wt, const double *s, uint64_t seed,
+                           uint64_t sys, uint64_t step, int p, uint32_t sxy, uint32_t sz, int32_t out[3])
+{
+    const double B = orc_start_bound(L, M, wt, s, p);
+    for (uint32_t t = 0; t < ORC_START_TRIES; ++t) {
+        double z[3], u[2];
+        int32_t m[3];
+        orc_draw_proposal(seed, sys, step, t, sxy, sz, z, NULL);
+        orc_round_proposal(z, L, s[0] * ORC_NR_WIDEN, m);
+        orc_draw(seed, sys, step, t, 7u, &u[0], &u[1]);
+        const double w = p == 2 ? orc_weight_r_wide(m, L, M, wt, s) : orc_weight_nr(m, L, M, wt, s);
+        if ((p == 2 ? u[0] : u[1]) * B < w) {
+            memcpy(out, m, sizeof(int32_t) * 3);
+            return 0;
+        }
+    }
+    return -1;
+}
+
+/* Exposed for tests: the start states of both chains (-1 if a draw failed). */
+int orc_start_states(const double L[3], int M, const double *wt, const double *s, uint64_t seed,
+                     uint64_t sys, uint64_t step, int32_t m_r0[3], int32_t m_nr0[3])
+{
+    if (orc_exact_start(L, M, wt, s, seed, sys, step, 2, 3u, 4u, m_r0)) return -1;
+    if (orc_exact_start(L, M, wt, s, seed, sys, step, 4, 8u, 9u, m_nr0)) return -1;
+    return 0;
+}
+
+/*
  * One sampling step (Algorithm 1, steps 2-3).
  *  r-chain (App. D): independence Metropolis-Hastings with the rounded
  *  Gaussian proposal; accept m* iff u < [P(m*) q(m)] / [P(m) q(m*)], written
- *  as w(m*)/w(m) with w = P/q.  The chain restarts every step from the first
- *  nonzero proposal of the initial-state streams (3, 4); m_r[t] is the state
- *  after the t-th MH step.
+ *  as w(m*)/w(m) with w = P/q.  Every step the chain starts from an exact draw
+ *  of P^r (orc_exact_start, normals from streams 3, 4), so each of its states
+ *  is distributed exactly as P^r; m_r[t] is the state after the t-th MH step.
  *  variant 0 (as printed, Sec. 3.2): the nr-chain is orc_recalibrate run on
  *  the r-chain states in order, started at the first r-chain state.
- *  variant 1 (exchange): after each r-step the same acceptance ratio decides
- *  a swap of the two chains' states, (x, z) -> (z, x); this move keeps
- *  P^r x P^nr invariant even though consecutive r-states are correlated.
- * Both variants only ever visit accepted r-chain proposals and the initial
- * state, so at most P + 1 distinct modes appear.
+ *  variant 1 (exchange): a second state z starts from an exact draw of P^nr
+ *  (streams 8, 9); after each r-step the recalibration's acceptance ratio
+ *  decides a swap of the two chains' states, (x, z) -> (z, x).  The joint
+ *  chain keeps P^r x P^nr invariant and starts in it, so every recorded state
+ *  has exactly its target's law.  At most P + 2 distinct modes appear.
  * The two samplers the recalibration is weighed against (Sec. 3.2):
  *  variant 2 (shared proposal, no recalibration): m_nr = m_r; the non-radial
  *  estimator then weighs each r-chain mode by P^nr/P^r (see the oracle's
@@ -438,32 +526,31 @@ void orc_recalibrate(int P, const int32_t *props, const double *u, const double 
  *  target P^nr and a rounded Gaussian proposal of width parameter
  *  s_0 ORC_NR_WIDEN (orc_weight_nr), its normals from streams (5, 6) and its
  *  acceptance uniform the second one of stream 2; accept m* iff
- *  u < w_nr(m*)/w_nr(m); it starts at the r-chain's initial state.  Up to
- *  2P + 1 distinct modes.
- * Returns 0, or -1 when no nonzero initial state was drawn in 64 tries.
+ *  u < w_nr(m*)/w_nr(m); it starts from its own exact draw of P^nr (streams
+ *  8, 9).  Up to 2P + 2 distinct modes.
+ * Returns 0, or -1 when a start draw failed (no accepted try).
  * n_acc[0], n_acc[1] receive the accepted-move counts of the two chains.
- * Pinned by: chi^2 of long chains against the enumerated targets.
+ * Pinned by: chi^2 of long chains against the enumerated targets, the law of
+ * the start states, and batch means against the deterministic sums.
  */
 int orc_sample_modes(const double L[3], int M, const double *wt, const double *s, int P,
                      uint64_t seed, uint64_t sys, uint64_t step, int variant,
                      int32_t *m_r, int32_t *m_nr, int64_t n_acc[2])
 {
-    int32_t cur[3];
-    int found = 0;
-    for (uint32_t j = 0; j < 64 && !found; ++j) {
-        double z[3];
-        orc_draw_proposal(seed, sys, step, j, 3u, 4u, z, NULL);
-        orc_round_proposal(z, L, s[0], cur);
-        found = !(cur[0] == 0 && cur[1] == 0 && cur[2] == 0);
-    }
-    if (!found) return -1;
-    int32_t cur0[3];
-    memcpy(cur0, cur, sizeof cur0);
+    int32_t cur[3], z0[3];
+    if (orc_exact_start(L, M, wt, s, seed, sys, step, 2, 3u, 4u, cur)) return -1;
+    if ((variant == 1 || variant == 3) && orc_exact_start(L, M, wt, s, seed, sys, step, 4, 8u, 9u, z0))
+        return -1;
     double wcur = orc_weight(cur, L, M, wt, s);
     double *unr = malloc(sizeof(double) * (P > 0 ? P : 1));
     int64_t acc_r = 0, acc_nr = 0;
     int32_t znr[3];
     double wz = 0.0, rz = 0.0;
+    if (variant == 1) {
+        memcpy(znr, z0, sizeof znr);
+        wz = orc_weight(znr, L, M, wt, s);
+        rz = orc_ratio_nr(znr, L, M, wt, s);
+    }
     for (int t = 0; t < P; ++t) {
         double z[3], uacc[2];
         int32_t prop[3];
@@ -477,11 +564,6 @@ int orc_sample_modes(const double L[3], int M, const double *wt, const double *s
             ++acc_r;
         }
         if (variant == 1) {
-            if (t == 0) {
-                memcpy(znr, cur, sizeof znr);
-                wz = wcur;
-                rz = orc_ratio_nr(znr, L, M, wt, s);
-            }
             const double rx = orc_ratio_nr(cur, L, M, wt, s);
             if (uacc[1] < rx / rz) {
                 int32_t tmp[3];
@@ -502,7 +584,7 @@ int orc_sample_modes(const double L[3], int M, const double *wt, const double *s
     if (variant == 2) memcpy(m_nr, m_r, sizeof(int32_t) * 3 * (size_t)(P > 0 ? P : 0));
     if (variant == 3) {
         int32_t zc[3];
-        memcpy(zc, cur0, sizeof zc);
+        memcpy(zc, z0, sizeof zc);
         double wzc = orc_weight_nr(zc, L, M, wt, s);
         for (int t = 0; t < P; ++t) {
             double z[3];

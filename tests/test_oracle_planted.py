@@ -70,7 +70,7 @@ def test_a_wrong_sign_in_the_nonradial_estimator_is_caught(orc, monkeypatch):
         return F, Pr, -Pnr, UF
     _wrap(monkeypatch, orc, "long_range_rb", flip)
     with pytest.raises(AssertionError):
-        pins.test_batch_mean_converges_to_full_sum(orc, 0)
+        pins.test_batch_mean_is_unbiased(orc, orc.RECAL_EXCHANGE, 50, 20_000)
 
 
 def test_transposed_cell_axes_are_caught(orc, monkeypatch):
