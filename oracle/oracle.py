@@ -76,6 +76,7 @@ def lib():
             "orc_self_energy": (d, [d, d, d, C.c_int, i64, pd]),
             "orc_ewald": (None, [i64, pd, pd, pd, pd, pd, d, d, d, pd, pd, pd, pd, pd]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_num_threads": (None, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -312,6 +313,28 @@ def nonradial_shared(q, pos, L, p: SOG, m_r, Sr):
     return -Sr / (8.0 * V * V * P) * acc
 
 
+def uf_rb_energy(q, pos, L, m_r, Sr, p_force: SOG, p_energy: SOG):
+    """Random-batch long-range energy when the energy kernel keeps more
+    Gaussians than the force (Table 1 gives the energy its own, larger M):
+    the importance-sampling estimate of eq. U_long under the radial proposal,
+        U^{F*} = (1/P) sum_p Fhat_e(k_p) |rho_p|^2 / (2 V P^r(k_p)),
+        Fhat_e(k) = pi^(3/2) sum_{l < M_e} w_l s_l^3 exp(-s_l^2 k^2 / 4)   (energy kernel),
+        P^r(k)    = pi^(3/2) |k|^2 sum_{l < M} wt_l s_l^5 exp(-s_l^2 k^2 / 4) / S^r   (eq. samplingP).
+    With M_e = M it is the U^{F*} of long_range_rb."""
+    L = _f64(L); V = float(np.prod(L))
+    m = np.ascontiguousarray(m_r, dtype=np.int32).reshape(-1, 3)
+    P = m.shape[0]
+    r = rho(q, pos, L, m)
+    tot = 0.0
+    for t in range(P):
+        k = 2.0 * np.pi * m[t] / L
+        k2 = float(k @ k)
+        Fe = np.pi ** 1.5 * np.sum(p_energy.w * p_energy.s ** 3 * np.exp(-p_energy.s ** 2 * k2 / 4.0))
+        Pr = np.pi ** 1.5 * k2 * np.sum(p_force.wt * p_force.s ** 5 * np.exp(-p_force.s ** 2 * k2 / 4.0)) / Sr
+        tot += Fe * abs(r[t]) ** 2 / (2.0 * V * Pr)
+    return tot / P
+
+
 def sog_kspace_full(q, pos, L, p: SOG, forces=True):
     q = _f64(q); x, y, z = _xyz(pos); n = q.shape[0]
     f = [np.zeros(n) for _ in range(3)] if forces else [None, None, None]
@@ -389,6 +412,10 @@ def rbsog_step(q, pos, L, p: SOG, P, seed, system_id, step, modes=None, sample=N
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

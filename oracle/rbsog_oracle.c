@@ -1086,3 +1086,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* threads of the oracle's parallel loops from now on (timing on one core) */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -115,7 +115,7 @@ int rbsog_params_init(rbsog_params *p, double rc)
     p->system_id = 0;
     p->coulomb_k = 1.0;
     p->precision = RBSOG_PREC_FP32C;
-    p->recalibration = RBSOG_RECAL_PRINTED;
+    p->recalibration = RBSOG_RECAL_EXCHANGE;
     return RBSOG_OK;
 }
 

@@ -133,6 +133,7 @@ __device__ inline double unit_open(uint32_t hi, uint32_t lo)
 
 struct SampArgs {
     double L[3];
+    double B[2];       // bounds of g_2/q' and g_4/q' (exact start draws)
     int P, M, variant, mcap;
     uint32_t key0, key1, step, sys;
     const SogTables *tab;
@@ -177,14 +178,17 @@ __device__ void round_proposal(const SampArgs &a, const double z[3], int m[3], d
 
 // importance weight w = P^r(m)/q(m) (unnormalised, 0 at m = 0) and the
 // recalibration ratio R = P^nr(m)/P^r(m) (unnormalised); with wnr, also the
-// independent non-radial chain's weight P^nr(m)/q'(m), q' the widened proposal
-__device__ void mode_weights(const SampArgs &a, const int m[3], double *w, double *R, double *wnr = nullptr)
+// non-radial weight P^nr(m)/q'(m), q' the widened proposal, and with wrw the
+// radial one P^r(m)/q'(m)
+__device__ void mode_weights(const SampArgs &a, const int m[3], double *w, double *R, double *wnr = nullptr,
+                             double *wrw = nullptr)
 {
 #pragma clang fp contract(off)
     if (m[0] == 0 && m[1] == 0 && m[2] == 0) {
         *w = 0.0;
         *R = 0.0;
         if (wnr) *wnr = 0.0;
+        if (wrw) *wrw = 0.0;
         return;
     }
     double k2 = 0.0;
@@ -218,31 +222,49 @@ __device__ void mode_weights(const SampArgs &a, const int m[3], double *w, doubl
     };
     *w = target / pmf(t->s[0]);
     *R = k2 * a7 / a5;
-    if (wnr) *wnr = target * *R / pmf(t->s[0] * kNrWiden);
+    if (wnr || wrw) {
+        const double qw = pmf(t->s[0] * kNrWiden);
+        if (wnr) *wnr = target * *R / qw;
+        if (wrw) *wrw = target / qw;
+    }
 }
 
+// Tries of the rejection draw that starts a chain (each accepted with
+// probability above 0.08 for the boxes tested: failing all has probability
+// below 1e-37).
+constexpr int kStartTries = 1024;
+
 // Algorithm 1 steps 2-3 for one system per workgroup of 256 threads.
-// Slot 0 holds the chain's initial state, slot t+1 the t-th proposal, and
-// with the independent non-radial chain slot P+1+t that chain's t-th proposal
-// (its weight in s_w).
+// Slot 0 holds the r-chain's start state, slot t+1 the t-th proposal.  The
+// exchange form's non-radial start state is slot P+1; the independent
+// non-radial chain's start state is slot P+1 and its t-th proposal slot
+// P+2+t (their weights P^nr/q' in s_w).
+//
+// Start states: every chain starts each step from an exact draw of its own
+// target, by rejection from the rounded Gaussian with width parameter
+// s_0/sqrt2: try t draws m (normals of streams 3, 4 for the r-chain, 8, 9 for
+// the non-radial one, at counter t) and passes iff u B < g(m)/q'(m), u the
+// first (r) or second (non-radial) uniform of stream 7 at counter t and B the
+// host's bound of g/q'.  The first passing try is the start state.
 __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp)
 {
 #pragma clang fp contract(off)
-    __shared__ int3 s_mode[kMaxP + 1];
-    __shared__ double s_w[kMaxP + 1], s_R[kMaxP + 1];
+    __shared__ int3 s_mode[kMaxModes];
+    __shared__ double s_w[kMaxModes], s_R[kMaxModes];
     __shared__ double s_ur[kMaxP], s_unr[kMaxP];
     __shared__ int16_t s_sr[kMaxP], s_snr[kMaxP];
-    __shared__ int16_t s_rep[kMaxP + 1], s_didx[kMaxP + 1];
-    __shared__ uint8_t s_used[kMaxP + 1];
-    __shared__ int s_cnt_r[kMaxP + 1], s_cnt_nr[kMaxP + 1];
-    __shared__ int s_init, s_nd;
-    __shared__ double s_wnr0;
+    __shared__ int16_t s_rep[kMaxModes], s_didx[kMaxModes];
+    __shared__ uint8_t s_used[kMaxModes];
+    __shared__ int s_cnt_r[kMaxModes], s_cnt_nr[kMaxModes];
+    __shared__ int s_first[2], s_nd;
     __shared__ long long s_acc[2];
 
     const SysDesc &D = desc[blockIdx.x];
     const SysStep &St = stp[blockIdx.x];
     SampArgs a;
     for (int d = 0; d < 3; ++d) a.L[d] = St.L[d];
+    a.B[0] = St.Bstart[0];
+    a.B[1] = St.Bstart[1];
     a.P = D.P;
     a.M = D.M;
     a.variant = D.variant;
@@ -260,25 +282,56 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
     const int tid = threadIdx.x;
     const int P = a.P;
     const bool indep = a.variant == RBSOG_RECAL_INDEPENDENT;
-    const int nslots = indep ? 2 * P + 1 : P + 1;  // == mcap
-    if (tid == 0) s_init = 64;
+    const bool exch = a.variant == RBSOG_RECAL_EXCHANGE;
+    const bool nrstart = indep || exch;
+    const int nslots = a.mcap;  // P + 1, P + 2 (exchange) or 2P + 2 (independent)
+    const int nr0 = P + 1;      // slot of the non-radial start state
+    if (tid == 0) {
+        s_first[0] = kStartTries;
+        s_first[1] = nrstart ? kStartTries : -1;
+    }
     __syncthreads();
-    // initial state: first nonzero draw of the initial-state streams (3, 4)
-    if (tid < 64) {
-        double z[3];
-        int m[3];
-        draw_normals(a, static_cast<uint32_t>(tid), 3u, 4u, z);
-        round_proposal(a, z, m);
-        const bool nz = (m[0] | m[1] | m[2]) != 0;
-        const unsigned long long ball = __ballot(nz);
-        const int first = ball ? __ffsll(ball) - 1 : 64;
-        if (tid == first) {
-            s_mode[0] = make_int3(m[0], m[1], m[2]);
-            double wnr0;
-            mode_weights(a, m, &s_w[0], &s_R[0], &wnr0);
-            s_wnr0 = wnr0;
-            s_init = first;
+    // start states: rounds of 256 tries until each chain has a passing one
+    for (int base = 0; base < kStartTries; base += blockDim.x) {
+        const bool need_r = s_first[0] == kStartTries, need_nr = s_first[1] == kStartTries;
+        __syncthreads();  // every thread has read s_first before this round's atomics
+        const uint32_t t = static_cast<uint32_t>(base + tid);
+        const uint4 o = philox4x32_10(make_uint4(t, 7u, a.step, a.sys), make_uint2(a.key0, a.key1));
+        int mr[3] = {0, 0, 0}, mn[3] = {0, 0, 0};
+        bool pass_r = false, pass_nr = false;
+        if (need_r) {
+            double z[3], w, R, wrw;
+            draw_normals(a, t, 3u, 4u, z);
+            round_proposal(a, z, mr, kNrWiden);
+            mode_weights(a, mr, &w, &R, nullptr, &wrw);
+            pass_r = unit_open(o.x, o.y) * a.B[0] < wrw;
+            if (pass_r) atomicMin(&s_first[0], static_cast<int>(t));
         }
+        if (need_nr) {
+            double z[3], w, R, wnr;
+            draw_normals(a, t, 8u, 9u, z);
+            round_proposal(a, z, mn, kNrWiden);
+            mode_weights(a, mn, &w, &R, &wnr);
+            pass_nr = unit_open(o.z, o.w) * a.B[1] < wnr;
+            if (pass_nr) atomicMin(&s_first[1], static_cast<int>(t));
+        }
+        __syncthreads();
+        if (pass_r && s_first[0] == static_cast<int>(t)) {
+            s_mode[0] = make_int3(mr[0], mr[1], mr[2]);
+            mode_weights(a, mr, &s_w[0], &s_R[0]);
+        }
+        if (pass_nr && s_first[1] == static_cast<int>(t)) {
+            s_mode[nr0] = make_int3(mn[0], mn[1], mn[2]);
+            double w, R, wnr;
+            mode_weights(a, mn, &w, &R, &wnr);
+            // the exchange form's state can move into the r-chain (radial weight);
+            // the independent chain weighs its states by P^nr/q'
+            s_w[nr0] = indep ? wnr : w;
+            s_R[nr0] = R;
+        }
+        const bool done = s_first[0] < kStartTries && s_first[1] < kStartTries;
+        __syncthreads();
+        if (done) break;
     }
     for (int t = tid; t < P; t += blockDim.x) {
         double z[3];
@@ -295,9 +348,9 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
             draw_normals(a, static_cast<uint32_t>(t), 5u, 6u, z);
             round_proposal(a, z, m, kNrWiden);
             double w, R;
-            s_mode[P + 1 + t] = make_int3(m[0], m[1], m[2]);
-            mode_weights(a, m, &w, &R, &s_w[P + 1 + t]);
-            s_R[P + 1 + t] = R;
+            s_mode[P + 2 + t] = make_int3(m[0], m[1], m[2]);
+            mode_weights(a, m, &w, &R, &s_w[P + 2 + t]);
+            s_R[P + 2 + t] = R;
         }
     }
     for (int s = tid; s < nslots; s += blockDim.x) {
@@ -306,7 +359,7 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
         s_cnt_nr[s] = 0;
     }
     __syncthreads();
-    if (s_init >= 64) {
+    if (s_first[0] >= kStartTries || s_first[1] >= kStartTries) {
         if (tid == 0) {
             a.res->status = -1;
             a.res->nd = 0;
@@ -318,18 +371,15 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
         long long acc_r = 0, acc_nr = 0;
         int cur = 0;
         double wcur = s_w[0];
-        if (a.variant == RBSOG_RECAL_EXCHANGE) {
-            int zs = 0;
-            double rz = 0.0;
+        if (exch) {
+            // the second state starts from its exact non-radial draw
+            int zs = nr0;
+            double rz = s_R[nr0];
             for (int t = 0; t < P; ++t) {
                 if (s_ur[t] < s_w[t + 1] / wcur) {
                     cur = t + 1;
                     wcur = s_w[t + 1];
                     ++acc_r;
-                }
-                if (t == 0) {
-                    zs = cur;
-                    rz = s_R[zs];
                 }
                 const double rx = s_R[cur];
                 if (s_unr[t] < rx / rz) {
@@ -353,11 +403,11 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
                 s_sr[t] = static_cast<int16_t>(cur);
             }
             if (indep) {
-                // its own chain from the same initial state, target P^nr
-                int zs = 0;
-                double wz = s_wnr0;
+                // its own chain from its exact start, target P^nr
+                int zs = nr0;
+                double wz = s_w[nr0];
                 for (int t = 0; t < P; ++t) {
-                    const int prop = P + 1 + t;
+                    const int prop = P + 2 + t;
                     if (s_unr[t] < s_w[prop] / wz) {
                         zs = prop;
                         wz = s_w[prop];

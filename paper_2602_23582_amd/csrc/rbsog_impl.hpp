@@ -22,7 +22,7 @@
 namespace rbsog {
 
 constexpr int kMaxP = 1024;        // samples per chain handled by the one-workgroup sampler
-constexpr int kMaxModes = kMaxP + 1; // distinct modes: accepted proposals plus the initial state
+constexpr int kMaxModes = kMaxP + 2; // distinct modes: accepted proposals plus the start states of both chains
 constexpr int kPairWave = 64;      // i-atoms per pair-kernel wavefront
 constexpr int kSkChunk = 1024;     // atoms per structure-factor workgroup
 constexpr int kPairRed = 64;       // workgroups reducing a system's pair-block partials (then summed in order)
@@ -35,11 +35,14 @@ constexpr int kPolyDeg = 10;       // degree of the FP32C polynomial form of the
 constexpr int kSuperCells = 4;     // most cells stacked in z into one pair-block segment
 constexpr int kOrderPart = 1024;   // keys one ordering workgroup ranks in a single-cell system
 
-// Distinct modes a step can visit: the r-chain's initial state and proposals,
-// plus the independent non-radial chain's proposals when it is drawn.
+// Distinct modes a step can visit: the r-chain's start state and proposals;
+// the exchange form adds the non-radial chain's start state, the independent
+// non-radial chain its start state and its own proposals.
 inline int mode_cap(const rbsog_params &p)
 {
-    return p.recalibration == RBSOG_RECAL_INDEPENDENT ? 2 * p.P + 1 : p.P + 1;
+    if (p.recalibration == RBSOG_RECAL_INDEPENDENT) return 2 * p.P + 2;
+    if (p.recalibration == RBSOG_RECAL_EXCHANGE) return p.P + 2;
+    return p.P + 1;
 }
 
 // SOG tables read by the kernels (device memory, uniform loads).
@@ -112,6 +115,7 @@ struct SysStep {
     double iL[3];         // 1/L, rounded once on the host
     double mu[3];         // scale factors of the next rescale
     double Sr, Snr;
+    double Bstart[2];     // bounds of g_2/q' and g_4/q' for the exact start draws of the chains
     int32_t nc[3];        // cells per edge; cell id = cz + nc[2] (cy + nc[1] cx), z fastest
     int32_t ncells;
     uint32_t step;
@@ -226,6 +230,7 @@ struct Batch {
 void sog_tables(const rbsog_params &p, double *w, double *wt, double *s);
 double omega_c0(double b, double sigma, double rc, int M);
 void norm_consts(const double L[3], int M, const double *wt, const double *s, double *Sr, double *Snr);
+double start_bound(const double L[3], int M, const double *wt, const double *s, int power);
 void cell_grid(const double L[3], double rc, int nc[3]);
 
 // ---------------------------------------------------------------------------

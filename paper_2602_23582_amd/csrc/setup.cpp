@@ -118,6 +118,36 @@ void norm_consts(const double L[3], int M, const double *wt, const double *s, do
     *Snr = snr;
 }
 
+// Bound of g_p(m) / q'(m) over the lattice for the rejection draws that start
+// the chains (App. D proposal with width parameter s_0/sqrt2, per-axis
+// deviation sig = L/(pi s_0); g_2 = |k|^2 sum wt s^5 e, g_4 = |k|^4 sum wt s^7 e,
+// e = exp(-s^2 |k|^2/4)).  A cell of the rounded normal holds at least the
+// density at its far end, so 1/q' <= prod_d sqrt(2 pi) sig_d exp((s_0 |k_d|/2 +
+// c_d)^2/2), c_d = 1/(2 sig_d); with sum_d c_d |k_d| <= |c||k| every Gaussian's
+// term is at most K coef kappa^p exp(-alpha kappa^2 + beta kappa) in kappa =
+// |k|, alpha = s^2/4 - s_0^2/8, beta = s_0|c|/2, largest at the positive root
+// of 2 alpha kappa^2 - beta kappa - p = 0.  The bound sums those maxima.
+double start_bound(const double L[3], int M, const double *wt, const double *s, int power)
+{
+    const double s0 = s[0];
+    double K = 1.0, csq = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double sig = L[d] / (kPi * s0);
+        const double c = 1.0 / (2.0 * sig);
+        K *= std::sqrt(2.0 * kPi) * sig * std::exp(0.5 * c * c);
+        csq += c * c;
+    }
+    const double beta = 0.5 * s0 * std::sqrt(csq);
+    double B = 0.0;
+    for (int l = 0; l < M; ++l) {
+        const double coef = wt[l] * std::pow(s[l], power == 2 ? 5 : 7);
+        const double alpha = s[l] * s[l] / 4.0 - s0 * s0 / 8.0;
+        const double kap = (beta + std::sqrt(beta * beta + 8.0 * alpha * power)) / (4.0 * alpha);
+        B += coef * std::pow(kap, power) * std::exp(-alpha * kap * kap + beta * kap);
+    }
+    return K * B;
+}
+
 // Cells no narrower than rc (so all partners of an atom lie in the 27 cells
 // around it); a dimension with fewer than three cells is searched whole.
 void cell_grid(const double L[3], double rc, int nc[3])

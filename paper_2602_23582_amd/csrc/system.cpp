@@ -203,7 +203,7 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
         err = "unknown recalibration";
         return RBSOG_EINVAL;
     }
-    if (p.recalibration == RBSOG_RECAL_INDEPENDENT && 2 * p.P + 1 > kMaxModes) {
+    if (mode_cap(p) > kMaxModes) {
         err = "the independent non-radial chain takes P <= 512";
         return RBSOG_EINVAL;
     }
@@ -306,6 +306,8 @@ void system_set_box(System &s, const double box[3])
     s.ncells = static_cast<int64_t>(s.nc[0]) * s.nc[1] * s.nc[2];
     norm_consts(s.L, s.prm.M, s.wt, s.s, &s.Sr, &s.Snr);
     SysStep &t = s.stp;
+    t.Bstart[0] = start_bound(s.L, s.prm.M, s.wt, s.s, 2);
+    t.Bstart[1] = start_bound(s.L, s.prm.M, s.wt, s.s, 4);
     for (int d = 0; d < 3; ++d) {
         t.L[d] = s.L[d];
         t.iL[d] = 1.0 / s.L[d];

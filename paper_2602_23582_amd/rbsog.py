@@ -154,7 +154,7 @@ def default_params(rc: float) -> rbsog_params:
 class Context:
     """One system: wraps rbsog_setup .. rbsog_destroy."""
 
-    def __init__(self, q, box, rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_PRINTED,
+    def __init__(self, q, box, rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_EXCHANGE,
                  M=10, b=None, sigma=None, omega=None, coulomb_k=1.0, stream=None, flags=0):
         L = load()
         p = default_params(rc)
@@ -314,7 +314,7 @@ def _timing_table(getter, handle):
     return rc, out
 
 
-def make_params(rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_PRINTED, M=10,
+def make_params(rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_EXCHANGE, M=10,
                 coulomb_k=1.0, flags=0):
     p = default_params(rc)
     p.P, p.seed, p.system_id, p.M = int(P), int(seed), int(system_id), int(M)
@@ -349,7 +349,7 @@ class Batch:
         for s, spec in enumerate(systems):
             arr[s] = make_params(spec["rc"], P=spec.get("P", 100), seed=spec.get("seed", 0),
                                  system_id=spec.get("system_id", 0), precision=precision,
-                                 recalibration=spec.get("recalibration", RECAL_PRINTED), M=spec.get("M", 10),
+                                 recalibration=spec.get("recalibration", RECAL_EXCHANGE), M=spec.get("M", 10),
                                  flags=spec.get("flags", 0))
             n[s] = len(spec["q"])
             qs.append(np.asarray(spec["q"], dtype=np.float64))
@@ -463,7 +463,7 @@ class Server:
             raise RBSOGError(rc_, f"{what}: {msg.decode() if msg else ''}")
 
     def submit(self, q, pos, box, rc, nsteps=10, growth=0.001, P=100, seed=0, system_id=0, M=10,
-               recalibration=RECAL_PRINTED):
+               recalibration=RECAL_EXCHANGE):
         """Queue one request; pos is (n, 3).  Returns its ticket."""
         p = make_params(rc, P=P, seed=seed, system_id=system_id, precision=self.precision, M=M,
                         recalibration=recalibration)

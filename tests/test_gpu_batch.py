@@ -51,7 +51,7 @@ def _alone(torch, rb, spec, step, box):
     """One step of one system through the single-system calls."""
     with rb.Context(spec["q"], spec["box"], spec["rc"], P=spec["P"], seed=spec["seed"],
                     system_id=spec["system_id"], M=spec.get("M", 10), flags=spec.get("flags", 0),
-                    recalibration=spec.get("recalibration", rb.RECAL_PRINTED)) as ctx:
+                    recalibration=spec.get("recalibration", rb.RECAL_EXCHANGE)) as ctx:
         x, y, z = (_dev(torch, spec["pos"][:, k]) for k in range(3))
         fx, fy, fz = (torch.empty_like(x) for _ in range(3))
         ctx.sample_modes(step, box)

@@ -54,7 +54,7 @@ def gpu_step(torch, ctx, pos, step, box, energy=True):
     return out
 
 
-def oracle_step(orc, d, box, pos, P, seed, sys, step, variant=0, sample=None):
+def oracle_step(orc, d, box, pos, P, seed, sys, step, variant=1, sample=None):
     p = orc.sog(d["rc"], row=2, M=10)
     return orc.rbsog_step(d["q"], pos, box, p, P, seed, sys, step, sample=sample, variant=variant)
 
