@@ -142,16 +142,18 @@ def valu_probe(iters=32768, blocks=2048):
     return res
 
 
-def served_bench(n_req, seed, pool_bytes, lam_frac=0.8, nsteps=10, growth=0.001):
+def served_bench(n_req, seed, pool_bytes, lam_fracs=(0.5, 0.8, 0.95), nsteps=10, growth=0.001):
     """The served stream: n_req independent systems (sizes log-uniform in
     [500, 50,000] atoms, +-1e on jittered lattices at 0.1 A^-3, P from
     {50, 100, 200}), each a request of nsteps steps under L_k = L_0 (1 + g k).
     Capacity is measured with every request submitted at once; then requests
-    arrive as a Poisson stream at lam_frac x that capacity.  Each is run with
-    continuous batching (all admitted requests per tick) and one request at a
-    time (the same server with one slot), on the same GPU and at the same
-    accuracy; every request is a force + pressure solve (no energy sum).
-    Latency = completion - submission."""
+    arrive as Poisson streams at each fraction of that capacity.  Each stream
+    runs with continuous batching (all admitted requests per tick); one
+    request at a time (the same server with one slot) runs at capacity and at
+    the middle fraction, on the same GPU and at the same accuracy; every
+    request is a force + pressure solve (no energy sum).  Latency =
+    completion - submission.  The pool is small enough that admission by
+    memory binds at capacity."""
     from paper_2602_23582_amd import rbsog
     from paper_2602_23582_amd import workloads as W
     sizes, seeds = W.served_stream(n_req, seed=seed)
@@ -179,28 +181,54 @@ def served_bench(n_req, seed, pool_bytes, lam_frac=0.8, nsteps=10, growth=0.001)
 
     burst = np.zeros(n_req)
     sat = run(65536, burst)
-    lam = lam_frac * sat["requests_per_s"]
-    arrivals = np.cumsum(np.random.default_rng(seed).exponential(1.0 / lam, n_req))
-    batched = run(65536, arrivals)
+    streams = {}
+    mid = lam_fracs[len(lam_fracs) // 2]
+    solo = None
+    for frac in lam_fracs:
+        lam = frac * sat["requests_per_s"]
+        arrivals = np.cumsum(np.random.default_rng(seed).exponential(1.0 / lam, n_req))
+        r = run(65536, arrivals)
+        r["arrival_rate_per_s"] = lam
+        streams[f"{frac:g}"] = r
+        if frac == mid:
+            solo = run(1, arrivals)
+            solo["arrival_rate_per_s"] = lam
     solo_sat = run(1, burst)
-    solo = run(1, arrivals)
     return {"requests": n_req, "steps_per_request": nsteps, "pool_mib": pool_bytes / 2**20, "energy": False,
-            "arrival_rate_per_s": lam, "arrival_rate_frac_of_capacity": lam_frac,
-            "continuous_batching": batched, "one_at_a_time": solo,
+            "atoms": int(sum(len(r["q"]) for r in reqs)),
+            "continuous_batching_by_load": streams,
+            "one_at_a_time": {"load": mid, **solo},
             "capacity": {"continuous_batching": sat, "one_at_a_time": solo_sat}}
 
 
-def cpu_baseline(d, P, seed, sample_atoms):
-    """The oracle as it stands on a bounded sample: long-range structure factors
-    of all atoms for every sampled mode (2P evaluations), short-range and
-    long-range forces of a random subset of atoms; the time scales to a full
-    step by the subset fraction."""
-    from oracle import oracle as orc
+def host_cpu():
+    """Model name and logical CPUs of the host, and the CPUs this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_step_time(orc, d, P, seed, sample_atoms):
+    """Seconds of one oracle step (Algorithm O) on the workload: mode
+    sampling, structure factors of all atoms for the 2P sampled modes and the
+    estimators, then short- and long-range forces of sample_atoms atoms; the
+    per-atom force time is scaled to all atoms (no scaling when the sample is
+    every atom)."""
     n = len(d["q"])
     p = orc.sog(d["rc"], row=2, M=10)
     rng = np.random.default_rng(0)
-    k = min(n, sample_atoms)
-    smp = np.sort(rng.choice(n, k, replace=False))
+    k = min(n, sample_atoms) if sample_atoms > 0 else n
+    smp = None if k == n else np.sort(rng.choice(n, k, replace=False))
     t0 = time.perf_counter()
     m_r, m_nr, _ = orc.sample_modes(d["L"], p, P, seed, 0, 0)
     Sr, Snr = orc.norm_consts(d["L"], p)
@@ -212,11 +240,33 @@ def cpu_baseline(d, P, seed, sample_atoms):
     t3 = time.perf_counter()
     # the second long_range_rb re-evaluates rho: subtract one full rho pass
     per_atom = max(t3 - t2 - (t2 - t1), 0.0) / k
-    t_step = (t1 - t0) + (t2 - t1) + per_atom * n
-    return {"value": n / t_step, "unit": "atom-steps/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{k} of {n} atoms for short- and long-range forces, structure factors of all atoms for "
-                      f"the {2 * P} sampled modes, one step; per-atom time scaled to all atoms",
-            "seconds": t3 - t0}
+    return (t1 - t0) + (t2 - t1) + per_atom * n, k, t3 - t0
+
+
+def cpu_baseline(d, P, seed, sample_atoms, single_sample):
+    """The oracle as it stands, timed on the host: every OpenMP thread it is
+    given on sample_atoms atoms (0: all of them, one full step), then one
+    thread on single_sample atoms."""
+    from oracle import oracle as orc
+    n = len(d["q"])
+    threads = orc.num_threads()
+    t_step, k, wall = oracle_step_time(orc, d, P, seed, sample_atoms)
+    out = {"value": n / t_step, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+           "sample": (f"one full step of all {n} atoms (sampling, structure factors of the {2 * P} sampled modes, "
+                      f"estimators, short- and long-range forces)" if k == n else
+                      f"{k} of {n} atoms for short- and long-range forces, structure factors of all atoms for "
+                      f"the {2 * P} sampled modes, one step; per-atom time scaled to all atoms"),
+           "seconds": wall, "host": host_cpu()}
+    if single_sample > 0:
+        orc.set_num_threads(1)
+        try:
+            t1, k1, w1 = oracle_step_time(orc, d, P, seed, single_sample)
+        finally:
+            orc.set_num_threads(threads)
+        out["single_core"] = {"value": n / t1, "cores": 1, "seconds": w1,
+                              "sample": f"{k1} of {n} atoms for the forces, structure factors of all atoms; "
+                                        f"per-atom time scaled to all atoms"}
+    return out
 
 
 def npt_bench(torch, ctx, d, x, y, z, nsteps, force_ms):
@@ -267,6 +317,8 @@ def variance_study(torch, reps, Ps=(50, 100, 200), sizes=(2000, 16000)):
     from paper_2602_23582_amd import rbsog
     from paper_2602_23582_amd import workloads as W
     rows = []
+    ref_path = os.path.join(ROOT, "tests", "golden", "variance_reference.json")
+    ref = json.load(open(ref_path))["systems"] if os.path.exists(ref_path) else {}
     for n in sizes:
         d = W.ionic_system(n, seed=11, P=100)
         x, y, z = (torch.tensor(np.ascontiguousarray(d["pos"][:, k]), dtype=torch.float64, device="cuda")
@@ -289,10 +341,77 @@ def variance_study(torch, reps, Ps=(50, 100, 200), sizes=(2000, 16000)):
                 m4 = np.mean((a - a.mean(0)) ** 4, axis=0)
                 se = np.sqrt(np.maximum(m4 - v * v, 0.0) / len(a))
                 vd, vo = float(v[[0, 4, 8]].mean()), float(v[[1, 2, 5]].mean())
-                rows.append({"n": n, "sampler": SAMPLERS[variant], "P": P, "var_diag": vd, "var_offdiag": vo,
-                             "var_diag_rel_se": float(se[[0, 4, 8]].mean() / 3 ** 0.5 / vd),
-                             "modes_per_step": float(np.mean(nd)), "var_diag_x_modes": vd * float(np.mean(nd))})
-    return {"system": "ionic, 0.1 A^-3, rc 10 A, +-1e on a jittered lattice", "reps": reps, "rows": rows}
+                row = {"n": n, "sampler": SAMPLERS[variant], "P": P, "var_diag": vd, "var_offdiag": vo,
+                       "var_diag_rel_se": float(se[[0, 4, 8]].mean() / 3 ** 0.5 / vd),
+                       "modes_per_step": float(np.mean(nd)), "var_diag_x_modes": vd * float(np.mean(nd))}
+                if str(n) in ref:
+                    # bias of the batch mean against the deterministic P^F, its
+                    # z-score, and the mean squared error per step var + bias^2
+                    PF = np.asarray(ref[str(n)]["PF"])
+                    bias = a.mean(0) - PF
+                    z = bias / np.sqrt(v / len(a))
+                    mse = v + bias ** 2
+                    row.update({"bias_diag": bias[[0, 4, 8]].tolist(), "bias_offdiag": bias[[1, 2, 5]].tolist(),
+                                "bias_rel_norm": float(np.linalg.norm(bias) / np.linalg.norm(PF)),
+                                "bias_max_abs_z": float(np.abs(z).max()),
+                                "mse_diag": float(mse[[0, 4, 8]].mean()), "mse_offdiag": float(mse[[1, 2, 5]].mean())})
+                rows.append(row)
+    return {"system": "ionic, 0.1 A^-3, rc 10 A, +-1e on a jittered lattice", "reps": reps, "rows": rows,
+            "reference": "P^F by the full k-space sum, tests/golden/variance_reference.json"}
+
+
+def extra_workload(torch, name, args, tw):
+    """Another workload through the same step (context calls, HIP events on the
+    pair launches): ms per step with its spread, atom-steps/s and the pair
+    kernel's roofline fraction."""
+    from paper_2602_23582_amd import rbsog
+    d, desc = make_workload(name)
+    n = len(d["q"])
+    x, y, z = (torch.tensor(np.ascontiguousarray(d["pos"][:, k]), dtype=torch.float64, device="cuda")
+               for k in range(3))
+    fx, fy, fz = (torch.empty_like(x) for _ in range(3))
+    L0 = np.asarray(d["L"], dtype=np.float64)
+    with rbsog.Context(d["q"], L0, d["rc"], P=int(d["P"]), seed=args.seed) as c:
+        def step(s):
+            mu = L0 * (1.0 + 0.001 * (s % 10)) / c.box
+            c.rescale(mu, x, y, z)
+            c.sample_modes(s, c.box)
+            c.force_virial(x, y, z, fx, fy, fz, energy=False)
+            return c.pressure()
+        for s in range(3):
+            step(s)
+        torch.cuda.synchronize()
+        c.set_timing(True)
+        t0 = time.perf_counter()
+        marks = []
+        for s in range(3, 3 + args.extra_steps):
+            step(s)
+            marks.append(time.perf_counter())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        timing = c.get_timing()
+        info = c.step_info()
+        c.set_timing(False)
+    per_step = 1e3 * np.diff(np.concatenate([[t0], marks]))
+    pair_ms, pair_cnt = timing.get("pair", (0.0, 1))
+    t_pair = pair_ms / max(pair_cnt, 1) * 1e-3
+    work = info["npairs"] * pair_work(tw)
+    del x, y, z, fx, fy, fz
+    torch.cuda.empty_cache()
+    return {"workload": desc, "n_atoms": n, "steps": args.extra_steps, "ms_per_step": 1e3 * (t1 - t0) / args.extra_steps,
+            "ms_per_step_percentiles": {"p10": float(np.percentile(per_step, 10)),
+                                        "median": float(np.percentile(per_step, 50)),
+                                        "p90": float(np.percentile(per_step, 90))},
+            "atom_steps_per_s": n * args.extra_steps / (t1 - t0),
+            "roofline": {"bound": "alu", "kernel": "k_pair (with its neighbourhood and gather launches)",
+                         "avg_launch_ms": 1e3 * t_pair, "unordered_pairs_per_launch": info["npairs"],
+                         "achieved": work / t_pair / 1e12 if t_pair > 0 else 0.0,
+                         "peak": VALU_LANE_OPS_PER_S / 1e12, "unit": "T FP32 lane-op/s",
+                         "frac": work / t_pair / VALU_LANE_OPS_PER_S if t_pair > 0 else 0.0},
+            "distinct_modes": info["nd"]}
+
+
+SHELL_FLAGS = {"auto": 0, "full": 2, "half": 4}
 
 
 def main():
@@ -302,14 +421,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="slab-1m")
     ap.add_argument("--seed", type=int, default=2026)
-    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="atoms whose forces the oracle computes on all host threads (0: every atom, one full step)")
+    ap.add_argument("--cpu-single-sample", type=int, default=20_000,
+                    help="atoms of the single-thread oracle timing (0: skip)")
+    ap.add_argument("--extra", default="electrolyte-10m",
+                    help="comma-separated further workloads timed after the main one (none: skip)")
+    ap.add_argument("--extra-steps", type=int, default=10)
+    ap.add_argument("--shell", choices=["auto", "full", "half"], default="auto",
+                    help="pair kernel: the library's choice, or force the full or the half shell")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-valu-probe", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="run the step as a batch of one replaying a captured HIP graph")
     ap.add_argument("--served", type=int, default=4096, help="requests of the served-stream run (0: skip)")
     ap.add_argument("--npt-steps", type=int, default=20, help="Langevin NPT steps timed after the main run (0: skip)")
-    ap.add_argument("--served-pool-mib", type=int, default=4096)
+    ap.add_argument("--served-pool-mib", type=int, default=1024)
     ap.add_argument("--other-p", type=int, default=400,
                     help="also time the workload at this batch size P (0: skip)")
     ap.add_argument("--variance-reps", type=int, default=1000,
@@ -349,7 +476,8 @@ def main():
             last["info"] = inf[0]
             return Pb[0]
     else:
-        ctx = rbsog.Context(d["q"], L0, d["rc"], P=P, seed=args.seed, precision=rbsog.PREC_FP32C)
+        ctx = rbsog.Context(d["q"], L0, d["rc"], P=P, seed=args.seed, precision=rbsog.PREC_FP32C,
+                            flags=SHELL_FLAGS[args.shell])
 
         def step(s):
             target = L0 * (1.0 + 0.001 * (s % 10))
@@ -366,10 +494,13 @@ def main():
         ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = []
     for s in range(args.warmup, args.warmup + args.steps):
-        step(s)
+        step(s)  # ends with the pressure copied to the host (a stream synchronisation)
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    per_step = 1e3 * np.diff(np.concatenate([[t0], marks]))
     if args.graph:
         # per-kernel times from a few eager steps of the same launches (events
         # cannot be recorded inside the replayed graph)
@@ -414,10 +545,14 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle on the host cores")
-        cpu = cpu_baseline(d, P, args.seed, args.cpu_sample)
+        cpu = cpu_baseline(d, P, args.seed, args.cpu_sample, args.cpu_single_sample)
     out = {
         "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": ms_step,
+        "ms_per_step_percentiles": {"p10": float(np.percentile(per_step, 10)),
+                                    "median": float(np.percentile(per_step, 50)),
+                                    "p90": float(np.percentile(per_step, 90))},
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "n_atoms": n, "box": L0.tolist(), "rc": d["rc"], "P": P,
                    "precision": "FP32C (FP32 arithmetic, FP64 partial sums and reductions)",
@@ -445,6 +580,11 @@ def main():
                               "atom_steps_per_s": n * args.steps / (tb - ta),
                               "distinct_modes": c2.step_info()["nd"],
                               "note": "no box rescale between these steps"}
+    if args.extra and args.extra != "none" and not args.graph:
+        out["extra"] = {}
+        for name in args.extra.split(","):
+            log(f"workload {name}: {args.extra_steps} steps")
+            out["extra"][name] = extra_workload(torch, name, args, tw)
     if args.npt_steps > 0 and not args.graph:
         log(f"NPT integration: {args.npt_steps} steps")
         out["npt"] = npt_bench(torch, ctx, d, x, y, z, args.npt_steps, ms_step)

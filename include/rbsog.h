@@ -57,15 +57,17 @@ extern "C" {
 #define RBSOG_PREC_FP64 0  /* every kernel in double precision                     */
 #define RBSOG_PREC_FP32C 1 /* FP32 arithmetic, FP64 partial sums and reductions     */
 
-#define RBSOG_RECAL_PRINTED 0  /* recalibration chain as printed in Sec. 3.2      */
-#define RBSOG_RECAL_EXCHANGE 1 /* swap of the two chain states on acceptance      */
+#define RBSOG_RECAL_PRINTED 0  /* recalibration chain as printed in Sec. 3.2 (biased, see below) */
+#define RBSOG_RECAL_EXCHANGE 1 /* swap of the two chain states on acceptance (the default)      */
 /* The samplers the recalibration is weighed against (Sec. 3.2): */
 #define RBSOG_RECAL_SHARED 2      /* no recalibration: the r-chain's modes, weighted by P^nr/P^r */
-#define RBSOG_RECAL_INDEPENDENT 3 /* a second MH chain for P^nr: up to 2P+1 modes, P <= 512      */
+#define RBSOG_RECAL_INDEPENDENT 3 /* a second MH chain for P^nr: up to 2P+2 modes, P <= 512      */
 
 #define RBSOG_MAX_M 64
 
-#define RBSOG_FLAG_EXP_FORM 1 /* FP32C: evaluate the M exponentials, not the polynomial form */
+#define RBSOG_FLAG_EXP_FORM 1  /* FP32C: evaluate the M exponentials, not the polynomial form   */
+#define RBSOG_FLAG_FULL_SHELL 2 /* FP32C: the full-shell pair kernel (the default)                */
+#define RBSOG_FLAG_HALF_SHELL 4 /* FP32C: the half-shell pair kernel (each unordered pair once)   */
 
 typedef struct rbsog_ctx rbsog_ctx;
 
@@ -83,15 +85,28 @@ typedef struct rbsog_ctx rbsog_ctx;
  *                   system_id and step must be < 2^32.
  *  coulomb_k        prefactor applied to every energy, force and pressure.
  *  precision        RBSOG_PREC_FP64 or RBSOG_PREC_FP32C.
- *  recalibration    how the non-radial modes of eq. P_approx_nr are drawn:
- *                   RBSOG_RECAL_PRINTED (default) or RBSOG_RECAL_EXCHANGE
- *                   recalibrate the r-chain's states (Sec. 3.2);
+ *  recalibration    how the non-radial modes of eq. P_approx_nr are drawn.
+ *                   Every chain starts each step from an exact draw of its
+ *                   own target (rejection from the rounded Gaussian sqrt(2)
+ *                   wider than App. D's, under a proven bound; Philox
+ *                   streams 3, 4, 7, 8, 9), so each recorded state has its
+ *                   target's law.
+ *                   RBSOG_RECAL_EXCHANGE (default) recalibrates the r-chain's
+ *                   states (Sec. 3.2) by swapping the two chains' states when
+ *                   the recalibration ratio accepts: both marginals stay
+ *                   exact and the estimators are unbiased at any P; up to
+ *                   P + 2 distinct modes.
+ *                   RBSOG_RECAL_PRINTED is the recalibration chain as
+ *                   printed: it treats the repeating r-chain states as
+ *                   independent proposals and its non-radial pressure is
+ *                   biased by a P-independent amount (+7% and +13% of two
+ *                   diagonal components of P^F on a 64-charge test box).
  *                   RBSOG_RECAL_SHARED uses the r-chain's modes themselves,
  *                   each weighted by P^nr/P^r (times S^r/S^nr);
  *                   RBSOG_RECAL_INDEPENDENT draws a second independence MH
  *                   chain for P^nr (Philox streams 5, 6; a rounded Gaussian
  *                   proposal sqrt(2) times wider than the radial one), so
- *                   up to 2P + 1 distinct modes and P <= 512.  The radial
+ *                   up to 2P + 2 distinct modes and P <= 512.  The radial
  *                   estimator, the force and the energy always use the r-chain.
  *  flags            0, or RBSOG_FLAG_EXP_FORM.  In FP32C the short-range
  *                   sums sum_l wt_l exp(-r^2/s_l^2) and sum_l w_l exp(-r^2/s_l^2)
@@ -100,6 +115,26 @@ typedef struct rbsog_ctx rbsog_ctx;
  *                   used when their truncation error is below 5e-8 of the sum
  *                   at r = 0, else the exponentials); RBSOG_FLAG_EXP_FORM asks
  *                   for the M exponentials of eqs. force_SOG and U_short.
+ *                   The FP32C pair kernel evaluates each pair from both of
+ *                   its atoms (the full shell; RBSOG_FLAG_FULL_SHELL states
+ *                   it explicitly).  RBSOG_FLAG_HALF_SHELL asks FP32C systems
+ *                   with four or more cells per edge to evaluate each
+ *                   unordered pair once (Newton's third law; the reactions
+ *                   meet in a fixed-order gather, so results stay bitwise
+ *                   reproducible) at about 1.2 KB per atom of extra device
+ *                   memory; on MI355X it is slower than the full shell (the
+ *                   reactions collide in LDS), so it is not the default.
+ *                   A step whose neighbourhoods outgrow the half shell's
+ *                   buffer (densities above 0.15 atoms/A^3) runs the full
+ *                   shell.  The two shells agree to FP32 rounding.
+ *  M_energy         0 (= M), or M..RBSOG_MAX_M: Gaussians of the energy
+ *                   kernel only (Table 1 asks 25 for the energy of row 2).
+ *                   U^N (eq. U_short), U_self and U^{F*} then use M_energy
+ *                   terms (w_l for l < M_energy); forces, virial, pressure
+ *                   and the sampling keep M.  U^{F*} stays the
+ *                   importance-sampled energy under the radial proposal:
+ *                   each mode carries the ratio of the M_energy-term energy
+ *                   kernel to the M-term one.
  */
 typedef struct rbsog_params {
     double b;
@@ -114,7 +149,8 @@ typedef struct rbsog_params {
     int32_t precision;
     int32_t recalibration;
     int32_t flags;
-    int32_t reserved[5];
+    int32_t M_energy;
+    int32_t reserved[4];
 } rbsog_params;
 
 /*
@@ -122,7 +158,8 @@ typedef struct rbsog_params {
  * 3.270345668108471, omega~ = 1.007806979343806 at r_c = 9 A; the row the
  * paper uses in all runs) rescaled to the cutoff rc by sigma = sigma9 * rc / 9
  * (the split is scale covariant), M = 10 (the pressure column's M~), P = 100,
- * seed 0, system 0, coulomb_k 1, FP32C, printed recalibration, flags 0.
+ * seed 0, system 0, coulomb_k 1, FP32C, exchange recalibration, flags 0,
+ * M_energy 0 (= M).
  * Returns RBSOG_EINVAL if p is NULL or rc <= 0.
  */
 int rbsog_params_init(rbsog_params *p, double rc);
@@ -204,6 +241,12 @@ const char *rbsog_last_error(const rbsog_ctx *ctx);
  *    Any output may be NULL; at most cap entries are written.
  */
 int rbsog_debug_cells(rbsog_ctx *ctx, int32_t *host_cell, int32_t host_ncell[3]);
+/*
+ *  rbsog_debug_long_range_force: the random-batch long-range force F^{F*} of
+ *    the last rbsog_force_virial alone (eq. f_approx, times coulomb_k), into
+ *    device arrays fx, fy, fz (n each, caller order).  Synchronises.
+ */
+int rbsog_debug_long_range_force(rbsog_ctx *ctx, double *fx, double *fy, double *fz);
 int rbsog_debug_modes(rbsog_ctx *ctx, int32_t cap, int32_t *host_nd, int32_t *host_modes,
                       int32_t *host_counts, double *host_rho);
 
@@ -368,6 +411,42 @@ int rbsog_batch_set_options(rbsog_batch *b, int32_t schedule, int32_t wg_per_cu,
 int rbsog_batch_autotune(rbsog_batch *b, const int64_t *host_steps, const double *host_boxes, const double *x,
                          const double *y, const double *z, double *fx, double *fy, double *fz, int32_t reps,
                          double *host_ms, int32_t *host_choice);
+
+/*
+ * A batch of existing contexts, admitted by device memory.
+ *  rbsog_batch_create   an empty batch whose admitted contexts may hold at most
+ *                       mem_budget_bytes of device memory together; work is
+ *                       queued on hip_stream (NULL = the null stream).
+ *  rbsog_batch_admit    adds a context (the contexts of one batch share one
+ *                       precision).  RBSOG_EAGAIN if its device memory (the
+ *                       buffers rbsog_setup allocated, grown to its current
+ *                       grid) exceeds what the budget has left or 65,536
+ *                       contexts are admitted; RBSOG_ESTATE if it is admitted
+ *                       elsewhere.  Waits for the context's own queued work.
+ *  rbsog_stage          the next step of an admitted context: step index, box
+ *                       and device arrays of positions and forces (n each,
+ *                       caller order), kept by the caller until the batched
+ *                       step has run.
+ *  rbsog_batch_step     with every array argument NULL, one step of every
+ *                       admitted context from its staged inputs (the launches
+ *                       of rbsog_batch_step below, one set for all contexts),
+ *                       then synchronises; host_P, host_energy, host_info as
+ *                       below, in admission order.  Each context's
+ *                       rbsog_pressure and rbsog_step_info then report its
+ *                       own results.  RBSOG_ESTATE if a context has no staged
+ *                       step.
+ *  rbsog_batch_release  removes a context (waits for the batch's queued work);
+ *                       rbsog_destroy of an admitted context releases it first.
+ * While admitted, a context's own evaluation calls (sample, force, rescale,
+ * debug, NPT) return RBSOG_ESTATE.  A context's results are bitwise the same
+ * alone and in any batch.  rbsog_batch_rescale and rbsog_batch_autotune's
+ * array arguments do not apply to a batch of contexts.
+ */
+int rbsog_batch_create(int64_t mem_budget_bytes, void *hip_stream, rbsog_batch **out);
+int rbsog_batch_admit(rbsog_batch *b, rbsog_ctx *ctx);
+int rbsog_stage(rbsog_ctx *ctx, int64_t step, const double host_box[3], const double *x, const double *y,
+                const double *z, double *fx, double *fy, double *fz);
+int rbsog_batch_release(rbsog_batch *b, rbsog_ctx *ctx);
 
 /* Per-kernel HIP-event timing of the batch's launches (as rbsog_set_timing). */
 int rbsog_batch_set_timing(rbsog_batch *b, int on);

@@ -74,7 +74,26 @@ int refresh_cells(rbsog_ctx *c)
 {
     bool recarved = false;
     RB_TRY(rbsog::system_ensure_cells(c->sys, c->err, &recarved));
-    if (recarved) c->batch.desc_dirty = true;
+    if (recarved) {
+        c->batch.desc_dirty = true;
+        c->desc_moved = true;
+    }
+    return RBSOG_OK;
+}
+
+// results of the last evaluation on the host: the context's own, or those a
+// batch of contexts left for it
+int fetch(rbsog_ctx *c)
+{
+    if (c->res_from_batch) return RBSOG_OK;
+    return rbsog::batch_fetch_results(c->batch, c->err);
+}
+
+// calls that launch the context's own work are refused while it is admitted
+int own_work(rbsog_ctx *c)
+{
+    if (c->in_batch) return fail(c, RBSOG_ESTATE, "the context is admitted to a batch (rbsog_stage, rbsog_batch_step)");
+    c->res_from_batch = false;
     return RBSOG_OK;
 }
 
@@ -146,6 +165,7 @@ int rbsog_sample_modes(rbsog_ctx *c, int64_t step, const double host_box[3], int
 {
     if (!c) return RBSOG_EINVAL;
     c->err.clear();
+    RB_TRY(own_work(c));
     if (step < 0 || (step >> 32)) return fail(c, RBSOG_EINVAL, "step must be in [0, 2^32)");
     RB_TRY(rbsog::check_box(host_box, c->sys.prm.rc, c->err));
     rbsog::system_set_box(c->sys, host_box);
@@ -161,7 +181,7 @@ int rbsog_sample_modes(rbsog_ctx *c, int64_t step, const double host_box[3], int
         if (host_m_nr)
             HIP_TRY(c, hipMemcpy(host_m_nr, c->sys.desc.mraw + 3 * P, 3 * P * sizeof(int32_t),
                                  hipMemcpyDeviceToHost));
-        if (c->batch.h_res[0].status != 0) return fail(c, RBSOG_EDEVICE, "sampler found no nonzero initial state");
+        if (c->batch.h_res[0].status != 0) return fail(c, RBSOG_EDEVICE, "sampler: no start draw accepted");
     }
     if (host_S) {
         host_S[0] = c->sys.Sr;
@@ -176,12 +196,16 @@ int rbsog_force_virial(rbsog_ctx *c, const double *x, const double *y, const dou
 {
     if (!c) return RBSOG_EINVAL;
     c->err.clear();
+    RB_TRY(own_work(c));
     if (!x || !y || !z || !fx || !fy || !fz) return fail(c, RBSOG_EINVAL, "null position or force array");
     if (c->state < 1) return fail(c, RBSOG_ESTATE, "rbsog_sample_modes must precede rbsog_force_virial");
     const int64_t n = c->sys.n;
     hipStream_t st = c->batch.stream;
-    const bool dev_in = is_device_ptr(x) && is_device_ptr(y) && is_device_ptr(z);
-    const bool dev_out = is_device_ptr(fx) && is_device_ptr(fy) && is_device_ptr(fz);
+    const int din = is_device_ptr(x) + is_device_ptr(y) + is_device_ptr(z);
+    const int dout = is_device_ptr(fx) + is_device_ptr(fy) + is_device_ptr(fz);
+    if (din % 3 || dout % 3)
+        return fail(c, RBSOG_EINVAL, "x, y, z (and fx, fy, fz) must be all host or all device arrays");
+    const bool dev_in = din == 3, dev_out = dout == 3;
     const double *px = x, *py = y, *pz = z;
     double *gx = fx, *gy = fy, *gz = fz;
     if ((!dev_in || !dev_out) && !c->d_stage) HIP_TRY(c, hipMalloc(&c->d_stage, 6 * n * sizeof(double)));
@@ -222,7 +246,8 @@ int rbsog_force_virial(rbsog_ctx *c, const double *x, const double *y, const dou
     if (host_energy || host_vir || !dev_out) {
         RB_TRY(rbsog::batch_fetch_results(c->batch, c->err));
         const rbsog::StepResults &r = c->batch.h_res[0];
-        if (r.status != 0) return fail(c, RBSOG_EDEVICE, "sampler found no nonzero initial state");
+        if (r.status != 0) return fail(c, RBSOG_EDEVICE, "sampler: no start draw accepted");
+        if (r.bad_input) return fail(c, RBSOG_EINVAL, "positions have NaN/Inf");
         if (host_energy) {
             host_energy[0] = r.UN;
             host_energy[1] = r.UF;
@@ -240,9 +265,10 @@ int rbsog_pressure(rbsog_ctx *c, double host_P[9], double host_parts[27])
     c->err.clear();
     if (!host_P) return fail(c, RBSOG_EINVAL, "null pressure output");
     if (c->state < 2) return fail(c, RBSOG_ESTATE, "rbsog_force_virial must precede rbsog_pressure");
-    RB_TRY(rbsog::batch_fetch_results(c->batch, c->err));
+    RB_TRY(fetch(c));
     const rbsog::StepResults &r = c->batch.h_res[0];
-    if (r.status != 0) return fail(c, RBSOG_EDEVICE, "sampler found no nonzero initial state");
+    if (r.status != 0) return fail(c, RBSOG_EDEVICE, "sampler: no start draw accepted");
+    if (r.bad_input) return fail(c, RBSOG_EINVAL, "positions have NaN/Inf");
     for (int k = 0; k < 9; ++k) host_P[k] = r.Ptot[k];
     if (host_parts)
         for (int k = 0; k < 9; ++k) {
@@ -257,6 +283,7 @@ int rbsog_rescale(rbsog_ctx *c, const double host_mu[3], double *x, double *y, d
 {
     if (!c) return RBSOG_EINVAL;
     c->err.clear();
+    RB_TRY(own_work(c));
     if (!host_mu || !host_box || !x || !y || !z) return fail(c, RBSOG_EINVAL, "null argument");
     if (!finite3(host_mu) || host_mu[0] <= 0 || host_mu[1] <= 0 || host_mu[2] <= 0)
         return fail(c, RBSOG_EINVAL, "scale factors must be positive and finite");
@@ -276,13 +303,41 @@ int rbsog_rescale(rbsog_ctx *c, const double host_mu[3], double *x, double *y, d
 int rbsog_destroy(rbsog_ctx *c)
 {
     if (!c) return RBSOG_OK;
+    if (c->in_batch) (void)rbsog_batch_release(c->in_batch, c);
     destroy(c);
+    return RBSOG_OK;
+}
+
+int rbsog_stage(rbsog_ctx *c, int64_t step, const double host_box[3], const double *x, const double *y,
+                const double *z, double *fx, double *fy, double *fz)
+{
+    if (!c) return RBSOG_EINVAL;
+    c->err.clear();
+    if (!c->in_batch) return fail(c, RBSOG_ESTATE, "rbsog_stage needs a context admitted to a batch");
+    if (step < 0 || (step >> 32)) return fail(c, RBSOG_EINVAL, "step must be in [0, 2^32)");
+    if (!x || !y || !z || !fx || !fy || !fz) return fail(c, RBSOG_EINVAL, "null position or force array");
+    if (!(is_device_ptr(x) && is_device_ptr(y) && is_device_ptr(z) && is_device_ptr(fx) && is_device_ptr(fy) &&
+          is_device_ptr(fz)))
+        return fail(c, RBSOG_EINVAL, "staged position and force arrays must be device memory");
+    RB_TRY(rbsog::check_box(host_box, c->sys.prm.rc, c->err));
+    rbsog::system_set_box(c->sys, host_box);
+    RB_TRY(refresh_cells(c));
+    rbsog::SysStep &t = c->sys.stp;
+    t.step = static_cast<uint32_t>(step);
+    t.x = x;
+    t.y = y;
+    t.z = z;
+    t.fx = fx;
+    t.fy = fy;
+    t.fz = fz;
+    c->staged = true;
     return RBSOG_OK;
 }
 
 int rbsog_debug_cells(rbsog_ctx *c, int32_t *host_cell, int32_t host_ncell[3])
 {
     if (!c) return RBSOG_EINVAL;
+    if (c->in_batch) return fail(c, RBSOG_ESTATE, "the context is admitted to a batch");
     if (c->state < 2) return fail(c, RBSOG_ESTATE, "no evaluation yet");
     HIP_TRY(c, hipStreamSynchronize(c->batch.stream));
     if (host_cell) {
@@ -300,13 +355,27 @@ int rbsog_debug_cells(rbsog_ctx *c, int32_t *host_cell, int32_t host_ncell[3])
     return RBSOG_OK;
 }
 
+int rbsog_debug_long_range_force(rbsog_ctx *c, double *fx, double *fy, double *fz)
+{
+    if (!c) return RBSOG_EINVAL;
+    c->err.clear();
+    if (c->in_batch) return fail(c, RBSOG_ESTATE, "the context is admitted to a batch");
+    if (c->state < 2) return fail(c, RBSOG_ESTATE, "no evaluation yet");
+    if (!(is_device_ptr(fx) && is_device_ptr(fy) && is_device_ptr(fz)))
+        return fail(c, RBSOG_EINVAL, "rbsog_debug_long_range_force needs device arrays");
+    HIP_TRY(c, rbsog::launch_long_range_force(c->batch, fx, fy, fz));
+    HIP_TRY(c, hipStreamSynchronize(c->batch.stream));
+    return RBSOG_OK;
+}
+
 int rbsog_debug_modes(rbsog_ctx *c, int32_t cap, int32_t *host_nd, int32_t *host_modes, int32_t *host_counts,
                       double *host_rho)
 {
     if (!c) return RBSOG_EINVAL;
+    if (c->in_batch) return fail(c, RBSOG_ESTATE, "the context is admitted to a batch");
     if (c->state < 1) return fail(c, RBSOG_ESTATE, "no sampled modes yet");
     if (cap < 0) return fail(c, RBSOG_EINVAL, "negative capacity");
-    RB_TRY(rbsog::batch_fetch_results(c->batch, c->err));
+    RB_TRY(fetch(c));
     const int nd = c->batch.h_res[0].nd;
     const int mcap = c->sys.desc.mcap;
     if (host_nd) *host_nd = nd;
@@ -339,7 +408,7 @@ int rbsog_step_info(rbsog_ctx *c, int64_t host_info[4])
 {
     if (!c || !host_info) return RBSOG_EINVAL;
     if (c->state < 1) return fail(c, RBSOG_ESTATE, "no sampled modes yet");
-    RB_TRY(rbsog::batch_fetch_results(c->batch, c->err));
+    RB_TRY(fetch(c));
     const rbsog::StepResults &r = c->batch.h_res[0];
     host_info[0] = r.nd;
     host_info[1] = r.acc_r;

@@ -23,6 +23,11 @@ struct rbsog_batch {
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     std::string err;
+    // a batch of contexts (rbsog_batch_create): admitted by device memory
+    bool of_contexts = false;
+    int64_t budget = 0, used = 0;
+    std::vector<rbsog_ctx *> ctxs;
+    std::vector<int64_t> ctx_bytes;  // bytes each admitted context was charged
 };
 
 namespace {
@@ -61,9 +66,13 @@ bool is_device_ptr(const void *p)
 
 void destroy(rbsog_batch *b)
 {
-    bool any = false;
+    bool any = !b->ctxs.empty();
     for (auto &s : b->systems) any = any || s->atom_mem;
     if (any) (void)hipStreamSynchronize(b->batch.stream);
+    for (rbsog_ctx *c : b->ctxs) {
+        c->in_batch = nullptr;
+        c->staged = false;
+    }
     for (auto &s : b->systems) rbsog::system_free(*s);
     rbsog::batch_free(b->batch);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -123,10 +132,63 @@ int run_graph(rbsog_batch *b)
     return RBSOG_OK;
 }
 
+// One step of every admitted context from its staged inputs; the results go
+// to each context (read back with rbsog_pressure, rbsog_step_info).
+int step_contexts(rbsog_batch *b, double *host_P, double *host_energy, int64_t *host_info)
+{
+    Batch &bt = b->batch;
+    if (b->ctxs.empty()) return fail(b, RBSOG_ESTATE, "no context admitted");
+    for (rbsog_ctx *c : b->ctxs)
+        if (!c->staged) return fail(b, RBSOG_ESTATE, "an admitted context has no staged step (rbsog_stage)");
+    for (rbsog_ctx *c : b->ctxs) {
+        if (c->desc_moved) bt.desc_dirty = true;
+        c->desc_moved = false;
+    }
+    bt.want_energy = host_energy != nullptr;
+    RB_TRY(rbsog::batch_upload(bt, b->err));
+    if (b->use_graph && !bt.timing) {
+        RB_TRY(run_graph(b));
+    } else {
+        HIP_TRY(b, launch_step(bt));
+    }
+    RB_TRY(rbsog::batch_fetch_results(bt, b->err));
+    const size_t S = b->ctxs.size();
+    int rc = RBSOG_OK;
+    for (size_t s = 0; s < S; ++s) {
+        rbsog_ctx *c = b->ctxs[s];
+        const rbsog::StepResults &r = bt.h_res[s];
+        c->batch.h_res[0] = r;
+        c->res_from_batch = true;
+        c->staged = false;
+        c->state = 2;
+        if (r.status != 0 && rc == RBSOG_OK) rc = fail(b, RBSOG_EDEVICE, "sampler: no start draw accepted");
+        if (r.bad_input && rc == RBSOG_OK) rc = fail(b, RBSOG_EINVAL, "positions have NaN/Inf");
+        if (host_P)
+            for (int k = 0; k < 9; ++k) host_P[9 * s + k] = r.Ptot[k];
+        if (host_energy) {
+            host_energy[3 * s] = r.UN;
+            host_energy[3 * s + 1] = r.UF;
+            host_energy[3 * s + 2] = r.Uself;
+        }
+        if (host_info) {
+            host_info[4 * s] = r.nd;
+            host_info[4 * s + 1] = r.acc_r;
+            host_info[4 * s + 2] = r.acc_nr;
+            host_info[4 * s + 3] = static_cast<int64_t>(std::llround(r.npairs));
+        }
+    }
+    return rc;
+}
+
 int step_impl(rbsog_batch *b, const int64_t *host_steps, const double *host_boxes, const double *x, const double *y,
               const double *z, double *fx, double *fy, double *fz, double *host_P, double *host_energy,
               int64_t *host_info)
 {
+    if (b->of_contexts) {
+        if (host_steps || host_boxes || x || y || z || fx || fy || fz)
+            return fail(b, RBSOG_EINVAL, "a batch of contexts takes its inputs from rbsog_stage (pass NULL)");
+        return step_contexts(b, host_P, host_energy, host_info);
+    }
     if (!host_steps || !host_boxes || !x || !y || !z || !fx || !fy || !fz)
         return fail(b, RBSOG_EINVAL, "null argument");
     if (!(is_device_ptr(x) && is_device_ptr(y) && is_device_ptr(z) && is_device_ptr(fx) && is_device_ptr(fy) &&
@@ -164,7 +226,8 @@ int step_impl(rbsog_batch *b, const int64_t *host_steps, const double *host_boxe
         RB_TRY(rbsog::batch_fetch_results(bt, b->err));
         for (size_t s = 0; s < S; ++s) {
             const rbsog::StepResults &r = bt.h_res[s];
-            if (r.status != 0) return fail(b, RBSOG_EDEVICE, "sampler found no nonzero initial state");
+            if (r.status != 0) return fail(b, RBSOG_EDEVICE, "sampler: no start draw accepted");
+            if (r.bad_input) return fail(b, RBSOG_EINVAL, "positions have NaN/Inf");
             if (host_P)
                 for (int k = 0; k < 9; ++k) host_P[9 * s + k] = r.Ptot[k];
             if (host_energy) {
@@ -224,6 +287,78 @@ int rbsog_batch_setup(const rbsog_params *params, int32_t nsys, const int64_t *n
     return RBSOG_OK;
 }
 
+int rbsog_batch_create(int64_t mem_budget_bytes, void *hip_stream, rbsog_batch **out)
+{
+    if (!out) return RBSOG_EINVAL;
+    *out = nullptr;
+    if (mem_budget_bytes <= 0) return RBSOG_EINVAL;
+    rbsog_batch *b = new (std::nothrow) rbsog_batch;
+    if (!b) return RBSOG_ENOMEM;
+    b->of_contexts = true;
+    b->budget = mem_budget_bytes;
+    const int rc = rbsog::batch_init(b->batch, static_cast<hipStream_t>(hip_stream), RBSOG_PREC_FP32C, b->err);
+    if (rc != RBSOG_OK) {
+        destroy(b);
+        return rc;
+    }
+    *out = b;
+    return RBSOG_OK;
+}
+
+int rbsog_batch_admit(rbsog_batch *b, rbsog_ctx *ctx)
+{
+    if (!b || !ctx) return RBSOG_EINVAL;
+    b->err.clear();
+    if (!b->of_contexts) return fail(b, RBSOG_EINVAL, "this batch was set up with its own systems");
+    if (ctx->in_batch) return fail(b, RBSOG_ESTATE, "the context is already admitted to a batch");
+    if (!b->ctxs.empty() && ctx->sys.prm.precision != b->batch.precision)
+        return fail(b, RBSOG_EINVAL, "every context of a batch uses one precision");
+    const int64_t bytes = static_cast<int64_t>(rbsog::system_device_bytes(ctx->sys));
+    if (b->ctxs.size() >= 65536 || bytes > b->budget - b->used)
+        return fail(b, RBSOG_EAGAIN, "memory budget or slots of the batch are full");
+    // the context's own queued work finishes before the batch's stream uses its buffers
+    HIP_TRY(b, hipStreamSynchronize(ctx->batch.stream));
+    if (b->ctxs.empty()) b->batch.precision = ctx->sys.prm.precision;
+    b->ctxs.push_back(ctx);
+    b->ctx_bytes.push_back(bytes);
+    std::vector<System *> sys;
+    for (rbsog_ctx *c : b->ctxs) sys.push_back(&c->sys);
+    const int rc = rbsog::batch_set_systems(b->batch, sys, b->err);
+    if (rc != RBSOG_OK) {
+        b->ctxs.pop_back();
+        b->ctx_bytes.pop_back();
+        return rc;
+    }
+    b->used += bytes;
+    ctx->in_batch = b;
+    ctx->staged = false;
+    ctx->desc_moved = false;
+    ctx->res_from_batch = false;
+    return RBSOG_OK;
+}
+
+int rbsog_batch_release(rbsog_batch *b, rbsog_ctx *ctx)
+{
+    if (!b || !ctx) return RBSOG_EINVAL;
+    b->err.clear();
+    if (ctx->in_batch != b) return fail(b, RBSOG_EINVAL, "the context is not admitted to this batch");
+    HIP_TRY(b, hipStreamSynchronize(b->batch.stream));
+    for (size_t s = 0; s < b->ctxs.size(); ++s)
+        if (b->ctxs[s] == ctx) {
+            b->used -= b->ctx_bytes[s];
+            b->ctxs.erase(b->ctxs.begin() + static_cast<std::ptrdiff_t>(s));
+            b->ctx_bytes.erase(b->ctx_bytes.begin() + static_cast<std::ptrdiff_t>(s));
+            break;
+        }
+    ctx->in_batch = nullptr;
+    ctx->staged = false;
+    // the context's own batch re-uploads its descriptor (the batch wrote other result slots)
+    ctx->batch.desc_dirty = true;
+    std::vector<System *> sys;
+    for (rbsog_ctx *c : b->ctxs) sys.push_back(&c->sys);
+    return rbsog::batch_set_systems(b->batch, sys, b->err);
+}
+
 int rbsog_batch_step(rbsog_batch *b, const int64_t *host_steps, const double *host_boxes, const double *x,
                      const double *y, const double *z, double *fx, double *fy, double *fz, double *host_P,
                      double *host_energy, int64_t *host_info)
@@ -237,6 +372,7 @@ int rbsog_batch_rescale(rbsog_batch *b, const double *host_mu, double *x, double
 {
     if (!b) return RBSOG_EINVAL;
     b->err.clear();
+    if (b->of_contexts) return fail(b, RBSOG_ESTATE, "a batch of contexts is rescaled per context");
     if (!host_mu || !host_boxes || !x || !y || !z) return fail(b, RBSOG_EINVAL, "null argument");
     if (!(is_device_ptr(x) && is_device_ptr(y) && is_device_ptr(z)))
         return fail(b, RBSOG_EINVAL, "rbsog_batch_rescale needs device position arrays");

@@ -543,6 +543,10 @@ __global__ __launch_bounds__(kCellBlock) void k_zero(const SysDesc *__restrict__
         D.count[c] = 0;
         D.cursor[c] = 0;
     }
+    if (e.y == 0 && threadIdx.x == 0) {
+        D.res->bad_input = 0;
+        if (stp[e.x].half) *D.hflag = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x < kNumPairGroups) ctrl[threadIdx.x] = 0;
 }
 
@@ -562,6 +566,10 @@ __global__ __launch_bounds__(kAtomBlock) void k_fix(const SysDesc *__restrict__ 
     if (!__any(active)) return;
     const int64_t ii = active ? i : 0;
     const double p[3] = {gp(St.x)[ii], gp(St.y)[ii], gp(St.z)[ii]};
+    // a NaN or infinite coordinate still gives a cell inside the grid (u < 2^32);
+    // the step is flagged and the host reports RBSOG_EINVAL
+    const bool bad = active && !(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]));
+    if (__any(bad) && threadIdx.x % 64 == 0) atomicOr(&D.res->bad_input, 1);
     const int nc[3] = {St.nc[0], St.nc[1], St.nc[2]};
     RB_GLOBAL typename T::fix *u = gp(static_cast<typename T::fix *>(D.u));
     uint32_t c[3];
@@ -905,7 +913,7 @@ __device__ inline void load_weights(Weights<T, M> &W, const SogTables *__restric
 
     } else if constexpr (M == 0) {
         W.tab = tab;
-        W.m = tab->M;
+        W.m = tab->Me;  // the force weights are zero past M
     } else {
 #pragma unroll
         for (int l = 0; l < M; ++l) {
@@ -1475,6 +1483,488 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         for (int k = 0; k < 8; ++k) gp(part)[k] = out[k];
 }
 
+// ----------------------------------------------------------------------------
+// Half-shell pair kernel (FP32 fast path): every unordered pair evaluated once
+// ----------------------------------------------------------------------------
+//
+// Newton's third law halves the SOG evaluations and the filter tests.  A block
+// takes its own column from its first atom up to the top of its padded
+// z-window (a candidate in the block itself only when it follows the lane's
+// atom in the sorted order) and the four neighbour columns (+1,-1), (+1,0),
+// (+1,+1), (0,+1), each cut to the window; with at least four cells per edge
+// every unordered pair inside rc is then visited by exactly one block.  The
+// lane's own force accumulates in registers as in the full shell.  The
+// reaction on the candidate accumulates per chunk in FP64 in the wavefront's
+// own LDS (ds_add_f64; the lanes of one instruction that add to one slot are
+// applied in a fixed order and no other wavefront touches the region, so the
+// sums are the same bits on every run), and goes out as FP32 to the block's
+// slot of a partial buffer, indexed by the candidate's position in the
+// block's neighbourhood.  k_pair_gather then adds, for every atom, the
+// partials of every block that listed it to its own block's sum, in a fixed
+// order.  Blocks whose neighbourhood exceeds the buffer's hcap candidates mark
+// their system in k_pair_prep; such a system runs the full shell that step.
+//
+// Candidates are dealt to chunks in groups of kHalfGroup consecutive records
+// (group g to chunk g mod nch): every chunk still samples the whole
+// neighbourhood, and the partials are written and read in 64-byte runs.
+
+constexpr int kHalfRanges = 10;  // own column (above the block, wrapped part), 4 columns x 2 pieces
+constexpr int kHalfGroup = 16;
+static_assert(kHalfGroup == 16 && kChunk % 32 == 0, "a hit word holds two candidate groups");
+static_assert(kHrngStride >= 2 * kHalfRanges + 2, "neighbourhood table entry");
+
+// forward neighbour column r = 0..3: (dx, dy) = (1,-1), (1,0), (1,1), (0,1)
+__device__ __forceinline__ int fwd_dx(int r) { return r < 3 ? 1 : 0; }
+__device__ __forceinline__ int fwd_dy(int r) { return r < 3 ? r - 1 : 1; }
+
+// Padded cutoff of the FP32 fast filter and the z reach of a block's window
+// in fixed-point units (the same in every kernel that cuts windows).
+__device__ __forceinline__ float fast_rcf(const SysDesc &D)
+{
+    return static_cast<float>(sqrt(static_cast<double>(D.tab.rc2_32))) + 1e-3f;
+}
+__device__ __forceinline__ uint32_t window_reach(const SysDesc &D, const SysStep &St)
+{
+    return static_cast<uint32_t>(ceil(static_cast<double>(fast_rcf(D)) / St.L[2] * 4294967296.0)) + 2u;
+}
+
+// first index of [l, h) whose z (fixed point) is >= v (above) or > v (!above)
+__device__ __forceinline__ int z_search(const RB_GLOBAL uint32_t *zw, int l, int h, uint32_t v, bool above)
+{
+    while (l < h) {
+        const int m = (l + h) >> 1;
+        const uint32_t zm = zw[4 * m + 2];
+        if (above ? zm < v : zm <= v) l = m + 1;
+        else h = m;
+    }
+    return l;
+}
+
+// The half-shell neighbourhood of every pair block: range starts beg[10],
+// flattened prefixes pre[11] (pre[10] = total), chunk count.
+__global__ __launch_bounds__(64) void k_pair_prep(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                  const int2 *__restrict__ plan)
+{
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const SysStep &St = stp[e.x];
+    const int b = e.y;
+    const int lane = threadIdx.x;
+    const RB_GLOBAL int32_t *start = gp(D.start);
+    if (b >= gp(D.bstart)[St.ncells]) return;
+    const int nx = St.nc[0], ny = St.nc[1], nz = St.nc[2];
+    const int2 cb = gload(D.blocks + b);
+    const int c = cb.x;
+    const int cz = c % nz, cy = (c / nz) % ny, cx = c / (nz * ny);
+    const int gs = min(St.g, nz - cz);
+    const int cs = start[c], ce = start[c + gs];
+    const int i0 = cs + cb.y * kPairWave;
+    const int nvalid = min(kPairWave, ce - i0);
+    const RB_GLOBAL uint32_t *zw = reinterpret_cast<const RB_GLOBAL uint32_t *>(gp(D.rec));
+    const uint32_t oz = zw[4 * i0 + 2];
+    const uint32_t zext = zw[4 * (i0 + nvalid - 1) + 2] - oz;  // a segment is sorted by z
+    const uint32_t reach = window_reach(D, St);
+    const uint32_t za = oz - reach, zb = oz + zext + reach;
+    int b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+    if (lane == 0) {
+        // own column: from the block's first atom to the window's top, and the
+        // part past the periodic seam
+        const int col = nz * (cy + ny * cx);
+        const int lo = start[col], hi = start[col + nz];
+        b0 = i0;
+        if (static_cast<uint64_t>(oz) + zext + reach < (1ull << 32)) {
+            e0 = z_search(zw, i0, hi, zb, false);
+        } else {
+            e0 = hi;
+            b1 = lo;
+            e1 = z_search(zw, lo, i0, zb, false);
+        }
+    } else if (lane <= 4) {
+        const int r = lane - 1;
+        const int jx = (cx + fwd_dx(r) + nx) % nx, jy = (cy + fwd_dy(r) + ny) % ny;
+        const int col = nz * (jy + ny * jx);
+        const int lo = start[col], hi = start[col + nz];
+        b0 = z_search(zw, lo, hi, za, true);
+        if (za <= zb) {
+            e0 = z_search(zw, b0, hi, zb, false);
+        } else {
+            e0 = hi;
+            b1 = lo;
+            e1 = z_search(zw, lo, b0, zb, false);
+        }
+    }
+    int beg[kHalfRanges], len[kHalfRanges];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        beg[2 * r] = __shfl(b0, r, 64);
+        len[2 * r] = __shfl(e0 - b0, r, 64);
+        beg[2 * r + 1] = __shfl(b1, r, 64);
+        len[2 * r + 1] = __shfl(e1 - b1, r, 64);
+    }
+    if (lane == 0) {
+        RB_GLOBAL int32_t *h = gp(D.hrng) + static_cast<int64_t>(b) * kHrngStride;
+        int pre = 0;
+        for (int r = 0; r < kHalfRanges; ++r) {
+            h[r] = beg[r];
+            h[kHalfRanges + r] = pre;
+            pre += len[r];
+        }
+        h[2 * kHalfRanges] = pre;
+        const int ngroups = (pre + kHalfGroup - 1) / kHalfGroup;
+        constexpr int gpc = kChunk / kHalfGroup;
+        h[2 * kHalfRanges + 1] = (ngroups + gpc - 1) / gpc;
+        if (pre > D.hcap) atomicOr(D.hflag, 1);
+    }
+}
+
+template <class T, bool E>
+struct PairSharedHalf {
+    float4 rt[kChunk];                        // (x, y, z) relative to the block origin, q
+    float r2[kChunk];                         // |r_j|^2 for the filter
+    typename T::Rec tile[E ? kChunk : 1];     // fixed-point records (the energy sum's displacements)
+    double jac[3][kChunk];                    // reactions on the chunk's candidates
+    uint32_t mask[kChunk / 32][64];           // hit bits of each lane
+    int beg[kHalfRanges];
+    int pre[kHalfRanges + 1];
+};
+
+// One pair's SOG terms with the charge product qij = q_i q_j applied: adds the
+// force on i, the virial and the energy to acc and returns the force on i in
+// (fx, fy, fz) (the reaction on j is its negative).
+template <class T, int M, bool E>
+__device__ __forceinline__ void pair_eval_r(float dx, float dy, float dz, float qij, bool active, float rc2,
+                                            const Weights<T, M> &W, PairAcc<T> &acc, float &fx, float &fy,
+                                            float &fz)
+{
+    const float r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const bool inside = active & (r2 < rc2) & (r2 > 0.0f);
+    float swt = 0.0f, sw = 0.0f;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    if constexpr (M == -1) {
+        const float t = r2 * W.pa - 1.0f;
+        swt = horner(W.pg, t);
+        if constexpr (E) sw = horner(W.pf, t);
+    } else if constexpr (M == 0) {
+        for (int l = 0; l < W.m; ++l) {
+            float wl;
+            swt += gauss<T, M, E>(W, l, r2, wl);
+            if constexpr (E) sw += wl;
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            float wl;
+            swt += gauss<T, M, E>(W, l, r2, wl);
+            if constexpr (E) sw += wl;
+        }
+    }
+    acc.n += inside;
+    const float f = inside ? qij * (rinv * rinv * rinv - swt) : 0.0f;
+    fx = f * dx;
+    fy = f * dy;
+    fz = f * dz;
+    acc.fx += fx;
+    acc.fy += fy;
+    acc.fz += fz;
+    acc.vxx += fx * dx;
+    acc.vyy += fy * dy;
+    acc.vzz += fz * dz;
+    acc.vxy += fx * dy;
+    acc.vxz += fx * dz;
+    acc.vyz += fy * dz;
+    if constexpr (E) acc.u += inside ? qij * (rinv - sw) : 0.0f;
+}
+
+// One half-shell pair block b of system D (one wavefront), FP32 fast path.
+template <class T, int M, bool E>
+__device__ __forceinline__ void pair_block_half(PairSharedHalf<T, E> &sh, const SysDesc &D, const SysStep &St, int b)
+{
+    using Rec = typename T::Rec;
+    const int lane = threadIdx.x;
+    const int ncells = St.ncells;
+    const int nb_total = gp(D.bstart)[ncells];
+    double *part = D.pair_part + 8 * static_cast<int64_t>(b);
+    if (b >= nb_total) return;
+    const Rec *__restrict__ rec = static_cast<const Rec *>(D.rec);
+    Weights<T, M> W;
+    load_weights<T, M>(W, &D.tab);
+    const int nz = St.nc[2];
+    const float sx = static_cast<float>(St.L[0] * 0x1.0p-32);
+    const float sy = static_cast<float>(St.L[1] * 0x1.0p-32);
+    const float sz = static_cast<float>(St.L[2] * 0x1.0p-32);
+    const float rc2 = D.tab.rc2_32;
+    const RB_GLOBAL int32_t *start = gp(D.start);
+    const int2 cb = gload(D.blocks + b);
+    const int c = cb.x;
+    const int cz = c % nz;
+    const int gs = min(St.g, nz - cz);
+    const int cs = start[c], ce = start[c + gs];
+    const int i = cs + cb.y * kPairWave + lane;
+    const bool valid = i < ce;
+    Rec ri{};
+    if (valid) ri = gload(rec + i);
+    const uint32_t ox = static_cast<uint32_t>(__shfl(static_cast<int>(ri.x), 0, 64));
+    const uint32_t oy = static_cast<uint32_t>(__shfl(static_cast<int>(ri.y), 0, 64));
+    const uint32_t oz = static_cast<uint32_t>(__shfl(static_cast<int>(ri.z), 0, 64));
+    const float rcf = fast_rcf(D);
+    const float xi = static_cast<float>(static_cast<int32_t>(ri.x - ox)) * sx;
+    const float yi = static_cast<float>(static_cast<int32_t>(ri.y - oy)) * sy;
+    const float zi = static_cast<float>(static_cast<int32_t>(ri.z - oz)) * sz;
+    const float ax = -2.0f * xi, ay = -2.0f * yi, az = -2.0f * zi;
+    const float thr = valid ? rcf * rcf - (xi * xi + yi * yi + zi * zi) : -INFINITY;
+    const float qi = valid ? ri.q : 0.0f;
+
+    // the neighbourhood from k_pair_prep
+    const RB_GLOBAL int32_t *h = gp(D.hrng) + static_cast<int64_t>(b) * kHrngStride;
+    if (lane < kHalfRanges) sh.beg[lane] = h[lane];
+    if (lane <= kHalfRanges) sh.pre[lane] = h[kHalfRanges + lane];
+    for (int k = lane; k < kChunk; k += 64) {
+        sh.jac[0][k] = 0.0;
+        sh.jac[1][k] = 0.0;
+        sh.jac[2][k] = 0.0;
+    }
+    __syncthreads();
+    const int total = sh.pre[kHalfRanges];
+    const int len0 = sh.pre[1];
+    constexpr int gpc = kChunk / kHalfGroup;
+    const int ngroups = (total + kHalfGroup - 1) / kHalfGroup;
+    const int nch = (ngroups + gpc - 1) / gpc;
+    const int hcap = D.hcap;
+    RB_GLOBAL float *hp = gp(D.hpart) + static_cast<int64_t>(b) * 3 * hcap;
+
+    double fx = 0, fy = 0, fz = 0, v[6] = {0, 0, 0, 0, 0, 0}, uu = 0;
+    int hits = 0;
+    // chunk ch holds the groups ch, ch + nch, ...: slot k is flattened index
+    // kHalfGroup (ch + nch (k / kHalfGroup)) + k % kHalfGroup, a prefix of them valid
+    auto flat = [&](int ch, int k) { return kHalfGroup * (ch + nch * (k / kHalfGroup)) + k % kHalfGroup; };
+    auto chunk_filled = [&](int ch) {
+        const int ng = ch < ngroups ? (ngroups - ch + nch - 1) / nch : 0;
+        const int glast = ch + nch * (ng - 1);
+        return ng > 0 ? kHalfGroup * (ng - 1) + min(kHalfGroup, total - kHalfGroup * glast) : 0;
+    };
+    for (int ch = 0; ch < nch; ++ch) {
+        const int filled = chunk_filled(ch);
+        for (int k = lane; k < filled; k += 64) {
+            const int f = flat(ch, k);
+            int r = 0;
+#pragma unroll
+            for (int step = 8; step >= 1; step >>= 1)
+                if (r + step < kHalfRanges && sh.pre[r + step] <= f) r += step;
+            const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
+            const float xj = static_cast<float>(static_cast<int32_t>(rj.x - ox)) * sx;
+            const float yj = static_cast<float>(static_cast<int32_t>(rj.y - oy)) * sy;
+            const float zj = static_cast<float>(static_cast<int32_t>(rj.z - oz)) * sz;
+            sh.rt[k] = make_float4(xj, yj, zj, rj.q);
+            sh.r2[k] = xj * xj + yj * yj + zj * zj;
+            if constexpr (E) sh.tile[k] = rj;
+        }
+        const int words = (filled + 31) >> 5;
+        for (int k = filled + lane; k < 32 * words; k += 64) {
+            sh.rt[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sh.r2[k] = INFINITY;
+            if constexpr (E) sh.tile[k] = Rec{};
+        }
+        __syncthreads();
+
+        for (int w = 0; w < words; ++w) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                float t[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 cj = sh.rt[32 * w + 4 * g + k];
+                    t[k] = fmaf(cj.x, ax, fmaf(cj.y, ay, fmaf(cj.z, az, sh.r2[32 * w + 4 * g + k])));
+                }
+                m = push_hits4(m, t[0], t[1], t[2], t[3], thr);
+            }
+            // own-column candidates at or below the lane's atom are not its
+            // forward partners: the first min(lane + 1, len0) - lo slots of a
+            // group starting at flattened index lo < 64
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int lo = kHalfGroup * (ch + nch * (2 * w + hh));
+                if (lo < min(len0, kPairWave)) {
+                    const int cnt = min(max(min(lane + 1, len0) - lo, 0), kHalfGroup);
+                    const uint32_t ex = cnt > 0 ? (0xFFFFu << (16 - cnt)) & 0xFFFFu : 0u;
+                    m &= ~(ex << (16 * (1 - hh)));
+                }
+            }
+            sh.mask[w][lane] = m;
+        }
+
+        // walk the hit bits, two per round; lanes start at different words
+        // so that fewer of them add to one candidate at once
+        PairAcc<T> acc;
+        {
+            int w = words > 0 ? lane % words : 0;
+            int seen = 1;
+            uint32_t cur = words > 0 ? sh.mask[w][lane] : 0u;
+            for (;;) {
+                bool adv = (cur == 0u) & (seen < words);
+                while (__any(adv)) {
+                    if (adv) {
+                        w = w + 1 == words ? 0 : w + 1;
+                        ++seen;
+                        cur = sh.mask[w][lane];
+                    }
+                    adv = (cur == 0u) & (seen < words);
+                }
+                if (!__any(cur != 0u)) break;
+                const bool a0 = cur != 0u;
+                const int k0 = 32 * w + __builtin_clz(cur | 1u);
+                cur &= ~(0x80000000u >> (k0 - 32 * w));
+                const bool a1 = cur != 0u;
+                const int k1 = 32 * w + __builtin_clz(cur | 1u);
+                cur &= ~(0x80000000u >> (k1 - 32 * w));
+                float f0x, f0y, f0z, f1x, f1y, f1z;
+                if constexpr (E) {
+                    float dx, dy, dz;
+                    const Rec r0 = sh.tile[k0], r1 = sh.tile[k1];
+                    displacement<T>(ri, r0, sx, sy, sz, dx, dy, dz);
+                    pair_eval_r<T, M, E>(dx, dy, dz, qi * r0.q, a0, rc2, W, acc, f0x, f0y, f0z);
+                    displacement<T>(ri, r1, sx, sy, sz, dx, dy, dz);
+                    pair_eval_r<T, M, E>(dx, dy, dz, qi * r1.q, a1, rc2, W, acc, f1x, f1y, f1z);
+                } else {
+                    const float4 t0 = sh.rt[k0], t1 = sh.rt[k1];
+                    pair_eval_r<T, M, E>(xi - t0.x, yi - t0.y, zi - t0.z, qi * t0.w, a0, rc2, W, acc, f0x, f0y, f0z);
+                    pair_eval_r<T, M, E>(xi - t1.x, yi - t1.y, zi - t1.z, qi * t1.w, a1, rc2, W, acc, f1x, f1y, f1z);
+                }
+                if (a0) {
+                    atomicAdd(&sh.jac[0][k0], -static_cast<double>(f0x));
+                    atomicAdd(&sh.jac[1][k0], -static_cast<double>(f0y));
+                    atomicAdd(&sh.jac[2][k0], -static_cast<double>(f0z));
+                }
+                if (a1) {
+                    atomicAdd(&sh.jac[0][k1], -static_cast<double>(f1x));
+                    atomicAdd(&sh.jac[1][k1], -static_cast<double>(f1y));
+                    atomicAdd(&sh.jac[2][k1], -static_cast<double>(f1z));
+                }
+            }
+        }
+        hits += acc.n;
+        fx += acc.fx;
+        fy += acc.fy;
+        fz += acc.fz;
+        v[0] += acc.vxx;
+        v[1] += acc.vyy;
+        v[2] += acc.vzz;
+        v[3] += acc.vxy;
+        v[4] += acc.vxz;
+        v[5] += acc.vyz;
+        uu += acc.u;
+        __syncthreads();
+        // the chunk's reactions to the block's partial slots, then cleared
+        for (int k = lane; k < 32 * words; k += 64) {
+            if (k < filled) {
+                const int f = flat(ch, k);
+                hp[f] = static_cast<float>(sh.jac[0][k]);
+                hp[hcap + f] = static_cast<float>(sh.jac[1][k]);
+                hp[2 * hcap + f] = static_cast<float>(sh.jac[2][k]);
+            }
+            sh.jac[0][k] = 0.0;
+            sh.jac[1][k] = 0.0;
+            sh.jac[2][k] = 0.0;
+        }
+        __syncthreads();
+    }
+    if (valid) {
+        RB_GLOBAL float *fsr = gp(static_cast<float *>(D.fsr));
+        fsr[i] = static_cast<float>(fx);
+        fsr[D.n + i] = static_cast<float>(fy);
+        fsr[2 * D.n + i] = static_cast<float>(fz);
+    }
+    // each unordered pair was evaluated once
+    double out[8] = {v[0], v[1], v[2], v[3], v[4], v[5], uu, static_cast<double>(hits)};
+    for (int k = 0; k < 8; ++k) out[k] = wave_sum(out[k]);
+    if (lane == 0)
+        for (int k = 0; k < 8; ++k) gp(part)[k] = out[k];
+}
+
+// Per atom of every half-shell block: its own block's sum plus the reactions
+// that the blocks listing it left in their partial slots, in a fixed order
+// (its own column's blocks, then the columns (-1,+1), (-1,0), (-1,-1), (0,-1),
+// each by block index).
+__global__ __launch_bounds__(64) void k_pair_gather(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                    const int2 *__restrict__ plan)
+{
+    const int2 e = plan[blockIdx.x];
+    const SysDesc &D = desc[e.x];
+    const SysStep &St = stp[e.x];
+    if (*gp(D.hflag)) return;  // the system ran the full shell this step
+    const int b = e.y;
+    const int lane = threadIdx.x;
+    const RB_GLOBAL int32_t *start = gp(D.start);
+    const RB_GLOBAL int32_t *bstart = gp(D.bstart);
+    if (b >= bstart[St.ncells]) return;
+    const int nx = St.nc[0], ny = St.nc[1], nz = St.nc[2];
+    const int2 cb = gload(D.blocks + b);
+    const int c = cb.x;
+    const int cz = c % nz, cy = (c / nz) % ny, cx = c / (nz * ny);
+    const int gs = min(St.g, nz - cz);
+    const int cs = start[c], ce = start[c + gs];
+    const int t0 = cs + cb.y * kPairWave, t1 = min(ce, t0 + kPairWave);
+    const int i = t0 + lane;
+    const bool valid = i < t1;
+    RB_GLOBAL float *fsr = gp(static_cast<float *>(D.fsr));
+    double f[3] = {0.0, 0.0, 0.0};
+    if (valid) {
+        f[0] = fsr[i];
+        f[1] = fsr[D.n + i];
+        f[2] = fsr[2 * D.n + i];
+    }
+    const int hcap = D.hcap;
+    const RB_GLOBAL int32_t *hr = gp(D.hrng);
+    const RB_GLOBAL float *hp = gp(D.hpart);
+    for (int src = 0; src < 5; ++src) {
+        int col;
+        if (src == 0) {
+            col = nz * (cy + ny * cx);
+        } else {
+            const int r = src - 1;
+            const int jx = (cx - fwd_dx(r) + nx) % nx, jy = (cy - fwd_dy(r) + ny) % ny;
+            col = nz * (jy + ny * jx);
+        }
+        const int p0 = 2 * src;  // the source blocks' pieces that lie in this block's column
+        const int bs = bstart[col], be = bstart[col + nz];
+        for (int sb0 = bs; sb0 < be; sb0 += 64) {
+            bool hit = false;
+            if (sb0 + lane < be) {
+                const RB_GLOBAL int32_t *h = hr + static_cast<int64_t>(sb0 + lane) * kHrngStride;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int beg = h[p0 + q], n = h[kHalfRanges + p0 + q + 1] - h[kHalfRanges + p0 + q];
+                    hit |= (n > 0) & (beg < t1) & (beg + n > t0);
+                }
+            }
+            uint64_t mset = __ballot(hit);
+            while (mset) {
+                const int k = __ffsll(static_cast<unsigned long long>(mset)) - 1;
+                mset &= mset - 1;
+                const int64_t s = sb0 + k;
+                const RB_GLOBAL int32_t *h = hr + s * kHrngStride;
+                const RB_GLOBAL float *ps = hp + s * 3 * hcap;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int beg = h[p0 + q], pre = h[kHalfRanges + p0 + q];
+                    const int n = h[kHalfRanges + p0 + q + 1] - pre;
+                    if (valid && i >= beg && i < beg + n) {
+                        const int fi = pre + (i - beg);
+                        f[0] += ps[fi];
+                        f[1] += ps[hcap + fi];
+                        f[2] += ps[2 * hcap + fi];
+                    }
+                }
+            }
+        }
+    }
+    if (valid) {
+        fsr[i] = static_cast<float>(f[0]);
+        fsr[D.n + i] = static_cast<float>(f[1]);
+        fsr[2 * D.n + i] = static_cast<float>(f[2]);
+    }
+}
+
 // Static schedule: workgroup g runs plan entry g.
 // Register budget of the FP32 pair kernel: RBSOG_PAIR_OCC waves per SIMD
 // without the energy sum, one fewer with it.  The kernel waits on LDS more
@@ -1509,6 +1999,46 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_min_wav
     __shared__ PairShared<T> sh;
     const int2 e = plan[xcd_grouped(blockIdx.x, gridDim.x)];
     pair_block<T, M, E, FAST>(sh, desc[e.x], stp[e.x], e.y);
+}
+
+// Half-shell launches: a system whose neighbourhoods outgrew the partial
+// buffer this step (flag set by k_pair_prep) runs the full-shell fast path.
+template <class T, bool E>
+struct PairSmem {
+    static constexpr size_t bytes =
+        sizeof(PairShared<T>) > sizeof(PairSharedHalf<T, E>) ? sizeof(PairShared<T>) : sizeof(PairSharedHalf<T, E>);
+};
+template <class T, int M, bool E>
+__device__ __forceinline__ void pair_block_hs(char *smem, const SysDesc &D, const SysStep &St, int b)
+{
+    if (*gp(D.hflag)) pair_block<T, M, E, true>(*reinterpret_cast<PairShared<T> *>(smem), D, St, b);
+    else pair_block_half<T, M, E>(*reinterpret_cast<PairSharedHalf<T, E> *>(smem), D, St, b);
+}
+
+template <class T, int M, bool E>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_min_waves<T, E>()))) void k_pair_half(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
+                                                  const int2 *__restrict__ plan)
+{
+    __shared__ __attribute__((aligned(16))) char smem[PairSmem<T, E>::bytes];
+    const int2 e = plan[xcd_grouped(blockIdx.x, gridDim.x)];
+    pair_block_hs<T, M, E>(smem, desc[e.x], stp[e.x], e.y);
+}
+
+template <class T, int M, bool E>
+__global__ __launch_bounds__(64) void k_pair_half_queue(const SysDesc *__restrict__ desc,
+                                                        const SysStep *__restrict__ stp,
+                                                        const int2 *__restrict__ plan, int nitems, int32_t *ctrl)
+{
+    __shared__ __attribute__((aligned(16))) char smem[PairSmem<T, E>::bytes];
+    for (;;) {
+        int idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(&ctrl[0], 1);
+        idx = __shfl(idx, 0, 64);
+        if (idx >= nitems) break;
+        const int2 e = plan[idx];
+        pair_block_hs<T, M, E>(smem, desc[e.x], stp[e.x], e.y);
+        __syncthreads();
+    }
 }
 
 // Persistent schedule: a fixed number of workgroups take plan entries from a
@@ -1615,20 +2145,25 @@ __global__ __launch_bounds__(256) void k_sk(const SysDesc *__restrict__ desc, co
             }
             __syncthreads();
             if (active) {
-                typename T::real sr = 0, si = 0;
+                // FP64 accumulation of each term: atoms sorted by cell have
+                // nearly equal phases at small |m|, so an FP32 running sum
+                // grows well above the result and loses bits at every add
+                // (FP64 adds run at the FP32 rate on this chip)
                 for (int k = sl; k < cnt; k += nsl) {
                     const Atom at = s_at[k];
-                    typename T::real sn, cs;
+                    const double q = static_cast<double>(at.q);
                     if constexpr (sizeof(typename T::real) == 4) {
+                        float sn, cs;
                         phase_sincos32(m, at, sn, cs);
+                        accr = fma(q, static_cast<double>(cs), accr);
+                        acci = fma(q, static_cast<double>(sn), acci);
                     } else {
+                        double sn, cs;
                         phase_sincos64(m, at, sn, cs);
+                        accr = fma(q, cs, accr);
+                        acci = fma(q, sn, acci);
                     }
-                    sr += at.q * cs;
-                    si += at.q * sn;
                 }
-                accr += sr;
-                acci += si;
             }
             __syncthreads();
         }
@@ -1742,7 +2277,8 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
         else r->npairs = s;
     }
     __syncthreads();
-    double sr = 0.0, snr[6] = {0, 0, 0, 0, 0, 0};
+    double sr = 0.0, su = 0.0, snr[6] = {0, 0, 0, 0, 0, 0};
+    const bool wide = D.tab.Me > D.tab.M;
     for (int d = tid; d < nd; d += 256) {
         const int4 m = D.modes[d];
         const double k[3] = {2.0 * kPi * m.x / L[0], 2.0 * kPi * m.y / L[1], 2.0 * kPi * m.z / L[2]};
@@ -1751,6 +2287,18 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
         const double r2 = re * re + im * im;
         const int cr = D.cnt[d], cnr = D.cnt[D.mcap + d];
         sr += cr * r2 / k2;
+        if (wide) {
+            // energy kernel of Me terms over the M-term one that the modes were drawn from:
+            // sum_{l<Me} w_l s_l^3 e_l / sum_{l<M} w_l s_l^3 e_l (w_l s_l^3 = wt_l s_l^5 / 2)
+            double num = 0.0, den = 0.0;
+            for (int l = 0; l < D.tab.Me; ++l) {
+                const double t = D.tab.w[l] * D.tab.s[l] * D.tab.s[l] * D.tab.s[l] *
+                                 exp(-D.tab.s[l] * D.tab.s[l] * k2 / 4.0);
+                num += t;
+                if (l < D.tab.M) den += t;
+            }
+            su += cr * r2 / k2 * (num / den);
+        }
         double g = cnr * r2 / (k2 * k2);
         if (shared) {
             double a5 = 0.0, a7 = 0.0;
@@ -1782,6 +2330,7 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
         static_cast<Coef<real> *>(D.coef)[d] = cf;
     }
     sr = block_sum_256(sr, s_tmp);
+    if (wide) su = block_sum_256(su, s_tmp);
     for (int k = 0; k < 6; ++k) snr[k] = block_sum_256(snr[k], s_tmp);
     if (tid == 0) {
         StepResults *r = D.res;
@@ -1797,7 +2346,7 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
                 r->PN[q] = ck * r->vir[ix[al][be]] / V;
                 r->Ptot[q] = r->PN[q] + r->Pr[q] + r->Pnr[q];
             }
-        r->UF = ck * S / (2.0 * V * P) * sr;
+        r->UF = ck * S / (2.0 * V * P) * (wide ? su : sr);
         r->UN = ck * r->UN;
         for (int k = 0; k < 6; ++k) r->vir[k] *= ck;
         r->Uself = D.Uself;
@@ -1810,9 +2359,12 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
 // Long-range force scatter (eq. f_approx) and the total force in caller order
 // ----------------------------------------------------------------------------
 
+// sr: add the short-range force (the step's output); without it the kernel
+// writes the long-range part alone to (ox, oy, oz) (inspection)
 template <class T>
 __global__ __launch_bounds__(kAtomBlock) void k_force(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
-                                                      const int2 *__restrict__ plan)
+                                                      const int2 *__restrict__ plan, int sr, double *ox, double *oy,
+                                                      double *oz)
 {
     using real = typename T::real;
     const int2 e = plan[blockIdx.x];
@@ -1868,9 +2420,15 @@ __global__ __launch_bounds__(kAtomBlock) void k_force(const SysDesc *__restrict_
     const double q = static_cast<double>(r.q);
     const int i = gp(D.perm)[t];
     const double ck = D.ck;
-    gp(St.fx)[i] = ck * (static_cast<double>(fsr[t]) - q * gx);
-    gp(St.fy)[i] = ck * (static_cast<double>(fsr[n + t]) - q * gy);
-    gp(St.fz)[i] = ck * (static_cast<double>(fsr[2 * n + t]) - q * gz);
+    if (sr) {
+        gp(St.fx)[i] = ck * (static_cast<double>(fsr[t]) - q * gx);
+        gp(St.fy)[i] = ck * (static_cast<double>(fsr[n + t]) - q * gy);
+        gp(St.fz)[i] = ck * (static_cast<double>(fsr[2 * n + t]) - q * gz);
+    } else {
+        gp(ox)[i] = ck * (-q * gx);
+        gp(oy)[i] = ck * (-q * gy);
+        gp(oz)[i] = ck * (-q * gz);
+    }
 }
 
 // r <- mu r (FP64) for the positions of each system
@@ -2065,12 +2623,35 @@ static void pair_launch_group(Batch &b, int group)
     }
 }
 
-// one launch per path: the FP32 relative-coordinate filter exists only in FP32
+// Half shell: neighbourhoods, pair kernel, gather of the reactions.
+template <class T, int M, bool E>
+static void pair_launch_half(Batch &b, int group)
+{
+    const int64_t first = b.pair_split[group], items = b.pair_split[group + 1] - first;
+    if (items <= 0) return;
+    const int2 *plan = plan_ptr(b, kPlanPair) + first;
+    const unsigned grid = static_cast<unsigned>(items);
+    hipLaunchKernelGGL(k_pair_prep, dim3(grid), dim3(64), 0, b.stream, b.d_desc, b.d_step, plan);
+    if (b.pair_schedule == kPairPersistent) {
+        const int64_t wgs = std::min<int64_t>(items, static_cast<int64_t>(b.num_cu) * b.pair_wg_per_cu);
+        hipLaunchKernelGGL((k_pair_half_queue<T, M, E>), dim3(static_cast<unsigned>(wgs)), dim3(64), 0, b.stream,
+                           b.d_desc, b.d_step, plan, static_cast<int>(items), b.d_ctrl + group);
+    } else {
+        hipLaunchKernelGGL((k_pair_half<T, M, E>), dim3(grid), dim3(64), 0, b.stream, b.d_desc, b.d_step, plan);
+    }
+    hipLaunchKernelGGL(k_pair_gather, dim3(grid), dim3(64), 0, b.stream, b.d_desc, b.d_step, plan);
+}
+
+// one launch per path: the FP32 relative-coordinate filter (full and half
+// shell) exists only in FP32
 template <class T, int M, bool E>
 static void pair_launch(Batch &b, int form)
 {
-    pair_launch_group<T, M, E, false>(b, 2 * form);
-    if constexpr (sizeof(typename T::real) == 4) pair_launch_group<T, M, E, true>(b, 2 * form + 1);
+    pair_launch_group<T, M, E, false>(b, kNumPaths * form);
+    if constexpr (sizeof(typename T::real) == 4) {
+        pair_launch_group<T, M, E, true>(b, kNumPaths * form + 1);
+        pair_launch_half<T, M, E>(b, kNumPaths * form + 2);
+    }
 }
 
 template <class T, bool E>
@@ -2120,7 +2701,7 @@ static hipError_t kspace_t(Batch &b)
     timer_end(b, "reduce", b.stream);
     timer_begin(b, "force", b.stream);
     hipLaunchKernelGGL(k_force<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc, b.d_step,
-                       plan_ptr(b, kPlanAtoms));
+                       plan_ptr(b, kPlanAtoms), 1, nullptr, nullptr, nullptr);
     timer_end(b, "force", b.stream);
     return hipGetLastError();
 }
@@ -2129,6 +2710,20 @@ hipError_t launch_kspace(Batch &b)
 {
     if (b.sys.empty()) return hipSuccess;
     return b.precision == RBSOG_PREC_FP64 ? kspace_t<F64>(b) : kspace_t<F32>(b);
+}
+
+// the long-range force of the last step alone, into caller-order device
+// arrays (a batch of one system)
+hipError_t launch_long_range_force(Batch &b, double *fx, double *fy, double *fz)
+{
+    if (b.sys.size() != 1) return hipErrorInvalidValue;
+    if (b.precision == RBSOG_PREC_FP64)
+        hipLaunchKernelGGL(k_force<F64>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
+                           b.d_step, plan_ptr(b, kPlanAtoms), 0, fx, fy, fz);
+    else
+        hipLaunchKernelGGL(k_force<F32>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
+                           b.d_step, plan_ptr(b, kPlanAtoms), 0, fx, fy, fz);
+    return hipGetLastError();
 }
 
 hipError_t launch_rescale(Batch &b)

@@ -34,6 +34,12 @@ constexpr int kMaxTimed = 24;
 constexpr int kPolyDeg = 10;       // degree of the FP32C polynomial form of the SOG sums
 constexpr int kSuperCells = 4;     // most cells stacked in z into one pair-block segment
 constexpr int kOrderPart = 1024;   // keys one ordering workgroup ranks in a single-cell system
+constexpr int kHrngStride = 24;    // ints per pair block of the half-shell neighbourhood table
+// Half-shell partial buffer: forward candidates per block are estimated at this
+// density (atoms per A^3, above condensed matter's 0.1) and margin; a block
+// with more runs its system on the full shell for that step.
+constexpr double kHalfRefDensity = 0.15;
+constexpr double kHalfMargin = 1.25;
 
 // Distinct modes a step can visit: the r-chain's start state and proposals;
 // the exchange form adds the non-radial chain's start state, the independent
@@ -47,8 +53,8 @@ inline int mode_cap(const rbsog_params &p)
 
 // SOG tables read by the kernels (device memory, uniform loads).
 struct SogTables {
-    int M;
-    int pad;
+    int M;                // Gaussians of the force, virial and sampling
+    int Me;               // Gaussians of the energy (>= M; wt_l = 0 for M <= l < Me)
     double rc2;
     // energy kernel F(r) = sum w_l exp(-r^2/s_l^2); force/pressure kernel F~ with wt_l
     double w[RBSOG_MAX_M], wt[RBSOG_MAX_M], inv_s2[RBSOG_MAX_M];
@@ -75,6 +81,8 @@ struct StepResults {
     int32_t nd, status;
     int64_t acc_r, acc_nr;
     double npairs;  // unordered in-cutoff pairs of the last evaluation
+    int32_t bad_input;  // nonzero: a position was NaN or infinite (set by k_fix)
+    int32_t pad1;
 };
 
 // Static description of one system (device copy read by every kernel).
@@ -107,6 +115,11 @@ struct SysDesc {
     double *pair_red;     // [kPairRed][8] slice sums of the pair-block partials
     void *coef;           // per-mode force coefficients [mcap]
     StepResults *res;     // this system's slot of the batch results
+    // half-shell pair kernel (FP32C fast path): reactions on forward candidates
+    float *hpart;         // [pair_cap][3][hcap] FP32 partials, by position in the block's neighbourhood
+    int32_t *hrng;        // [pair_cap][kHrngStride]: range starts, flattened prefixes, chunk count
+    int32_t *hflag;       // [1] set when a block's neighbourhood exceeds hcap (full shell this step)
+    int32_t hcap, pad2;   // candidates per block the partial buffer holds
 };
 
 // Per-step data of one system (rewritten by the host every step).
@@ -122,6 +135,8 @@ struct SysStep {
     int32_t g;            // cells per pair-block segment along z (a column's cells cz = 0, g, 2g, ... start one)
     int32_t fast;         // FP32 relative-coordinate filter over whole neighbour columns (4+ cells per edge, nz >= 2g + 2)
     uint32_t thr16;       // FP32 exact filter: bound on sum (d_d / u_d)^2 of a pair inside rc, u_d = L_d / 2^16
+    int32_t half;         // fast path with Newton's third law (half-shell pair kernel, partials, gather)
+    int32_t pad3;
     const double *x, *y, *z;  // positions (device, system order)
     double *fx, *fy, *fz;     // forces (device, system order)
 };
@@ -144,9 +159,11 @@ enum PairForm {
     kFormExpM = 2,   // runtime M exponentials
     kNumForms = 3,
 };
-// Pair launches: one per (form, path); path 1 is the FP32 relative-coordinate
-// filter over whole neighbour columns (SysStep::fast), path 0 the exact one.
-constexpr int kNumPairGroups = 2 * kNumForms;
+// Pair launches: one per (form, path); path 0 is the exact filter, path 1 the
+// FP32 relative-coordinate filter over whole neighbour columns (SysStep::fast)
+// with the full shell, path 2 the same with the half shell (SysStep::half).
+constexpr int kNumPaths = 3;
+constexpr int kNumPairGroups = kNumPaths * kNumForms;
 
 // Pair-kernel schedules (none changes any result).
 enum PairSchedule {
@@ -173,6 +190,10 @@ struct System {
     size_t cell_bytes = 0;
     int64_t ncells_cap = 0;
     bool own_mem = true;  // false: the memory belongs to a pool
+    // half-shell buffers (own memory only): partials, neighbourhood table, flag
+    void *half_mem = nullptr;
+    int64_t half_blocks = 0;  // pair-block slots they cover
+    int32_t half_hcap = 0;    // candidates per block
     int pair_form = kFormExpM;
     SysDesc desc{};       // host copy of the device descriptor
     SysStep stp{};        // host copy of the per-step data
@@ -244,6 +265,8 @@ int check_box(const double *box, double rc, std::string &err);
 // Bytes of the atom-sized and cell-sized device parts of a system.
 size_t system_atom_bytes(const rbsog_params &p, int64_t n);
 size_t system_cell_bytes(int64_t n, int64_t ncells_cap);
+// Device bytes a system holds now (atom, cell and half-shell parts).
+size_t system_device_bytes(const System &s);
 // Point the descriptor into memory the caller provides (aligned to 256 bytes).
 void system_carve_atoms(System &s, void *mem);
 void system_carve_cells(System &s, void *mem, int64_t ncells_cap);
@@ -259,8 +282,12 @@ void system_free(System &s);
 // left in flight: the caller keeps host_q and *stage until the stream is synchronised.
 int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err,
                     std::vector<float> *stage = nullptr);
-// New box: grid, S^r, S^nr.
+// New box: grid, S^r, S^nr, the pair path.
 void system_set_box(System &s, const double box[3]);
+// Whether the system takes the half-shell pair kernel on the fast path, and
+// the forward candidates per block its partial buffer holds for the grid.
+bool wants_half_shell(const System &s);
+int32_t half_hcap(const System &s);
 // Cells needed by a box.
 int64_t cells_for_box(const double box[3], double rc);
 
@@ -270,6 +297,8 @@ void batch_free(Batch &b);
 int batch_set_systems(Batch &b, const std::vector<System *> &sys, std::string &err);
 // Copy descriptors (if changed), per-step data and plans (if sizes changed) to the device.
 int batch_upload(Batch &b, std::string &err);
+// Whether the next batch_upload would allocate (more systems or plan entries than held).
+bool batch_upload_allocates(const Batch &b);
 // Results of every system to the host (synchronises).
 int batch_fetch_results(Batch &b, std::string &err);
 // Per-kernel HIP-event timing of the batch's launches.
@@ -284,6 +313,7 @@ hipError_t launch_bin_and_sort(Batch &b);
 hipError_t launch_pair(Batch &b);
 hipError_t launch_kspace(Batch &b);
 hipError_t launch_rescale(Batch &b);
+hipError_t launch_long_range_force(Batch &b, double *fx, double *fy, double *fz);
 
 // timing hooks used by the launchers (system.cpp)
 void timer_begin(Batch &b, const char *name, hipStream_t s);
@@ -315,7 +345,9 @@ hipError_t launch_npt_kinetic(hipStream_t s, int64_t n, const double *mass, cons
 
 }  // namespace rbsog
 
-// A single-system context: one system evaluated as a batch of one.
+// A single-system context: one system evaluated as a batch of one.  It can
+// also be admitted to a batch of contexts (rbsog_batch_create); while
+// admitted its step inputs are staged and the batch evaluates them.
 struct rbsog_ctx {
     rbsog::System sys;
     rbsog::Batch batch;
@@ -323,4 +355,8 @@ struct rbsog_ctx {
     double *d_stage = nullptr;  // host-array staging (6 n doubles), allocated on first use
     rbsog::NptState npt;
     std::string err;
+    rbsog_batch *in_batch = nullptr;  // the batch of contexts it is admitted to
+    bool staged = false;              // inputs of the next batched step are set
+    bool desc_moved = false;          // its buffers were re-carved since the batch last uploaded them
+    bool res_from_batch = false;      // batch.h_res[0] holds the results of the last batched step
 };

@@ -191,6 +191,10 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
         err = "M or P out of range";
         return RBSOG_EINVAL;
     }
+    if (p.M_energy != 0 && (p.M_energy < p.M || p.M_energy > RBSOG_MAX_M)) {
+        err = "M_energy must be 0 or in [M, 64]";
+        return RBSOG_EINVAL;
+    }
     if (!(p.rc > 0.0) || !std::isfinite(p.rc) || !std::isfinite(p.coulomb_k)) {
         err = "bad cutoff or prefactor";
         return RBSOG_EINVAL;
@@ -211,8 +215,12 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
         err = "system_id must be < 2^32";
         return RBSOG_EINVAL;
     }
-    if (p.flags & ~RBSOG_FLAG_EXP_FORM) {
+    if (p.flags & ~(RBSOG_FLAG_EXP_FORM | RBSOG_FLAG_FULL_SHELL | RBSOG_FLAG_HALF_SHELL)) {
         err = "unknown flags";
+        return RBSOG_EINVAL;
+    }
+    if ((p.flags & RBSOG_FLAG_FULL_SHELL) && (p.flags & RBSOG_FLAG_HALF_SHELL)) {
+        err = "full-shell and half-shell flags together";
         return RBSOG_EINVAL;
     }
     double qs = 0.0, qa = 0.0;
@@ -234,9 +242,16 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
     s.prm = p;
     s.n = n;
     if (s.prm.omega <= 0.0) s.prm.omega = omega_c0(p.b, p.sigma, p.rc, p.M);
-    sog_tables(s.prm, s.w, s.wt, s.s);
+    // the energy's Gaussians extend the force's (R1): Me terms of w, M of wt
+    const int Me = p.M_energy > 0 ? p.M_energy : p.M;
+    {
+        rbsog_params pe = s.prm;
+        pe.M = Me;
+        sog_tables(pe, s.w, s.wt, s.s);
+        for (int l = p.M; l < Me; ++l) s.wt[l] = 0.0;
+    }
     double wsum = 0.0;
-    for (int l = 0; l < p.M; ++l) wsum += s.w[l];
+    for (int l = 0; l < Me; ++l) wsum += s.w[l];
     s.q2sum = 0.0;
     for (int64_t i = 0; i < n; ++i) s.q2sum += host_q[i] * host_q[i];
     // U_self = (1/2) F(0) sum q^2 (App. A)
@@ -245,10 +260,11 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
     SogTables &tab = s.tab;
     tab = SogTables{};
     tab.M = p.M;
+    tab.Me = Me;
     tab.rc2 = p.rc * p.rc;
     tab.rc2_32 = static_cast<float>(p.rc * p.rc);
     const double log2e = 1.4426950408889634073599246810018921;
-    for (int l = 0; l < p.M; ++l) {
+    for (int l = 0; l < Me; ++l) {
         tab.w[l] = s.w[l];
         tab.wt[l] = s.wt[l];
         tab.s[l] = s.s[l];
@@ -261,12 +277,12 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
     }
     // FP32C: the SOG sums as polynomials in r^2 when the fit is within
     // kPolyTol of the exponential form; otherwise the M exponentials
-    s.pair_form = p.M == 10 ? kFormExp10 : kFormExpM;
+    s.pair_form = p.M == 10 && Me == p.M ? kFormExp10 : kFormExpM;
     if (p.precision == RBSOG_PREC_FP32C) {
         const double X = p.rc * p.rc;
         double mg[kPolyDeg + 1], mf[kPolyDeg + 1], eg = 1.0, ef = 1.0;
         poly_fit_cached(s.wt, s.s, p.M, X, mg, &eg);
-        poly_fit_cached(s.w, s.s, p.M, X, mf, &ef);
+        poly_fit_cached(s.w, s.s, Me, X, mf, &ef);
         tab.poly_err = static_cast<float>(std::max(eg, ef));
         if (eg <= kPolyTol && ef <= kPolyTol && !(p.flags & RBSOG_FLAG_EXP_FORM)) {
             tab.poly = 1;
@@ -299,6 +315,28 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
     return RBSOG_OK;
 }
 
+bool wants_half_shell(const System &s)
+{
+    if (is_fp64(s.prm) || !s.own_mem || (s.prm.flags & RBSOG_FLAG_FULL_SHELL)) return false;
+    return (s.prm.flags & RBSOG_FLAG_HALF_SHELL) != 0;
+}
+
+// Forward candidates a half-shell block can hold.  A full block of 64 atoms in
+// a column of cross-section A spans 64/(rho A) in z, so each of its four
+// neighbour columns contributes about 64 + 2 rho A rc atoms to its window and
+// its own column 64 + rho A rc; A is at most rc^2 (n_x+1)/n_x (n_y+1)/n_y for
+// the grid, and rho the reference density.  The margin and a last chunk for
+// rounding go on top.
+int32_t half_hcap(const System &s)
+{
+    const double rc = s.prm.rc + 1e-3;
+    const double A = s.prm.rc * s.prm.rc * (s.nc[0] + 1.0) / s.nc[0] * (s.nc[1] + 1.0) / s.nc[1];
+    const double rhoA = kHalfRefDensity * A;
+    const double est = 4.0 * (kPairWave + 2.0 * rhoA * rc) + (kPairWave + rhoA * rc);
+    const int64_t c = static_cast<int64_t>(std::ceil(kHalfMargin * est / 128.0)) + 1;
+    return static_cast<int32_t>(std::min<int64_t>(c * 128, int64_t(1) << 24));
+}
+
 void system_set_box(System &s, const double box[3])
 {
     for (int d = 0; d < 3; ++d) s.L[d] = box[d];
@@ -323,6 +361,9 @@ void system_set_box(System &s, const double box[3])
     // difference is the displacement.  The other paths use single cells.
     const bool fast = !is_fp64(s.prm) && s.nc[0] >= 4 && s.nc[1] >= 4 && s.nc[2] >= 4;
     t.fast = fast ? 1 : 0;
+    // Newton's third law on the fast path for systems that own their memory
+    // (the served pool's requests keep the full shell and its smaller footprint)
+    t.half = fast && wants_half_shell(s) ? 1 : 0;
     t.g = fast ? std::max(1, std::min(kSuperCells, (s.nc[2] - 3) / 2)) : 1;
     // The FP32 exact filter compares 16-bit wrapped differences of the
     // fixed-point coordinates, in units u_d = L_d / 2^16 truncated (under one
@@ -337,6 +378,15 @@ void system_set_box(System &s, const double box[3])
 }
 
 size_t system_atom_bytes(const rbsog_params &p, int64_t n) { return atom_layout(p, n).total(); }
+
+size_t system_device_bytes(const System &s)
+{
+    size_t b = s.atom_bytes + s.cell_bytes;
+    if (s.half_mem)
+        b += align_up(static_cast<size_t>(s.half_blocks) * 3 * s.half_hcap * sizeof(float)) +
+             align_up(static_cast<size_t>(s.half_blocks) * kHrngStride * sizeof(int32_t)) + kAlign;
+    return b;
+}
 
 size_t system_cell_bytes(int64_t n, int64_t ncells_cap)
 {
@@ -408,10 +458,45 @@ int system_alloc(System &s, std::string &err)
     return system_ensure_cells(s, err);
 }
 
+// Half-shell buffers for the current grid: partials [pair_cap][3][hcap] FP32,
+// the neighbourhood table and the overflow flag, reallocated when the grid
+// needs more slots or candidates per block than they hold.
+static int ensure_half(System &s, std::string &err, bool *recarved)
+{
+    if (!s.stp.half) return RBSOG_OK;
+    const int64_t blocks = s.desc.pair_cap;
+    const int32_t hcap = half_hcap(s);
+    if (s.half_mem && blocks <= s.half_blocks && hcap <= s.half_hcap) return RBSOG_OK;
+    if (s.half_mem) {
+        (void)hipFree(s.half_mem);  // synchronises the device
+        s.half_mem = nullptr;
+    }
+    const int64_t nb = std::max(blocks, s.half_blocks);
+    const int32_t hc = std::max(hcap, s.half_hcap);
+    const size_t part = align_up(static_cast<size_t>(nb) * 3 * hc * sizeof(float));
+    const size_t rng = align_up(static_cast<size_t>(nb) * kHrngStride * sizeof(int32_t));
+    void *m = nullptr;
+    if (hipMalloc(&m, part + rng + kAlign) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "device allocation failed (half-shell partials)";
+        return RBSOG_ENOMEM;
+    }
+    s.half_mem = m;
+    s.half_blocks = nb;
+    s.half_hcap = hc;
+    char *p = static_cast<char *>(m);
+    s.desc.hpart = reinterpret_cast<float *>(p);
+    s.desc.hrng = reinterpret_cast<int32_t *>(p + part);
+    s.desc.hflag = reinterpret_cast<int32_t *>(p + part + rng);
+    s.desc.hcap = hc;
+    if (recarved) *recarved = true;
+    return RBSOG_OK;
+}
+
 int system_ensure_cells(System &s, std::string &err, bool *recarved)
 {
     if (recarved) *recarved = false;
-    if (s.ncells <= s.ncells_cap) return RBSOG_OK;
+    if (s.ncells <= s.ncells_cap) return ensure_half(s, err, recarved);
     if (!s.own_mem && s.cell_mem) {
         err = "cell grid outgrew the memory reserved at admission";
         return RBSOG_EBOX;
@@ -428,7 +513,7 @@ int system_ensure_cells(System &s, std::string &err, bool *recarved)
     }
     system_carve_cells(s, cm, s.ncells);
     if (recarved) *recarved = true;
-    return RBSOG_OK;
+    return ensure_half(s, err, recarved);
 }
 
 void system_free(System &s)
@@ -437,7 +522,8 @@ void system_free(System &s)
         if (s.atom_mem) (void)hipFree(s.atom_mem);
         if (s.cell_mem) (void)hipFree(s.cell_mem);
     }
-    s.atom_mem = s.cell_mem = nullptr;
+    if (s.half_mem) (void)hipFree(s.half_mem);
+    s.atom_mem = s.cell_mem = s.half_mem = nullptr;
 }
 
 int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err,
@@ -621,6 +707,7 @@ static std::vector<int64_t> plan_sizes(const Batch &b)
         k.push_back(s->prm.P);
         k.push_back(s->pair_form);
         k.push_back(s->stp.fast);
+        k.push_back(s->stp.half);
     }
     return k;
 }
@@ -690,12 +777,26 @@ static int build_plans(Batch &b, std::string &err)
         b.pair_split[g] = pos[kPlanPair] - b.plan_off[kPlanPair];
         for (int s = 0; s < S; ++s) {
             const System *y = b.sys[s];
-            if (2 * y->pair_form + (y->stp.fast ? 1 : 0) == g)
+            const int path = y->stp.half ? 2 : (y->stp.fast ? 1 : 0);
+            if (kNumPaths * y->pair_form + path == g)
                 put(kPlanPair, s, (y->n + kPairWave - 1) / kPairWave + y->ncells);
         }
     }
     b.pair_split[kNumPairGroups] = pos[kPlanPair] - b.plan_off[kPlanPair];
     return RBSOG_OK;
+}
+
+bool batch_upload_allocates(const Batch &b)
+{
+    if (static_cast<int64_t>(b.sys.size()) > b.cap_sys) return true;
+    if (!b.plan_dirty && plan_sizes(b) == b.plan_key) return false;
+    int64_t total = 0;
+    for (const System *s : b.sys) {
+        total += (s->n + kAtomBlock - 1) / kAtomBlock + (s->ncells + 1 + kCellBlock - 1) / kCellBlock +
+                 (s->ncells + kScanBlock - 1) / kScanBlock + (s->n + kPairWave - 1) / kPairWave + s->ncells +
+                 (s->n + kSkChunk - 1) / kSkChunk + mode_cap(s->prm) + kPairRed + order_parts(*s);
+    }
+    return total > b.cap_plan;
 }
 
 int batch_upload(Batch &b, std::string &err)

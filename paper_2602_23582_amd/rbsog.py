@@ -23,8 +23,10 @@ RECAL_EXCHANGE = 1
 RECAL_SHARED = 2
 RECAL_INDEPENDENT = 3
 FLAG_EXP_FORM = 1
+FLAG_FULL_SHELL = 2
+FLAG_HALF_SHELL = 4
 MAX_P = 1024
-MAX_MODES = MAX_P + 1
+MAX_MODES = MAX_P + 2
 
 ERRORS = {0: "RBSOG_OK", -1: "RBSOG_EINVAL", -2: "RBSOG_ENEUTRAL", -3: "RBSOG_EBOX", -4: "RBSOG_ENOMEM",
           -5: "RBSOG_EDEVICE", -6: "RBSOG_ESTATE", -7: "RBSOG_EAGAIN"}
@@ -40,7 +42,8 @@ EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_forc
            "rbsog_batch_autotune", "rbsog_batch_set_timing", "rbsog_batch_get_timing", "rbsog_batch_destroy",
            "rbsog_batch_last_error", "rbsog_server_create", "rbsog_server_submit", "rbsog_server_wait",
            "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_set_energy", "rbsog_server_last_error",
-           "rbsog_npt_init", "rbsog_npt_run"]
+           "rbsog_npt_init", "rbsog_npt_run", "rbsog_batch_create", "rbsog_batch_admit", "rbsog_stage",
+           "rbsog_batch_release", "rbsog_debug_long_range_force"]
 
 COUPLE_ANISO = 0
 COUPLE_SEMI = 1
@@ -57,7 +60,7 @@ class rbsog_params(C.Structure):
     _fields_ = [("b", C.c_double), ("sigma", C.c_double), ("omega", C.c_double), ("M", C.c_int32),
                 ("rc", C.c_double), ("P", C.c_int32), ("seed", C.c_uint64), ("system_id", C.c_uint64),
                 ("coulomb_k", C.c_double), ("precision", C.c_int32), ("recalibration", C.c_int32),
-                ("flags", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("flags", C.c_int32), ("M_energy", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class RBSOGError(RuntimeError):
@@ -114,6 +117,11 @@ def load(path: str | None = None):
         "rbsog_server_last_error": (C.c_char_p, [vp]),
         "rbsog_npt_init": (C.c_int, [vp, C.POINTER(rbsog_npt_params), pd]),
         "rbsog_npt_run": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, i64, i32, pd, pd, pd, pd]),
+        "rbsog_batch_create": (C.c_int, [i64, vp, C.POINTER(vp)]),
+        "rbsog_batch_admit": (C.c_int, [vp, vp]),
+        "rbsog_stage": (C.c_int, [vp, i64, pd, vp, vp, vp, vp, vp, vp]),
+        "rbsog_batch_release": (C.c_int, [vp, vp]),
+        "rbsog_debug_long_range_force": (C.c_int, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -131,16 +139,37 @@ def _pi32(a):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
 
 
-def _ptr(a):
-    """Device pointer of a torch tensor or host pointer of a numpy array (float64, contiguous)."""
+def _ptr(a, n=None, device=None):
+    """Device pointer of a torch tensor or host pointer of a numpy array
+    (float64, contiguous).  With n, the array must hold exactly n entries;
+    with device (a CUDA device index), a tensor must live on that device.  The
+    C ABI sees only pointers and cannot check either."""
     if hasattr(a, "data_ptr"):
         import torch
         if a.dtype != torch.float64 or not a.is_contiguous():
             raise TypeError("position/force tensors must be contiguous float64")
+        if n is not None and a.numel() != n:
+            raise ValueError(f"position/force tensor has {a.numel()} entries, expected {n}")
+        if device is not None and a.is_cuda and a.device.index != device:
+            raise ValueError(f"tensor on cuda:{a.device.index}, the library's work runs on cuda:{device}")
         return C.c_void_p(a.data_ptr())
     if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous):
         raise TypeError("position/force arrays must be contiguous float64")
+    if n is not None and a.size != n:
+        raise ValueError(f"position/force array has {a.size} entries, expected {n}")
     return C.c_void_p(a.ctypes.data)
+
+
+def _ptrs(arrs, n, device):
+    return [_ptr(a, n, device) for a in arrs]
+
+
+def _current_device():
+    try:
+        import torch
+        return torch.cuda.current_device() if torch.cuda.is_available() else None
+    except ImportError:
+        return None
 
 
 def default_params(rc: float) -> rbsog_params:
@@ -155,12 +184,12 @@ class Context:
     """One system: wraps rbsog_setup .. rbsog_destroy."""
 
     def __init__(self, q, box, rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_EXCHANGE,
-                 M=10, b=None, sigma=None, omega=None, coulomb_k=1.0, stream=None, flags=0):
+                 M=10, b=None, sigma=None, omega=None, coulomb_k=1.0, stream=None, flags=0, M_energy=0):
         L = load()
         p = default_params(rc)
         p.P, p.seed, p.system_id, p.M = int(P), int(seed), int(system_id), int(M)
         p.precision, p.recalibration, p.coulomb_k = int(precision), int(recalibration), float(coulomb_k)
-        p.flags = int(flags)
+        p.flags, p.M_energy = int(flags), int(M_energy)
         if b is not None:
             p.b = b
         if sigma is not None:
@@ -185,6 +214,7 @@ class Context:
             raise RBSOGError(rc_, "rbsog_setup")
         self._h = h
         self.box = box.copy()
+        self.device = _current_device()
 
     def _check(self, rc_, what):
         if rc_ != 0:
@@ -209,8 +239,8 @@ class Context:
     def force_virial(self, x, y, z, fx, fy, fz, energy=True):
         e = np.zeros(3)
         v = np.zeros(6)
-        self._check(load().rbsog_force_virial(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(fx), _ptr(fy), _ptr(fz),
-                                              _pd(e) if energy else None, _pd(v) if energy else None),
+        px = _ptrs((x, y, z, fx, fy, fz), self.n, self.device)
+        self._check(load().rbsog_force_virial(self._h, *px, _pd(e) if energy else None, _pd(v) if energy else None),
                     "rbsog_force_virial")
         return (e, v) if energy else (None, None)
 
@@ -222,15 +252,26 @@ class Context:
 
     def rescale(self, mu, x, y, z):
         mu = np.ascontiguousarray(mu, dtype=np.float64)
-        self._check(load().rbsog_rescale(self._h, _pd(mu), _ptr(x), _ptr(y), _ptr(z), _pd(self.box)),
+        self._check(load().rbsog_rescale(self._h, _pd(mu), *_ptrs((x, y, z), self.n, self.device), _pd(self.box)),
                     "rbsog_rescale")
         return self.box
+
+    def stage(self, step, box, x, y, z, fx, fy, fz):
+        """Inputs of the next step of a batch of contexts (device tensors)."""
+        self.box = np.ascontiguousarray(box, dtype=np.float64).copy()
+        self._check(load().rbsog_stage(self._h, int(step), _pd(self.box), *_ptrs((x, y, z, fx, fy, fz), self.n,
+                                                                                  self.device)), "rbsog_stage")
 
     def debug_cells(self):
         cell = np.zeros(self.n, dtype=np.int32)
         nc = np.zeros(3, dtype=np.int32)
         self._check(load().rbsog_debug_cells(self._h, _pi32(cell), _pi32(nc)), "rbsog_debug_cells")
         return cell, nc
+
+    def debug_long_range_force(self, fx, fy, fz):
+        """F^{F*} of the last evaluation alone into device tensors (caller order)."""
+        self._check(load().rbsog_debug_long_range_force(self._h, *_ptrs((fx, fy, fz), self.n, self.device)),
+                    "rbsog_debug_long_range_force")
 
     def debug_modes(self, with_rho=True):
         nd = np.zeros(1, dtype=np.int32)
@@ -271,7 +312,7 @@ class Context:
         pbox = np.ascontiguousarray(pbox, dtype=np.float64).copy()
         Pi = np.zeros(9)
         Pk = np.zeros(9)
-        self._check(load().rbsog_npt_run(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(px), _ptr(py), _ptr(pz),
+        self._check(load().rbsog_npt_run(self._h, *_ptrs((x, y, z, px, py, pz), self.n, self.device),
                                          int(first_step), int(nsteps), _pd(box), _pd(pbox), _pd(Pi), _pd(Pk)),
                     "rbsog_npt_run")
         self.box = box.copy()
@@ -315,11 +356,11 @@ def _timing_table(getter, handle):
 
 
 def make_params(rc, P=100, seed=0, system_id=0, precision=PREC_FP32C, recalibration=RECAL_EXCHANGE, M=10,
-                coulomb_k=1.0, flags=0):
+                coulomb_k=1.0, flags=0, M_energy=0):
     p = default_params(rc)
     p.P, p.seed, p.system_id, p.M = int(P), int(seed), int(system_id), int(M)
     p.precision, p.recalibration, p.coulomb_k = int(precision), int(recalibration), float(coulomb_k)
-    p.flags = int(flags)
+    p.flags, p.M_energy = int(flags), int(M_energy)
     return p
 
 
@@ -350,7 +391,7 @@ class Batch:
             arr[s] = make_params(spec["rc"], P=spec.get("P", 100), seed=spec.get("seed", 0),
                                  system_id=spec.get("system_id", 0), precision=precision,
                                  recalibration=spec.get("recalibration", RECAL_EXCHANGE), M=spec.get("M", 10),
-                                 flags=spec.get("flags", 0))
+                                 flags=spec.get("flags", 0), M_energy=spec.get("M_energy", 0))
             n[s] = len(spec["q"])
             qs.append(np.asarray(spec["q"], dtype=np.float64))
             boxes[s] = spec["box"]
@@ -366,11 +407,15 @@ class Batch:
         if rc_ != 0:
             raise RBSOGError(rc_, "rbsog_batch_setup")
         self._h = h
+        self.device = _current_device()
 
     def _check(self, rc_, what):
         if rc_ != 0:
             msg = load().rbsog_batch_last_error(self._h)
             raise RBSOGError(rc_, f"{what}: {msg.decode() if msg else ''}")
+
+    def _arrays(self, arrs):
+        return _ptrs(arrs, int(self.offsets[-1]), self.device)
 
     def step(self, steps, boxes, x, y, z, fx, fy, fz, results=True, energy=True):
         """One step of every system.  With results, returns the pressure
@@ -379,20 +424,20 @@ class Batch:
         steps = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.int64), (self.nsys,)))
         boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(self.nsys, 3)
         if not results:
-            self._check(load().rbsog_batch_step(self._h, _pi64(steps), _pd(boxes), _ptr(x), _ptr(y), _ptr(z),
-                                                _ptr(fx), _ptr(fy), _ptr(fz), None, None, None), "rbsog_batch_step")
+            self._check(load().rbsog_batch_step(self._h, _pi64(steps), _pd(boxes), *self._arrays((x, y, z, fx, fy, fz)),
+                                                None, None, None), "rbsog_batch_step")
             return None
         P = np.zeros((self.nsys, 9))
         U = np.zeros((self.nsys, 3))
         info = np.zeros((self.nsys, 4), dtype=np.int64)
-        self._check(load().rbsog_batch_step(self._h, _pi64(steps), _pd(boxes), _ptr(x), _ptr(y), _ptr(z), _ptr(fx),
-                                            _ptr(fy), _ptr(fz), _pd(P), _pd(U) if energy else None, _pi64(info)),
+        self._check(load().rbsog_batch_step(self._h, _pi64(steps), _pd(boxes), *self._arrays((x, y, z, fx, fy, fz)),
+                                            _pd(P), _pd(U) if energy else None, _pi64(info)),
                     "rbsog_batch_step")
         return P.reshape(self.nsys, 3, 3), U, info
 
     def rescale(self, mu, x, y, z):
         mu = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), (self.nsys, 3)))
-        self._check(load().rbsog_batch_rescale(self._h, _pd(mu), _ptr(x), _ptr(y), _ptr(z), _pd(self.boxes)),
+        self._check(load().rbsog_batch_rescale(self._h, _pd(mu), *self._arrays((x, y, z)), _pd(self.boxes)),
                     "rbsog_batch_rescale")
         return self.boxes
 
@@ -405,8 +450,8 @@ class Batch:
         boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(self.nsys, 3)
         ms = np.zeros(len(AUTOTUNE_CANDIDATES))
         choice = np.zeros(1, dtype=np.int32)
-        self._check(load().rbsog_batch_autotune(self._h, _pi64(steps), _pd(boxes), _ptr(x), _ptr(y), _ptr(z),
-                                                _ptr(fx), _ptr(fy), _ptr(fz), int(reps), _pd(ms), _pi32(choice)),
+        self._check(load().rbsog_batch_autotune(self._h, _pi64(steps), _pd(boxes), *self._arrays((x, y, z, fx, fy, fz)),
+                                                int(reps), _pd(ms), _pi32(choice)),
                     "rbsog_batch_autotune")
         return int(choice[0]), ms
 
@@ -422,6 +467,68 @@ class Batch:
         if getattr(self, "_h", None):
             load().rbsog_batch_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class ContextBatch:
+    """A batch of existing contexts admitted by device memory: wraps
+    rbsog_batch_create, rbsog_batch_admit, rbsog_batch_release and the
+    context form of rbsog_batch_step."""
+
+    def __init__(self, mem_budget, stream=None):
+        stream = _stream_or_default(stream)
+        h = C.c_void_p()
+        rc_ = load().rbsog_batch_create(int(mem_budget), C.c_void_p(stream) if stream else None, C.byref(h))
+        if rc_ != 0:
+            raise RBSOGError(rc_, "rbsog_batch_create")
+        self._h = h
+        self.members = []
+
+    def _check(self, rc_, what):
+        if rc_ != 0:
+            msg = load().rbsog_batch_last_error(self._h)
+            raise RBSOGError(rc_, f"{what}: {msg.decode() if msg else ''}")
+
+    def admit(self, ctx):
+        """Admit a Context; returns False (RBSOG_EAGAIN) when the budget or the slots are full."""
+        rc_ = load().rbsog_batch_admit(self._h, ctx._h)
+        if rc_ == -7:
+            return False
+        self._check(rc_, "rbsog_batch_admit")
+        self.members.append(ctx)
+        return True
+
+    def release(self, ctx):
+        self._check(load().rbsog_batch_release(self._h, ctx._h), "rbsog_batch_release")
+        self.members.remove(ctx)
+
+    def step(self, energy=True):
+        """One step of every admitted context from its staged inputs; returns
+        pressures (S, 3, 3), energies (S, 3) and counters (S, 4) in admission order."""
+        S = len(self.members)
+        P = np.zeros((max(S, 1), 9))
+        U = np.zeros((max(S, 1), 3))
+        info = np.zeros((max(S, 1), 4), dtype=np.int64)
+        self._check(load().rbsog_batch_step(self._h, None, None, None, None, None, None, None, None, _pd(P),
+                                            _pd(U) if energy else None, _pi64(info)), "rbsog_batch_step")
+        return P[:S].reshape(S, 3, 3), U[:S], info[:S]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rbsog_batch_destroy(self._h)
+            self._h = None
+            self.members = []
 
     def __del__(self):
         try:

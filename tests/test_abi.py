@@ -48,7 +48,7 @@ def test_params_struct_layout_matches_header(lib):
     assert offs["b"] == 0 and offs["sigma"] == 8 and offs["omega"] == 16 and offs["M"] == 24
     assert offs["rc"] == 32 and offs["P"] == 40 and offs["seed"] == 48 and offs["system_id"] == 56
     assert offs["coulomb_k"] == 64 and offs["precision"] == 72 and offs["recalibration"] == 76
-    assert offs["flags"] == 80
+    assert offs["flags"] == 80 and offs["M_energy"] == 84
     assert C.sizeof(rbsog.rbsog_params) == 104
 
 
@@ -97,12 +97,27 @@ def test_setup_rejects_bad_input_before_touching_the_device(lib):
     assert _setup(lib, q, box, P=513, recalibration=3)[0] == -1     # independent chain: 2P + 1 mode slots
     assert _setup(lib, q, box, system_id=1 << 33)[0] == -1
     assert _setup(lib, np.array([1.0, np.inf]), box)[0] == -1
+    assert _setup(lib, q, box, M_energy=5)[0] == -1                # fewer energy terms than M
+    assert _setup(lib, q, box, M_energy=65)[0] == -1
+    assert _setup(lib, q, box, flags=2 | 4)[0] == -1               # full and half shell together
+    assert _setup(lib, q, box, flags=8)[0] == -1                   # unknown flag
     # zero atoms
     from paper_2602_23582_amd import rbsog
     p = rbsog.default_params(10.0)
     h = C.c_void_p()
     assert lib.rbsog_setup(C.byref(p), 0, None, rbsog._pd(box), None, C.byref(h)) == -1
     assert lib.rbsog_setup(C.byref(p), 4, rbsog._pd(q), rbsog._pd(box), None, None) == -1
+
+
+def test_batch_of_contexts_rejects_bad_arguments_before_any_device_call(lib):
+    h = C.c_void_p()
+    assert lib.rbsog_batch_create(0, None, C.byref(h)) == -1        # no budget
+    assert lib.rbsog_batch_create(-5, None, C.byref(h)) == -1
+    assert lib.rbsog_batch_create(1 << 20, None, None) == -1
+    assert lib.rbsog_batch_admit(None, None) == -1
+    assert lib.rbsog_batch_release(None, None) == -1
+    assert lib.rbsog_stage(None, 0, None, None, None, None, None, None, None) == -1
+    assert lib.rbsog_debug_long_range_force(None, None, None, None) == -1
 
 
 def test_null_context_calls_are_rejected(lib):
