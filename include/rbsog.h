@@ -212,6 +212,28 @@ int rbsog_force_virial(rbsog_ctx *ctx, const double *x, const double *y, const d
 int rbsog_pressure(rbsog_ctx *ctx, double host_P[9], double host_parts[27]);
 
 /*
+ * rbsog_force_virial for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, same kernels and bitwise the same results as
+ * rbsog_force_virial; x, y, z and fx, fy, fz must be device arrays.  The
+ * step's partial results (structure-factor partials per block and mode, pair
+ * sums per pair block) go to a fixed 32 MiB device array of the library, one
+ * per GPU, held until the process ends; everything else is the context's.
+ * The call allocates nothing, so what rbsog_force_virial would allocate must
+ * exist already: after rbsog_setup, and after a box change that grows the
+ * cell grid, run rbsog_force_virial once.  Returns RBSOG_ESTATE when the
+ * grid, the half-shell buffers or the launch plans would have to grow, and
+ * RBSOG_EINVAL (message naming the scratch) when the partials exceed 32 MiB:
+ * 16 B per mode and structure-factor block (a block per 1,024 atoms) plus
+ * 64 B per pair block.  Calls on one GPU share the array: calls that overlap
+ * on one GPU (other streams, other threads, other contexts) race, so a
+ * caller serialises them.
+ */
+int rbsog_force_virial_noalloc(rbsog_ctx *ctx, const double *x, const double *y, const double *z,
+                               double *fx, double *fy, double *fz, double host_energy[3],
+                               double host_vir[6]);
+
+/*
  * Isotropic or anisotropic box rescale in FP64 on the device (NPT update of
  * Algorithm 1 step 7 for a diagonal h): r <- mu r for the n positions (device
  * arrays) and host_box <- mu host_box.  Fractional coordinates, hence the

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbsog.so")
 PROBE_LIB = os.path.join(HERE, "libvaluprobe.so")
-SOURCES = ["kernels.hip", "setup.cpp", "system.cpp", "api.cpp", "batch_api.cpp", "server.cpp", "npt.cpp"]
+SOURCES = ["kernels.hip", "setup.cpp", "system.cpp", "api.cpp", "batch_api.cpp", "server.cpp", "npt.cpp", "noalloc.cpp"]
 ARCH = os.environ.get("RBSOG_OFFLOAD_ARCH", "gfx950")
 
 

@@ -43,7 +43,7 @@ EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_forc
            "rbsog_batch_last_error", "rbsog_server_create", "rbsog_server_submit", "rbsog_server_wait",
            "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_set_energy", "rbsog_server_last_error",
            "rbsog_npt_init", "rbsog_npt_run", "rbsog_batch_create", "rbsog_batch_admit", "rbsog_stage",
-           "rbsog_batch_release", "rbsog_debug_long_range_force"]
+           "rbsog_batch_release", "rbsog_debug_long_range_force", "rbsog_force_virial_noalloc"]
 
 COUPLE_ANISO = 0
 COUPLE_SEMI = 1
@@ -122,6 +122,7 @@ def load(path: str | None = None):
         "rbsog_stage": (C.c_int, [vp, i64, pd, vp, vp, vp, vp, vp, vp]),
         "rbsog_batch_release": (C.c_int, [vp, vp]),
         "rbsog_debug_long_range_force": (C.c_int, [vp, vp, vp, vp]),
+        "rbsog_force_virial_noalloc": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, pd, pd]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -242,6 +243,17 @@ class Context:
         px = _ptrs((x, y, z, fx, fy, fz), self.n, self.device)
         self._check(load().rbsog_force_virial(self._h, *px, _pd(e) if energy else None, _pd(v) if energy else None),
                     "rbsog_force_virial")
+        return (e, v) if energy else (None, None)
+
+    def force_virial_noalloc(self, x, y, z, fx, fy, fz, energy=True):
+        """rbsog_force_virial_noalloc: force_virial with the step's partial
+        results in the library's fixed per-GPU array; device arrays only."""
+        e = np.zeros(3)
+        v = np.zeros(6)
+        px = _ptrs((x, y, z, fx, fy, fz), self.n, self.device)
+        self._check(load().rbsog_force_virial_noalloc(self._h, *px, _pd(e) if energy else None,
+                                                      _pd(v) if energy else None),
+                    "rbsog_force_virial_noalloc")
         return (e, v) if energy else (None, None)
 
     def pressure(self):
