@@ -307,7 +307,7 @@ SAMPLERS = {0: "recalibrated (as printed)", 1: "recalibrated (exchange form)", 2
 def variance_study(torch, reps, Ps=(50, 100, 200), sizes=(2000, 16000)):
     """Variance of the long-range pressure estimator P^{F,r*} + P^{F,nr*}
     under the four samplers of the non-radial modes (Sec. 3.2), against P and
-    N: seeded ionic systems at 0.1 A^-3 (rc 10 A).  For each sampler, P and
+    N: seeded disordered ionic systems at 0.1 A^-3 (rc 10 A).  For each sampler, P and
     system size, reps steps (the step index draws the modes) give the variance
     of every tensor component about its mean; reported as the mean over the
     diagonal and over the off-diagonal components, with the mean number of
@@ -320,7 +320,7 @@ def variance_study(torch, reps, Ps=(50, 100, 200), sizes=(2000, 16000)):
     ref_path = os.path.join(ROOT, "tests", "golden", "variance_reference.json")
     ref = json.load(open(ref_path))["systems"] if os.path.exists(ref_path) else {}
     for n in sizes:
-        d = W.ionic_system(n, seed=11, P=100)
+        d = W.ionic_melt(n, seed=11)
         x, y, z = (torch.tensor(np.ascontiguousarray(d["pos"][:, k]), dtype=torch.float64, device="cuda")
                    for k in range(3))
         fx, fy, fz = (torch.empty_like(x) for _ in range(3))
@@ -349,14 +349,14 @@ def variance_study(torch, reps, Ps=(50, 100, 200), sizes=(2000, 16000)):
                     # z-score, and the mean squared error per step var + bias^2
                     PF = np.asarray(ref[str(n)]["PF"])
                     bias = a.mean(0) - PF
-                    z = bias / np.sqrt(v / len(a))
+                    zsc = bias / np.sqrt(v / len(a))
                     mse = v + bias ** 2
                     row.update({"bias_diag": bias[[0, 4, 8]].tolist(), "bias_offdiag": bias[[1, 2, 5]].tolist(),
                                 "bias_rel_norm": float(np.linalg.norm(bias) / np.linalg.norm(PF)),
-                                "bias_max_abs_z": float(np.abs(z).max()),
+                                "bias_max_abs_z": float(np.abs(zsc).max()),
                                 "mse_diag": float(mse[[0, 4, 8]].mean()), "mse_offdiag": float(mse[[1, 2, 5]].mean())})
                 rows.append(row)
-    return {"system": "ionic, 0.1 A^-3, rc 10 A, +-1e on a jittered lattice", "reps": reps, "rows": rows,
+    return {"system": "ionic, 0.1 A^-3, rc 10 A, +-1e at uniform random positions", "reps": reps, "rows": rows,
             "reference": "P^F by the full k-space sum, tests/golden/variance_reference.json"}
 
 

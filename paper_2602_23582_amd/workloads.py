@@ -247,6 +247,22 @@ def ionic_system(n: int, seed: int, density: float = 0.1, jitter: float = 0.1, r
     return dict(name=f"ionic-{n}", q=q, pos=_wrap(sites, L), L=L, rc=min(rc_max, 0.5 * L1), P=P)
 
 
+def ionic_melt(n: int, seed: int, density: float = 0.1, rc_max: float = 10.0, P: int = 100):
+    """n (even) charges +-1e at independent uniform positions in a cubic box
+    at number density 0.1 A^-3, cutoff min(10 A, L/2): a disordered ionic
+    system without the lattice's Bragg peaks.  (On the jittered lattices of
+    ionic_system with an even number of sites per side the alternating
+    charges form layers, and |rho(k)|^2 ~ n^2 at the layers' wave vector, far
+    in the tail of the radial proposal.)"""
+    rng = _rng(seed)
+    n = 2 * (n // 2)
+    L1 = (n / density) ** (1.0 / 3.0)
+    L = np.full(3, L1)
+    pos = rng.uniform(0.0, 1.0, (n, 3)) * L
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    return dict(name=f"melt-{n}", q=q, pos=_wrap(pos, L), L=L, rc=min(rc_max, 0.5 * L1), P=P)
+
+
 def served_stream(n_systems: int = 4096, seed: int = 5, n_min: int = 500, n_max: int = 50_000):
     """Sizes, seeds and batch sizes of the served stream: sizes log-uniform in
     [500, 50,000] (rounded down to even), one seed per system."""

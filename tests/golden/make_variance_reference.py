@@ -1,7 +1,7 @@
 """Write variance_reference.json: the deterministic long-range SOG pressure
 P^F (Theorem 1: the full k-space sum over every mode, M = 10, Table 1 row 2
-scaled to the cutoff) of the seeded ionic systems of the benchmark's
-estimator study, so that the benchmark can report each sampler's bias and
+scaled to the cutoff) of the seeded disordered ionic systems of the
+benchmark's estimator study, so that the benchmark can report each sampler's bias and
 mean squared error against it.  Calls the oracle only.
 
 usage: python tests/golden/make_variance_reference.py
@@ -21,11 +21,11 @@ SIZES = (2000, 16000)
 
 
 def main():
-    out = {"note": "P^F of W.ionic_system(n, seed=11, P=100) by the oracle's full k-space SOG sum "
+    out = {"note": "P^F of W.ionic_melt(n, seed=11) by the oracle's full k-space SOG sum "
                    "(sog_kspace_full), Table 1 row 2 at M = 10, Gaussian units; row-major 3x3",
            "systems": {}}
     for n in SIZES:
-        d = W.ionic_system(n, seed=11, P=100)
+        d = W.ionic_melt(n, seed=11)
         p = orc.sog(d["rc"], row=2, M=10)
         _, PF, UF = orc.sog_kspace_full(d["q"], d["pos"], d["L"], p, forces=False)
         out["systems"][str(n)] = {"L": d["L"].tolist(), "rc": d["rc"], "PF": PF.ravel().tolist(), "UF": UF}
