@@ -77,6 +77,27 @@ def lib():
             "orc_ewald": (None, [i64, pd, pd, pd, pd, pd, d, d, d, pd, pd, pd, pd, pd]),
             "orc_num_threads": (C.c_int, []),
             "orc_set_num_threads": (None, [C.c_int]),
+            "orc_tri_H_direct": (None, [pd, d, d, pd, pd]),
+            "orc_tri_H_poisson": (None, [pd, d, d, pd, pd]),
+            "orc_tri_norm_consts": (None, [pd, C.c_int, pd, pd, C.c_int, pd, pd]),
+            "orc_tri_target_r": (d, [pi32, pd, C.c_int, pd, pd]),
+            "orc_tri_ratio_nr": (d, [pi32, pd, C.c_int, pd, pd]),
+            "orc_tri_proposal_pmf": (d, [pi32, pd, d]),
+            "orc_tri_round": (None, [pd, pd, d, pi32]),
+            "orc_tri_start_bound": (d, [pd, C.c_int, pd, pd, C.c_int]),
+            "orc_tri_start_states": (C.c_int, [pd, C.c_int, pd, pd, u64, u64, u64, pi32, pi32]),
+            "orc_tri_sample_modes": (C.c_int, [pd, C.c_int, pd, pd, C.c_int, u64, u64, u64, C.c_int,
+                                               pi32, pi32, pi64]),
+            "orc_tri_chains": (None, [pd, C.c_int, pd, pd, C.c_int, u64, u64, u64, C.c_int, pi32, pi32,
+                                      pi32, pi32, pi64]),
+            "orc_tri_rho": (None, [i64, pd, pd, pd, pd, pd, i64, pi32, pd, pd]),
+            "orc_tri_long_range_rb": (None, [i64, pd, pd, pd, pd, pd, C.c_int, pi32, pi32, d, d,
+                                             pd, pd, pd, pd, pd, pd]),
+            "orc_tri_short_range": (None, [i64, pd, pd, pd, pd, pd, d, C.c_int, pd, pd, pd,
+                                           pd, pd, pd, pd, pd]),
+            "orc_tri_sog_kspace_full": (None, [i64, pd, pd, pd, pd, pd, C.c_int, pd, pd, pd,
+                                               pd, pd, pd, pd, pd]),
+            "orc_tri_ewald": (None, [i64, pd, pd, pd, pd, pd, d, d, d, pd, pd, pd, pd, pd]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -505,3 +526,143 @@ def npt_run(q, pos, mom, mass, L, pbox, prm, p: SOG, P, seed, system_id, first_s
         npt_kick_box(ph, L, Pi, groups, prm["p_ext"], kT, tau)
     pbox_out = np.array([ph[next(k for k, g in enumerate(groups) if d in g)] for d in range(3)])
     return pos, mom, L, pbox_out, Pi, Pk
+
+
+# ---------------------------------------------------------------------------
+# General (triclinic) cells: h = [h_1, h_2, h_3] (columns are the cell
+# vectors), r = h s (Sec. 2.1), k = 2 pi h^-T m.  h is a 3 x 3 array.
+# ---------------------------------------------------------------------------
+
+def _h(h):
+    h = np.ascontiguousarray(h, dtype=np.float64).reshape(3, 3)
+    return h
+
+
+def tri_H(h, wt, s, form):
+    """(H^r_l, H^nr_l) of one Gaussian: form 1 direct sums (eqs. Sr, Snr), 2 Poisson forms (Prop. 1)."""
+    hr = C.c_double(); hnr = C.c_double()
+    f = lib().orc_tri_H_direct if form == 1 else lib().orc_tri_H_poisson
+    f(_pd(_h(h)), float(wt), float(s), C.byref(hr), C.byref(hnr))
+    return hr.value, hnr.value
+
+
+def tri_norm_consts(h, p: SOG, form: int = 0):
+    sr = C.c_double(); snr = C.c_double()
+    lib().orc_tri_norm_consts(_pd(_h(h)), p.M, _pd(p.wt), _pd(p.s), form, C.byref(sr), C.byref(snr))
+    return sr.value, snr.value
+
+
+def tri_target_r(m, h, p: SOG):
+    return lib().orc_tri_target_r(_pi32(np.ascontiguousarray(m, dtype=np.int32)), _pd(_h(h)), p.M, _pd(p.wt), _pd(p.s))
+
+
+def tri_ratio_nr(m, h, p: SOG):
+    return lib().orc_tri_ratio_nr(_pi32(np.ascontiguousarray(m, dtype=np.int32)), _pd(_h(h)), p.M, _pd(p.wt), _pd(p.s))
+
+
+def tri_proposal_pmf(m, h, s0):
+    """q(m) of eq. proposal for a general cell (Gauss-Legendre over the unit cube)."""
+    return lib().orc_tri_proposal_pmf(_pi32(np.ascontiguousarray(m, dtype=np.int32)), _pd(_h(h)), float(s0))
+
+
+def tri_round(z, h, s0):
+    """round(h^T u) for u = z / (sqrt2 pi s0)."""
+    m = np.zeros(3, dtype=np.int32)
+    lib().orc_tri_round(_pd(_f64(z)), _pd(_h(h)), float(s0), _pi32(m))
+    return m
+
+
+def tri_start_bound(h, p: SOG, power):
+    return lib().orc_tri_start_bound(_pd(_h(h)), p.M, _pd(p.wt), _pd(p.s), power)
+
+
+def tri_start_states(h, p: SOG, seed, system_id, step):
+    a = np.zeros(3, dtype=np.int32); b = np.zeros(3, dtype=np.int32)
+    rc = lib().orc_tri_start_states(_pd(_h(h)), p.M, _pd(p.wt), _pd(p.s), seed, system_id, step, _pi32(a), _pi32(b))
+    if rc != 0:
+        raise RuntimeError("oracle sampler: no start draw accepted")
+    return a, b
+
+
+def tri_sample_modes(h, p: SOG, P, seed, system_id, step, variant=RECAL_EXCHANGE):
+    m_r = np.zeros((P, 3), dtype=np.int32)
+    m_nr = np.zeros((P, 3), dtype=np.int32)
+    acc = np.zeros(2, dtype=np.int64)
+    rc = lib().orc_tri_sample_modes(_pd(_h(h)), p.M, _pd(p.wt), _pd(p.s), P, seed, system_id, step, variant,
+                                    _pi32(m_r), _pi32(m_nr), _pi64(acc))
+    if rc != 0:
+        raise RuntimeError("oracle sampler: no start draw accepted")
+    return m_r, m_nr, acc
+
+
+def tri_chains(h, p: SOG, P, seed, system_id, step, variant, start_r, start_nr):
+    """The chains of one step on a general cell from given start states."""
+    m_r = np.zeros((P, 3), dtype=np.int32)
+    m_nr = np.zeros((P, 3), dtype=np.int32)
+    acc = np.zeros(2, dtype=np.int64)
+    lib().orc_tri_chains(_pd(_h(h)), p.M, _pd(p.wt), _pd(p.s), P, seed, system_id, step, variant,
+                         _pi32(np.ascontiguousarray(start_r, dtype=np.int32)),
+                         _pi32(np.ascontiguousarray(start_nr, dtype=np.int32)), _pi32(m_r), _pi32(m_nr), _pi64(acc))
+    return m_r, m_nr, acc
+
+
+def tri_rho(q, pos, h, modes):
+    q = _f64(q); x, y, z = _xyz(pos)
+    m = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, 3)
+    re = np.zeros(m.shape[0]); im = np.zeros(m.shape[0])
+    lib().orc_tri_rho(q.shape[0], _pd(q), _pd(x), _pd(y), _pd(z), _pd(_h(h)), m.shape[0], _pi32(m), _pd(re), _pd(im))
+    return re + 1j * im
+
+
+def tri_long_range_rb(q, pos, h, m_r, m_nr, Sr, Snr, forces=True):
+    q = _f64(q); x, y, z = _xyz(pos); n = q.shape[0]
+    m_r = np.ascontiguousarray(m_r, dtype=np.int32); m_nr = np.ascontiguousarray(m_nr, dtype=np.int32)
+    f = [np.zeros(n) for _ in range(3)] if forces else [None, None, None]
+    Pr = np.zeros(9); Pnr = np.zeros(9); UF = C.c_double()
+    lib().orc_tri_long_range_rb(n, _pd(q), _pd(x), _pd(y), _pd(z), _pd(_h(h)), m_r.shape[0], _pi32(m_r), _pi32(m_nr),
+                                Sr, Snr, *map(_pd, f), _pd(Pr), _pd(Pnr), C.byref(UF))
+    return (np.stack(f, axis=1) if forces else None), Pr.reshape(3, 3), Pnr.reshape(3, 3), UF.value
+
+
+def tri_short_range(q, pos, h, p: SOG):
+    """Short-range force (n x 3), virial sum (6) and U^N over every image inside rc."""
+    q = _f64(q); x, y, z = _xyz(pos); n = q.shape[0]
+    vir = np.zeros(6); U = C.c_double()
+    f = [np.zeros(n) for _ in range(3)]
+    lib().orc_tri_short_range(n, _pd(q), _pd(x), _pd(y), _pd(z), _pd(_h(h)), p.rc, p.M, _pd(p.w), _pd(p.wt), _pd(p.s),
+                              *map(_pd, f), _pd(vir), C.byref(U))
+    return np.stack(f, axis=1), vir, U.value
+
+
+def tri_sog_kspace_full(q, pos, h, p: SOG, forces=True):
+    q = _f64(q); x, y, z = _xyz(pos); n = q.shape[0]
+    f = [np.zeros(n) for _ in range(3)] if forces else [None, None, None]
+    Pf = np.zeros(9); UF = C.c_double()
+    lib().orc_tri_sog_kspace_full(n, _pd(q), _pd(x), _pd(y), _pd(z), _pd(_h(h)), p.M, _pd(p.w), _pd(p.wt), _pd(p.s),
+                                  *map(_pd, f), _pd(Pf), C.byref(UF))
+    return (np.stack(f, axis=1) if forces else None), Pf.reshape(3, 3), UF.value
+
+
+def tri_ewald(q, pos, h, beta, rcut, kcut, forces=True):
+    q = _f64(q); x, y, z = _xyz(pos); n = q.shape[0]
+    f = [np.zeros(n) for _ in range(3)] if forces else [None, None, None]
+    Pt = np.zeros(9); U = C.c_double()
+    lib().orc_tri_ewald(n, _pd(q), _pd(x), _pd(y), _pd(z), _pd(_h(h)), beta, rcut, kcut, *map(_pd, f), _pd(Pt),
+                        C.byref(U))
+    return (np.stack(f, axis=1) if forces else None), Pt.reshape(3, 3), U.value
+
+
+def tri_rbsog_step(q, pos, h, p: SOG, P, seed, system_id, step, variant=RECAL_EXCHANGE, modes=None):
+    """One evaluation of Algorithm 1 steps 2-6 on a general cell (as rbsog_step)."""
+    h = _h(h); V = abs(float(np.linalg.det(h)))
+    if modes is None:
+        m_r, m_nr, acc = tri_sample_modes(h, p, P, seed, system_id, step, variant)
+    else:
+        (m_r, m_nr), acc = modes, None
+    Sr, Snr = tri_norm_consts(h, p)
+    FN, vir, UN = tri_short_range(q, pos, h, p)
+    FF, Pr, Pnr, UF = tri_long_range_rb(q, pos, h, m_r, m_nr, Sr, Snr, forces=True)
+    US = self_energy(p, q)
+    PN = vir_to_tensor(vir) / V
+    return dict(F=FN + FF, FN=FN, FF=FF, UN=UN, UF=UF, Uself=US, U=UN + UF - US, PN=PN, Pr=Pr, Pnr=Pnr,
+                P=PN + Pr + Pnr, vir=vir, Sr=Sr, Snr=Snr, m_r=m_r, m_nr=m_nr, acc=acc)

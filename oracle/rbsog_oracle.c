@@ -10,7 +10,8 @@
  * is written out again from the paper, in plain double-precision loops, with
  * no blocking, fusion or reordering beyond what the formula itself states.
  *
- * Orthorhombic cells only: h = diag(Lx, Ly, Lz).  Gaussian units (prefactor 1).
+ * Orthorhombic cells h = diag(Lx, Ly, Lz) throughout, and general (triclinic)
+ * cells in the orc_tri_* functions at the end.  Gaussian units (prefactor 1).
  *
  * Parity status per function is given in its comment; "parity unpinned" marks
  * a function that no test pins to anything but itself.
@@ -1067,6 +1068,755 @@ void orc_ewald(int64_t n, const double *q, const double *x, const double *y, con
             for (int64_t p = 0; p < cnt; ++p) {
                 double k[3];
                 for (int d = 0; d < 3; ++d) k[d] = 2.0 * ORC_PI * mm[3 * p + d] / L[d];
+                const double th = k[0] * x[i] + k[1] * y[i] + k[2] * z[i];
+                const double imv = rim[p] * cos(th) - rre[p] * sin(th);
+                for (int d = 0; d < 3; ++d) f[d] -= q[i] / V * k[d] * G[p] * imv;
+            }
+            fx[i] = f[0]; fy[i] = f[1]; fz[i] = f[2];
+        }
+    }
+    free(acc); free(mm); free(rre); free(rim); free(G);
+}
+
+/* ------------------------------------------------------------------------- */
+/* General (triclinic) cells: h = [h_1, h_2, h_3], r = h s (Sec. 2.1)          */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * The cell tensor h is passed row-major, h[3 i + j] = (h)_ij: column j is the
+ * cell vector h_j.  Positions are Cartesian, r = h s with s the fractional
+ * coordinates.  Reciprocal vectors are k = 2 pi h^-T m (eq. FourierTransform),
+ * so k . r = 2 pi m . s (eq. rho_k).  The short-range sums need r_c no larger
+ * than half the smallest perpendicular width of the cell only where a
+ * function says so; the brute-force sums below take every image inside r_c.
+ */
+
+/* inverse and determinant of h by cofactors */
+static double tri_inverse(const double h[9], double hi[9])
+{
+    const double a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], k = h[7], l = h[8];
+    const double A = e * l - f * k, B = -(d * l - f * g), C = d * k - e * g;
+    const double det = a * A + b * B + c * C;
+    hi[0] = A / det;
+    hi[3] = B / det;
+    hi[6] = C / det;
+    hi[1] = -(b * l - c * k) / det;
+    hi[4] = (a * l - c * g) / det;
+    hi[7] = -(a * k - b * g) / det;
+    hi[2] = (b * f - c * e) / det;
+    hi[5] = -(a * f - c * d) / det;
+    hi[8] = (a * e - b * d) / det;
+    return det;
+}
+
+/* k = 2 pi h^-T m: k_i = 2 pi sum_j (h^-1)_ji m_j */
+static void tri_k(const int32_t m[3], const double hi[9], double k[3])
+{
+    for (int i = 0; i < 3; ++i) k[i] = 2.0 * ORC_PI * (hi[i] * m[0] + hi[3 + i] * m[1] + hi[6 + i] * m[2]);
+}
+
+static double tri_k2(const int32_t m[3], const double hi[9])
+{
+    double k[3];
+    tri_k(m, hi, k);
+    return k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+}
+
+/* perpendicular widths w_i = 1 / |row i of h^-1| (distance between the faces s_i = 0 and 1) */
+static void tri_widths(const double hi[9], double w[3])
+{
+    for (int i = 0; i < 3; ++i)
+        w[i] = 1.0 / sqrt(hi[3 * i] * hi[3 * i] + hi[3 * i + 1] * hi[3 * i + 1] + hi[3 * i + 2] * hi[3 * i + 2]);
+}
+
+/* length of the cell vector h_j (column j) */
+static double tri_col_len(const double h[9], int j)
+{
+    return sqrt(h[j] * h[j] + h[3 + j] * h[3 + j] + h[6 + j] * h[6 + j]);
+}
+
+/*
+ * H^r_l and H^nr_l by the direct sums of eqs. Sr and Snr over m with
+ * s^2 |k|^2 / 4 <= ORC_TRUNC.  Since m_j = h_j . k / (2 pi), the box
+ * |m_j| <= |h_j| kmax / (2 pi) + 1 holds every such m.
+ * Pinned by: the Poisson forms (Prop. 1), h = diag(L) against orc_H_direct,
+ * invariance under h -> h U for unimodular U.
+ */
+void orc_tri_H_direct(const double h[9], double wt, double s, double *Hr, double *Hnr)
+{
+    double hi[9];
+    tri_inverse(h, hi);
+    const double kmax = sqrt(4.0 * ORC_TRUNC) / s;
+    int mmax[3];
+    for (int j = 0; j < 3; ++j) mmax[j] = (int)ceil(tri_col_len(h, j) * kmax / (2.0 * ORC_PI)) + 1;
+    const double pre = pow(ORC_PI, 1.5) * wt;
+    double ar = 0.0, anr = 0.0;
+    for (int a = -mmax[0]; a <= mmax[0]; ++a)
+        for (int b = -mmax[1]; b <= mmax[1]; ++b)
+            for (int c = -mmax[2]; c <= mmax[2]; ++c) {
+                const int32_t m[3] = {a, b, c};
+                const double k2 = tri_k2(m, hi);
+                const double e = exp(-s * s * k2 / 4.0);
+                ar += pow(s, 5) * k2 * e;
+                anr += pow(s, 7) * k2 * k2 * e;
+            }
+    *Hr = pre * ar;
+    *Hnr = pre * anr;
+}
+
+/*
+ * Prop. 1 for a general cell: A_j = sum_n |h n|^j exp(-|h n|^2 / s^2) over n
+ * with |h n|^2 / s^2 <= ORC_TRUNC; n_i = (h^-1 (h n))_i, so |n_i| <= |h n| / w_i.
+ * Pinned by: the direct sums.
+ */
+void orc_tri_H_poisson(const double h[9], double wt, double s, double *Hr, double *Hnr)
+{
+    double hi[9], w[3];
+    const double V = fabs(tri_inverse(h, hi));
+    tri_widths(hi, w);
+    const double rmax = s * sqrt(ORC_TRUNC);
+    int nmax[3];
+    for (int i = 0; i < 3; ++i) nmax[i] = (int)ceil(rmax / w[i]) + 1;
+    double A0 = 0.0, A2 = 0.0, A4 = 0.0;
+    for (int a = -nmax[0]; a <= nmax[0]; ++a)
+        for (int b = -nmax[1]; b <= nmax[1]; ++b)
+            for (int c = -nmax[2]; c <= nmax[2]; ++c) {
+                double r[3];
+                for (int i = 0; i < 3; ++i) r[i] = h[3 * i] * a + h[3 * i + 1] * b + h[3 * i + 2] * c;
+                const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                const double e = exp(-r2 / (s * s));
+                A0 += e;
+                A2 += r2 * e;
+                A4 += r2 * r2 * e;
+            }
+    *Hr = V * wt * (6.0 * A0 - 4.0 * A2 / (s * s));
+    *Hnr = V * wt * (60.0 * A0 - 80.0 * A2 / (s * s) + 16.0 * A4 / (s * s * s * s));
+}
+
+/* S^r, S^nr (eqs. Sr, Snr): Poisson form when s_l < the smallest width, form as in orc_norm_consts */
+void orc_tri_norm_consts(const double h[9], int M, const double *wt, const double *s, int form, double *Sr,
+                         double *Snr)
+{
+    double hi[9], w[3];
+    tri_inverse(h, hi);
+    tri_widths(hi, w);
+    const double wmin = fmin(w[0], fmin(w[1], w[2]));
+    double sr = 0.0, snr = 0.0;
+    for (int l = 0; l < M; ++l) {
+        double hr, hnr;
+        const int poisson = (form == 2) || (form == 0 && s[l] < wmin);
+        if (poisson) orc_tri_H_poisson(h, wt[l], s[l], &hr, &hnr);
+        else orc_tri_H_direct(h, wt[l], s[l], &hr, &hnr);
+        sr += hr;
+        snr += hnr;
+    }
+    *Sr = sr;
+    *Snr = snr;
+}
+
+/* unnormalised radial target (eq. samplingP) and the ratio P^nr/P^r up to S^r/S^nr, general k */
+double orc_tri_target_r(const int32_t m[3], const double h[9], int M, const double *wt, const double *s)
+{
+    double hi[9];
+    tri_inverse(h, hi);
+    const double k2 = tri_k2(m, hi);
+    double acc = 0.0;
+    for (int l = 0; l < M; ++l) acc += wt[l] * pow(s[l], 5) * exp(-s[l] * s[l] * k2 / 4.0);
+    return k2 * acc;
+}
+
+double orc_tri_ratio_nr(const int32_t m[3], const double h[9], int M, const double *wt, const double *s)
+{
+    double hi[9];
+    tri_inverse(h, hi);
+    const double k2 = tri_k2(m, hi);
+    double a7 = 0.0, a5 = 0.0;
+    for (int l = 0; l < M; ++l) {
+        const double e = exp(-s[l] * s[l] * k2 / 4.0);
+        a7 += wt[l] * pow(s[l], 7) * e;
+        a5 += wt[l] * pow(s[l], 5) * e;
+    }
+    return k2 * a7 / a5;
+}
+
+/*
+ * Gauss-Legendre rule of ORC_GL points on [-1/2, 1/2]: nodes are the roots of
+ * P_n found by Newton's method from the Chebyshev guesses, weights
+ * 1 / ((1 - x^2) P_n'(x)^2), halved for the unit interval.
+ */
+#define ORC_GL 24
+static double orc_gl_x[ORC_GL], orc_gl_w[ORC_GL];
+static int orc_gl_ready = 0;
+static void orc_gl_init(void)
+{
+    if (orc_gl_ready) return;
+    const int n = ORC_GL;
+    for (int i = 0; i < n; ++i) {
+        double x = cos(ORC_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        orc_gl_x[i] = 0.5 * x;
+        orc_gl_w[i] = 0.5 * 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    orc_gl_ready = 1;
+}
+
+/*
+ * Proposal pmf of eq. proposal for a general cell: with C = (h^T h)^-1 =
+ * h^-1 h^-T,
+ *   q(m) = (sqrt(pi) s0)^3 / det h  int_{m + [-1/2,1/2]^3} exp(-pi^2 s0^2 g^T C g) dg,
+ * the probability that round(h^T u) = m for u ~ N(0, I / (2 pi^2 s0^2)).
+ * The integral has no closed form; it is taken by the tensor Gauss-Legendre
+ * rule of ORC_GL^3 points with the factor exp(-pi^2 s0^2 m^T C m) outside.
+ * Pinned by: the erf product of orc_proposal_pmf at h = diag(L), the
+ * normalisation over the lattice, and chi^2 of rounded draws on a sheared cell.
+ */
+/*
+ * exp(-a (lin + dCd)) = exp(-a dCd) prod_i exp(-2 a (Cm)_i d_i): the first
+ * factor, times the three weights, depends on the cell and s0 only, and is
+ * tabulated once per (h, s0) (two tables kept: the chains alternate between
+ * the proposal and its widened form).  Not thread-safe.
+ */
+struct orc_gl_table {
+    double h[9], s0, V, C[9];
+    int used;
+    double t[ORC_GL * ORC_GL * ORC_GL];
+};
+static struct orc_gl_table orc_gl_tab[2];
+static int orc_gl_next = 0;
+
+static const struct orc_gl_table *orc_gl_lookup(const double h[9], double s0)
+{
+    for (int e = 0; e < 2; ++e)
+        if (orc_gl_tab[e].used && orc_gl_tab[e].s0 == s0 && memcmp(orc_gl_tab[e].h, h, sizeof(double) * 9) == 0)
+            return &orc_gl_tab[e];
+    struct orc_gl_table *T = &orc_gl_tab[orc_gl_next];
+    orc_gl_next ^= 1;
+    double hi[9];
+    T->V = fabs(tri_inverse(h, hi));
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            T->C[3 * i + j] = hi[3 * i] * hi[3 * j] + hi[3 * i + 1] * hi[3 * j + 1] + hi[3 * i + 2] * hi[3 * j + 2];
+    const double a = ORC_PI * ORC_PI * s0 * s0;
+    for (int i = 0; i < ORC_GL; ++i)
+        for (int j = 0; j < ORC_GL; ++j)
+            for (int k = 0; k < ORC_GL; ++k) {
+                const double d[3] = {orc_gl_x[i], orc_gl_x[j], orc_gl_x[k]};
+                double dcd = 0.0;
+                for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q < 3; ++q) dcd += d[p] * T->C[3 * p + q] * d[q];
+                T->t[(i * ORC_GL + j) * ORC_GL + k] = orc_gl_w[i] * orc_gl_w[j] * orc_gl_w[k] * exp(-a * dcd);
+            }
+    memcpy(T->h, h, sizeof(double) * 9);
+    T->s0 = s0;
+    T->used = 1;
+    return T;
+}
+
+double orc_tri_proposal_pmf(const int32_t m[3], const double h[9], double s0)
+{
+    orc_gl_init();
+    const struct orc_gl_table *T = orc_gl_lookup(h, s0);
+    const double a = ORC_PI * ORC_PI * s0 * s0;
+    double cm[3], mm = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        cm[i] = T->C[3 * i] * m[0] + T->C[3 * i + 1] * m[1] + T->C[3 * i + 2] * m[2];
+        mm += m[i] * cm[i];
+    }
+    double e[3][ORC_GL];
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < ORC_GL; ++i) e[d][i] = exp(-2.0 * a * cm[d] * orc_gl_x[i]);
+    double acc = 0.0;
+    for (int i = 0; i < ORC_GL; ++i)
+        for (int j = 0; j < ORC_GL; ++j) {
+            double row = 0.0;
+            for (int k = 0; k < ORC_GL; ++k) row += T->t[(i * ORC_GL + j) * ORC_GL + k] * e[2][k];
+            acc += e[0][i] * e[1][j] * row;
+        }
+    return pow(sqrt(ORC_PI) * s0, 3) / T->V * exp(-a * mm) * acc;
+}
+
+/* m* = round(h^T u), u = z / (sqrt2 pi s0): (h^T u)_i = sum_j h_ji u_j, half away from zero */
+static void tri_round_proposal(const double z[3], const double h[9], double s0, int32_t m[3])
+{
+    const double c = 1.0 / (sqrt(2.0) * ORC_PI * s0);
+    for (int i = 0; i < 3; ++i) {
+        double v = round(c * (h[i] * z[0] + h[3 + i] * z[1] + h[6 + i] * z[2]));
+        if (v > 1073741824.0) v = 1073741824.0;
+        if (v < -1073741824.0) v = -1073741824.0;
+        m[i] = (int32_t)v;
+    }
+}
+
+/* exposed for tests: the rounded proposal of a normal triple */
+void orc_tri_round(const double z[3], const double h[9], double s0, int32_t m[3]) { tri_round_proposal(z, h, s0, m); }
+
+static double tri_weight(const int32_t m[3], const double h[9], int M, const double *wt, const double *s, double s0q)
+{
+    if (m[0] == 0 && m[1] == 0 && m[2] == 0) return 0.0;
+    return orc_tri_target_r(m, h, M, wt, s) / orc_tri_proposal_pmf(m, h, s0q);
+}
+
+static double tri_weight_nr(const int32_t m[3], const double h[9], int M, const double *wt, const double *s)
+{
+    if (m[0] == 0 && m[1] == 0 && m[2] == 0) return 0.0;
+    return orc_tri_target_r(m, h, M, wt, s) * orc_tri_ratio_nr(m, h, M, wt, s) /
+           orc_tri_proposal_pmf(m, h, s[0] * ORC_NR_WIDEN);
+}
+
+/*
+ * Bound B_p >= g_p(m) / q'(m) over the lattice for a general cell (the start
+ * draws' rejection constant; g_p and q' as in orc_start_bound, q' of width
+ * parameter s' = s_0 / sqrt2).  The integrand of q' is at least its minimum
+ * over the unit cube around m, and for g = m + d with |d| <= sqrt3/2,
+ * |h^-T g| <= |k|/(2 pi) + c, c = ||h^-T||_F sqrt3/2 (Frobenius above the
+ * spectral norm), so
+ *   1/q'(m) <= V / (sqrt(pi) s')^3 exp(s'^2 |k|^2/4 + pi s'^2 c |k| + pi^2 s'^2 c^2).
+ * Term l of g_p/q' is then at most K coef_l kappa^p exp(-alpha_l kappa^2 + beta kappa)
+ * with alpha_l = (s_l^2 - s'^2)/4 > 0, beta = pi s'^2 c, K = V/(sqrt(pi) s')^3
+ * exp(pi^2 s'^2 c^2); its maximum over kappa lies at
+ * kappa* = (beta + sqrt(beta^2 + 8 alpha_l p)) / (4 alpha_l).
+ * Pinned by: B_p above every ratio found by enumeration on sheared cells.
+ */
+double orc_tri_start_bound(const double h[9], int M, const double *wt, const double *s, int p)
+{
+    double hi[9];
+    const double V = fabs(tri_inverse(h, hi));
+    double fro = 0.0;
+    for (int i = 0; i < 9; ++i) fro += hi[i] * hi[i];
+    const double c = sqrt(fro) * sqrt(3.0) / 2.0;
+    const double sp = s[0] * ORC_NR_WIDEN;
+    const double K = V / pow(sqrt(ORC_PI) * sp, 3) * exp(ORC_PI * ORC_PI * sp * sp * c * c);
+    const double beta = ORC_PI * sp * sp * c;
+    double B = 0.0;
+    for (int l = 0; l < M; ++l) {
+        const double coef = wt[l] * pow(s[l], p == 2 ? 5 : 7);
+        const double alpha = (s[l] * s[l] - sp * sp) / 4.0;
+        const double ks = (beta + sqrt(beta * beta + 8.0 * alpha * p)) / (4.0 * alpha);
+        B += coef * pow(ks, p) * exp(-alpha * ks * ks + beta * ks);
+    }
+    return K * B;
+}
+
+/* start state by rejection from the widened proposal (as orc_exact_start, general cell) */
+static int tri_exact_start(const double h[9], int M, const double *wt, const double *s, uint64_t seed, uint64_t sys,
+                           uint64_t step, int p, uint32_t sxy, uint32_t sz, int32_t out[3])
+{
+    const double B = orc_tri_start_bound(h, M, wt, s, p);
+    for (uint32_t t = 0; t < ORC_START_TRIES; ++t) {
+        double z[3], u[2];
+        int32_t m[3];
+        orc_draw_proposal(seed, sys, step, t, sxy, sz, z, NULL);
+        tri_round_proposal(z, h, s[0] * ORC_NR_WIDEN, m);
+        orc_draw(seed, sys, step, t, 7u, &u[0], &u[1]);
+        const double w = p == 2 ? tri_weight(m, h, M, wt, s, s[0] * ORC_NR_WIDEN) : tri_weight_nr(m, h, M, wt, s);
+        if ((p == 2 ? u[0] : u[1]) * B < w) {
+            memcpy(out, m, sizeof(int32_t) * 3);
+            return 0;
+        }
+    }
+    return -1;
+}
+
+int orc_tri_start_states(const double h[9], int M, const double *wt, const double *s, uint64_t seed, uint64_t sys,
+                         uint64_t step, int32_t m_r0[3], int32_t m_nr0[3])
+{
+    if (tri_exact_start(h, M, wt, s, seed, sys, step, 2, 3u, 4u, m_r0)) return -1;
+    if (tri_exact_start(h, M, wt, s, seed, sys, step, 4, 8u, 9u, m_nr0)) return -1;
+    return 0;
+}
+
+/*
+ * One sampling step on a general cell: orc_sample_modes with k = 2 pi h^-T m,
+ * the proposal round(h^T u) and its pmf by quadrature; the same draws,
+ * streams and variants (0 as printed, 1 exchange, 2 shared, 3 independent).
+ * Pinned by: equality with orc_sample_modes at h = diag(L), chi^2 of the
+ * start states and batch means on a sheared cell.
+ */
+/* the chains of one step from given start states (start_nr read by variants 1 and 3) */
+void orc_tri_chains(const double h[9], int M, const double *wt, const double *s, int P, uint64_t seed, uint64_t sys,
+                    uint64_t step, int variant, const int32_t start_r[3], const int32_t start_nr[3], int32_t *m_r,
+                    int32_t *m_nr, int64_t n_acc[2])
+{
+    int32_t cur[3] = {start_r[0], start_r[1], start_r[2]};
+    int32_t z0[3] = {start_nr[0], start_nr[1], start_nr[2]};
+    double wcur = tri_weight(cur, h, M, wt, s, s[0]);
+    double *unr = malloc(sizeof(double) * (P > 0 ? P : 1));
+    int64_t acc_r = 0, acc_nr = 0;
+    int32_t znr[3];
+    double wz = 0.0, rz = 0.0;
+    if (variant == 1) {
+        memcpy(znr, z0, sizeof znr);
+        wz = tri_weight(znr, h, M, wt, s, s[0]);
+        rz = orc_tri_ratio_nr(znr, h, M, wt, s);
+    }
+    for (int t = 0; t < P; ++t) {
+        double z[3], uacc[2];
+        int32_t prop[3];
+        orc_draw_proposal(seed, sys, step, (uint32_t)t, 0u, 1u, z, uacc);
+        unr[t] = uacc[1];
+        tri_round_proposal(z, h, s[0], prop);
+        const double wprop = tri_weight(prop, h, M, wt, s, s[0]);
+        if (uacc[0] < wprop / wcur) {
+            memcpy(cur, prop, sizeof cur);
+            wcur = wprop;
+            ++acc_r;
+        }
+        if (variant == 1) {
+            const double rx = orc_tri_ratio_nr(cur, h, M, wt, s);
+            if (uacc[1] < rx / rz) {
+                int32_t tmp[3];
+                memcpy(tmp, cur, sizeof tmp);
+                memcpy(cur, znr, sizeof cur);
+                memcpy(znr, tmp, sizeof znr);
+                const double tw = wcur;
+                wcur = wz;
+                wz = tw;
+                rz = rx;
+                ++acc_nr;
+            }
+            memcpy(&m_nr[3 * t], znr, sizeof znr);
+        }
+        memcpy(&m_r[3 * t], cur, sizeof cur);
+    }
+    if (variant == 0) {
+        int32_t c0[3] = {m_r[0], m_r[1], m_r[2]};
+        double rc = orc_tri_ratio_nr(c0, h, M, wt, s);
+        for (int t = 0; t < P; ++t) {
+            const double rp = orc_tri_ratio_nr(&m_r[3 * t], h, M, wt, s);
+            if (unr[t] < rp / rc) {
+                memcpy(c0, &m_r[3 * t], sizeof c0);
+                rc = rp;
+                ++acc_nr;
+            }
+            memcpy(&m_nr[3 * t], c0, sizeof c0);
+        }
+    }
+    if (variant == 2) memcpy(m_nr, m_r, sizeof(int32_t) * 3 * (size_t)(P > 0 ? P : 0));
+    if (variant == 3) {
+        int32_t zc[3];
+        memcpy(zc, z0, sizeof zc);
+        double wzc = tri_weight_nr(zc, h, M, wt, s);
+        for (int t = 0; t < P; ++t) {
+            double z[3];
+            int32_t prop[3];
+            orc_draw_proposal(seed, sys, step, (uint32_t)t, 5u, 6u, z, NULL);
+            tri_round_proposal(z, h, s[0] * ORC_NR_WIDEN, prop);
+            const double wprop = tri_weight_nr(prop, h, M, wt, s);
+            if (unr[t] < wprop / wzc) {
+                memcpy(zc, prop, sizeof zc);
+                wzc = wprop;
+                ++acc_nr;
+            }
+            memcpy(&m_nr[3 * t], zc, sizeof zc);
+        }
+    }
+    free(unr);
+    if (n_acc) {
+        n_acc[0] = acc_r;
+        n_acc[1] = acc_nr;
+    }
+}
+
+int orc_tri_sample_modes(const double h[9], int M, const double *wt, const double *s, int P, uint64_t seed,
+                         uint64_t sys, uint64_t step, int variant, int32_t *m_r, int32_t *m_nr, int64_t n_acc[2])
+{
+    int32_t cur[3], z0[3] = {0, 0, 0};
+    if (tri_exact_start(h, M, wt, s, seed, sys, step, 2, 3u, 4u, cur)) return -1;
+    if ((variant == 1 || variant == 3) && tri_exact_start(h, M, wt, s, seed, sys, step, 4, 8u, 9u, z0)) return -1;
+    orc_tri_chains(h, M, wt, s, P, seed, sys, step, variant, cur, z0, m_r, m_nr, n_acc);
+    return 0;
+}
+
+/* rho(k) = sum_j q_j exp(i k . r_j), k = 2 pi h^-T m (eq. rho_k) */
+void orc_tri_rho(int64_t n, const double *q, const double *x, const double *y, const double *z, const double h[9],
+                 int64_t nm, const int32_t *m, double *re, double *im)
+{
+    double hi[9];
+    tri_inverse(h, hi);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < nm; ++p) {
+        double k[3];
+        tri_k(&m[3 * p], hi, k);
+        double a = 0.0, b = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double th = k[0] * x[j] + k[1] * y[j] + k[2] * z[j];
+            a += q[j] * cos(th);
+            b += q[j] * sin(th);
+        }
+        re[p] = a;
+        im[p] = b;
+    }
+}
+
+/* the random-batch long-range part of orc_long_range_rb for a general cell (V = det h) */
+void orc_tri_long_range_rb(int64_t n, const double *q, const double *x, const double *y, const double *z,
+                           const double h[9], int P, const int32_t *m_r, const int32_t *m_nr, double Sr, double Snr,
+                           double *fx, double *fy, double *fz, double Pr[9], double Pnr[9], double *UF)
+{
+    double hi[9];
+    const double V = fabs(tri_inverse(h, hi));
+    double *rr = malloc(sizeof(double) * P), *ri = malloc(sizeof(double) * P);
+    double *nr_re = malloc(sizeof(double) * P), *nr_im = malloc(sizeof(double) * P);
+    orc_tri_rho(n, q, x, y, z, h, P, m_r, rr, ri);
+    orc_tri_rho(n, q, x, y, z, h, P, m_nr, nr_re, nr_im);
+    double sum_r = 0.0;
+    for (int p = 0; p < P; ++p) sum_r += (rr[p] * rr[p] + ri[p] * ri[p]) / tri_k2(&m_r[3 * p], hi);
+    for (int a = 0; a < 9; ++a) Pr[a] = 0.0;
+    Pr[0] = Pr[4] = Pr[8] = Sr / (4.0 * V * V * P) * sum_r;
+    double acc[9] = {0};
+    for (int p = 0; p < P; ++p) {
+        double k[3];
+        tri_k(&m_nr[3 * p], hi, k);
+        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        const double a2 = nr_re[p] * nr_re[p] + nr_im[p] * nr_im[p];
+        for (int al = 0; al < 3; ++al)
+            for (int be = 0; be < 3; ++be) acc[3 * al + be] += a2 * k[al] * k[be] / (k2 * k2);
+    }
+    for (int a = 0; a < 9; ++a) Pnr[a] = -Snr / (8.0 * V * V * P) * acc[a];
+    const double S = 0.5 * Sr;
+    *UF = S / (2.0 * V * P) * sum_r;
+    if (fx) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double f[3] = {0, 0, 0};
+            for (int p = 0; p < P; ++p) {
+                double k[3];
+                tri_k(&m_r[3 * p], hi, k);
+                const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                const double th = k[0] * x[i] + k[1] * y[i] + k[2] * z[i];
+                const double imv = ri[p] * cos(th) - rr[p] * sin(th);
+                for (int d = 0; d < 3; ++d) f[d] += k[d] * imv / k2;
+            }
+            fx[i] = -(S / P) * (q[i] / V) * f[0];
+            fy[i] = -(S / P) * (q[i] / V) * f[1];
+            fz[i] = -(S / P) * (q[i] / V) * f[2];
+        }
+    }
+    free(rr); free(ri); free(nr_re); free(nr_im);
+}
+
+/*
+ * Short-range force, virial sum and energy (eqs. force_SOG, P_short,
+ * U_short) over every image r_i - r_j + h n inside r_c (no minimum-image
+ * assumption), O(N^2 x images).  Pinned by: orc_short_range_brute at
+ * h = diag(L), invariance under h -> h U, and the SOG totals against Ewald.
+ */
+void orc_tri_short_range(int64_t n, const double *q, const double *x, const double *y, const double *z,
+                         const double h[9], double rc, int M, const double *w, const double *wt, const double *s,
+                         double *fx, double *fy, double *fz, double vir[6], double *U)
+{
+    double hi[9], wd[3];
+    tri_inverse(h, hi);
+    tri_widths(hi, wd);
+    int nimg[3];
+    for (int i = 0; i < 3; ++i) nimg[i] = (int)ceil(rc / wd[i]) + 1;
+    double *vi = calloc((size_t)n * 7, sizeof(double));
+    const double rc2 = rc * rc;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; ++i) {
+        double f[3] = {0, 0, 0}, v[6] = {0, 0, 0, 0, 0, 0}, u = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            /* the fractional difference wrapped to [-1/2, 1/2), then every image near it */
+            const double dr[3] = {x[i] - x[j], y[i] - y[j], z[i] - z[j]};
+            double ds[3];
+            for (int a = 0; a < 3; ++a) {
+                ds[a] = hi[3 * a] * dr[0] + hi[3 * a + 1] * dr[1] + hi[3 * a + 2] * dr[2];
+                ds[a] -= round(ds[a]);
+            }
+            for (int a = -nimg[0]; a <= nimg[0]; ++a)
+                for (int b = -nimg[1]; b <= nimg[1]; ++b)
+                    for (int c = -nimg[2]; c <= nimg[2]; ++c) {
+                        const double t[3] = {ds[0] + a, ds[1] + b, ds[2] + c};
+                        double d[3];
+                        for (int e = 0; e < 3; ++e) d[e] = h[3 * e] * t[0] + h[3 * e + 1] * t[1] + h[3 * e + 2] * t[2];
+                        orc_pair(q[i], q[j], d, rc2, M, w, wt, s, f, v, &u);
+                    }
+        }
+        fx[i] = f[0]; fy[i] = f[1]; fz[i] = f[2];
+        for (int k = 0; k < 6; ++k) vi[7 * i + k] = v[k];
+        vi[7 * i + 6] = u;
+    }
+    for (int k = 0; k < 6; ++k) vir[k] = 0.0;
+    *U = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < 6; ++k) vir[k] += vi[7 * i + k];
+        *U += vi[7 * i + 6];
+    }
+    free(vi);
+}
+
+/* every m != 0 with s0^2 |k|^2 / 4 <= ORC_TRUNC, k = 2 pi h^-T m; returns the count, *out malloc'd */
+static int64_t tri_modes(const double h[9], const double hi[9], double kmax, int32_t **out)
+{
+    int mmax[3];
+    for (int j = 0; j < 3; ++j) mmax[j] = (int)ceil(tri_col_len(h, j) * kmax / (2.0 * ORC_PI)) + 1;
+    const int64_t nk = (int64_t)(2 * mmax[0] + 1) * (2 * mmax[1] + 1) * (2 * mmax[2] + 1);
+    int32_t *mm = malloc(sizeof(int32_t) * 3 * nk);
+    int64_t cnt = 0;
+    for (int a = -mmax[0]; a <= mmax[0]; ++a)
+        for (int b = -mmax[1]; b <= mmax[1]; ++b)
+            for (int c = -mmax[2]; c <= mmax[2]; ++c) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                const int32_t mv[3] = {a, b, c};
+                if (tri_k2(mv, hi) > kmax * kmax) continue;
+                mm[3 * cnt] = a; mm[3 * cnt + 1] = b; mm[3 * cnt + 2] = c;
+                ++cnt;
+            }
+    *out = mm;
+    return cnt;
+}
+
+/* the full k-space sums of orc_sog_kspace_full (Theorem 1) for a general cell */
+void orc_tri_sog_kspace_full(int64_t n, const double *q, const double *x, const double *y, const double *z,
+                             const double h[9], int M, const double *w, const double *wt, const double *s,
+                             double *fx, double *fy, double *fz, double Pf[9], double *UF)
+{
+    double hi[9];
+    const double V = fabs(tri_inverse(h, hi));
+    int32_t *mm;
+    const int64_t cnt = tri_modes(h, hi, sqrt(4.0 * ORC_TRUNC) / s[0], &mm);
+    double *rre = malloc(sizeof(double) * (cnt + 1)), *rim = malloc(sizeof(double) * (cnt + 1));
+    double *fh = malloc(sizeof(double) * (cnt + 1));
+    orc_tri_rho(n, q, x, y, z, h, cnt, mm, rre, rim);
+    double u = 0.0, pf[9] = {0};
+    for (int64_t p = 0; p < cnt; ++p) {
+        double k[3];
+        tri_k(&mm[3 * p], hi, k);
+        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        const double a2 = rre[p] * rre[p] + rim[p] * rim[p];
+        double F = 0.0;
+        for (int l = 0; l < M; ++l) F += pow(ORC_PI, 1.5) * w[l] * pow(s[l], 3) * exp(-s[l] * s[l] * k2 / 4.0);
+        fh[p] = F;
+        u += F * a2;
+        for (int l = 0; l < M; ++l) {
+            const double g = wt[l] * pow(s[l], 5) * exp(-s[l] * s[l] * k2 / 4.0) * a2;
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be)
+                    pf[3 * al + be] += g * ((al == be ? 1.0 : 0.0) - 0.5 * s[l] * s[l] * k[al] * k[be]);
+        }
+    }
+    *UF = u / (2.0 * V);
+    for (int a = 0; a < 9; ++a) Pf[a] = pow(ORC_PI, 1.5) / (4.0 * V * V) * pf[a];
+    if (fx) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double f[3] = {0, 0, 0};
+            for (int64_t p = 0; p < cnt; ++p) {
+                double k[3];
+                tri_k(&mm[3 * p], hi, k);
+                const double th = k[0] * x[i] + k[1] * y[i] + k[2] * z[i];
+                const double imv = rim[p] * cos(th) - rre[p] * sin(th);
+                for (int d = 0; d < 3; ++d) f[d] += k[d] * fh[p] * imv;
+            }
+            fx[i] = -q[i] / V * f[0];
+            fy[i] = -q[i] / V * f[1];
+            fz[i] = -q[i] / V * f[2];
+        }
+    }
+    free(rre); free(rim); free(mm); free(fh);
+}
+
+/*
+ * Ewald energy, forces and pressure tensor of orc_ewald for a general cell:
+ * real space over every image inside rcut, reciprocal space over k = 2 pi
+ * h^-T m with |k| < kcut.  Pinned by: the rock-salt Madelung constant in a
+ * primitive (rhombohedral) fcc cell and orc_ewald at h = diag(L).
+ */
+void orc_tri_ewald(int64_t n, const double *q, const double *x, const double *y, const double *z, const double h[9],
+                   double beta, double rcut, double kcut, double *fx, double *fy, double *fz, double Pt[9], double *U)
+{
+    double hi[9], wd[3];
+    const double V = fabs(tri_inverse(h, hi));
+    tri_widths(hi, wd);
+    int nimg[3];
+    for (int i = 0; i < 3; ++i) nimg[i] = (int)ceil(rcut / wd[i]) + 1;
+    double *acc = calloc((size_t)n * 10, sizeof(double));
+    const double rcut2 = rcut * rcut;
+    const double tb = 2.0 * beta / sqrt(ORC_PI);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        double f[3] = {0, 0, 0}, v[6] = {0}, u = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double dr[3] = {x[i] - x[j], y[i] - y[j], z[i] - z[j]};
+            double ds[3];
+            for (int a = 0; a < 3; ++a) {
+                ds[a] = hi[3 * a] * dr[0] + hi[3 * a + 1] * dr[1] + hi[3 * a + 2] * dr[2];
+                ds[a] -= round(ds[a]);
+            }
+            for (int a = -nimg[0]; a <= nimg[0]; ++a)
+                for (int b = -nimg[1]; b <= nimg[1]; ++b)
+                    for (int c = -nimg[2]; c <= nimg[2]; ++c) {
+                        const double t[3] = {ds[0] + a, ds[1] + b, ds[2] + c};
+                        double d[3];
+                        for (int e = 0; e < 3; ++e) d[e] = h[3 * e] * t[0] + h[3 * e + 1] * t[1] + h[3 * e + 2] * t[2];
+                        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        if (r2 >= rcut2 || r2 == 0.0) continue;
+                        const double r = sqrt(r2);
+                        const double qq = q[i] * q[j];
+                        const double g = erfc(beta * r) / (r2 * r) + tb * exp(-beta * beta * r2) / r2;
+                        for (int k = 0; k < 3; ++k) f[k] += qq * g * d[k];
+                        v[0] += 0.5 * qq * g * d[0] * d[0];
+                        v[1] += 0.5 * qq * g * d[1] * d[1];
+                        v[2] += 0.5 * qq * g * d[2] * d[2];
+                        v[3] += 0.5 * qq * g * d[0] * d[1];
+                        v[4] += 0.5 * qq * g * d[0] * d[2];
+                        v[5] += 0.5 * qq * g * d[1] * d[2];
+                        u += 0.5 * qq * erfc(beta * r) / r;
+                    }
+        }
+        for (int k = 0; k < 3; ++k) acc[10 * i + k] = f[k];
+        for (int k = 0; k < 6; ++k) acc[10 * i + 3 + k] = v[k];
+        acc[10 * i + 9] = u;
+    }
+    double vr[6] = {0}, ur = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < 6; ++k) vr[k] += acc[10 * i + 3 + k];
+        ur += acc[10 * i + 9];
+    }
+    int32_t *mm;
+    const int64_t cnt = tri_modes(h, hi, kcut, &mm);
+    double *rre = malloc(sizeof(double) * (cnt + 1)), *rim = malloc(sizeof(double) * (cnt + 1)),
+           *G = malloc(sizeof(double) * (cnt + 1));
+    orc_tri_rho(n, q, x, y, z, h, cnt, mm, rre, rim);
+    double uk = 0.0, pk[9] = {0};
+    for (int64_t p = 0; p < cnt; ++p) {
+        double k[3];
+        tri_k(&mm[3 * p], hi, k);
+        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        G[p] = 4.0 * ORC_PI * exp(-k2 / (4.0 * beta * beta)) / k2;
+        const double a2 = rre[p] * rre[p] + rim[p] * rim[p];
+        uk += G[p] * a2;
+        for (int al = 0; al < 3; ++al)
+            for (int be = 0; be < 3; ++be)
+                pk[3 * al + be] += G[p] * a2 *
+                    ((al == be ? 1.0 : 0.0) - 2.0 * (1.0 + k2 / (4.0 * beta * beta)) * k[al] * k[be] / k2);
+    }
+    uk /= 2.0 * V;
+    for (int a = 0; a < 9; ++a) pk[a] /= 2.0 * V * V;
+    double q2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) q2 += q[i] * q[i];
+    *U = ur + uk - beta / sqrt(ORC_PI) * q2;
+    const int idx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be) Pt[3 * al + be] = vr[idx[al][be]] / V + pk[3 * al + be];
+    if (fx) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double f[3] = {acc[10 * i], acc[10 * i + 1], acc[10 * i + 2]};
+            for (int64_t p = 0; p < cnt; ++p) {
+                double k[3];
+                tri_k(&mm[3 * p], hi, k);
                 const double th = k[0] * x[i] + k[1] * y[i] + k[2] * z[i];
                 const double imv = rim[p] * cos(th) - rre[p] * sin(th);
                 for (int d = 0; d < 3; ++d) f[d] -= q[i] / V * k[d] * G[p] * imv;
