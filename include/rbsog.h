@@ -192,6 +192,27 @@ int rbsog_sample_modes(rbsog_ctx *ctx, int64_t step, const double host_box[3],
                        int32_t *host_m_r, int32_t *host_m_nr, double host_S[2]);
 
 /*
+ * rbsog_sample_modes for a general (triclinic) cell, Sec. 2.1:
+ * host_h[9] is the cell tensor h = [h_1, h_2, h_3] row-major, its columns the
+ * cell vectors (h[3 i + j] = component i of h_j), det h > 0, and positions
+ * are r = h s with s the fractional coordinates.  Modes are k = 2 pi h^-T m;
+ * S^r and S^nr are the lattice sums of eqs. Sr, Snr (Prop. 1 forms per
+ * Gaussian); the r-chain's proposal is round(h^T u) (App. D) and its pmf, eq.
+ * proposal, a Gaussian integral over the unit cube with no closed form, is
+ * taken by a 24-point tensor Gauss-Legendre rule.  The following
+ * rbsog_force_virial and rbsog_pressure use this cell: short-range pairs by
+ * the component-wise fractional minimum image, exact while r_c is at most half
+ * the smallest perpendicular width of the cell (RBSOG_EBOX otherwise), on the
+ * exact pair path (FP32C and FP64); the pressure tensor is full, shear
+ * components included.  A diagonal h is the box of its diagonal.  The first
+ * call with a non-diagonal h allocates a 221 KB quadrature table.  General
+ * cells are a single-context form: rbsog_rescale refuses them (pass the next
+ * cell here) and the batched and served forms take boxes.
+ */
+int rbsog_sample_modes_cell(rbsog_ctx *ctx, int64_t step, const double host_h[9],
+                            int32_t *host_m_r, int32_t *host_m_nr, double host_S[2]);
+
+/*
  * Algorithm 1 steps 4-6 for the positions x, y, z (n each, FP64, the caller's
  * atom order, any periodic image) in the box of the last rbsog_sample_modes:
  * writes the total force F = F^N + F^{F*} into fx, fy, fz (n each, FP64,
@@ -433,6 +454,35 @@ int rbsog_batch_set_options(rbsog_batch *b, int32_t schedule, int32_t wg_per_cu,
 int rbsog_batch_autotune(rbsog_batch *b, const int64_t *host_steps, const double *host_boxes, const double *x,
                          const double *y, const double *z, double *fx, double *fy, double *fz, int32_t reps,
                          double *host_ms, int32_t *host_choice);
+
+/*
+ * Cached autotuner.  The candidates are the pair kernel's schedules of
+ * rbsog_batch_autotune, each with and without graph replay of the step
+ * (RBSOG_TUNE_CANDIDATES = 10: index c < 5 is schedule c of that list
+ * without, c + 5 the same with graph replay).  None changes any operation or
+ * the order of any sum, so results are bitwise the same under every choice.
+ * The key is the device (architecture and number of compute units), the
+ * batch's total atoms rounded down to a power of two and its largest P
+ * rounded up to one.
+ *  cache_path    a text file, one line per tuning: "<key>|<index> <ms> ..."
+ *                (created when missing; the last line of a key counts).
+ *  force         nonzero: time the candidates even when the key is cached.
+ * When the key is found (and force is 0) its choice is applied without a
+ * step; otherwise every candidate is timed as in rbsog_batch_autotune (one
+ * untimed step, then reps timed steps on the given arrays) and the fastest
+ * is applied and appended to the file.  host_ms[RBSOG_TUNE_CANDIDATES]
+ * (optional) receives the mean step time of each timed candidate (on a hit,
+ * only the chosen one's, from the file; the others 0), *host_choice the index
+ * applied and *host_cached 1 on a hit.  RBSOG_EINVAL when the file cannot be
+ * written or for a batch of contexts.  Calls within one process read and
+ * write the file one at a time; several processes sharing a file may each
+ * append a line for the same key.
+ */
+#define RBSOG_TUNE_CANDIDATES 10
+int rbsog_batch_autotune_cached(rbsog_batch *b, const char *cache_path, int32_t force, const int64_t *host_steps,
+                                const double *host_boxes, const double *x, const double *y, const double *z,
+                                double *fx, double *fy, double *fz, int32_t reps, double *host_ms,
+                                int32_t *host_choice, int32_t *host_cached);
 
 /*
  * A batch of existing contexts, admitted by device memory.

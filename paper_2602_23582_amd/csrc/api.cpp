@@ -160,6 +160,8 @@ int rbsog_setup(const rbsog_params *params, int64_t n, const double *host_q, con
     return RBSOG_OK;
 }
 
+static int sample_tail(rbsog_ctx *c, int64_t step, int32_t *host_m_r, int32_t *host_m_nr, double host_S[2]);
+
 int rbsog_sample_modes(rbsog_ctx *c, int64_t step, const double host_box[3], int32_t *host_m_r,
                        int32_t *host_m_nr, double host_S[2])
 {
@@ -169,6 +171,25 @@ int rbsog_sample_modes(rbsog_ctx *c, int64_t step, const double host_box[3], int
     if (step < 0 || (step >> 32)) return fail(c, RBSOG_EINVAL, "step must be in [0, 2^32)");
     RB_TRY(rbsog::check_box(host_box, c->sys.prm.rc, c->err));
     rbsog::system_set_box(c->sys, host_box);
+    return sample_tail(c, step, host_m_r, host_m_nr, host_S);
+}
+
+int rbsog_sample_modes_cell(rbsog_ctx *c, int64_t step, const double host_h[9], int32_t *host_m_r,
+                            int32_t *host_m_nr, double host_S[2])
+{
+    if (!c) return RBSOG_EINVAL;
+    c->err.clear();
+    RB_TRY(own_work(c));
+    if (!host_h) return fail(c, RBSOG_EINVAL, "cell tensor is NULL");
+    if (step < 0 || (step >> 32)) return fail(c, RBSOG_EINVAL, "step must be in [0, 2^32)");
+    const bool had_table = c->sys.gl_mem != nullptr;
+    RB_TRY(rbsog::system_set_cell(c->sys, host_h, c->err));
+    if (c->sys.gl_mem && !had_table) c->batch.desc_dirty = true;  // the descriptor now points at the table
+    return sample_tail(c, step, host_m_r, host_m_nr, host_S);
+}
+
+static int sample_tail(rbsog_ctx *c, int64_t step, int32_t *host_m_r, int32_t *host_m_nr, double host_S[2])
+{
     RB_TRY(refresh_cells(c));
     c->sys.stp.step = static_cast<uint32_t>(step);
     RB_TRY(rbsog::batch_upload(c->batch, c->err));
@@ -289,6 +310,8 @@ int rbsog_rescale(rbsog_ctx *c, const double host_mu[3], double *x, double *y, d
         return fail(c, RBSOG_EINVAL, "scale factors must be positive and finite");
     if (!(is_device_ptr(x) && is_device_ptr(y) && is_device_ptr(z)))
         return fail(c, RBSOG_EINVAL, "rbsog_rescale needs device position arrays");
+    if (c->sys.tri)
+        return fail(c, RBSOG_ESTATE, "rbsog_rescale scales a box; a general cell is passed to rbsog_sample_modes_cell");
     rbsog::SysStep &t = c->sys.stp;
     for (int d = 0; d < 3; ++d) t.mu[d] = host_mu[d];
     t.x = x;

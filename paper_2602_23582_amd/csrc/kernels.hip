@@ -133,6 +133,9 @@ __device__ inline double unit_open(uint32_t hi, uint32_t lo)
 
 struct SampArgs {
     double L[3];
+    int tri;              // general cell: h, h^-1 and the quadrature table below
+    double h[9], hi[9], V;
+    const double *gltab;  // [2][kGl^3]: w_i w_j w_k exp(-pi^2 s^2 d^T C d) for s = s_0 and s_0/sqrt2
     double B[2];       // bounds of g_2/q' and g_4/q' (exact start draws)
     int P, M, variant, mcap;
     uint32_t key0, key1, step, sys;
@@ -168,6 +171,16 @@ __device__ void round_proposal(const SampArgs &a, const double z[3], int m[3], d
 {
 #pragma clang fp contract(off)
     const double s0 = a.tab->s[0] * widen;
+    if (a.tri) {
+        // (h^T u)_i = sum_j h_ji u_j, u = z / (sqrt2 pi s0)
+        const double c = 1.0 / (sqrt(2.0) * kPi * s0);
+        for (int i = 0; i < 3; ++i) {
+            double v = round(c * (a.h[i] * z[0] + a.h[3 + i] * z[1] + a.h[6 + i] * z[2]));
+            v = fmin(fmax(v, -1073741824.0), 1073741824.0);
+            m[i] = static_cast<int>(v);
+        }
+        return;
+    }
     for (int d = 0; d < 3; ++d) {
         const double sig = a.L[d] / (sqrt(2.0) * kPi * s0);
         double v = round(sig * z[d]);
@@ -192,9 +205,17 @@ __device__ void mode_weights(const SampArgs &a, const int m[3], double *w, doubl
         return;
     }
     double k2 = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        const double k = 2.0 * kPi * m[d] / a.L[d];
-        k2 += k * k;
+    if (a.tri) {
+        // k = 2 pi h^-T m
+        for (int i = 0; i < 3; ++i) {
+            const double k = 2.0 * kPi * (a.hi[i] * m[0] + a.hi[3 + i] * m[1] + a.hi[6 + i] * m[2]);
+            k2 += k * k;
+        }
+    } else {
+        for (int d = 0; d < 3; ++d) {
+            const double k = 2.0 * kPi * m[d] / a.L[d];
+            k2 += k * k;
+        }
     }
     const SogTables *t = a.tab;
     double a5 = 0.0, a7 = 0.0;
@@ -204,7 +225,38 @@ __device__ void mode_weights(const SampArgs &a, const int m[3], double *w, doubl
         a7 += t->wt[l] * t->s7[l] * e;
     }
     const double target = k2 * a5;
+    // general cell: eq. proposal's integral over the unit cube around m by the
+    // tensor Gauss-Legendre rule, exp(-a (2 (Cm).d + d^T C d)) split into the
+    // tabulated exp(-a d^T C d) (times the weights) and one factor per axis,
+    // with exp(-a m^T C m) outside; C = h^-1 h^-T, a = pi^2 s^2
+    auto pmf_cell = [&](double s0, int tabi) {
+        const double aa = kPi * kPi * s0 * s0;
+        double C[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                C[3 * i + j] = a.hi[3 * i] * a.hi[3 * j] + a.hi[3 * i + 1] * a.hi[3 * j + 1] +
+                               a.hi[3 * i + 2] * a.hi[3 * j + 2];
+        double cm[3], mm = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            cm[i] = C[3 * i] * m[0] + C[3 * i + 1] * m[1] + C[3 * i + 2] * m[2];
+            mm += m[i] * cm[i];
+        }
+        double e[3][kGl];
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i < kGl; ++i) e[d][i] = exp(-2.0 * aa * cm[d] * t->glx[i]);
+        const double *T = a.gltab + tabi * (kGl * kGl * kGl);
+        double acc = 0.0;
+        for (int i = 0; i < kGl; ++i)
+            for (int j = 0; j < kGl; ++j) {
+                double row = 0.0;
+                for (int k = 0; k < kGl; ++k) row += T[(i * kGl + j) * kGl + k] * e[2][k];
+                acc += e[0][i] * e[1][j] * row;
+            }
+        const double rs = sqrt(kPi) * s0;
+        return rs * rs * rs / a.V * exp(-aa * mm) * acc;
+    };
     auto pmf = [&](double s0) {
+        if (a.tri) return pmf_cell(s0, s0 == t->s[0] ? 0 : 1);
         double q = 1.0;
         for (int d = 0; d < 3; ++d) {
             const double sig = a.L[d] / (sqrt(2.0) * kPi * s0);
@@ -263,6 +315,13 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
     const SysStep &St = stp[blockIdx.x];
     SampArgs a;
     for (int d = 0; d < 3; ++d) a.L[d] = St.L[d];
+    a.tri = St.tri;
+    for (int i = 0; i < 9; ++i) {
+        a.h[i] = St.h[i];
+        a.hi[i] = St.hi[i];
+    }
+    a.V = St.V;
+    a.gltab = D.gltab;
     a.B[0] = St.Bstart[0];
     a.B[1] = St.Bstart[1];
     a.P = D.P;
@@ -286,6 +345,29 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
     const bool nrstart = indep || exch;
     const int nslots = a.mcap;  // P + 1, P + 2 (exchange) or 2P + 2 (independent)
     const int nr0 = P + 1;      // slot of the non-radial start state
+    if (a.tri) {
+        // the proposal pmf's quadrature table for this step's cell, both widths
+        constexpr int nn = kGl * kGl * kGl;
+        double C[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                C[3 * i + j] = a.hi[3 * i] * a.hi[3 * j] + a.hi[3 * i + 1] * a.hi[3 * j + 1] +
+                               a.hi[3 * i + 2] * a.hi[3 * j + 2];
+        RB_GLOBAL double *gt = gp(D.gltab);
+        for (int idx = tid; idx < 2 * nn; idx += blockDim.x) {
+            const int wi = idx / nn, r = idx % nn;
+            const int i = r / (kGl * kGl), j = (r / kGl) % kGl, k = r % kGl;
+            const double s0 = D.tab.s[0] * (wi ? kNrWiden : 1.0);
+            const double aa = kPi * kPi * s0 * s0;
+            const double d[3] = {D.tab.glx[i], D.tab.glx[j], D.tab.glx[k]};
+            double dcd = 0.0;
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) dcd += d[p] * C[3 * p + q] * d[q];
+            gt[idx] = D.tab.glw[i] * D.tab.glw[j] * D.tab.glw[k] * exp(-aa * dcd);
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
     if (tid == 0) {
         s_first[0] = kStartTries;
         s_first[1] = nrstart ? kStartTries : -1;
@@ -573,8 +655,15 @@ __global__ __launch_bounds__(kAtomBlock) void k_fix(const SysDesc *__restrict__ 
     const int nc[3] = {St.nc[0], St.nc[1], St.nc[2]};
     RB_GLOBAL typename T::fix *u = gp(static_cast<typename T::fix *>(D.u));
     uint32_t c[3];
+    // fractional coordinates s = h^-1 r (a general cell) or r / L
+    double sv[3];
+    if (St.tri) {
+        for (int d = 0; d < 3; ++d) sv[d] = St.hi[3 * d] * p[0] + St.hi[3 * d + 1] * p[1] + St.hi[3 * d + 2] * p[2];
+    } else {
+        for (int d = 0; d < 3; ++d) sv[d] = p[d] * St.iL[d];
+    }
     for (int d = 0; d < 3; ++d) {
-        double s = p[d] * St.iL[d];
+        double s = sv[d];
         s -= floor(s);
         uint32_t top;
         if constexpr (sizeof(typename T::fix) == 4) {
@@ -1043,6 +1132,34 @@ __device__ __forceinline__ void pair_eval(const typename T::Rec &ri, const typen
     pair_eval_d<T, M, E>(dx, dy, dz, rj.q, active, rc2, W, acc);
 }
 
+// General cell: the fractional difference of two fixed-point records (a
+// minimum image component by component, exact while r_c is at most half the
+// cell's smallest perpendicular width), times h.  d_ji = -d_ij exactly, so a
+// pair is inside r_c from both of its atoms.
+template <class T>
+__device__ __forceinline__ void displacement_cell(const typename T::Rec &ri, const typename T::Rec &rj,
+                                                  const typename T::real hm[9], typename T::real unit,
+                                                  typename T::real &dx, typename T::real &dy, typename T::real &dz)
+{
+    using sfix = typename T::sfix;
+    const typename T::real s0 = fix_to_real(static_cast<sfix>(ri.x - rj.x), unit);
+    const typename T::real s1 = fix_to_real(static_cast<sfix>(ri.y - rj.y), unit);
+    const typename T::real s2 = fix_to_real(static_cast<sfix>(ri.z - rj.z), unit);
+    dx = hm[0] * s0 + hm[1] * s1 + hm[2] * s2;
+    dy = hm[3] * s0 + hm[4] * s1 + hm[5] * s2;
+    dz = hm[6] * s0 + hm[7] * s1 + hm[8] * s2;
+}
+
+template <class T, int M, bool E>
+__device__ __forceinline__ void pair_eval_cell(const typename T::Rec &ri, const typename T::Rec &rj, bool active,
+                                               const typename T::real hm[9], typename T::real unit,
+                                               typename T::real rc2, const Weights<T, M> &W, PairAcc<T> &acc)
+{
+    typename T::real dx, dy, dz;
+    displacement_cell<T>(ri, rj, hm, unit, dx, dy, dz);
+    pair_eval_d<T, M, E>(dx, dy, dz, rj.q, active, rc2, W, acc);
+}
+
 // m <- 16 m + the four bits (t_k < thr), t0 first: per candidate one compare
 // into VCC and one add with carry (the compiler's own form of this step takes
 // three instructions).  The t_k come from FMAs, whose results a following VALU
@@ -1090,7 +1207,7 @@ struct PairShared {
 };
 
 // One pair block b of system D (one wavefront).
-template <class T, int M, bool E, bool FAST>
+template <class T, int M, bool E, bool FAST, bool TRI = false>
 __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, const SysStep &St, int b)
 {
     using real = typename T::real;
@@ -1119,6 +1236,11 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         sz = St.L[2] * 0x1.0p-64;
         rc2 = D.tab.rc2;
     }
+    // general cell (TRI): displacements h ds with ds in units of the fixed point
+    real hm[9];
+    real unit = sizeof(real) == 4 ? static_cast<real>(0x1.0p-32) : static_cast<real>(0x1.0p-64);
+    if constexpr (TRI)
+        for (int k = 0; k < 9; ++k) hm[k] = static_cast<real>(St.h[k]);
     const RB_GLOBAL int32_t *start = gp(D.start);
     const int2 cb = gload(D.blocks + b);
     // the block's segment: cells c .. c + gs - 1 of one column
@@ -1230,8 +1352,15 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         if constexpr (kIsF32) {
             const int nvalid = min(kPairWave, ce - cs - cb.y * kPairWave);
             const uint32_t zext = __shfl(static_cast<uint32_t>(ri.z - oz_), nvalid - 1, 64);
-            const uint32_t reach =
-                static_cast<uint32_t>(ceil(static_cast<double>(rcf) / St.L[2] * 4294967296.0)) + 2u;
+            // a partner within rc differs by at most rc / w_z in s_z (w_z the
+            // distance between the cell's z faces; L_z for a box)
+            double zspan;
+            if constexpr (TRI)
+                zspan = static_cast<double>(rcf) *
+                        sqrt(St.hi[6] * St.hi[6] + St.hi[7] * St.hi[7] + St.hi[8] * St.hi[8]);
+            else
+                zspan = static_cast<double>(rcf) / St.L[2];
+            const uint32_t reach = static_cast<uint32_t>(ceil(zspan * 4294967296.0)) + 2u;
             cut = static_cast<uint64_t>(zext) + 2ull * reach < (1ull << 32);
             za = static_cast<uint32_t>(oz_) - reach;
             zb = static_cast<uint32_t>(oz_) + zext + reach;
@@ -1334,7 +1463,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                 else sh.tile[k] = rj;
             } else {
                 sh.tile[k] = rj;
-                if constexpr (kIsF32 && !FAST) sh.pk[k] = pack16(rj);
+                if constexpr (kIsF32 && !FAST && !TRI) sh.pk[k] = pack16(rj);
             }
         }
         // the filter reads whole 32-candidate words: padding candidates never pass
@@ -1374,7 +1503,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                     }
                     m = push_hits4(m, t[0], t[1], t[2], t[3], thr);
                 }
-            } else if constexpr (kIsF32 && !FAST) {
+            } else if constexpr (kIsF32 && !FAST && !TRI) {
                 // The top 16 bits of the fixed-point coordinates wrap like the
                 // box, so their 16-bit differences are minimum images in units
                 // u_d = L_d / 2^16; a pair inside rc has sum (d_d/u_d)^2 below
@@ -1404,7 +1533,8 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                     bool hit = false;
                     if (s < s_end) {
                         real dx, dy, dz;
-                        displacement<T>(ri, sh.tile[s], sx, sy, sz, dx, dy, dz);
+                        if constexpr (TRI) displacement_cell<T>(ri, sh.tile[s], hm, unit, dx, dy, dz);
+                        else displacement<T>(ri, sh.tile[s], sx, sy, sz, dx, dy, dz);
                         const real d2 = dx * dx + dy * dy + dz * dz;
                         hit = (d2 < rc2_lane) & (d2 > 0);
                     }
@@ -1449,8 +1579,13 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                     pair_eval_d<T, M, E>(xi - t1.x, yi - t1.y, zi - t1.z, t1.w, a1, rc2, W, acc);
                 } else {
                     const Rec r0 = sh.tile[32 * w + k0], r1 = sh.tile[32 * w + k1];
-                    pair_eval<T, M, E>(ri, r0, a0, sx, sy, sz, rc2, W, acc);
-                    pair_eval<T, M, E>(ri, r1, a1, sx, sy, sz, rc2, W, acc);
+                    if constexpr (TRI) {
+                        pair_eval_cell<T, M, E>(ri, r0, a0, hm, unit, rc2, W, acc);
+                        pair_eval_cell<T, M, E>(ri, r1, a1, hm, unit, rc2, W, acc);
+                    } else {
+                        pair_eval<T, M, E>(ri, r0, a0, sx, sy, sz, rc2, W, acc);
+                        pair_eval<T, M, E>(ri, r1, a1, sx, sy, sz, rc2, W, acc);
+                    }
                 }
             }
         };
@@ -1992,13 +2127,13 @@ __device__ inline int xcd_grouped(int w, int G)
     return base + x * q + min(x, r) + o / kXcd;
 }
 
-template <class T, int M, bool E, bool FAST>
+template <class T, int M, bool E, bool FAST, bool TRI = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_min_waves<T, E>()))) void k_pair(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                              const int2 *__restrict__ plan)
 {
     __shared__ PairShared<T> sh;
     const int2 e = plan[xcd_grouped(blockIdx.x, gridDim.x)];
-    pair_block<T, M, E, FAST>(sh, desc[e.x], stp[e.x], e.y);
+    pair_block<T, M, E, FAST, TRI>(sh, desc[e.x], stp[e.x], e.y);
 }
 
 // Half-shell launches: a system whose neighbourhoods outgrew the partial
@@ -2044,7 +2179,7 @@ __global__ __launch_bounds__(64) void k_pair_half_queue(const SysDesc *__restric
 // Persistent schedule: a fixed number of workgroups take plan entries from a
 // global counter (zeroed by k_zero) until all nitems are taken; every
 // workgroup leaves once the counter has passed nitems.
-template <class T, int M, bool E, bool FAST>
+template <class T, int M, bool E, bool FAST, bool TRI = false>
 __global__ __launch_bounds__(64) void k_pair_queue(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
                                                    const int2 *__restrict__ plan, int nitems, int32_t *ctrl)
 {
@@ -2055,7 +2190,7 @@ __global__ __launch_bounds__(64) void k_pair_queue(const SysDesc *__restrict__ d
         idx = __shfl(idx, 0, 64);
         if (idx >= nitems) break;
         const int2 e = plan[idx];
-        pair_block<T, M, E, FAST>(sh, desc[e.x], stp[e.x], e.y);
+        pair_block<T, M, E, FAST, TRI>(sh, desc[e.x], stp[e.x], e.y);
         __syncthreads();
     }
 }
@@ -2263,7 +2398,7 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
     const int tid = threadIdx.x;
     const int nd = gp(D.res)->nd;
     const double L[3] = {St.L[0], St.L[1], St.L[2]};
-    const double V = L[0] * L[1] * L[2];
+    const double V = St.V;
     const double S = 0.5 * St.Sr;
     const int P = D.P;
     const bool shared = D.variant == RBSOG_RECAL_SHARED;
@@ -2281,7 +2416,15 @@ __global__ __launch_bounds__(256) void k_estimators(const SysDesc *__restrict__ 
     const bool wide = D.tab.Me > D.tab.M;
     for (int d = tid; d < nd; d += 256) {
         const int4 m = D.modes[d];
-        const double k[3] = {2.0 * kPi * m.x / L[0], 2.0 * kPi * m.y / L[1], 2.0 * kPi * m.z / L[2]};
+        double k[3];
+        if (St.tri) {
+            // k = 2 pi h^-T m
+            for (int i = 0; i < 3; ++i) k[i] = 2.0 * kPi * (St.hi[i] * m.x + St.hi[3 + i] * m.y + St.hi[6 + i] * m.z);
+        } else {
+            k[0] = 2.0 * kPi * m.x / L[0];
+            k[1] = 2.0 * kPi * m.y / L[1];
+            k[2] = 2.0 * kPi * m.z / L[2];
+        }
         const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
         const double re = D.rho[2 * d], im = D.rho[2 * d + 1];
         const double r2 = re * re + im * im;
@@ -2607,7 +2750,7 @@ hipError_t launch_bin_and_sort(Batch &b)
     return b.precision == RBSOG_PREC_FP64 ? bin_and_sort_t<F64>(b) : bin_and_sort_t<F32>(b);
 }
 
-template <class T, int M, bool E, bool FAST>
+template <class T, int M, bool E, bool FAST, bool TRI = false>
 static void pair_launch_group(Batch &b, int group)
 {
     const int64_t first = b.pair_split[group], items = b.pair_split[group + 1] - first;
@@ -2615,10 +2758,10 @@ static void pair_launch_group(Batch &b, int group)
     const int2 *plan = plan_ptr(b, kPlanPair) + first;
     if (b.pair_schedule == kPairPersistent) {
         const int64_t wgs = std::min<int64_t>(items, static_cast<int64_t>(b.num_cu) * b.pair_wg_per_cu);
-        hipLaunchKernelGGL((k_pair_queue<T, M, E, FAST>), dim3(static_cast<unsigned>(wgs)), dim3(64), 0, b.stream,
-                           b.d_desc, b.d_step, plan, static_cast<int>(items), b.d_ctrl + group);
+        hipLaunchKernelGGL((k_pair_queue<T, M, E, FAST, TRI>), dim3(static_cast<unsigned>(wgs)), dim3(64), 0,
+                           b.stream, b.d_desc, b.d_step, plan, static_cast<int>(items), b.d_ctrl + group);
     } else {
-        hipLaunchKernelGGL((k_pair<T, M, E, FAST>), dim3(static_cast<unsigned>(items)), dim3(64), 0, b.stream,
+        hipLaunchKernelGGL((k_pair<T, M, E, FAST, TRI>), dim3(static_cast<unsigned>(items)), dim3(64), 0, b.stream,
                            b.d_desc, b.d_step, plan);
     }
 }
@@ -2648,6 +2791,7 @@ template <class T, int M, bool E>
 static void pair_launch(Batch &b, int form)
 {
     pair_launch_group<T, M, E, false>(b, kNumPaths * form);
+    pair_launch_group<T, M, E, false, true>(b, kNumPaths * form + 3);
     if constexpr (sizeof(typename T::real) == 4) {
         pair_launch_group<T, M, E, true>(b, kNumPaths * form + 1);
         pair_launch_half<T, M, E>(b, kNumPaths * form + 2);

@@ -40,6 +40,11 @@ constexpr int kHrngStride = 24;    // ints per pair block of the half-shell neig
 // with more runs its system on the full shell for that step.
 constexpr double kHalfRefDensity = 0.15;
 constexpr double kHalfMargin = 1.25;
+// General cells: Gauss-Legendre points per axis of the proposal pmf's
+// integral over the unit cube (eq. proposal), and the size of the per-system
+// table of w_i w_j w_k exp(-pi^2 s^2 d^T C d) for the two proposal widths.
+constexpr int kGl = 24;
+constexpr int kGlTab = 2 * kGl * kGl * kGl;
 
 // Distinct modes a step can visit: the r-chain's start state and proposals;
 // the exchange form adds the non-radial chain's start state, the independent
@@ -70,6 +75,8 @@ struct SogTables {
     float poly_err;       // max |p - sum| / sum(0) of the fit, both sums
     // sampler: s_l, and wt_l s_l^5, wt_l s_l^7 are formed from s5, s7
     double s[RBSOG_MAX_M], s5[RBSOG_MAX_M], s7[RBSOG_MAX_M];
+    // Gauss-Legendre nodes and weights on [-1/2, 1/2] (general cells)
+    double glx[kGl], glw[kGl];
 };
 
 // Results of one step of one system, written on the device, read by the host.
@@ -120,6 +127,7 @@ struct SysDesc {
     int32_t *hrng;        // [pair_cap][kHrngStride]: range starts, flattened prefixes, chunk count
     int32_t *hflag;       // [1] set when a block's neighbourhood exceeds hcap (full shell this step)
     int32_t hcap, pad2;   // candidates per block the partial buffer holds
+    double *gltab;        // general cells: [2][kGl^3] quadrature table of the proposal pmf (null otherwise)
 };
 
 // Per-step data of one system (rewritten by the host every step).
@@ -136,7 +144,9 @@ struct SysStep {
     int32_t fast;         // FP32 relative-coordinate filter over whole neighbour columns (4+ cells per edge, nz >= 2g + 2)
     uint32_t thr16;       // FP32 exact filter: bound on sum (d_d / u_d)^2 of a pair inside rc, u_d = L_d / 2^16
     int32_t half;         // fast path with Newton's third law (half-shell pair kernel, partials, gather)
-    int32_t pad3;
+    int32_t tri;          // general cell: h below is not diagonal (exact path with d = h ds, sampler by quadrature)
+    double h[9], hi[9];   // cell tensor (row-major, columns the cell vectors) and its inverse
+    double V;             // det h
     const double *x, *y, *z;  // positions (device, system order)
     double *fx, *fy, *fz;     // forces (device, system order)
 };
@@ -161,8 +171,9 @@ enum PairForm {
 };
 // Pair launches: one per (form, path); path 0 is the exact filter, path 1 the
 // FP32 relative-coordinate filter over whole neighbour columns (SysStep::fast)
-// with the full shell, path 2 the same with the half shell (SysStep::half).
-constexpr int kNumPaths = 3;
+// with the full shell, path 2 the same with the half shell (SysStep::half),
+// path 3 the exact filter on a general cell (SysStep::tri).
+constexpr int kNumPaths = 4;
 constexpr int kNumPairGroups = kNumPaths * kNumForms;
 
 // Pair-kernel schedules (none changes any result).
@@ -178,8 +189,11 @@ struct System {
     double w[RBSOG_MAX_M]{}, wt[RBSOG_MAX_M]{}, s[RBSOG_MAX_M]{};
     double q2sum = 0.0, Uself = 0.0;
     SogTables tab{};
-    // box state
+    // box state (a general cell keeps h; L holds its diagonal)
     double L[3]{};
+    bool tri = false;
+    double h[9]{};
+    void *gl_mem = nullptr;  // general cells: the pmf quadrature table (allocated on first use)
     double Sr = 0.0, Snr = 0.0;
     int nc[3]{1, 1, 1};
     int64_t ncells = 0;
@@ -253,6 +267,13 @@ double omega_c0(double b, double sigma, double rc, int M);
 void norm_consts(const double L[3], int M, const double *wt, const double *s, double *Sr, double *Snr);
 double start_bound(const double L[3], int M, const double *wt, const double *s, int power);
 void cell_grid(const double L[3], double rc, int nc[3]);
+// General cells (row-major h, columns the cell vectors): S^r, S^nr, the start
+// bound, the perpendicular widths, and the Gauss-Legendre rule on [-1/2, 1/2].
+void norm_consts_cell(const double h[9], int M, const double *wt, const double *s, double *Sr, double *Snr);
+double start_bound_cell(const double h[9], int M, const double *wt, const double *s, int power);
+double cell_inverse(const double h[9], double hi[9]);
+void cell_widths(const double hi[9], double w[3]);
+void gauss_legendre_unit(int n, double *x, double *w);
 
 // ---------------------------------------------------------------------------
 // systems and batches (system.cpp)
@@ -284,6 +305,9 @@ int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::st
                     std::vector<float> *stage = nullptr);
 // New box: grid, S^r, S^nr, the pair path.
 void system_set_box(System &s, const double box[3]);
+// New general cell (row-major h); a diagonal h is the box of its diagonal.
+// RBSOG_EBOX unless r_c is at most half the smallest perpendicular width.
+int system_set_cell(System &s, const double h[9], std::string &err);
 // Whether the system takes the half-shell pair kernel on the fast path, and
 // the forward candidates per block its partial buffer holds for the grid.
 bool wants_half_shell(const System &s);

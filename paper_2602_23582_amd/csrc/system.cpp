@@ -263,6 +263,7 @@ int system_init(System &s, const rbsog_params &p, int64_t n, const double *host_
     tab.Me = Me;
     tab.rc2 = p.rc * p.rc;
     tab.rc2_32 = static_cast<float>(p.rc * p.rc);
+    gauss_legendre_unit(kGl, tab.glx, tab.glw);
     const double log2e = 1.4426950408889634073599246810018921;
     for (int l = 0; l < Me; ++l) {
         tab.w[l] = s.w[l];
@@ -339,6 +340,19 @@ int32_t half_hcap(const System &s)
 
 void system_set_box(System &s, const double box[3])
 {
+    s.tri = false;
+    s.stp.tri = 0;
+    for (int d = 0; d < 9; ++d) {
+        s.h[d] = 0.0;
+        s.stp.h[d] = 0.0;
+        s.stp.hi[d] = 0.0;
+    }
+    for (int d = 0; d < 3; ++d) {
+        s.h[4 * d] = box[d];
+        s.stp.h[4 * d] = box[d];
+        s.stp.hi[4 * d] = 1.0 / box[d];
+    }
+    s.stp.V = box[0] * box[1] * box[2];
     for (int d = 0; d < 3; ++d) s.L[d] = box[d];
     cell_grid(s.L, s.prm.rc, s.nc);
     s.ncells = static_cast<int64_t>(s.nc[0]) * s.nc[1] * s.nc[2];
@@ -377,6 +391,77 @@ void system_set_box(System &s, const double box[3])
     t.Snr = s.Snr;
 }
 
+int system_set_cell(System &s, const double h[9], std::string &err)
+{
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(h[i])) {
+            err = "cell tensor has NaN/Inf";
+            return RBSOG_EINVAL;
+        }
+    const bool diag = h[1] == 0.0 && h[2] == 0.0 && h[3] == 0.0 && h[5] == 0.0 && h[6] == 0.0 && h[7] == 0.0;
+    if (diag) {
+        const double box[3] = {h[0], h[4], h[8]};
+        const int rc = check_box(box, s.prm.rc, err);
+        if (rc != RBSOG_OK) return rc;
+        system_set_box(s, box);
+        return RBSOG_OK;
+    }
+    double hi[9], wd[3];
+    const double det = cell_inverse(h, hi);
+    if (!(det > 0.0)) {
+        err = "the cell tensor must have a positive determinant";
+        return RBSOG_EBOX;
+    }
+    cell_widths(hi, wd);
+    const double wmin = std::min(wd[0], std::min(wd[1], wd[2]));
+    if (2.0 * s.prm.rc > wmin) {
+        err = "rc must be at most half the smallest perpendicular width of the cell";
+        return RBSOG_EBOX;
+    }
+    s.tri = true;
+    SysStep &t = s.stp;
+    t.tri = 1;
+    for (int i = 0; i < 9; ++i) {
+        s.h[i] = h[i];
+        t.h[i] = h[i];
+        t.hi[i] = hi[i];
+    }
+    t.V = det;
+    // cells no thinner than rc between their faces: every partner of an atom
+    // lies in the 27 cells around it; fewer than three cells: one, searched whole
+    for (int d = 0; d < 3; ++d) {
+        s.L[d] = h[4 * d];
+        const int k = static_cast<int>(std::floor(wd[d] / s.prm.rc));
+        s.nc[d] = k >= 3 ? k : 1;
+    }
+    s.ncells = static_cast<int64_t>(s.nc[0]) * s.nc[1] * s.nc[2];
+    norm_consts_cell(h, s.prm.M, s.wt, s.s, &s.Sr, &s.Snr);
+    t.Bstart[0] = start_bound_cell(h, s.prm.M, s.wt, s.s, 2);
+    t.Bstart[1] = start_bound_cell(h, s.prm.M, s.wt, s.s, 4);
+    for (int d = 0; d < 3; ++d) {
+        t.L[d] = s.L[d];
+        t.iL[d] = 1.0 / s.L[d];
+        t.nc[d] = s.nc[d];
+    }
+    t.ncells = static_cast<int32_t>(s.ncells);
+    t.fast = 0;
+    t.half = 0;
+    t.g = 1;
+    t.thr16 = 0;
+    t.Sr = s.Sr;
+    t.Snr = s.Snr;
+    if (!s.gl_mem) {
+        const hipError_t e = hipMalloc(&s.gl_mem, kGlTab * sizeof(double));
+        if (e != hipSuccess) {
+            s.gl_mem = nullptr;
+            err = std::string("hipMalloc (proposal quadrature table): ") + hipGetErrorString(e);
+            return RBSOG_EDEVICE;
+        }
+    }
+    s.desc.gltab = static_cast<double *>(s.gl_mem);
+    return RBSOG_OK;
+}
+
 size_t system_atom_bytes(const rbsog_params &p, int64_t n) { return atom_layout(p, n).total(); }
 
 size_t system_device_bytes(const System &s)
@@ -385,6 +470,7 @@ size_t system_device_bytes(const System &s)
     if (s.half_mem)
         b += align_up(static_cast<size_t>(s.half_blocks) * 3 * s.half_hcap * sizeof(float)) +
              align_up(static_cast<size_t>(s.half_blocks) * kHrngStride * sizeof(int32_t)) + kAlign;
+    if (s.gl_mem) b += kGlTab * sizeof(double);
     return b;
 }
 
@@ -523,7 +609,8 @@ void system_free(System &s)
         if (s.cell_mem) (void)hipFree(s.cell_mem);
     }
     if (s.half_mem) (void)hipFree(s.half_mem);
-    s.atom_mem = s.cell_mem = s.half_mem = nullptr;
+    if (s.gl_mem) (void)hipFree(s.gl_mem);
+    s.atom_mem = s.cell_mem = s.half_mem = s.gl_mem = nullptr;
 }
 
 int system_upload_q(System &s, const double *host_q, hipStream_t stream, std::string &err,
@@ -708,6 +795,7 @@ static std::vector<int64_t> plan_sizes(const Batch &b)
         k.push_back(s->pair_form);
         k.push_back(s->stp.fast);
         k.push_back(s->stp.half);
+        k.push_back(s->stp.tri);
     }
     return k;
 }
@@ -777,7 +865,7 @@ static int build_plans(Batch &b, std::string &err)
         b.pair_split[g] = pos[kPlanPair] - b.plan_off[kPlanPair];
         for (int s = 0; s < S; ++s) {
             const System *y = b.sys[s];
-            const int path = y->stp.half ? 2 : (y->stp.fast ? 1 : 0);
+            const int path = y->stp.tri ? 3 : (y->stp.half ? 2 : (y->stp.fast ? 1 : 0));
             if (kNumPaths * y->pair_form + path == g)
                 put(kPlanPair, s, (y->n + kPairWave - 1) / kPairWave + y->ncells);
         }

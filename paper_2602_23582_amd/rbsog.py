@@ -34,6 +34,8 @@ ERRORS = {0: "RBSOG_OK", -1: "RBSOG_EINVAL", -2: "RBSOG_ENEUTRAL", -3: "RBSOG_EB
 SCHED_STATIC = 0
 SCHED_PERSISTENT = 1
 AUTOTUNE_CANDIDATES = [("static", 1), ("persistent", 4), ("persistent", 8), ("persistent", 16), ("persistent", 32)]
+# rbsog_batch_autotune_cached: the same schedules without, then with graph replay
+TUNE_CANDIDATES = [(s, w, g) for g in (False, True) for s, w in AUTOTUNE_CANDIDATES]
 
 EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_force_virial", "rbsog_pressure",
            "rbsog_rescale", "rbsog_destroy", "rbsog_strerror", "rbsog_last_error", "rbsog_debug_cells",
@@ -43,7 +45,8 @@ EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_forc
            "rbsog_batch_last_error", "rbsog_server_create", "rbsog_server_submit", "rbsog_server_wait",
            "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_set_energy", "rbsog_server_last_error",
            "rbsog_npt_init", "rbsog_npt_run", "rbsog_batch_create", "rbsog_batch_admit", "rbsog_stage",
-           "rbsog_batch_release", "rbsog_debug_long_range_force", "rbsog_force_virial_noalloc"]
+           "rbsog_batch_release", "rbsog_debug_long_range_force", "rbsog_force_virial_noalloc",
+           "rbsog_batch_autotune_cached", "rbsog_sample_modes_cell"]
 
 COUPLE_ANISO = 0
 COUPLE_SEMI = 1
@@ -123,6 +126,9 @@ def load(path: str | None = None):
         "rbsog_batch_release": (C.c_int, [vp, vp]),
         "rbsog_debug_long_range_force": (C.c_int, [vp, vp, vp, vp]),
         "rbsog_force_virial_noalloc": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, pd, pd]),
+        "rbsog_sample_modes_cell": (C.c_int, [vp, i64, pd, pi32, pi32, pd]),
+        "rbsog_batch_autotune_cached": (C.c_int, [vp, C.c_char_p, i32, pi64, pd, vp, vp, vp, vp, vp, vp, i32, pd,
+                                                  pi32, pi32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -236,6 +242,19 @@ class Context:
         self._check(load().rbsog_sample_modes(self._h, int(step), _pd(self.box), None, None, _pd(S)),
                     "rbsog_sample_modes")
         return None, None, S
+
+    def sample_modes_cell(self, step, h, return_modes=False):
+        """rbsog_sample_modes_cell: sampling on a general cell h (3 x 3, columns the cell vectors)."""
+        self.cell = np.ascontiguousarray(h, dtype=np.float64).reshape(3, 3).copy()
+        S = np.zeros(2)
+        P = self.params.P
+        m_r = np.zeros((P, 3), dtype=np.int32) if return_modes else None
+        m_nr = np.zeros((P, 3), dtype=np.int32) if return_modes else None
+        self._check(load().rbsog_sample_modes_cell(self._h, int(step), _pd(self.cell),
+                                                   _pi32(m_r) if return_modes else None,
+                                                   _pi32(m_nr) if return_modes else None, _pd(S)),
+                    "rbsog_sample_modes_cell")
+        return m_r, m_nr, S
 
     def force_virial(self, x, y, z, fx, fy, fz, energy=True):
         e = np.zeros(3)
@@ -466,6 +485,20 @@ class Batch:
                                                 int(reps), _pd(ms), _pi32(choice)),
                     "rbsog_batch_autotune")
         return int(choice[0]), ms
+
+    def autotune_cached(self, cache_path, steps, boxes, x, y, z, fx, fy, fz, reps=3, force=False):
+        """rbsog_batch_autotune_cached: (index into TUNE_CANDIDATES, per-candidate ms, found in the cache)."""
+        steps = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.int64), (self.nsys,)))
+        boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(self.nsys, 3)
+        ms = np.zeros(len(TUNE_CANDIDATES))
+        choice = np.zeros(1, dtype=np.int32)
+        cached = np.zeros(1, dtype=np.int32)
+        self._check(load().rbsog_batch_autotune_cached(self._h, os.fsencode(cache_path), 1 if force else 0,
+                                                       _pi64(steps), _pd(boxes),
+                                                       *self._arrays((x, y, z, fx, fy, fz)), int(reps), _pd(ms),
+                                                       _pi32(choice), _pi32(cached)),
+                    "rbsog_batch_autotune_cached")
+        return int(choice[0]), ms, bool(cached[0])
 
     def set_timing(self, on=True):
         self._check(load().rbsog_batch_set_timing(self._h, 1 if on else 0), "rbsog_batch_set_timing")
