@@ -5,8 +5,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -455,6 +457,147 @@ int rbsog_batch_autotune(rbsog_batch *b, const int64_t *host_steps, const double
     b->batch.pair_schedule = cands[choice].schedule;
     b->batch.pair_wg_per_cu = cands[choice].wg;
     if (host_choice) *host_choice = choice;
+    return RBSOG_OK;
+}
+
+namespace {
+
+// The cached autotuner's candidates: the pair kernel's schedule and the step's
+// graph replay.  None changes an operation or the order of any sum, so every
+// candidate gives the same bits.
+struct TuneCand {
+    int schedule, wg, graph;
+};
+constexpr TuneCand kTuneCands[] = {
+    {RBSOG_SCHED_STATIC, 1, 0},      {RBSOG_SCHED_PERSISTENT, 4, 0},  {RBSOG_SCHED_PERSISTENT, 8, 0},
+    {RBSOG_SCHED_PERSISTENT, 16, 0}, {RBSOG_SCHED_PERSISTENT, 32, 0}, {RBSOG_SCHED_STATIC, 1, 1},
+    {RBSOG_SCHED_PERSISTENT, 4, 1},  {RBSOG_SCHED_PERSISTENT, 8, 1},  {RBSOG_SCHED_PERSISTENT, 16, 1},
+    {RBSOG_SCHED_PERSISTENT, 32, 1}};
+constexpr int kNumTuneCands = sizeof(kTuneCands) / sizeof(kTuneCands[0]);
+static_assert(kNumTuneCands == RBSOG_TUNE_CANDIDATES, "candidate count of the header");
+
+std::mutex g_tune_mu;  // one reader or writer of a cache file at a time in this process
+
+// The cache key: the device (architecture and compute units), the batch's
+// atoms rounded down to a power of two and its largest batch size P rounded
+// up to one.
+int tune_key(rbsog_batch *b, std::string &key)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(b, hipGetDevice(&dev));
+    HIP_TRY(b, hipGetDeviceProperties(&prop, dev));
+    std::string arch(prop.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));
+    int nb = 0;
+    while ((int64_t{2} << nb) <= b->ntot) ++nb;
+    int pmax = 1;
+    for (const auto &s : b->systems) pmax = std::max(pmax, static_cast<int>(s->prm.P));
+    int pb = 1;
+    while (pb < pmax) pb <<= 1;
+    key = arch + " cu" + std::to_string(prop.multiProcessorCount) + " n2^" + std::to_string(nb) + " P" +
+          std::to_string(pb);
+    return RBSOG_OK;
+}
+
+// the last line of the file for this key: candidate index and its step time
+bool tune_lookup(const char *path, const std::string &key, int &choice, double &ms)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        const char *bar = std::strchr(line, '|');
+        if (!bar || std::string(line, bar - line) != key) continue;
+        int c = -1;
+        double m = 0.0;
+        if (std::sscanf(bar + 1, "%d %lf", &c, &m) == 2 && c >= 0 && c < kNumTuneCands) {
+            choice = c;
+            ms = m;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+}  // namespace
+
+int rbsog_batch_autotune_cached(rbsog_batch *b, const char *cache_path, int32_t force, const int64_t *host_steps,
+                                const double *host_boxes, const double *x, const double *y, const double *z,
+                                double *fx, double *fy, double *fz, int32_t reps, double *host_ms,
+                                int32_t *host_choice, int32_t *host_cached)
+{
+    if (!b || !cache_path) return RBSOG_EINVAL;
+    b->err.clear();
+    if (b->of_contexts) return fail(b, RBSOG_EINVAL, "the autotuner times batches built by rbsog_batch_setup");
+    if (reps < 1 || reps > 1000) return fail(b, RBSOG_EINVAL, "reps must be in [1, 1000]");
+    std::string key;
+    RB_TRY(tune_key(b, key));
+    if (host_ms)
+        for (int c = 0; c < kNumTuneCands; ++c) host_ms[c] = 0.0;
+    int choice = 0;
+    double best = 0.0;
+    bool hit = false;
+    if (!force) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        hit = tune_lookup(cache_path, key, choice, best);
+    }
+    if (!hit) {
+        hipEvent_t e0, e1;
+        HIP_TRY(b, hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(b, RBSOG_EDEVICE, "event creation failed");
+        }
+        best = 1e300;
+        int rc = RBSOG_OK;
+        for (int c = 0; c < kNumTuneCands && rc == RBSOG_OK; ++c) {
+            b->batch.pair_schedule = kTuneCands[c].schedule;
+            b->batch.pair_wg_per_cu = kTuneCands[c].wg;
+            b->use_graph = kTuneCands[c].graph != 0;
+            // one untimed step (it captures the graph when one is replayed)
+            rc = step_impl(b, host_steps, host_boxes, x, y, z, fx, fy, fz, nullptr, nullptr, nullptr);
+            if (rc == RBSOG_OK && hipStreamSynchronize(b->batch.stream) != hipSuccess) rc = RBSOG_EDEVICE;
+            if (rc != RBSOG_OK) break;
+            (void)hipEventRecord(e0, b->batch.stream);
+            for (int r = 0; r < reps && rc == RBSOG_OK; ++r)
+                rc = step_impl(b, host_steps, host_boxes, x, y, z, fx, fy, fz, nullptr, nullptr, nullptr);
+            (void)hipEventRecord(e1, b->batch.stream);
+            float ms = 0.f;
+            if (rc == RBSOG_OK &&
+                (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = RBSOG_EDEVICE;
+            const double mean = ms / reps;
+            if (host_ms) host_ms[c] = mean;
+            if (mean < best) {
+                best = mean;
+                choice = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != RBSOG_OK) {
+            if (b->err.empty()) b->err = "autotune step failed";
+            return rc;
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        FILE *f = std::fopen(cache_path, "a");
+        if (!f) return fail(b, RBSOG_EINVAL, (std::string("cannot append to the tuning cache ") + cache_path).c_str());
+        const bool ok = std::fprintf(f, "%s|%d %.6f schedule=%s wg_per_cu=%d graph=%d\n", key.c_str(), choice, best,
+                                     kTuneCands[choice].schedule == RBSOG_SCHED_STATIC ? "static" : "persistent",
+                                     kTuneCands[choice].wg, kTuneCands[choice].graph) > 0;
+        if (std::fclose(f) != 0 || !ok)
+            return fail(b, RBSOG_EINVAL, (std::string("cannot write the tuning cache ") + cache_path).c_str());
+    } else if (host_ms) {
+        host_ms[choice] = best;
+    }
+    b->batch.pair_schedule = kTuneCands[choice].schedule;
+    b->batch.pair_wg_per_cu = kTuneCands[choice].wg;
+    b->use_graph = kTuneCands[choice].graph != 0;
+    if (host_choice) *host_choice = choice;
+    if (host_cached) *host_cached = hit ? 1 : 0;
     return RBSOG_OK;
 }
 

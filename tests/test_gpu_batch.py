@@ -162,6 +162,43 @@ def test_autotune_keeps_results(torch, rb):
         assert np.array_equal(P0, P1) and np.array_equal(U0, U1)
 
 
+def test_cached_autotune_reads_back_its_choice(torch, rb, tmp_path):
+    """rbsog_batch_autotune_cached: a first call times the ten candidates
+    (schedules with and without graph replay) and appends the fastest to the
+    cache file; a second call for the same key applies it without timing; a
+    forced call times again.  Results are bitwise the same under every
+    choice."""
+    systems = _systems()
+    steps = [9] * len(systems)
+    boxes = np.array([s["box"] for s in systems])
+    path = tmp_path / "tune.txt"
+    with rb.Batch(systems) as b:
+        (x, y, z), f = _concat(torch, systems)
+        P0, U0, _ = b.step(steps, boxes, x, y, z, *f, energy=False)
+        F0 = torch.stack(f, 1).clone()
+        c1, ms1, hit1 = b.autotune_cached(path, steps, boxes, x, y, z, *f, reps=2)
+        print("autotune_cached", c1, rb.TUNE_CANDIDATES[c1], ms1, flush=True)
+        assert not hit1 and 0 <= c1 < len(rb.TUNE_CANDIDATES) and np.all(ms1 > 0)
+        assert ms1[c1] == ms1.min()
+        lines = path.read_text().splitlines()
+        assert len(lines) == 1 and lines[0].split("|")[1].split()[0] == str(c1)
+        P1, U1, _ = b.step(steps, boxes, x, y, z, *f, energy=False)
+        assert np.array_equal(P0, P1) and np.array_equal(U0, U1) and torch.equal(F0, torch.stack(f, 1))
+        c2, ms2, hit2 = b.autotune_cached(path, steps, boxes, x, y, z, *f, reps=2)
+        assert hit2 and c2 == c1 and abs(ms2[c1] - ms1[c1]) < 1e-5 and np.count_nonzero(ms2) == 1
+        assert len(path.read_text().splitlines()) == 1
+        P2, U2, _ = b.step(steps, boxes, x, y, z, *f, energy=False)
+        assert np.array_equal(P0, P2) and np.array_equal(U0, U2) and torch.equal(F0, torch.stack(f, 1))
+        c3, ms3, hit3 = b.autotune_cached(path, steps, boxes, x, y, z, *f, reps=1, force=True)
+        assert not hit3 and np.all(ms3 > 0) and len(path.read_text().splitlines()) == 2
+    # a batch of another size bucket is a key of its own
+    with rb.Batch(systems[:1]) as b1:
+        (x, y, z), f = _concat(torch, systems[:1])
+        _, _, hit = b1.autotune_cached(path, steps[:1], boxes[:1], x, y, z, *f, reps=1)
+        keys = [l.split("|")[0] for l in path.read_text().splitlines()]
+        assert not hit and len(set(keys)) == 2
+
+
 def test_energy_request_keeps_forces_and_pressure(torch, rb):
     """With the energy sum the fast path takes pair displacements from exact
     fixed-point differences, without it from FP32 block-relative coordinates:
