@@ -74,6 +74,15 @@ def make_workload(name):
     elif name == "electrolyte-10m":
         d = W.electrolyte()
         desc = "electrolyte-10m: 10,000,000 atoms, 1 M ion pairs in water-like molecules, 467.5 A cube, rc 10, P 100"
+    elif name == "sheared-slab-1m":
+        # the slab's fractional positions in a general (triclinic) cell: the
+        # columns of h are the cell vectors (200, 0, 0), (30, 200, 0), (0, 20, 500)
+        d = W.slab()
+        h = np.array([[200.0, 30.0, 0.0], [0.0, 200.0, 20.0], [0.0, 0.0, 500.0]])
+        d["pos"] = (d["pos"] / np.asarray(d["L"])) @ h.T
+        d["h"] = h
+        desc = ("sheared-slab-1m: slab-1m's fractional positions in the general cell with vectors (200, 0, 0), "
+                "(30, 200, 0), (0, 20, 500) A, rc 12 A, P 100 (general-cell sampler and exact pair path)")
     elif name == "water-30k":
         d = W.water_box()
         desc = "water-30k: 10,000 three-site molecules at 1 g/cm^3 (66.9 A cube), rc 10, P 100"
@@ -371,17 +380,22 @@ def extra_workload(torch, name, args, tw):
                for k in range(3))
     fx, fy, fz = (torch.empty_like(x) for _ in range(3))
     L0 = np.asarray(d["L"], dtype=np.float64)
-    with rbsog.Context(d["q"], L0, d["rc"], P=int(d["P"]), seed=args.seed) as c:
+    cell = d.get("h")
+    with rbsog.Context(d["q"], L0 if cell is None else np.diag(cell).copy(), d["rc"], P=int(d["P"]),
+                       seed=args.seed) as c:
         def step(s):
-            mu = L0 * (1.0 + 0.001 * (s % 10)) / c.box
-            c.rescale(mu, x, y, z)
-            c.sample_modes(s, c.box)
+            if cell is None:
+                mu = L0 * (1.0 + 0.001 * (s % 10)) / c.box
+                c.rescale(mu, x, y, z)
+                c.sample_modes(s, c.box)
+            else:  # a general cell: fixed cell and positions (the device rescale is diagonal)
+                c.sample_modes_cell(s, cell)
             c.force_virial(x, y, z, fx, fy, fz, energy=False)
             return c.pressure()
         for s in range(3):
             step(s)
         torch.cuda.synchronize()
-        c.set_timing(True)
+        c.set_timing(2)  # the pair kernel's launches only
         t0 = time.perf_counter()
         marks = []
         for s in range(3, 3 + args.extra_steps):
@@ -408,7 +422,8 @@ def extra_workload(torch, name, args, tw):
                          "achieved": work / t_pair / 1e12 if t_pair > 0 else 0.0,
                          "peak": VALU_LANE_OPS_PER_S / 1e12, "unit": "T FP32 lane-op/s",
                          "frac": work / t_pair / VALU_LANE_OPS_PER_S if t_pair > 0 else 0.0},
-            "distinct_modes": info["nd"]}
+            "distinct_modes": info["nd"],
+            **({"note": "general cell: cell and positions fixed between steps"} if cell is not None else {})}
 
 
 SHELL_FLAGS = {"auto": 0, "full": 2, "half": 4}
@@ -425,7 +440,7 @@ def main():
                     help="atoms whose forces the oracle computes on all host threads (0: every atom, one full step)")
     ap.add_argument("--cpu-single-sample", type=int, default=20_000,
                     help="atoms of the single-thread oracle timing (0: skip)")
-    ap.add_argument("--extra", default="electrolyte-10m",
+    ap.add_argument("--extra", default="electrolyte-10m,sheared-slab-1m",
                     help="comma-separated further workloads timed after the main one (none: skip)")
     ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--shell", choices=["auto", "full", "half"], default="auto",
@@ -491,7 +506,7 @@ def main():
         step(s)
     torch.cuda.synchronize()
     if not args.graph:
-        ctx.set_timing(True)
+        ctx.set_timing(2)  # events around the pair kernel only: each recorded event delays the next launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     marks = []
@@ -501,7 +516,18 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     per_step = 1e3 * np.diff(np.concatenate([[t0], marks]))
-    if args.graph:
+    if not args.graph:
+        timing_pair = ctx.get_timing()["pair"]
+        info = ctx.step_info()
+        # the other kernels' times from a few more steps with every launch timed
+        ctx.set_timing(1)
+        for s in range(args.warmup + args.steps, args.warmup + args.steps + 5):
+            step(s)
+        torch.cuda.synchronize()
+        timing = ctx.get_timing()
+        timing["pair"] = timing_pair
+        ctx.set_timing(False)
+    else:
         # per-kernel times from a few eager steps of the same launches (events
         # cannot be recorded inside the replayed graph)
         ctx.set_timing(True)
@@ -512,10 +538,6 @@ def main():
         ctx.set_timing(False)
         inf = last["info"]
         info = dict(nd=int(inf[0]), acc_r=int(inf[1]), acc_nr=int(inf[2]), npairs=int(inf[3]))
-    else:
-        timing = ctx.get_timing()
-        info = ctx.step_info()
-        ctx.set_timing(False)
     T = t1 - t0
     ms_step = 1e3 * T / args.steps
     value = n * args.steps / T

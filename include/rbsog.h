@@ -304,7 +304,9 @@ int rbsog_step_info(rbsog_ctx *ctx, int64_t host_info[4]);
 /*
  * Per-kernel device timing with HIP events on the context's stream.
  * rbsog_set_timing(ctx, 1) starts recording every kernel launch of
- * rbsog_sample_modes and rbsog_force_virial; rbsog_get_timing writes, for
+ * rbsog_sample_modes and rbsog_force_virial, rbsog_set_timing(ctx, 2) the
+ * pair kernel's launches only (each recorded event can delay the next
+ * launch by a few microseconds); rbsog_get_timing writes, for
  * each kernel k < cap, its name into host_names[k] (up to 31 chars + NUL,
  * 32 bytes per entry), total milliseconds into host_ms[k] and launch count
  * into host_count[k], returning the number of kernels through *host_nk.

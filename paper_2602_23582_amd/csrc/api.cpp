@@ -443,7 +443,7 @@ int rbsog_step_info(rbsog_ctx *c, int64_t host_info[4])
 int rbsog_set_timing(rbsog_ctx *c, int on)
 {
     if (!c) return RBSOG_EINVAL;
-    rbsog::batch_set_timing(c->batch, on != 0);
+    rbsog::batch_set_timing(c->batch, on);
     return RBSOG_OK;
 }
 

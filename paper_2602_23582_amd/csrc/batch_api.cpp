@@ -604,7 +604,7 @@ int rbsog_batch_autotune_cached(rbsog_batch *b, const char *cache_path, int32_t 
 int rbsog_batch_set_timing(rbsog_batch *b, int on)
 {
     if (!b) return RBSOG_EINVAL;
-    rbsog::batch_set_timing(b->batch, on != 0);
+    rbsog::batch_set_timing(b->batch, on);
     return RBSOG_OK;
 }
 

@@ -256,7 +256,7 @@ struct Batch {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<int64_t> graph_key;
     // timing
-    bool timing = false;
+    int timing = 0;  // 0 off, 1 every kernel group, 2 the pair kernel only
     std::vector<Timer> timers;
 };
 
@@ -326,7 +326,7 @@ bool batch_upload_allocates(const Batch &b);
 // Results of every system to the host (synchronises).
 int batch_fetch_results(Batch &b, std::string &err);
 // Per-kernel HIP-event timing of the batch's launches.
-void batch_set_timing(Batch &b, bool on);
+void batch_set_timing(Batch &b, int level);
 int batch_get_timing(Batch &b, int32_t cap, int32_t *host_nk, char *host_names, double *host_ms,
                      int64_t *host_count, std::string &err);
 

@@ -964,9 +964,14 @@ int batch_fetch_results(Batch &b, std::string &err)
     return RBSOG_OK;
 }
 
+static bool timed(const Batch &b, const char *name)
+{
+    return b.timing == 1 || (b.timing == 2 && std::strcmp(name, "pair") == 0);
+}
+
 void timer_begin(Batch &b, const char *name, hipStream_t stream)
 {
-    if (!b.timing) return;
+    if (!timed(b, name)) return;
     Timer *t = nullptr;
     for (auto &x : b.timers)
         if (x.name == name) t = &x;
@@ -990,7 +995,7 @@ void timer_begin(Batch &b, const char *name, hipStream_t stream)
 
 void timer_end(Batch &b, const char *name, hipStream_t stream)
 {
-    if (!b.timing) return;
+    if (!timed(b, name)) return;
     for (auto &x : b.timers)
         if (x.name == name && !x.pending.empty()) {
             (void)hipEventRecord(x.pending.back().second, stream);
@@ -998,12 +1003,12 @@ void timer_end(Batch &b, const char *name, hipStream_t stream)
         }
 }
 
-void batch_set_timing(Batch &b, bool on)
+void batch_set_timing(Batch &b, int level)
 {
     (void)hipStreamSynchronize(b.aux);
     (void)hipStreamSynchronize(b.stream);
     free_timers(b);
-    b.timing = on;
+    b.timing = level == 1 || level == 2 ? level : 0;
 }
 
 int batch_get_timing(Batch &b, int32_t cap, int32_t *host_nk, char *host_names, double *host_ms,

@@ -321,7 +321,8 @@ class Context:
         return dict(nd=int(info[0]), acc_r=int(info[1]), acc_nr=int(info[2]), npairs=int(info[3]))
 
     def set_timing(self, on=True):
-        self._check(load().rbsog_set_timing(self._h, 1 if on else 0), "rbsog_set_timing")
+        """rbsog_set_timing: True or 1 every kernel group, 2 the pair kernel only, False off."""
+        self._check(load().rbsog_set_timing(self._h, int(on)), "rbsog_set_timing")
 
     def get_timing(self):
         rc_, out = _timing_table(load().rbsog_get_timing, self._h)
@@ -501,7 +502,7 @@ class Batch:
         return int(choice[0]), ms, bool(cached[0])
 
     def set_timing(self, on=True):
-        self._check(load().rbsog_batch_set_timing(self._h, 1 if on else 0), "rbsog_batch_set_timing")
+        self._check(load().rbsog_batch_set_timing(self._h, int(on)), "rbsog_batch_set_timing")
 
     def get_timing(self):
         rc_, out = _timing_table(load().rbsog_batch_get_timing, self._h)

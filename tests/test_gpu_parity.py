@@ -455,6 +455,27 @@ def test_bitwise_reproducible(torch, rb):
     assert out[0]["U"] == out[1]["U"]
 
 
+def test_timing_levels(torch, rb):
+    """rbsog_set_timing: level 1 times every kernel group, level 2 the pair
+    kernel alone; timing never changes a result."""
+    d = W.water_box(n_mol=3000, seed=3)
+    out = []
+    for level in (0, 1, 2):
+        with rb.Context(d["q"], d["L"], d["rc"], P=100, seed=4) as ctx:
+            if level:
+                ctx.set_timing(level)
+            out.append(gpu_step(torch, ctx, d["pos"], 2, d["L"]))
+            if level:
+                t = ctx.get_timing()
+                if level == 1:
+                    assert {"sampler", "bin", "pair", "sk", "reduce", "force"} <= set(t), t
+                else:
+                    assert set(t) == {"pair"}, t
+                assert t["pair"][1] == 1 and t["pair"][0] > 0
+    for o in out[1:]:
+        assert np.array_equal(o["F"], out[0]["F"]) and np.array_equal(o["P"], out[0]["P"])
+
+
 GROWTH = [1.0, 1.15, 1.30, 1.0, 1.45, 1.15]  # 6, 7, 8, 6, 9, 7 cells per edge at rc 10
 
 
