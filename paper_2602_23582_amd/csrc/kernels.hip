@@ -244,12 +244,19 @@ __device__ void mode_weights(const SampArgs &a, const int m[3], double *w, doubl
         double e[3][kGl];
         for (int d = 0; d < 3; ++d)
             for (int i = 0; i < kGl; ++i) e[d][i] = exp(-2.0 * aa * cm[d] * t->glx[i]);
-        const double *T = a.gltab + tabi * (kGl * kGl * kGl);
+        // every lane reads the same table entries: a row's kGl loads are
+        // issued together (the sum keeps its order)
+        const RB_GLOBAL double *T = gp(a.gltab) + tabi * (kGl * kGl * kGl);
         double acc = 0.0;
         for (int i = 0; i < kGl; ++i)
             for (int j = 0; j < kGl; ++j) {
+                const RB_GLOBAL double *Tr = T + (i * kGl + j) * kGl;
+                double t[kGl];
+#pragma unroll
+                for (int k = 0; k < kGl; ++k) t[k] = Tr[k];
                 double row = 0.0;
-                for (int k = 0; k < kGl; ++k) row += T[(i * kGl + j) * kGl + k] * e[2][k];
+#pragma unroll
+                for (int k = 0; k < kGl; ++k) row += t[k] * e[2][k];
                 acc += e[0][i] * e[1][j] * row;
             }
         const double rs = sqrt(kPi) * s0;
@@ -835,32 +842,38 @@ __global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restric
     if (!__any(active)) return;
     const int c = active ? gp(D.cell)[i] : 0;
     const int slot = aggregated_increment<true>(D.cursor, c, active);
-    if (active) gp(D.keys)[gp(D.start)[c] + slot] = cell_key<T>(D, i);
+    if (active) {
+        // the key and the whole record go to the binned slot, so that the
+        // ordering kernel reads each cell's records as one contiguous range
+        const int64_t pos = gp(D.start)[c] + slot;
+        const int64_t n = D.n;
+        const RB_GLOBAL typename T::fix *u = gp(static_cast<const typename T::fix *>(D.u));
+        typename T::Rec r;
+        r.x = u[i];
+        r.y = u[n + i];
+        r.z = u[2 * n + i];
+        r.q = gp(static_cast<const typename T::real *>(D.q))[i];
+        gp(D.keys)[pos] = cell_key<T>(D, i);
+        gstore(static_cast<typename T::Rec *>(D.urec) + pos, r);
+    }
 }
 
 // Within each cell, atoms are ordered by their key (z, then index); keys are
 // unique, so the order does not depend on the scatter's.  One workgroup per
-// cell: a cell of up to 256 atoms is sorted in LDS (bitonic network over the
-// next power of two); a larger cell ranks each atom against all keys of the
-// cell, which pass through LDS 256 at a time while every thread holds
-// kRankKeys of the keys it ranks in registers.  A single-cell system has one
-// workgroup per kOrderPart of its keys instead.  The sorted slot receives the
-// atom's index and its record.
+// cell ranks each of the cell's keys against all of them (the keys pass
+// through LDS 256 at a time, every thread holding kRankKeys of the keys it
+// ranks in registers; a cell of up to 256 atoms is one tile and one key a
+// thread).  A single-cell system has one workgroup per kOrderPart of its keys
+// instead.  The record in binned slot j goes to sorted slot rank j, with the
+// atom's index: both reads and writes stay inside the cell's range.
 constexpr int kRankKeys = 4;
 static_assert(256 * kRankKeys == kOrderPart, "one rank pass per part of a single cell");
 template <class T>
-__device__ inline void write_sorted(const SysDesc &D, int slot, uint64_t key)
+__device__ inline void move_sorted(const SysDesc &D, int from, int to, uint64_t key)
 {
-    const int64_t n = D.n;
-    const int i = static_cast<int>(key & 0xFFFFFFFFull);
-    gp(D.perm)[slot] = i;
-    const RB_GLOBAL typename T::fix *u = gp(static_cast<const typename T::fix *>(D.u));
-    typename T::Rec r;
-    r.x = u[i];
-    r.y = u[n + i];
-    r.z = u[2 * n + i];
-    r.q = gp(static_cast<const typename T::real *>(D.q))[i];
-    gstore(static_cast<typename T::Rec *>(D.rec) + slot, r);
+    gp(D.perm)[to] = static_cast<int>(key & 0xFFFFFFFFull);
+    const typename T::Rec r = gload(static_cast<const typename T::Rec *>(D.urec) + from);
+    gstore(static_cast<typename T::Rec *>(D.rec) + to, r);
 }
 
 template <class T>
@@ -878,25 +891,12 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
     if (cnt == 0) return;
     const RB_GLOBAL uint64_t *keys = gp(D.keys);
     if (cnt <= 256) {  // a single cell this small has one part
-        int N = 1;
-        while (N < cnt) N <<= 1;
-        s_key[tid] = tid < cnt ? keys[s0 + tid] : ~0ull;
+        const uint64_t mine = tid < cnt ? keys[s0 + tid] : ~0ull;
+        s_key[tid] = mine;
         __syncthreads();
-        for (int k = 2; k <= N; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                const int p = tid ^ j;
-                if (tid < N && p > tid) {
-                    const uint64_t a = s_key[tid], b = s_key[p];
-                    const bool up = (tid & k) == 0;
-                    if ((a > b) == up) {
-                        s_key[tid] = b;
-                        s_key[p] = a;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        if (tid < cnt) write_sorted<T>(D, s0 + tid, s_key[tid]);
+        int rank = 0;
+        for (int j = 0; j < cnt; ++j) rank += s_key[j] < mine;
+        if (tid < cnt) move_sorted<T>(D, s0 + tid, s0 + rank, mine);
     } else {
         const int lo = single ? e.y * kOrderPart : 0;
         const int hi = single ? min(cnt, lo + kOrderPart) : cnt;
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
             }
             for (int r = 0; r < kRankKeys; ++r) {
                 const int t = base + 256 * r + tid;
-                if (t < hi) write_sorted<T>(D, s0 + rank[r], mine[r]);
+                if (t < hi) move_sorted<T>(D, s0 + t, s0 + rank[r], mine[r]);
             }
         }
     }
@@ -949,7 +949,7 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
 #define RBSOG_PAIR_CHUNK 128
 #endif
 #ifndef RBSOG_PAIR_OCC
-#define RBSOG_PAIR_OCC 6
+#define RBSOG_PAIR_OCC 5
 #endif
 #ifndef RBSOG_FAST_FILTER
 #define RBSOG_FAST_FILTER 1
@@ -1277,9 +1277,27 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const fix oy_ = static_cast<fix>(__shfl(static_cast<long long>(ri.y), 0, 64));
     const fix oz_ = static_cast<fix>(__shfl(static_cast<long long>(ri.z), 0, 64));
     const float rcf = static_cast<float>(sqrt(static_cast<double>(rc2))) + 1e-3f;
-    const float xi = static_cast<float>(static_cast<sfix>(ri.x - ox)) * static_cast<float>(sx);
-    const float yi = static_cast<float>(static_cast<sfix>(ri.y - oy_)) * static_cast<float>(sy);
-    const float zi = static_cast<float>(static_cast<sfix>(ri.z - oz_)) * static_cast<float>(sz);
+    // coordinates of a record relative to o: the wrapped fixed-point offset
+    // scaled by L (a box) or, as a fractional offset, times h (a general cell)
+    float hf[9];
+    if constexpr (TRI)
+        for (int k = 0; k < 9; ++k) hf[k] = static_cast<float>(St.h[k]);
+    auto relpos = [&](const Rec &r, float &px, float &py, float &pz) {
+        if constexpr (TRI) {
+            const float a = static_cast<float>(static_cast<sfix>(r.x - ox)) * 0x1.0p-32f;
+            const float b = static_cast<float>(static_cast<sfix>(r.y - oy_)) * 0x1.0p-32f;
+            const float c = static_cast<float>(static_cast<sfix>(r.z - oz_)) * 0x1.0p-32f;
+            px = fmaf(hf[0], a, fmaf(hf[1], b, hf[2] * c));
+            py = fmaf(hf[3], a, fmaf(hf[4], b, hf[5] * c));
+            pz = fmaf(hf[6], a, fmaf(hf[7], b, hf[8] * c));
+        } else {
+            px = static_cast<float>(static_cast<sfix>(r.x - ox)) * static_cast<float>(sx);
+            py = static_cast<float>(static_cast<sfix>(r.y - oy_)) * static_cast<float>(sy);
+            pz = static_cast<float>(static_cast<sfix>(r.z - oz_)) * static_cast<float>(sz);
+        }
+    };
+    float xi, yi, zi;
+    relpos(ri, xi, yi, zi);
     const float ax = -2.0f * xi, ay = -2.0f * yi, az = -2.0f * zi;
     const float thr = valid ? rcf * rcf - (xi * xi + yi * yi + zi * zi) : -INFINITY;
 
@@ -1293,8 +1311,14 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         const int nvalid = min(kPairWave, ce - cs - cb.y * kPairWave);
         const sfix rzi = static_cast<sfix>(ri.z - oz_);
         const sfix zext = __shfl(rzi, nvalid - 1, 64);
-        const uint32_t reach =
-            static_cast<uint32_t>(ceil(static_cast<double>(rcf) / St.L[2] * 4294967296.0)) + 2u;
+        // a partner within rc differs by at most rc / w_z in s_z (w_z the
+        // distance between the cell's z faces; L_z for a box)
+        double zspan;
+        if constexpr (TRI)
+            zspan = static_cast<double>(rcf) * sqrt(St.hi[6] * St.hi[6] + St.hi[7] * St.hi[7] + St.hi[8] * St.hi[8]);
+        else
+            zspan = static_cast<double>(rcf) / St.L[2];
+        const uint32_t reach = static_cast<uint32_t>(ceil(zspan * 4294967296.0)) + 2u;
         const uint32_t za = static_cast<uint32_t>(oz_) - reach;
         const uint32_t zb = static_cast<uint32_t>(oz_) + static_cast<uint32_t>(zext) + reach;
         if (lane < 9) {
@@ -1455,9 +1479,8 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                 if (r + step < kMaxRanges && sh.pre[r + step] <= f) r += step;
             const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
             if (fast) {
-                const float xj = static_cast<float>(static_cast<sfix>(rj.x - ox)) * static_cast<float>(sx);
-                const float yj = static_cast<float>(static_cast<sfix>(rj.y - oy_)) * static_cast<float>(sy);
-                const float zj = static_cast<float>(static_cast<sfix>(rj.z - oz_)) * static_cast<float>(sz);
+                float xj, yj, zj;
+                relpos(rj, xj, yj, zj);
                 sh.rel[k] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
                 if constexpr (kRelEval) sh.rtile[k] = make_float4(xj, yj, zj, static_cast<float>(rj.q));
                 else sh.tile[k] = rj;
@@ -2102,11 +2125,11 @@ __global__ __launch_bounds__(64) void k_pair_gather(const SysDesc *__restrict__ 
 
 // Static schedule: workgroup g runs plan entry g.
 // Register budget of the FP32 pair kernel: RBSOG_PAIR_OCC waves per SIMD
-// without the energy sum, one fewer with it.  The kernel waits on LDS more
-// than it computes, so occupancy pays: at 6 waves the relative-coordinate
-// kernel spills 40 bytes per lane to scratch, and fewer waves without
-// spills measured slower.
-// FP64 keeps the default.
+// without the energy sum, one fewer with it (which the compiler meets with 5
+// waves' registers).  At 5 waves the relative-coordinate kernel holds its
+// state in 94 registers with no scratch; at 6 it spilled 40 bytes per lane
+// (about 4e7 bytes of scratch traffic a launch on 1e6 atoms) and measured
+// even with 5; 7 waves were slower.  FP64 keeps the default.
 template <class T, bool E>
 constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? (E ? RBSOG_PAIR_OCC - 1 : RBSOG_PAIR_OCC) : 1; }
 
@@ -2791,7 +2814,7 @@ template <class T, int M, bool E>
 static void pair_launch(Batch &b, int form)
 {
     pair_launch_group<T, M, E, false>(b, kNumPaths * form);
-    pair_launch_group<T, M, E, false, true>(b, kNumPaths * form + 3);
+    pair_launch_group<T, M, E, true, true>(b, kNumPaths * form + 3);
     if constexpr (sizeof(typename T::real) == 4) {
         pair_launch_group<T, M, E, true>(b, kNumPaths * form + 1);
         pair_launch_half<T, M, E>(b, kNumPaths * form + 2);

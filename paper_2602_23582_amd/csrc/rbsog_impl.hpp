@@ -110,6 +110,7 @@ struct SysDesc {
     int32_t *scan_tmp;    // [2 * 1024 + 2] block sums of the two-level scan
     int2 *blocks;         // pair-block table (cell, sub-block) [pair_cap]
     uint64_t *keys;       // binned slot -> (z sort key << 32) | system atom index
+    void *urec;           // binned slot -> the atom's record (fixed-point position + charge), unsorted within its cell
     int32_t *perm;        // sorted slot -> system atom index
     void *rec;            // sorted records (fixed-point position + charge)
     void *fsr;            // short-range force, sorted order (3 SoA planes)
@@ -172,7 +173,8 @@ enum PairForm {
 // Pair launches: one per (form, path); path 0 is the exact filter, path 1 the
 // FP32 relative-coordinate filter over whole neighbour columns (SysStep::fast)
 // with the full shell, path 2 the same with the half shell (SysStep::half),
-// path 3 the exact filter on a general cell (SysStep::tri).
+// path 3 a general cell (SysStep::tri): the relative-coordinate filter when
+// SysStep::fast (FP32, four or more cells per edge), else the exact one.
 constexpr int kNumPaths = 4;
 constexpr int kNumPairGroups = kNumPaths * kNumForms;
 

@@ -23,10 +23,10 @@ bool is_fp64(const rbsog_params &p) { return p.precision == RBSOG_PREC_FP64; }
 
 // byte sizes of the per-atom and per-mode buffers, in carving order
 struct AtomLayout {
-    size_t q, u, cell, keys, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, pair_red, coef, scan_tmp;
+    size_t q, u, cell, keys, urec, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, pair_red, coef, scan_tmp;
     size_t total() const
     {
-        return q + u + cell + keys + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + pair_red + coef +
+        return q + u + cell + keys + urec + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + pair_red + coef +
                scan_tmp;
     }
 };
@@ -42,6 +42,7 @@ AtomLayout atom_layout(const rbsog_params &p, int64_t n)
     a.u = align_up(3 * n * fsz);
     a.cell = align_up(n * 4);
     a.keys = align_up(n * 8);
+    a.urec = align_up(n * recsz);
     a.perm = align_up(n * 4);
     a.rec = align_up(n * recsz);
     a.fsr = align_up(3 * n * rsz);
@@ -444,9 +445,14 @@ int system_set_cell(System &s, const double h[9], std::string &err)
         t.nc[d] = s.nc[d];
     }
     t.ncells = static_cast<int32_t>(s.ncells);
-    t.fast = 0;
+    // The FP32 relative-coordinate path of a box holds for the fractional
+    // grid too (every partner of a block atom within two cells of its first
+    // atom along each fractional axis, under half the cell): offsets from
+    // that atom are wrapped fractional differences, times h.
+    const bool fast = !is_fp64(s.prm) && s.nc[0] >= 4 && s.nc[1] >= 4 && s.nc[2] >= 4;
+    t.fast = fast ? 1 : 0;
     t.half = 0;
-    t.g = 1;
+    t.g = fast ? std::max(1, std::min(kSuperCells, (s.nc[2] - 3) / 2)) : 1;
     t.thr16 = 0;
     t.Sr = s.Sr;
     t.Snr = s.Snr;
@@ -494,6 +500,7 @@ void system_carve_atoms(System &s, void *mem)
     d.u = take(a.u);
     d.cell = static_cast<int32_t *>(take(a.cell));
     d.keys = static_cast<uint64_t *>(take(a.keys));
+    d.urec = take(a.urec);
     d.perm = static_cast<int32_t *>(take(a.perm));
     d.rec = take(a.rec);
     d.fsr = take(a.fsr);

@@ -29,6 +29,8 @@ CELLS = {
     "sheared": np.array([[21.0, 4.0, 2.0], [0.0, 20.0, -3.5], [0.0, 0.0, 22.0]]),
     "skewed": np.array([[24.0, -6.0, 5.0], [0.0, 22.0, 4.0], [1.5, 0.0, 23.0]]),
     "thin": np.array([[13.0, 3.0, 0.0], [0.0, 14.0, 2.0], [0.0, 0.0, 15.0]]),  # fewer than 3 cells per edge
+    # four or more cells per edge: FP32C takes the relative-coordinate filter and evaluation
+    "wide": np.array([[30.0, 5.0, 3.0], [0.0, 28.0, -4.0], [2.0, 0.0, 32.0]]),
 }
 
 
@@ -84,7 +86,7 @@ def _check(g, o, tol, atol, what):
         assert abs(g["U"] - o["U"]) <= tol * abs(o["U"]), what
 
 
-@pytest.mark.parametrize("cell", ["sheared", "skewed", "thin"])
+@pytest.mark.parametrize("cell", ["sheared", "skewed", "thin", "wide"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_cell_matches_oracle(torch, rb, orc, cell, precision):
     h = CELLS[cell]
