@@ -108,6 +108,18 @@ __device__ inline T wave_sum(T v)
     return v;
 }
 
+// wave-wide minimum and maximum, returned as wave-uniform (scalar) values
+__device__ inline float wave_min_uniform(float v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ inline float wave_max_uniform(float v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 // ----------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11) and the sampler's draws
 // ----------------------------------------------------------------------------
@@ -1300,6 +1312,16 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     relpos(ri, xi, yi, zi);
     const float ax = -2.0f * xi, ay = -2.0f * yi, az = -2.0f * zi;
     const float thr = valid ? rcf * rcf - (xi * xi + yi * yi + zi * zi) : -INFINITY;
+    // the block's bounding box in relative coordinates (fast path)
+    float bx0 = 0.f, bx1 = 0.f, by0 = 0.f, by1 = 0.f, bz0 = 0.f, bz1 = 0.f;
+    if (kIsF32 && fast) {
+        bx0 = wave_min_uniform(valid ? xi : INFINITY);
+        bx1 = wave_max_uniform(valid ? xi : -INFINITY);
+        by0 = wave_min_uniform(valid ? yi : INFINITY);
+        by1 = wave_max_uniform(valid ? yi : -INFINITY);
+        bz0 = wave_min_uniform(valid ? zi : INFINITY);
+        bz1 = wave_max_uniform(valid ? zi : -INFINITY);
+    }
 
     if (kIsF32 && fast) {
         // The block's atoms are sorted by z and span [0, zext] in fixed point
@@ -1469,22 +1491,51 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         return ng > 0 ? 4 * (ng - 1) + min(4, total - 4 * glast) : 0;
     };
     for (int ch = 0; ch < nch; ++ch) {
-        const int filled = chunk_filled(ch);
-        for (int k = lane; k < filled; k += 64) {
-            const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
-            // the range holding flattened index f: the last r with pre[r] <= f
+        int filled = chunk_filled(ch);
+        // the range holding flattened index f: the last r with pre[r] <= f
+        auto range_of = [&](int f) {
             int r = 0;
 #pragma unroll
             for (int step = 16; step >= 1; step >>= 1)
                 if (r + step < kMaxRanges && sh.pre[r + step] <= f) r += step;
-            const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
-            if (fast) {
-                float xj, yj, zj;
-                relpos(rj, xj, yj, zj);
-                sh.rel[k] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
-                if constexpr (kRelEval) sh.rtile[k] = make_float4(xj, yj, zj, static_cast<float>(rj.q));
-                else sh.tile[k] = rj;
-            } else {
+            return r;
+        };
+        if (fast) {
+            // Candidates farther than the padded cutoff from the block's
+            // bounding box cannot pass the filter for any lane: they are
+            // dropped here, and the survivors are packed in their order (the
+            // walk then meets every pair in the same order as without the cut).
+            int kept = 0;
+            for (int k0 = 0; k0 < filled; k0 += 64) {
+                const int k = k0 + lane;
+                bool keep = false;
+                Rec rj{};
+                float xj = 0.f, yj = 0.f, zj = 0.f;
+                if (k < filled) {
+                    const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
+                    const int r = range_of(f);
+                    rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
+                    relpos(rj, xj, yj, zj);
+                    const float ex = fmaxf(fmaxf(bx0 - xj, xj - bx1), 0.f);
+                    const float ey = fmaxf(fmaxf(by0 - yj, yj - by1), 0.f);
+                    const float ez = fmaxf(fmaxf(bz0 - zj, zj - bz1), 0.f);
+                    keep = fmaf(ez, ez, fmaf(ey, ey, ex * ex)) < rcf * rcf;
+                }
+                const uint64_t bal = __ballot(keep);
+                if (keep) {
+                    const int pos = kept + __popcll(bal & ((1ull << lane) - 1ull));
+                    sh.rel[pos] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
+                    if constexpr (kRelEval) sh.rtile[pos] = make_float4(xj, yj, zj, static_cast<float>(rj.q));
+                    else sh.tile[pos] = rj;
+                }
+                kept += __popcll(bal);
+            }
+            filled = kept;
+        } else {
+            for (int k = lane; k < filled; k += 64) {
+                const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
+                const int r = range_of(f);
+                const Rec rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
                 sh.tile[k] = rj;
                 if constexpr (kIsF32 && !FAST && !TRI) sh.pk[k] = pack16(rj);
             }
@@ -2124,14 +2175,14 @@ __global__ __launch_bounds__(64) void k_pair_gather(const SysDesc *__restrict__ 
 }
 
 // Static schedule: workgroup g runs plan entry g.
-// Register budget of the FP32 pair kernel: RBSOG_PAIR_OCC waves per SIMD
-// without the energy sum, one fewer with it (which the compiler meets with 5
-// waves' registers).  At 5 waves the relative-coordinate kernel holds its
-// state in 94 registers with no scratch; at 6 it spilled 40 bytes per lane
-// (about 4e7 bytes of scratch traffic a launch on 1e6 atoms) and measured
-// even with 5; 7 waves were slower.  FP64 keeps the default.
+// Register budget of the FP32 pair kernel: RBSOG_PAIR_OCC waves per SIMD,
+// with or without the energy sum.  At 5 waves the relative-coordinate kernel
+// holds its state in 96 registers (100 with the energy sum) with no scratch;
+// at 6 it spilled 40 bytes per lane (about 4e7 bytes of scratch traffic a
+// launch on 1e6 atoms) and measured even with 5; 7 waves were slower.  FP64
+// keeps the default.
 template <class T, bool E>
-constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? (E ? RBSOG_PAIR_OCC - 1 : RBSOG_PAIR_OCC) : 1; }
+constexpr int pair_min_waves() { return sizeof(typename T::real) == 4 ? RBSOG_PAIR_OCC : 1; }
 
 // Workgroups go to the eight XCDs in turn (workgroup w to XCD w mod 8), each
 // XCD with its own L2.  Consecutive plan entries are neighbouring blocks of one
