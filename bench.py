@@ -102,23 +102,41 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(config):
-    """HBM bytes per pair-kernel launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
+def read_counters(config):
+    """The committed counter summary of the pair kernel (name -> value text), if
+    it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"pair_kernel_{config}_counters.txt")
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line:
+        if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
+            vals[k.strip()] = v.split("#")[0].strip()
     if vals.get("kernels_sha256") != kernel_hash():
         return None
+    return vals
+
+
+def read_traffic(config):
+    """HBM bytes per pair-kernel launch from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    vals = read_counters(config)
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
     except (KeyError, ValueError):
         return None
+
+
+def read_issued(config, tw):
+    """VALU lane-instructions the pair kernel issues per launch (transcendentals
+    weighed by tw, FP32 lane-op equivalents), from the same counter summary."""
+    vals = read_counters(config)
+    try:
+        valu, trans = float(vals["SQ_INSTS_VALU"]), float(vals["SQ_INSTS_VALU_TRANS_F32"])
+    except (TypeError, KeyError, ValueError):
+        return None
+    return 64.0 * ((valu - trans) + trans * tw)
 
 
 PROBE_KINDS = [  # (name, FP32 FMA per iteration, transcendentals per iteration), per lane
@@ -559,6 +577,12 @@ def main():
                 "work_per_pair": pair_work(tw), "trans_weight": tw, "avg_launch_ms": 1e3 * t_pair,
                 "implemented_form": {"work_per_pair": pair_work_implemented(tw),
                                      "frac": work_impl / t_pair / VALU_LANE_OPS_PER_S if t_pair > 0 else 0.0}}
+    issued = read_issued(args.config, tw)
+    if issued is not None and t_pair > 0:
+        # every VALU instruction the kernel issues (filter, walk, staging, both
+        # sides of each pair), from the committed counters of this source
+        roofline["issued"] = {"lane_ops_per_launch": issued, "per_unordered_pair": issued / info["npairs"],
+                              "frac": issued / t_pair / VALU_LANE_OPS_PER_S}
     sk_w, fo_w = mode_work(tw)
     kernels = {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in timing.items()}
     for k, per in (("sk", sk_w), ("force", fo_w)):
