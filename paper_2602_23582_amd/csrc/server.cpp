@@ -103,6 +103,7 @@ struct Request {
     System sys;
     double *d_pos = nullptr, *d_frc = nullptr;
     int k = 0;  // next step
+    int box_step = -1;  // the step whose box the host-side System holds (set_box done)
     std::vector<double> P, U, fx, fy, fz;
     Clock::time_point t_submit, t_admit, t_done;
     int shared_ticks = 0;
@@ -249,7 +250,10 @@ int tick_launch(rbsog_server *sv, std::string &err)
     }
     for (Request *r : sv->active) {
         System &s = r->sys;
-        rbsog::system_set_box(s, &r->boxes[3 * r->k]);
+        if (r->box_step != r->k) {
+            rbsog::system_set_box(s, &r->boxes[3 * r->k]);
+            r->box_step = r->k;
+        }
         if (s.ncells > s.ncells_cap) {
             err = "cell grid outgrew its reservation";
             return RBSOG_EBOX;
@@ -374,6 +378,15 @@ void worker_main(rbsog_server *sv)
                 }
                 for (Request *r : next)
                     if (rc == RBSOG_OK) rc = admit(sv, r, err);
+                // while the step runs: the next step's box, cell grid,
+                // normalisation sums and start bounds of every request that
+                // continues (this step's SysStep is already in its upload
+                // buffer, so the host copy is free to change)
+                for (Request *r : sv->active)
+                    if (r->k + 1 < r->nsteps) {
+                        rbsog::system_set_box(r->sys, &r->boxes[3 * (r->k + 1)]);
+                        r->box_step = r->k + 1;
+                    }
             }
             const Clock::time_point tw = Clock::now();
             admit2_s = std::chrono::duration<double>(tw - tl).count();
