@@ -1131,6 +1131,30 @@ __device__ __forceinline__ void pair_eval_d(typename T::real dx, typename T::rea
     if constexpr (E) acc.u += inside ? qj * (rinv - sw) : static_cast<real>(0);
 }
 
+// rinv^3 - sum_l wt_l e_l (eq. force_SOG) at r^2 = r2 in FP32: the
+// charge-free factor of a pair's force and virial, unmasked.
+template <class T, int M>
+__device__ __forceinline__ float sog_force_factor(float r2, const Weights<T, M> &W)
+{
+    float swt = 0.0f;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    if constexpr (M == -1) {
+        swt = horner(W.pg, r2 * W.pa - 1.0f);
+    } else if constexpr (M == 0) {
+        for (int l = 0; l < W.m; ++l) {
+            float wl;
+            swt += gauss<T, M, false>(W, l, r2, wl);
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            float wl;
+            swt += gauss<T, M, false>(W, l, r2, wl);
+        }
+    }
+    return rinv * rinv * rinv - swt;
+}
+
 // A pair from fixed-point records: exact minimum-image displacement (integer
 // difference, then scaled), r^2 in one fixed evaluation order, so a pair is
 // inside from both of its atoms.
@@ -1260,7 +1284,9 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const int cz = c % nz, cy = (c / nz) % ny, cx = c / (nz * ny);
     const int gs = min(St.g, nz - cz);
     const int cs = start[c], ce = start[c + gs];
-    const int i = cs + cb.y * kPairWave + lane;
+    const int i0 = cs + cb.y * kPairWave;            // the block's first record
+    const int nblock = min(kPairWave, ce - i0);      // its atoms
+    const int i = i0 + lane;
     const bool valid = i < ce;
     Rec ri{};
     if (valid) ri = gload(rec + i);
@@ -1483,6 +1509,60 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     double fx = 0, fy = 0, fz = 0, v[6] = {0, 0, 0, 0, 0, 0}, uu = 0;
     int hits = 0;    // in-cutoff partners of this lane's atom
 
+    // Pairs inside the block (relative-coordinate path): each unordered pair
+    // once, by Newton's third law within the wavefront.  In round t lane l
+    // meets lane l + t (mod 64), t = 1 .. 32 (t = 32 for l < 32 only), and
+    // lane l + t takes the reaction from it by a shuffle, so every sum keeps
+    // a fixed order.  The virial and the count of such a pair go in twice,
+    // as the full shell's other side would have.  The block's atoms are then
+    // left out of the staged neighbourhood.
+    const bool intra = kRelEval && kIsF32 && fast;
+    if constexpr (kRelEval) {
+        if (intra) {
+            const float qf = valid ? static_cast<float>(ri.q) : 0.0f;
+            PairAcc<T> ia;
+            for (int t = 1; t <= 32; ++t) {
+                const int j = (lane + t) & 63;
+                const float xj = __shfl(xi, j, 64), yj = __shfl(yi, j, 64), zj = __shfl(zi, j, 64);
+                const float qj = __shfl(qf, j, 64);
+                const float dx = xi - xj, dy = yi - yj, dz = zi - zj;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const bool act = valid & (j < nblock) & ((t < 32) | (lane < 32)) & (r2 < rc2) & (r2 > 0.0f);
+                const float k = act ? sog_force_factor<T, M>(r2, W) : 0.0f;
+                const float fq = k * qj;
+                const float fdx = fq * dx, fdy = fq * dy, fdz = fq * dz;
+                const float dx2 = dx + dx, dy2 = dy + dy, dz2 = dz + dz;
+                ia.fx += fdx;
+                ia.fy += fdy;
+                ia.fz += fdz;
+                ia.vxx += fdx * dx2;
+                ia.vyy += fdy * dy2;
+                ia.vzz += fdz * dz2;
+                ia.vxy += fdx * dy2;
+                ia.vxz += fdx * dz2;
+                ia.vyz += fdy * dz2;
+                ia.n += act ? 2 : 0;
+                // the reaction carries this lane's charge; lane l takes it from lane l - t
+                const float kq = k * qf;
+                const int src = (lane - t) & 63;
+                ia.fx -= __shfl(kq * dx, src, 64);
+                ia.fy -= __shfl(kq * dy, src, 64);
+                ia.fz -= __shfl(kq * dz, src, 64);
+            }
+            const double qi = ri.q;
+            hits += ia.n;
+            fx += qi * ia.fx;
+            fy += qi * ia.fy;
+            fz += qi * ia.fz;
+            v[0] += qi * ia.vxx;
+            v[1] += qi * ia.vyy;
+            v[2] += qi * ia.vzz;
+            v[3] += qi * ia.vxy;
+            v[4] += qi * ia.vxz;
+            v[5] += qi * ia.vyz;
+        }
+    }
+
     // this chunk's groups: ch, ch + nch, ...; slots k of the chunk map to
     // flattened indices 4 (ch + nch (k/4)) + k%4, a prefix of them valid
     auto chunk_filled = [&](int ch) {
@@ -1514,12 +1594,14 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                 if (k < filled) {
                     const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
                     const int r = range_of(f);
-                    rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
+                    const int idx = sh.beg[r] + (f - sh.pre[r]);
+                    rj = gload(rec + idx);
                     relpos(rj, xj, yj, zj);
                     const float ex = fmaxf(fmaxf(bx0 - xj, xj - bx1), 0.f);
                     const float ey = fmaxf(fmaxf(by0 - yj, yj - by1), 0.f);
                     const float ez = fmaxf(fmaxf(bz0 - zj, zj - bz1), 0.f);
                     keep = fmaf(ez, ez, fmaf(ey, ey, ex * ex)) < rcf * rcf;
+                    if (intra) keep = keep && (idx < i0 || idx >= i0 + nblock);
                 }
                 const uint64_t bal = __ballot(keep);
                 if (keep) {
