@@ -642,7 +642,6 @@ __global__ __launch_bounds__(kCellBlock) void k_zero(const SysDesc *__restrict__
     const int64_t c = e.y * static_cast<int64_t>(kCellBlock) + threadIdx.x;
     if (c <= stp[e.x].ncells) {
         D.count[c] = 0;
-        D.cursor[c] = 0;
     }
     if (e.y == 0 && threadIdx.x == 0) {
         D.res->bad_input = 0;
@@ -700,7 +699,10 @@ __global__ __launch_bounds__(kAtomBlock) void k_fix(const SysDesc *__restrict__ 
     // atoms are one range of the sorted arrays, ordered by z
     const int32_t id = static_cast<int32_t>(c[2] + static_cast<uint32_t>(nc[2]) * (c[1] + static_cast<uint32_t>(nc[1]) * c[0]));
     if (active) gp(D.cell)[i] = id;
-    aggregated_increment<false>(D.count, id, active);
+    // the atom's place among its cell's atoms, in the order the counts were
+    // taken (the ordering kernel makes the final order independent of it)
+    const int slot = aggregated_increment<true>(D.count, id, active);
+    if (active) gp(D.slot)[i] = slot;
 }
 
 // Two-level exclusive scan of the per-cell counts (and of the per-cell number
@@ -769,64 +771,63 @@ __global__ __launch_bounds__(256) void k_scan_local(const SysDesc *__restrict__ 
     }
 }
 
-// one workgroup per system: exclusive scan of the block sums
-__global__ __launch_bounds__(256) void k_scan_top(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp)
-{
-    __shared__ int s_a[256], s_b[256];
-    const SysDesc &D = desc[blockIdx.x];
-    const int nb = static_cast<int>((stp[blockIdx.x].ncells + kScanBlock - 1) / kScanBlock);
-    int32_t *sums = D.scan_tmp;
-    const int tid = threadIdx.x;
-    int va[4], vb[4], ta = 0, tb = 0;
-    for (int k = 0; k < 4; ++k) {
-        const int i = 4 * tid + k;
-        va[k] = i < nb ? sums[2 * i] : 0;
-        vb[k] = i < nb ? sums[2 * i + 1] : 0;
-        ta += va[k];
-        tb += vb[k];
-    }
-    s_a[tid] = ta;
-    s_b[tid] = tb;
-    __syncthreads();
-    block_scan_256(s_a, tid);
-    block_scan_256(s_b, tid);
-    int ea = s_a[tid] - ta, eb = s_b[tid] - tb;
-    __syncthreads();
-    for (int k = 0; k < 4; ++k) {
-        const int i = 4 * tid + k;
-        if (i < nb) {
-            sums[2 * i] = ea;
-            sums[2 * i + 1] = eb;
-        }
-        ea += va[k];
-        eb += vb[k];
-    }
-    if (tid == 255) {
-        sums[2 * 1024] = ea;      // grand totals
-        sums[2 * 1024 + 1] = eb;
-    }
-}
-
-// final starts, and the pair-block table (cell, sub-block) of each cell
+// Final starts, and the pair-block table (cell, sub-block) of each cell.  A
+// workgroup's cells lie in one scan block b (kScanBlock is a multiple of
+// kCellBlock); it adds the sums of the scan blocks before b itself, and the
+// workgroup holding cell m = ncells also all of them for the totals.
+static_assert(kScanBlock % kCellBlock == 0, "a cell workgroup lies in one scan block");
 __global__ __launch_bounds__(kCellBlock) void k_scan_add(const SysDesc *__restrict__ desc,
                                                          const SysStep *__restrict__ stp,
                                                          const int2 *__restrict__ plan)
 {
+    __shared__ int s_a[256], s_b[256];
     const int2 e = plan[blockIdx.x];
     const SysDesc &D = desc[e.x];
     const int64_t m = stp[e.x].ncells;
-    const int64_t i = e.y * static_cast<int64_t>(kCellBlock) + threadIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t c0 = e.y * static_cast<int64_t>(kCellBlock);
+    const int64_t i = c0 + tid;
     const int32_t *sums = D.scan_tmp;
+    const int nb = static_cast<int>((m + kScanBlock - 1) / kScanBlock);
+    const int b = static_cast<int>(c0 / kScanBlock);
+    const bool holds_m = c0 <= m && m < c0 + kCellBlock;
+    // offsets of scan block b: the block sums before it
+    int pa = 0, pb = 0;
+    for (int k = tid; k < b; k += 256) {
+        pa += sums[2 * k];
+        pb += sums[2 * k + 1];
+    }
+    s_a[tid] = pa;
+    s_b[tid] = pb;
+    __syncthreads();
+    block_scan_256(s_a, tid);
+    block_scan_256(s_b, tid);
+    const int oa = s_a[255], ob = s_b[255];
+    int ta = 0, tb = 0;
+    if (holds_m) {  // uniform over the workgroup
+        pa = pb = 0;
+        for (int k = tid; k < nb; k += 256) {
+            pa += sums[2 * k];
+            pb += sums[2 * k + 1];
+        }
+        __syncthreads();
+        s_a[tid] = pa;
+        s_b[tid] = pb;
+        __syncthreads();
+        block_scan_256(s_a, tid);
+        block_scan_256(s_b, tid);
+        ta = s_a[255];
+        tb = s_b[255];
+    }
     if (i < m) {
-        const int64_t b = i / kScanBlock;
-        D.start[i] += sums[2 * b];
-        const int b0 = D.bstart[i] + sums[2 * b + 1];
+        D.start[i] += oa;
+        const int b0 = D.bstart[i] + ob;
         D.bstart[i] = b0;
-        const int nb = D.nblk[i];
-        for (int k = 0; k < nb; ++k) D.blocks[b0 + k] = make_int2(static_cast<int>(i), k);
+        const int nbk = D.nblk[i];
+        for (int k = 0; k < nbk; ++k) D.blocks[b0 + k] = make_int2(static_cast<int>(i), k);
     } else if (i == m) {
-        D.start[m] = sums[2 * 1024];
-        D.bstart[m] = sums[2 * 1024 + 1];
+        D.start[m] = ta;
+        D.bstart[m] = tb;
     }
 }
 
@@ -852,9 +853,9 @@ __global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restric
     const int64_t i = e.y * static_cast<int64_t>(kAtomBlock) + threadIdx.x;
     const bool active = i < D.n;
     if (!__any(active)) return;
-    const int c = active ? gp(D.cell)[i] : 0;
-    const int slot = aggregated_increment<true>(D.cursor, c, active);
     if (active) {
+        const int c = gp(D.cell)[i];
+        const int slot = gp(D.slot)[i];
         // the key and the whole record go to the binned slot, so that the
         // ordering kernel reads each cell's records as one contiguous range
         const int64_t pos = gp(D.start)[c] + slot;
@@ -2888,7 +2889,6 @@ static hipError_t bin_and_sort_t(Batch &b)
                        plan_ptr(b, kPlanAtoms));
     hipLaunchKernelGGL(k_scan_local, dim3(plan_grid(b, kPlanScan)), dim3(256), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanScan));
-    hipLaunchKernelGGL(k_scan_top, dim3(nsys(b)), dim3(256), 0, b.stream, b.d_desc, b.d_step);
     hipLaunchKernelGGL(k_scan_add, dim3(plan_grid(b, kPlanCells)), dim3(kCellBlock), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanCells));
     hipLaunchKernelGGL(k_scatter<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,

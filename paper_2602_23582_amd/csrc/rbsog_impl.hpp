@@ -106,7 +106,8 @@ struct SysDesc {
     const void *q;        // charges, system order (float or double)
     void *u;              // fixed-point fractional coordinates (3 SoA planes of n)
     int32_t *cell;        // cell of each atom
-    int32_t *count, *cursor, *start, *nblk, *bstart;  // per cell [ncells_cap + 1]
+    int32_t *slot;        // each atom's place among its cell's atoms (binned slot = start + slot)
+    int32_t *count, *start, *nblk, *bstart;  // per cell [ncells_cap + 1]
     int32_t *scan_tmp;    // [2 * 1024 + 2] block sums of the two-level scan
     int2 *blocks;         // pair-block table (cell, sub-block) [pair_cap]
     uint64_t *keys;       // binned slot -> (z sort key << 32) | system atom index

@@ -23,10 +23,10 @@ bool is_fp64(const rbsog_params &p) { return p.precision == RBSOG_PREC_FP64; }
 
 // byte sizes of the per-atom and per-mode buffers, in carving order
 struct AtomLayout {
-    size_t q, u, cell, keys, urec, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, pair_red, coef, scan_tmp;
+    size_t q, u, cell, slot, keys, urec, perm, rec, fsr, mraw, modes, cnt, rho_part, rho, pair_red, coef, scan_tmp;
     size_t total() const
     {
-        return q + u + cell + keys + urec + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + pair_red + coef +
+        return q + u + cell + slot + keys + urec + perm + rec + fsr + mraw + modes + cnt + rho_part + rho + pair_red + coef +
                scan_tmp;
     }
 };
@@ -41,6 +41,7 @@ AtomLayout atom_layout(const rbsog_params &p, int64_t n)
     a.q = align_up(n * rsz);
     a.u = align_up(3 * n * fsz);
     a.cell = align_up(n * 4);
+    a.slot = align_up(n * 4);
     a.keys = align_up(n * 8);
     a.urec = align_up(n * recsz);
     a.perm = align_up(n * 4);
@@ -483,7 +484,7 @@ size_t system_device_bytes(const System &s)
 size_t system_cell_bytes(int64_t n, int64_t ncells_cap)
 {
     const size_t pair_cap = static_cast<size_t>((n + kPairWave - 1) / kPairWave + ncells_cap);
-    return 5 * align_up((ncells_cap + 1) * 4) + align_up(pair_cap * sizeof(int2)) + align_up(pair_cap * 8 * 8);
+    return 4 * align_up((ncells_cap + 1) * 4) + align_up(pair_cap * sizeof(int2)) + align_up(pair_cap * 8 * 8);
 }
 
 void system_carve_atoms(System &s, void *mem)
@@ -499,6 +500,7 @@ void system_carve_atoms(System &s, void *mem)
     d.q = take(a.q);
     d.u = take(a.u);
     d.cell = static_cast<int32_t *>(take(a.cell));
+    d.slot = static_cast<int32_t *>(take(a.slot));
     d.keys = static_cast<uint64_t *>(take(a.keys));
     d.urec = take(a.urec);
     d.perm = static_cast<int32_t *>(take(a.perm));
@@ -521,7 +523,7 @@ void system_carve_cells(System &s, void *mem, int64_t ncells_cap)
     char *p = static_cast<char *>(mem);
     SysDesc &d = s.desc;
     const size_t cb = align_up((ncells_cap + 1) * 4);
-    int32_t **arrs[] = {&d.count, &d.cursor, &d.start, &d.nblk, &d.bstart};
+    int32_t **arrs[] = {&d.count, &d.start, &d.nblk, &d.bstart};
     for (auto a : arrs) {
         *a = reinterpret_cast<int32_t *>(p);
         p += cb;
