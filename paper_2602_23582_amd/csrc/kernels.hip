@@ -607,30 +607,34 @@ __global__ __launch_bounds__(256) void k_sampler(const SysDesc *__restrict__ des
 
 // Wave-aggregated counter increment: every active lane adds 1 to
 // counter[key]; lanes with equal keys are served by one atomic of their
-// leader, and each lane receives the counter's old value plus its rank among
-// those lanes (by lane order).  One atomic per distinct key in the wavefront.
+// leader (the group's first lane), and each lane receives the counter's old
+// value plus its rank among those lanes (by lane order).  The groups are
+// found with ballots first; then every leader issues its atomic in the same
+// instruction, so a wavefront waits for one round trip, not one per key.
 template <bool kReturn>
 __device__ inline int aggregated_increment(int32_t *counter, int key, bool active)
 {
     const int lane = threadIdx.x & 63;
     uint64_t todo = __ballot(active);
-    int result = 0;
+    int leader = lane, rank = 0, size = 0;
     while (todo) {
-        const int leader = __ffsll(static_cast<unsigned long long>(todo)) - 1;
-        const int lkey = __shfl(key, leader, 64);
+        const int first = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+        const int lkey = __shfl(key, first, 64);
         const uint64_t peers = __ballot(active && key == lkey) & todo;
-        int base = 0;
-        if (lane == leader) {
-            if constexpr (kReturn) base = atomicAdd(&counter[lkey], __popcll(peers));
-            else atomicAdd(&counter[lkey], __popcll(peers));
-        }
-        if constexpr (kReturn) {
-            base = __shfl(base, leader, 64);
-            if ((peers >> lane) & 1ull) result = base + __popcll(peers & ((1ull << lane) - 1ull));
+        if ((peers >> lane) & 1ull) {
+            leader = first;
+            rank = __popcll(peers & ((1ull << lane) - 1ull));
+            size = __popcll(peers);
         }
         todo &= ~peers;
     }
-    return result;
+    int base = 0;
+    if (active && lane == leader) {
+        if constexpr (kReturn) base = atomicAdd(&counter[key], size);
+        else atomicAdd(&counter[key], size);
+    }
+    if constexpr (kReturn) return __shfl(base, leader, 64) + rank;
+    return 0;
 }
 
 // per-cell counters to zero; block 0 also resets the pair work-queue counters
@@ -872,15 +876,17 @@ __global__ __launch_bounds__(kAtomBlock) void k_scatter(const SysDesc *__restric
 }
 
 // Within each cell, atoms are ordered by their key (z, then index); keys are
-// unique, so the order does not depend on the scatter's.  One workgroup per
-// cell ranks each of the cell's keys against all of them (the keys pass
-// through LDS 256 at a time, every thread holding kRankKeys of the keys it
-// ranks in registers; a cell of up to 256 atoms is one tile and one key a
-// thread).  A single-cell system has one workgroup per kOrderPart of its keys
-// instead.  The record in binned slot j goes to sorted slot rank j, with the
-// atom's index: both reads and writes stay inside the cell's range.
-constexpr int kRankKeys = 4;
-static_assert(256 * kRankKeys == kOrderPart, "one rank pass per part of a single cell");
+// unique, so the order does not depend on the scatter's.  One workgroup of
+// kOrderThreads per cell ranks each of the cell's keys against all of them
+// (the keys pass through LDS kOrderThreads at a time, every thread holding
+// kRankKeys of the keys it ranks in registers; a cell of up to kOrderThreads
+// atoms is one tile and one key a thread).  A single-cell system has one
+// workgroup per kOrderPart of its keys instead.  The record in binned slot j
+// goes to sorted slot rank j, with the atom's index: both reads and writes
+// stay inside the cell's range.
+constexpr int kOrderThreads = 256;
+constexpr int kRankKeys = kOrderPart / kOrderThreads;
+static_assert(kOrderThreads * kRankKeys == kOrderPart, "one rank pass per part of a single cell");
 template <class T>
 __device__ inline void move_sorted(const SysDesc &D, int from, int to, uint64_t key)
 {
@@ -890,10 +896,11 @@ __device__ inline void move_sorted(const SysDesc &D, int from, int to, uint64_t 
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc, const SysStep *__restrict__ stp,
-                                               const int2 *__restrict__ plan)
+__global__ __launch_bounds__(kOrderThreads) void k_order(const SysDesc *__restrict__ desc,
+                                                         const SysStep *__restrict__ stp, const int2 *__restrict__ plan)
 {
-    __shared__ uint64_t s_key[256];
+    constexpr int NT = kOrderThreads;
+    __shared__ uint64_t s_key[NT];
     const int2 e = plan[blockIdx.x];
     const SysDesc &D = desc[e.x];
     const bool single = stp[e.x].ncells == 1;
@@ -903,7 +910,7 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
     const int cnt = s1 - s0;
     if (cnt == 0) return;
     const RB_GLOBAL uint64_t *keys = gp(D.keys);
-    if (cnt <= 256) {  // a single cell this small has one part
+    if (cnt <= NT) {  // a single cell this small has one part
         const uint64_t mine = tid < cnt ? keys[s0 + tid] : ~0ull;
         s_key[tid] = mine;
         __syncthreads();
@@ -916,23 +923,26 @@ __global__ __launch_bounds__(256) void k_order(const SysDesc *__restrict__ desc,
         for (int base = lo; base < hi; base += kOrderPart) {
             uint64_t mine[kRankKeys];
             int rank[kRankKeys];
+#pragma unroll
             for (int r = 0; r < kRankKeys; ++r) {
-                const int t = base + 256 * r + tid;
+                const int t = base + NT * r + tid;
                 mine[r] = t < hi ? keys[s0 + t] : 0ull;
                 rank[r] = 0;
             }
-            for (int j0 = 0; j0 < cnt; j0 += 256) {
+            for (int j0 = 0; j0 < cnt; j0 += NT) {
                 __syncthreads();  // the previous tile is no longer read
                 s_key[tid] = j0 + tid < cnt ? keys[s0 + j0 + tid] : 0ull;
                 __syncthreads();
-                const int m = min(256, cnt - j0);
+                const int m = min(NT, cnt - j0);
                 for (int j = 0; j < m; ++j) {
                     const uint64_t k = s_key[j];
+#pragma unroll
                     for (int r = 0; r < kRankKeys; ++r) rank[r] += k < mine[r];
                 }
             }
+#pragma unroll
             for (int r = 0; r < kRankKeys; ++r) {
-                const int t = base + 256 * r + tid;
+                const int t = base + NT * r + tid;
                 if (t < hi) move_sorted<T>(D, s0 + t, s0 + rank[r], mine[r]);
             }
         }
@@ -2893,7 +2903,7 @@ static hipError_t bin_and_sort_t(Batch &b)
                        plan_ptr(b, kPlanCells));
     hipLaunchKernelGGL(k_scatter<T>, dim3(plan_grid(b, kPlanAtoms)), dim3(kAtomBlock), 0, b.stream, b.d_desc,
                        plan_ptr(b, kPlanAtoms));
-    hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanCell1)), dim3(256), 0, b.stream, b.d_desc, b.d_step,
+    hipLaunchKernelGGL(k_order<T>, dim3(plan_grid(b, kPlanCell1)), dim3(kOrderThreads), 0, b.stream, b.d_desc, b.d_step,
                        plan_ptr(b, kPlanCell1));
     timer_end(b, "bin", b.stream);
     const hipError_t e = hipGetLastError();
