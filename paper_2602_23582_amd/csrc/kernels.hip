@@ -1097,13 +1097,20 @@ __device__ inline void displacement(const typename T::Rec &ri, const typename T:
 // false) and a listed pair farther than rc (possible only through the padded
 // fast filter) contribute nothing.  The terms carry q_j only; the caller
 // multiplies the sums by q_i.
-template <class T, int M, bool E>
+template <class T, int M, bool E, bool kLaneCount = true>
 __device__ __forceinline__ void pair_eval_d(typename T::real dx, typename T::real dy, typename T::real dz,
                                             typename T::real qj, bool active, typename T::real rc2,
-                                            const Weights<T, M> &W, PairAcc<T> &acc)
+                                            const Weights<T, M> &W, PairAcc<T> &acc, uint64_t *wave_inside = nullptr)
 {
     using real = typename T::real;
     const real r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if constexpr (!kLaneCount) {
+        // the wavefront's lanes with the pair inside, as a lane mask (the
+        // same two compares as below, taken as a scalar value)
+        static_assert(sizeof(real) == 4, "wave-mask count on the FP32 path only");
+        *wave_inside = __builtin_amdgcn_fcmpf(r2, rc2, 4 /* ordered less */) &
+                       __builtin_amdgcn_fcmpf(r2, 0.0f, 2 /* ordered greater */);
+    }
     const bool inside = active & (r2 < rc2) & (r2 > static_cast<real>(0));  // the atom itself is listed too
     real swt = 0, sw = 0, rinv;
     if constexpr (sizeof(real) == 4) rinv = __builtin_amdgcn_rsqf(r2);
@@ -1127,7 +1134,7 @@ __device__ __forceinline__ void pair_eval_d(typename T::real dx, typename T::rea
         }
     }
     // the mask selects the products (r = 0 gives rinv = inf for the atom itself)
-    acc.n += inside;
+    if constexpr (kLaneCount) acc.n += inside;
     const real f = inside ? qj * (rinv * rinv * rinv - swt) : static_cast<real>(0);
     const real fdx = f * dx, fdy = f * dy, fdz = f * dz;
     acc.fx += fdx;
@@ -1238,11 +1245,16 @@ __device__ __forceinline__ uint2 pack16(const Rec &r)
                       static_cast<uint32_t>(r.z) >> 16);
 }
 
+// Candidate k of a chunk in the block-relative tile: each 32-candidate word
+// is preceded by a sentinel slot, read by a lane whose hit word is spent.
+constexpr int kRelTile = kChunk + kChunk / 32;
+__device__ __forceinline__ int rel_slot(int k) { return k + (k >> 5) + 1; }
+
 template <class T>
 struct PairShared {
     union {
         typename T::Rec tile[kChunk];  // exact path: fixed-point records
-        float4 rtile[kChunk];          // fast path: (x, y, z) relative to the block origin, q
+        float4 rtile[kRelTile];        // fast path: (x, y, z) relative to the block origin, q; sentinels
     };
     union {
         float4 rel[kChunk];  // fast filter: coordinates relative to the block origin and their squared norm
@@ -1251,6 +1263,7 @@ struct PairShared {
     uint32_t mask[kChunk / 32][64];  // hit bits of each lane, one word per 32 candidates
     int pre[kMaxRanges + 1];  // flattened-neighbourhood offset of each range
     int beg[kMaxRanges];
+    int split;  // fast path: the block's own atoms are cut out of its ranges
 };
 
 // One pair block b of system D (one wavefront).
@@ -1407,11 +1420,35 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                 b1 = lo;
                 e1 = search(lo, b0, zb, false);
             }
+            // The block's own column (lane 4): on the relative-coordinate
+            // path the block's atoms, a run inside one of its two pieces,
+            // are cut out (their pairs are taken inside the block), and the
+            // piece's part above them becomes range 18.
+            int b2 = 0, e2 = 0, split = 0;
+            if (kRelEval && lane == 4) {
+                const int i1 = i0 + nblock;
+                if (b0 <= i0 && i1 <= e0) {
+                    b2 = i1;
+                    e2 = e0;
+                    e0 = i0;
+                    split = 1;
+                } else if (b1 <= i0 && i1 <= e1) {
+                    b2 = i1;
+                    e2 = e1;
+                    e1 = i0;
+                    split = 1;
+                }
+            }
             sh.beg[2 * lane] = b0;
             sh.pre[2 * lane + 1] = e0 - b0;  // lengths for now
             sh.beg[2 * lane + 1] = b1;
             sh.pre[2 * lane + 2] = e1 - b1;
-        } else if (lane >= 18 && lane < kMaxRanges) {
+            if (lane == 4) {
+                sh.beg[18] = b2;
+                sh.pre[19] = e2 - b2;
+                sh.split = split;
+            }
+        } else if (lane >= 19 && lane < kMaxRanges) {
             sh.beg[lane] = 0;
             sh.pre[lane + 1] = 0;
         }
@@ -1517,8 +1554,28 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     const int gpc = kChunk / 4;
     const int nch = (ngroups + gpc - 1) / gpc;
 
+    // chunk ch's groups: ch, ch + nch, ...; slots k of the chunk map to
+    // flattened indices 4 (ch + nch (k/4)) + k%4, a prefix of them valid
+    auto chunk_filled = [&](int ch) {
+        const int ng = ch < ngroups ? (ngroups - ch + nch - 1) / nch : 0;
+        const int glast = ch + nch * (ng - 1);
+        return ng > 0 ? 4 * (ng - 1) + min(4, total - 4 * glast) : 0;
+    };
+    // the range holding flattened index f: the last r with pre[r] <= f
+    auto range_of = [&](int f) {
+        int r = 0;
+#pragma unroll
+        for (int step = 16; step >= 1; step >>= 1)
+            if (r + step < kMaxRanges && sh.pre[r + step] <= f) r += step;
+        return r;
+    };
+
     double fx = 0, fy = 0, fz = 0, v[6] = {0, 0, 0, 0, 0, 0}, uu = 0;
     int hits = 0;    // in-cutoff partners of this lane's atom
+    int hits_w = 0;  // in-cutoff pairs counted for the whole wavefront (relative-coordinate walk)
+    // Sentinels of the relative-coordinate walk: far enough that no pair with
+    // them is inside rc, near enough that every product stays finite, charge 0.
+    if (kRelEval && fast && lane < kChunk / 32) sh.rtile[33 * lane] = make_float4(1e15f, 1e15f, 1e15f, 0.0f);
 
     // Pairs inside the block (relative-coordinate path): each unordered pair
     // once, by Newton's third law within the wavefront.  In round t lane l
@@ -1526,8 +1583,9 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
     // lane l + t takes the reaction from it by a shuffle, so every sum keeps
     // a fixed order.  The virial and the count of such a pair go in twice,
     // as the full shell's other side would have.  The block's atoms are then
-    // left out of the staged neighbourhood.
-    const bool intra = kRelEval && kIsF32 && fast;
+    // cut out of its neighbour ranges (without that cut, which needs them to
+    // be one run inside one piece of their column, the phase is skipped).
+    const bool intra = kRelEval && kIsF32 && fast && sh.split;
     if constexpr (kRelEval) {
         if (intra) {
             const float qf = valid ? static_cast<float>(ri.q) : 0.0f;
@@ -1574,23 +1632,8 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         }
     }
 
-    // this chunk's groups: ch, ch + nch, ...; slots k of the chunk map to
-    // flattened indices 4 (ch + nch (k/4)) + k%4, a prefix of them valid
-    auto chunk_filled = [&](int ch) {
-        const int ng = ch < ngroups ? (ngroups - ch + nch - 1) / nch : 0;
-        const int glast = ch + nch * (ng - 1);
-        return ng > 0 ? 4 * (ng - 1) + min(4, total - 4 * glast) : 0;
-    };
     for (int ch = 0; ch < nch; ++ch) {
         int filled = chunk_filled(ch);
-        // the range holding flattened index f: the last r with pre[r] <= f
-        auto range_of = [&](int f) {
-            int r = 0;
-#pragma unroll
-            for (int step = 16; step >= 1; step >>= 1)
-                if (r + step < kMaxRanges && sh.pre[r + step] <= f) r += step;
-            return r;
-        };
         if (fast) {
             // Candidates farther than the padded cutoff from the block's
             // bounding box cannot pass the filter for any lane: they are
@@ -1605,20 +1648,18 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                 if (k < filled) {
                     const int f = 4 * (ch + nch * (k >> 2)) + (k & 3);
                     const int r = range_of(f);
-                    const int idx = sh.beg[r] + (f - sh.pre[r]);
-                    rj = gload(rec + idx);
+                    rj = gload(rec + sh.beg[r] + (f - sh.pre[r]));
                     relpos(rj, xj, yj, zj);
                     const float ex = fmaxf(fmaxf(bx0 - xj, xj - bx1), 0.f);
                     const float ey = fmaxf(fmaxf(by0 - yj, yj - by1), 0.f);
                     const float ez = fmaxf(fmaxf(bz0 - zj, zj - bz1), 0.f);
                     keep = fmaf(ez, ez, fmaf(ey, ey, ex * ex)) < rcf * rcf;
-                    if (intra) keep = keep && (idx < i0 || idx >= i0 + nblock);
                 }
                 const uint64_t bal = __ballot(keep);
                 if (keep) {
                     const int pos = kept + __popcll(bal & ((1ull << lane) - 1ull));
                     sh.rel[pos] = make_float4(xj, yj, zj, xj * xj + yj * yj + zj * zj);
-                    if constexpr (kRelEval) sh.rtile[pos] = make_float4(xj, yj, zj, static_cast<float>(rj.q));
+                    if constexpr (kRelEval) sh.rtile[rel_slot(pos)] = make_float4(xj, yj, zj, static_cast<float>(rj.q));
                     else sh.tile[pos] = rj;
                 }
                 kept += __popcll(bal);
@@ -1638,8 +1679,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         if (fast)
             for (int k = filled + lane; k < 32 * words; k += 64) {
                 sh.rel[k] = make_float4(0.f, 0.f, 0.f, INFINITY);
-                // read (masked off) by lanes whose word is spent: keep it finite
-                sh.rtile[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if constexpr (!kRelEval) sh.rtile[k] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
         __syncthreads();
 
@@ -1720,31 +1760,44 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         auto walk = [&](auto rel_tag) {
             constexpr bool kRel = decltype(rel_tag)::value;
             int w = 0;
+            int wb = 1;  // the relative tile's slot of candidate 32 w
             uint32_t cur = words > 0 ? sh.mask[0][lane] : 0u;
             for (;;) {
                 bool adv = (cur == 0u) & (w + 1 < words);
                 while (__any(adv)) {
                     if (adv) {
                         ++w;
+                        wb += 33;
                         cur = sh.mask[w][lane];
                     }
                     adv = (cur == 0u) & (w + 1 < words);
                 }
                 if (!__any(cur != 0u)) break;
-                // a spent word gives slot 31, a valid record, masked off by active
-                const bool a0 = cur != 0u;
-                const int k0 = __builtin_clz(cur | 1u);
-                cur &= ~(0x80000000u >> k0);
-                const bool a1 = cur != 0u;
-                const int k1 = __builtin_clz(cur | 1u);
-                cur &= ~(0x80000000u >> k1);
                 if constexpr (kRel) {
+                    // The leading set bit; a spent word gives -1 (the hardware's
+                    // result for zero), the word's sentinel slot, whose pair
+                    // fails the cutoff test.  Clearing bit (k & 31) leaves a
+                    // spent word at zero.
+                    int k0, k1;
+                    asm("v_ffbh_u32 %0, %1" : "=v"(k0) : "v"(cur));
+                    cur &= ~(0x80000000u >> (k0 & 31));
+                    asm("v_ffbh_u32 %0, %1" : "=v"(k1) : "v"(cur));
+                    cur &= ~(0x80000000u >> (k1 & 31));
                     // FP32 block-relative coordinates: the difference of two exact
                     // minimum-image offsets from o, each rounded once to FP32
-                    const float4 t0 = sh.rtile[32 * w + k0], t1 = sh.rtile[32 * w + k1];
-                    pair_eval_d<T, M, E>(xi - t0.x, yi - t0.y, zi - t0.z, t0.w, a0, rc2, W, acc);
-                    pair_eval_d<T, M, E>(xi - t1.x, yi - t1.y, zi - t1.z, t1.w, a1, rc2, W, acc);
+                    const float4 t0 = sh.rtile[wb + k0], t1 = sh.rtile[wb + k1];
+                    uint64_t in0, in1;
+                    pair_eval_d<T, M, E, false>(xi - t0.x, yi - t0.y, zi - t0.z, t0.w, true, rc2, W, acc, &in0);
+                    pair_eval_d<T, M, E, false>(xi - t1.x, yi - t1.y, zi - t1.z, t1.w, true, rc2, W, acc, &in1);
+                    hits_w += __popcll(in0) + __popcll(in1);
                 } else {
+                    // a spent word gives slot 31, a valid record, masked off by active
+                    const bool a0 = cur != 0u;
+                    const int k0 = __builtin_clz(cur | 1u);
+                    cur &= ~(0x80000000u >> k0);
+                    const bool a1 = cur != 0u;
+                    const int k1 = __builtin_clz(cur | 1u);
+                    cur &= ~(0x80000000u >> k1);
                     const Rec r0 = sh.tile[32 * w + k0], r1 = sh.tile[32 * w + k1];
                     if constexpr (TRI) {
                         pair_eval_cell<T, M, E>(ri, r0, a0, hm, unit, rc2, W, acc);
@@ -1779,6 +1832,7 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         fsr[2 * D.n + i] = static_cast<real>(fz);
     }
     // full shell: each pair was seen from both sides
+    hits += lane == 0 ? hits_w : 0;
     double out[8] = {0.5 * v[0], 0.5 * v[1], 0.5 * v[2], 0.5 * v[3], 0.5 * v[4], 0.5 * v[5], 0.5 * uu, 0.5 * hits};
     for (int k = 0; k < 8; ++k) out[k] = wave_sum(out[k]);
     if (lane == 0)
