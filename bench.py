@@ -404,12 +404,14 @@ def extra_workload(torch, name, args, tw):
         def step(s):
             if cell is None:
                 mu = L0 * (1.0 + 0.001 * (s % 10)) / c.box
+                if not args.separate_calls:
+                    return c.step(s, mu, x, y, z, fx, fy, fz)[0]
                 c.rescale(mu, x, y, z)
                 c.sample_modes(s, c.box)
             else:  # a general cell: fixed cell and positions (the device rescale is diagonal)
                 c.sample_modes_cell(s, cell)
             c.force_virial(x, y, z, fx, fy, fz, energy=False)
-            return c.pressure()
+            return c.pressure()[0]
         for s in range(3):
             step(s)
         torch.cuda.synchronize()
@@ -465,6 +467,9 @@ def main():
                     help="pair kernel: the library's choice, or force the full or the half shell")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-valu-probe", action="store_true")
+    ap.add_argument("--separate-calls", action="store_true",
+                    help="step with rbsog_rescale, rbsog_sample_modes, rbsog_force_virial and rbsog_pressure "
+                         "instead of the one-call rbsog_step")
     ap.add_argument("--graph", action="store_true",
                     help="run the step as a batch of one replaying a captured HIP graph")
     ap.add_argument("--served", type=int, default=4096, help="requests of the served-stream run (0: skip)")
@@ -515,10 +520,13 @@ def main():
         def step(s):
             target = L0 * (1.0 + 0.001 * (s % 10))
             mu = target / ctx.box
+            if not args.separate_calls:
+                # rbsog_step: rescale, sampling, forces and pressure in one call
+                return ctx.step(s, mu, x, y, z, fx, fy, fz)[0]
             ctx.rescale(mu, x, y, z)
             ctx.sample_modes(s, ctx.box)
             ctx.force_virial(x, y, z, fx, fy, fz, energy=False)
-            return ctx.pressure()
+            return ctx.pressure()[0]
 
     for s in range(args.warmup):
         step(s)
@@ -602,7 +610,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "n_atoms": n, "box": L0.tolist(), "rc": d["rc"], "P": P,
                    "precision": "FP32C (FP32 arithmetic, FP64 partial sums and reductions)",
-                   "parallelism": "single GPU", "api": "batch of one, HIP graph" if args.graph else "context"},
+                   "parallelism": "single GPU",
+                   "api": "batch of one, HIP graph" if args.graph else
+                          ("context, four calls a step" if args.separate_calls else "context, rbsog_step")},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
         "distinct_modes": info["nd"], "valu_probe": probe,
     }
@@ -611,9 +621,11 @@ def main():
         log(f"P = {args.other_p}: {args.steps} steps")
         with rbsog.Context(d["q"], ctx.box, d["rc"], P=args.other_p, seed=args.seed) as c2:
             def step2(s):
+                if not args.separate_calls:
+                    return c2.step(s, None, x, y, z, fx, fy, fz)[0]
                 c2.sample_modes(s, c2.box)
                 c2.force_virial(x, y, z, fx, fy, fz, energy=False)
-                return c2.pressure()
+                return c2.pressure()[0]
             for s in range(args.warmup):
                 step2(s)
             torch.cuda.synchronize()

@@ -263,6 +263,34 @@ int rbsog_force_virial_noalloc(rbsog_ctx *ctx, const double *x, const double *y,
 int rbsog_rescale(rbsog_ctx *ctx, const double host_mu[3], double *x, double *y, double *z,
                   double host_box[3]);
 
+/*
+ * One whole step of Algorithm 1 for a box in one call: the rescale of
+ * rbsog_rescale (skipped when host_mu is NULL), the mode sampling of
+ * rbsog_sample_modes at the box after it, the forces of rbsog_force_virial
+ * and the pressure of rbsog_pressure.  Same kernels, same results, bitwise,
+ * as those four calls; the step's data goes to the device in one upload and
+ * the binning is queued before the sampler, so fewer host calls sit between
+ * the kernels.
+ *   step         step index k in [0, 2^32) (the sampler's random stream)
+ *   host_mu      scale factors (positive, finite) or NULL
+ *   host_box     in: the box before the rescale; out: the box after it
+ *   x, y, z      positions (device arrays, n each, FP64), rescaled in place
+ *   fx, fy, fz   forces out (device arrays, n each, FP64)
+ *   host_P       pressure tensor out (row-major, as rbsog_pressure) or NULL
+ *   host_energy  U^N, U^F*, U_self out (as rbsog_force_virial) or NULL;
+ *                the energy sum runs only when it is given
+ * With host_P or host_energy the call synchronises the stream; with both
+ * NULL it only queues work (rbsog_pressure reads the pressure later).
+ * Errors: RBSOG_EINVAL for NULL or host arrays, a bad step or bad scale
+ * factors; RBSOG_EBOX for a box the cut-off does not fit; RBSOG_ESTATE for a
+ * context holding a general cell or admitted to a batch; RBSOG_EDEVICE for a
+ * HIP error or a sampler without an accepted start.  An error found before
+ * any work is queued leaves host_box and the positions unchanged.
+ */
+int rbsog_step(rbsog_ctx *ctx, int64_t step, const double host_mu[3], double host_box[3], double *x,
+               double *y, double *z, double *fx, double *fy, double *fz, double host_P[9],
+               double host_energy[3]);
+
 /* Free the context and its device buffers (NULL is a no-op). */
 int rbsog_destroy(rbsog_ctx *ctx);
 

@@ -323,6 +323,66 @@ int rbsog_rescale(rbsog_ctx *c, const double host_mu[3], double *x, double *y, d
     return RBSOG_OK;
 }
 
+int rbsog_step(rbsog_ctx *c, int64_t step, const double host_mu[3], double host_box[3], double *x, double *y,
+               double *z, double *fx, double *fy, double *fz, double host_P[9], double host_energy[3])
+{
+    if (!c) return RBSOG_EINVAL;
+    c->err.clear();
+    RB_TRY(own_work(c));
+    if (!host_box || !x || !y || !z || !fx || !fy || !fz) return fail(c, RBSOG_EINVAL, "null argument");
+    if (step < 0 || (step >> 32)) return fail(c, RBSOG_EINVAL, "step must be in [0, 2^32)");
+    if (c->sys.tri)
+        return fail(c, RBSOG_ESTATE, "rbsog_step takes a box; a general cell is passed to rbsog_sample_modes_cell");
+    if (!(is_device_ptr(x) && is_device_ptr(y) && is_device_ptr(z) && is_device_ptr(fx) && is_device_ptr(fy) &&
+          is_device_ptr(fz)))
+        return fail(c, RBSOG_EINVAL, "rbsog_step needs device position and force arrays");
+    double box[3] = {host_box[0], host_box[1], host_box[2]};
+    if (host_mu) {
+        if (!finite3(host_mu) || host_mu[0] <= 0 || host_mu[1] <= 0 || host_mu[2] <= 0)
+            return fail(c, RBSOG_EINVAL, "scale factors must be positive and finite");
+        for (int d = 0; d < 3; ++d) box[d] *= host_mu[d];
+    }
+    RB_TRY(rbsog::check_box(box, c->sys.prm.rc, c->err));
+    rbsog::SysStep &t = c->sys.stp;
+    if (host_mu)
+        for (int d = 0; d < 3; ++d) t.mu[d] = host_mu[d];
+    rbsog::system_set_box(c->sys, box);
+    RB_TRY(refresh_cells(c));
+    t.step = static_cast<uint32_t>(step);
+    t.x = x;
+    t.y = y;
+    t.z = z;
+    t.fx = fx;
+    t.fy = fy;
+    t.fz = fz;
+    c->batch.want_energy = host_energy != nullptr;
+    // one upload; the rescale and the binning are queued before the sampler
+    // (second stream), which waits only for the upload
+    RB_TRY(rbsog::batch_upload(c->batch, c->err));
+    HIP_TRY(c, rbsog::record_sample_fence(c->batch));
+    if (host_mu) HIP_TRY(c, rbsog::launch_rescale(c->batch));
+    HIP_TRY(c, rbsog::launch_bin_and_sort(c->batch));
+    HIP_TRY(c, rbsog::launch_sample_fenced(c->batch));
+    HIP_TRY(c, rbsog::launch_pair(c->batch));
+    HIP_TRY(c, rbsog::launch_kspace(c->batch));
+    for (int d = 0; d < 3; ++d) host_box[d] = box[d];
+    c->state = 2;
+    if (host_P || host_energy) {
+        RB_TRY(rbsog::batch_fetch_results(c->batch, c->err));
+        const rbsog::StepResults &r = c->batch.h_res[0];
+        if (r.status != 0) return fail(c, RBSOG_EDEVICE, "sampler: no start draw accepted");
+        if (r.bad_input) return fail(c, RBSOG_EINVAL, "positions have NaN/Inf");
+        if (host_P)
+            for (int k = 0; k < 9; ++k) host_P[k] = r.Ptot[k];
+        if (host_energy) {
+            host_energy[0] = r.UN;
+            host_energy[1] = r.UF;
+            host_energy[2] = r.Uself;
+        }
+    }
+    return RBSOG_OK;
+}
+
 int rbsog_destroy(rbsog_ctx *c)
 {
     if (!c) return RBSOG_OK;

@@ -84,8 +84,12 @@ void destroy(rbsog_batch *b)
 // the device work of one step after the uploads
 hipError_t launch_step(Batch &bt)
 {
-    hipError_t e = rbsog::launch_sample(bt);
+    // the sampler's fence first, then the binning launches, then the sampler
+    // (on the second stream): the binning does not wait for the host's
+    // cross-stream calls
+    hipError_t e = rbsog::record_sample_fence(bt);
     if (e == hipSuccess) e = rbsog::launch_bin_and_sort(bt);
+    if (e == hipSuccess) e = rbsog::launch_sample_fenced(bt);
     if (e == hipSuccess) e = rbsog::launch_pair(bt);
     if (e == hipSuccess) e = rbsog::launch_kspace(bt);
     return e;

@@ -2930,17 +2930,29 @@ inline unsigned nsys(const Batch &b) { return static_cast<unsigned>(b.sys.size()
 // Launchers (every launch covers all systems of the batch)
 // ----------------------------------------------------------------------------
 
-hipError_t launch_sample(Batch &b)
+hipError_t record_sample_fence(Batch &b)
 {
     if (b.sys.empty()) return hipSuccess;
-    // on the second stream, after everything queued so far on the first
-    hipError_t e = hipEventRecord(b.ev_up, b.stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b.aux, b.ev_up, 0);
+    return hipEventRecord(b.ev_up, b.stream);
+}
+
+hipError_t launch_sample_fenced(Batch &b)
+{
+    if (b.sys.empty()) return hipSuccess;
+    // on the second stream, after what the first held at the fence
+    hipError_t e = hipStreamWaitEvent(b.aux, b.ev_up, 0);
     if (e != hipSuccess) return e;
     timer_begin(b, "sampler", b.aux);
     hipLaunchKernelGGL(k_sampler, dim3(nsys(b)), dim3(256), 0, b.aux, b.d_desc, b.d_step);
     timer_end(b, "sampler", b.aux);
     return hipGetLastError();
+}
+
+hipError_t launch_sample(Batch &b)
+{
+    // on the second stream, after everything queued so far on the first
+    const hipError_t e = record_sample_fence(b);
+    return e == hipSuccess ? launch_sample_fenced(b) : e;
 }
 
 template <class T>

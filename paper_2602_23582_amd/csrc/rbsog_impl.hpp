@@ -336,6 +336,10 @@ int batch_get_timing(Batch &b, int32_t cap, int32_t *host_nk, char *host_names, 
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels.hip); each returns a hipError_t
 hipError_t launch_sample(Batch &b);
+// launch_sample in two parts: the fence on the first stream (the sampler waits
+// for what that stream held at it) and the sampler itself, launched later
+hipError_t record_sample_fence(Batch &b);
+hipError_t launch_sample_fenced(Batch &b);
 hipError_t launch_bin_and_sort(Batch &b);
 hipError_t launch_pair(Batch &b);
 hipError_t launch_kspace(Batch &b);

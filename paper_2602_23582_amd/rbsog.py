@@ -46,7 +46,7 @@ EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_forc
            "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_set_energy", "rbsog_server_last_error",
            "rbsog_npt_init", "rbsog_npt_run", "rbsog_batch_create", "rbsog_batch_admit", "rbsog_stage",
            "rbsog_batch_release", "rbsog_debug_long_range_force", "rbsog_force_virial_noalloc",
-           "rbsog_batch_autotune_cached", "rbsog_sample_modes_cell"]
+           "rbsog_batch_autotune_cached", "rbsog_sample_modes_cell", "rbsog_step"]
 
 COUPLE_ANISO = 0
 COUPLE_SEMI = 1
@@ -93,6 +93,7 @@ def load(path: str | None = None):
         "rbsog_force_virial": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, pd, pd]),
         "rbsog_pressure": (C.c_int, [vp, pd, pd]),
         "rbsog_rescale": (C.c_int, [vp, pd, vp, vp, vp, pd]),
+        "rbsog_step": (C.c_int, [vp, i64, pd, pd, vp, vp, vp, vp, vp, vp, pd, pd]),
         "rbsog_destroy": (C.c_int, [vp]),
         "rbsog_strerror": (C.c_char_p, [C.c_int]),
         "rbsog_last_error": (C.c_char_p, [vp]),
@@ -286,6 +287,20 @@ class Context:
         self._check(load().rbsog_rescale(self._h, _pd(mu), *_ptrs((x, y, z), self.n, self.device), _pd(self.box)),
                     "rbsog_rescale")
         return self.box
+
+    def step(self, step, mu, x, y, z, fx, fy, fz, pressure=True, energy=False):
+        """rbsog_step: rescale by mu (None: no rescale), sample at the new box,
+        forces and pressure in one call (device tensors).  Returns the
+        pressure tensor (3, 3) or None, and the energies or None."""
+        box = self.box.copy()
+        P = np.zeros(9) if pressure else None
+        e = np.zeros(3) if energy else None
+        m = None if mu is None else np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), (3,)))
+        self._check(load().rbsog_step(self._h, int(step), _pd(m) if m is not None else None, _pd(box),
+                                      *_ptrs((x, y, z, fx, fy, fz), self.n, self.device),
+                                      _pd(P) if pressure else None, _pd(e) if energy else None), "rbsog_step")
+        self.box = box
+        return (P.reshape(3, 3) if pressure else None), e
 
     def stage(self, step, box, x, y, z, fx, fy, fz):
         """Inputs of the next step of a batch of contexts (device tensors)."""
