@@ -387,6 +387,30 @@ def variance_study(torch, reps, Ps=(50, 100, 200), sizes=(2000, 16000)):
             "reference": "P^F by the full k-space sum, tests/golden/variance_reference.json"}
 
 
+def pipelined(args):
+    """The default stepping: each step queued with rbsog_step_async and its
+    pressure read (rbsog_step_wait) once the next step is queued."""
+    return not (args.graph or args.separate_calls or args.sync_steps)
+
+
+def run_queued(c, steps, mu_of, arrays):
+    """Step context c through the step indices `steps` with rbsog_step_async,
+    reading each step's pressure after the next step is queued; returns the
+    host time at which each step's pressure had arrived."""
+    x, y, z, fx, fy, fz = arrays
+    marks, pending = [], None
+    for s in steps:
+        t = c.step_async(s, mu_of(s), x, y, z, fx, fy, fz)
+        if pending is not None:
+            c.step_wait(pending)
+            marks.append(time.perf_counter())
+        pending = t
+    if pending is not None:
+        c.step_wait(pending)
+        marks.append(time.perf_counter())
+    return marks
+
+
 def extra_workload(torch, name, args, tw):
     """Another workload through the same step (context calls, HIP events on the
     pair launches): ms per step with its spread, atom-steps/s and the pair
@@ -412,15 +436,20 @@ def extra_workload(torch, name, args, tw):
                 c.sample_modes_cell(s, cell)
             c.force_virial(x, y, z, fx, fy, fz, energy=False)
             return c.pressure()[0]
+        queued = pipelined(args) and cell is None
+        mu_of = lambda s: L0 * (1.0 + 0.001 * (s % 10)) / c.box
         for s in range(3):
             step(s)
         torch.cuda.synchronize()
         c.set_timing(2)  # the pair kernel's launches only
         t0 = time.perf_counter()
-        marks = []
-        for s in range(3, 3 + args.extra_steps):
-            step(s)
-            marks.append(time.perf_counter())
+        if queued:
+            marks = run_queued(c, range(3, 3 + args.extra_steps), mu_of, (x, y, z, fx, fy, fz))
+        else:
+            marks = []
+            for s in range(3, 3 + args.extra_steps):
+                step(s)
+                marks.append(time.perf_counter())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         timing = c.get_timing()
@@ -467,6 +496,9 @@ def main():
                     help="pair kernel: the library's choice, or force the full or the half shell")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-valu-probe", action="store_true")
+    ap.add_argument("--sync-steps", action="store_true",
+                    help="read each step's pressure before queuing the next (rbsog_step) instead of one step "
+                         "later (rbsog_step_async / rbsog_step_wait)")
     ap.add_argument("--separate-calls", action="store_true",
                     help="step with rbsog_rescale, rbsog_sample_modes, rbsog_force_virial and rbsog_pressure "
                          "instead of the one-call rbsog_step")
@@ -535,10 +567,15 @@ def main():
         ctx.set_timing(2)  # events around the pair kernel only: each recorded event delays the next launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    marks = []
-    for s in range(args.warmup, args.warmup + args.steps):
-        step(s)  # ends with the pressure copied to the host (a stream synchronisation)
-        marks.append(time.perf_counter())
+    if pipelined(args):
+        # every step's pressure reaches the host, read once the next step is queued
+        marks = run_queued(ctx, range(args.warmup, args.warmup + args.steps),
+                           lambda s: L0 * (1.0 + 0.001 * (s % 10)) / ctx.box, (x, y, z, fx, fy, fz))
+    else:
+        marks = []
+        for s in range(args.warmup, args.warmup + args.steps):
+            step(s)  # ends with the pressure copied to the host (a stream synchronisation)
+            marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     per_step = 1e3 * np.diff(np.concatenate([[t0], marks]))
@@ -612,7 +649,9 @@ def main():
                    "precision": "FP32C (FP32 arithmetic, FP64 partial sums and reductions)",
                    "parallelism": "single GPU",
                    "api": "batch of one, HIP graph" if args.graph else
-                          ("context, four calls a step" if args.separate_calls else "context, rbsog_step")},
+                          ("context, four calls a step" if args.separate_calls else
+                           ("context, rbsog_step" if args.sync_steps else
+                            "context, rbsog_step_async (each step's pressure read once the next step is queued)"))},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
         "distinct_modes": info["nd"], "valu_probe": probe,
     }
@@ -630,8 +669,11 @@ def main():
                 step2(s)
             torch.cuda.synchronize()
             ta = time.perf_counter()
-            for s in range(args.warmup, args.warmup + args.steps):
-                step2(s)
+            if pipelined(args):
+                run_queued(c2, range(args.warmup, args.warmup + args.steps), lambda s: None, (x, y, z, fx, fy, fz))
+            else:
+                for s in range(args.warmup, args.warmup + args.steps):
+                    step2(s)
             torch.cuda.synchronize()
             tb = time.perf_counter()
             out["other_P"] = {"P": args.other_p, "ms_per_step": 1e3 * (tb - ta) / args.steps,

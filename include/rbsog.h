@@ -291,6 +291,33 @@ int rbsog_step(rbsog_ctx *ctx, int64_t step, const double host_mu[3], double hos
                double *y, double *z, double *fx, double *fy, double *fz, double host_P[9],
                double host_energy[3]);
 
+/*
+ * rbsog_step without waiting for its results: queues the step (arguments as
+ * rbsog_step; energy nonzero runs the energy sum) and, behind it on the same
+ * stream, the copy of its results into one of four pinned slots of the
+ * context, and returns a ticket in *ticket (0, 1, 2, ... per context).  The
+ * host is then free to queue the next step while the device works, so a
+ * stepping loop that reads each step's pressure one step later keeps the
+ * device busy across step boundaries.  A fifth queued step reuses the slot
+ * of the first: the call then waits for that slot's copy, and that ticket's
+ * results are gone.  host_box is updated when the call returns, as in
+ * rbsog_step; the forces are in fx, fy, fz once the step has run.
+ */
+int rbsog_step_async(rbsog_ctx *ctx, int64_t step, const double host_mu[3], double host_box[3], double *x,
+                     double *y, double *z, double *fx, double *fy, double *fz, int32_t energy,
+                     int64_t *ticket);
+
+/*
+ * Waits for the step of a ticket from rbsog_step_async and returns its
+ * pressure tensor (host_P, row-major, as rbsog_pressure) and energies
+ * (host_energy, as rbsog_force_virial; zeros unless that step ran the energy
+ * sum); either may be NULL.  RBSOG_EINVAL for a ticket that was never issued
+ * or whose slot a later step has taken (more than four steps ago);
+ * RBSOG_EDEVICE and RBSOG_EINVAL as rbsog_pressure for that step's sampler
+ * and input checks.  A ticket may be waited on more than once.
+ */
+int rbsog_step_wait(rbsog_ctx *ctx, int64_t ticket, double host_P[9], double host_energy[3]);
+
 /* Free the context and its device buffers (NULL is a no-op). */
 int rbsog_destroy(rbsog_ctx *ctx);
 

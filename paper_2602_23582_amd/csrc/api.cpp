@@ -64,6 +64,9 @@ void destroy(rbsog_ctx *c)
     rbsog::system_free(c->sys);
     rbsog::batch_free(c->batch);
     if (c->d_stage) (void)hipFree(c->d_stage);
+    if (c->h_ring) (void)hipHostFree(c->h_ring);
+    for (hipEvent_t e : c->ring_ev)
+        if (e) (void)hipEventDestroy(e);
     for (double *p : {c->npt.d_mass, c->npt.d_F, c->npt.d_part, c->npt.d_kin})
         if (p) (void)hipFree(p);
     delete c;
@@ -323,11 +326,10 @@ int rbsog_rescale(rbsog_ctx *c, const double host_mu[3], double *x, double *y, d
     return RBSOG_OK;
 }
 
-int rbsog_step(rbsog_ctx *c, int64_t step, const double host_mu[3], double host_box[3], double *x, double *y,
-               double *z, double *fx, double *fy, double *fz, double host_P[9], double host_energy[3])
+// The work of rbsog_step up to its last launch (no synchronisation).
+static int step_queue(rbsog_ctx *c, int64_t step, const double host_mu[3], double host_box[3], double *x, double *y,
+                      double *z, double *fx, double *fy, double *fz, bool energy)
 {
-    if (!c) return RBSOG_EINVAL;
-    c->err.clear();
     RB_TRY(own_work(c));
     if (!host_box || !x || !y || !z || !fx || !fy || !fz) return fail(c, RBSOG_EINVAL, "null argument");
     if (step < 0 || (step >> 32)) return fail(c, RBSOG_EINVAL, "step must be in [0, 2^32)");
@@ -355,7 +357,7 @@ int rbsog_step(rbsog_ctx *c, int64_t step, const double host_mu[3], double host_
     t.fx = fx;
     t.fy = fy;
     t.fz = fz;
-    c->batch.want_energy = host_energy != nullptr;
+    c->batch.want_energy = energy;
     // one upload; the rescale and the binning are queued before the sampler
     // (second stream), which waits only for the upload
     RB_TRY(rbsog::batch_upload(c->batch, c->err));
@@ -367,6 +369,15 @@ int rbsog_step(rbsog_ctx *c, int64_t step, const double host_mu[3], double host_
     HIP_TRY(c, rbsog::launch_kspace(c->batch));
     for (int d = 0; d < 3; ++d) host_box[d] = box[d];
     c->state = 2;
+    return RBSOG_OK;
+}
+
+int rbsog_step(rbsog_ctx *c, int64_t step, const double host_mu[3], double host_box[3], double *x, double *y,
+               double *z, double *fx, double *fy, double *fz, double host_P[9], double host_energy[3])
+{
+    if (!c) return RBSOG_EINVAL;
+    c->err.clear();
+    RB_TRY(step_queue(c, step, host_mu, host_box, x, y, z, fx, fy, fz, host_energy != nullptr));
     if (host_P || host_energy) {
         RB_TRY(rbsog::batch_fetch_results(c->batch, c->err));
         const rbsog::StepResults &r = c->batch.h_res[0];
@@ -379,6 +390,52 @@ int rbsog_step(rbsog_ctx *c, int64_t step, const double host_mu[3], double host_
             host_energy[1] = r.UF;
             host_energy[2] = r.Uself;
         }
+    }
+    return RBSOG_OK;
+}
+
+int rbsog_step_async(rbsog_ctx *c, int64_t step, const double host_mu[3], double host_box[3], double *x,
+                     double *y, double *z, double *fx, double *fy, double *fz, int32_t energy, int64_t *ticket)
+{
+    if (!c) return RBSOG_EINVAL;
+    c->err.clear();
+    if (!ticket) return fail(c, RBSOG_EINVAL, "null ticket");
+    if (!c->h_ring) {
+        HIP_TRY(c, hipHostMalloc(reinterpret_cast<void **>(&c->h_ring),
+                                 rbsog_ctx::kResRing * sizeof(rbsog::StepResults)));
+        for (hipEvent_t &e : c->ring_ev) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    // the slot this step's results go to: its last copy must have run
+    const int slot = static_cast<int>(c->next_ticket % rbsog_ctx::kResRing);
+    if (c->ring_ticket[slot] >= 0) HIP_TRY(c, hipEventSynchronize(c->ring_ev[slot]));
+    c->ring_ticket[slot] = -1;
+    RB_TRY(step_queue(c, step, host_mu, host_box, x, y, z, fx, fy, fz, energy != 0));
+    HIP_TRY(c, hipMemcpyAsync(c->h_ring + slot, c->batch.d_res, sizeof(rbsog::StepResults), hipMemcpyDeviceToHost,
+                              c->batch.stream));
+    HIP_TRY(c, hipEventRecord(c->ring_ev[slot], c->batch.stream));
+    c->ring_ticket[slot] = c->next_ticket;
+    *ticket = c->next_ticket++;
+    return RBSOG_OK;
+}
+
+int rbsog_step_wait(rbsog_ctx *c, int64_t ticket, double host_P[9], double host_energy[3])
+{
+    if (!c) return RBSOG_EINVAL;
+    c->err.clear();
+    if (ticket < 0) return fail(c, RBSOG_EINVAL, "negative ticket");
+    const int slot = static_cast<int>(ticket % rbsog_ctx::kResRing);
+    if (c->ring_ticket[slot] != ticket)
+        return fail(c, RBSOG_EINVAL, "no results for this ticket (unknown, or more than 4 steps ago)");
+    HIP_TRY(c, hipEventSynchronize(c->ring_ev[slot]));
+    const rbsog::StepResults &r = c->h_ring[slot];
+    if (r.status != 0) return fail(c, RBSOG_EDEVICE, "sampler: no start draw accepted");
+    if (r.bad_input) return fail(c, RBSOG_EINVAL, "positions have NaN/Inf");
+    if (host_P)
+        for (int k = 0; k < 9; ++k) host_P[k] = r.Ptot[k];
+    if (host_energy) {
+        host_energy[0] = r.UN;
+        host_energy[1] = r.UF;
+        host_energy[2] = r.Uself;
     }
     return RBSOG_OK;
 }

@@ -390,4 +390,12 @@ struct rbsog_ctx {
     bool staged = false;              // inputs of the next batched step are set
     bool desc_moved = false;          // its buffers were re-carved since the batch last uploaded them
     bool res_from_batch = false;      // batch.h_res[0] holds the results of the last batched step
+    // results of queued steps (rbsog_step_async): pinned slots, each filled by
+    // a copy queued behind its step and marked by an event
+    static constexpr int kResRing = 4;
+    rbsog::StepResults *h_ring = nullptr;
+    hipEvent_t ring_ev[kResRing] = {};
+    int64_t ring_ticket[kResRing] = {-1, -1, -1, -1};  // the ticket each slot holds, -1 for none
+    static_assert(kResRing == 4, "ring_ticket's initialiser and the error message name four slots");
+    int64_t next_ticket = 0;
 };

@@ -46,7 +46,8 @@ EXPORTS = ["rbsog_params_init", "rbsog_setup", "rbsog_sample_modes", "rbsog_forc
            "rbsog_server_stats", "rbsog_server_destroy", "rbsog_server_set_energy", "rbsog_server_last_error",
            "rbsog_npt_init", "rbsog_npt_run", "rbsog_batch_create", "rbsog_batch_admit", "rbsog_stage",
            "rbsog_batch_release", "rbsog_debug_long_range_force", "rbsog_force_virial_noalloc",
-           "rbsog_batch_autotune_cached", "rbsog_sample_modes_cell", "rbsog_step"]
+           "rbsog_batch_autotune_cached", "rbsog_sample_modes_cell", "rbsog_step",
+           "rbsog_step_async", "rbsog_step_wait"]
 
 COUPLE_ANISO = 0
 COUPLE_SEMI = 1
@@ -94,6 +95,8 @@ def load(path: str | None = None):
         "rbsog_pressure": (C.c_int, [vp, pd, pd]),
         "rbsog_rescale": (C.c_int, [vp, pd, vp, vp, vp, pd]),
         "rbsog_step": (C.c_int, [vp, i64, pd, pd, vp, vp, vp, vp, vp, vp, pd, pd]),
+        "rbsog_step_async": (C.c_int, [vp, i64, pd, pd, vp, vp, vp, vp, vp, vp, i32, C.POINTER(C.c_int64)]),
+        "rbsog_step_wait": (C.c_int, [vp, i64, pd, pd]),
         "rbsog_destroy": (C.c_int, [vp]),
         "rbsog_strerror": (C.c_char_p, [C.c_int]),
         "rbsog_last_error": (C.c_char_p, [vp]),
@@ -301,6 +304,27 @@ class Context:
                                       _pd(P) if pressure else None, _pd(e) if energy else None), "rbsog_step")
         self.box = box
         return (P.reshape(3, 3) if pressure else None), e
+
+    def step_async(self, step, mu, x, y, z, fx, fy, fz, energy=False):
+        """rbsog_step_async: queue the step and the copy of its results;
+        returns the ticket for step_wait."""
+        box = self.box.copy()
+        m = None if mu is None else np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), (3,)))
+        t = C.c_int64(-1)
+        self._check(load().rbsog_step_async(self._h, int(step), _pd(m) if m is not None else None, _pd(box),
+                                            *_ptrs((x, y, z, fx, fy, fz), self.n, self.device), 1 if energy else 0,
+                                            C.byref(t)), "rbsog_step_async")
+        self.box = box
+        return t.value
+
+    def step_wait(self, ticket, energy=False):
+        """rbsog_step_wait: the pressure tensor (3, 3) of a queued step, and
+        its energies when asked for."""
+        P = np.zeros(9)
+        e = np.zeros(3) if energy else None
+        self._check(load().rbsog_step_wait(self._h, int(ticket), _pd(P), _pd(e) if energy else None),
+                    "rbsog_step_wait")
+        return P.reshape(3, 3), e
 
     def stage(self, step, box, x, y, z, fx, fy, fz):
         """Inputs of the next step of a batch of contexts (device tensors)."""

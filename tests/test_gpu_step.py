@@ -93,3 +93,49 @@ def test_step_refusals(torch, rb):
         assert np.array_equal(x.cpu().numpy(), d["pos"][:, 0])
         P, _ = ctx.step(0, None, x, y, z, fx, fy, fz)
         assert np.all(np.isfinite(P))
+
+
+@pytest.mark.parametrize("energy", [False, True])
+def test_queued_steps_equal_the_one_call_step(torch, rb, energy):
+    """rbsog_step_async + rbsog_step_wait, each pressure read one step late:
+    the same pressures, energies, forces and positions as rbsog_step."""
+    d = W.ionic_system(20000, seed=7)
+    mus = [None, np.array([1.001, 1.001, 1.0]), np.array([0.999, 1.0, 1.002]), None, np.array([1.0, 0.999, 1.0]),
+           None]
+    ref = []
+    x, y, z = (_dev(torch, d["pos"][:, k]) for k in range(3))
+    fx, fy, fz = (torch.empty_like(x) for _ in range(3))
+    with rb.Context(d["q"], d["L"], d["rc"], P=60, seed=5) as ctx:
+        for s, mu in enumerate(mus):
+            P, e = ctx.step(s, mu, x, y, z, fx, fy, fz, energy=energy)
+            ref.append((P.copy(), None if e is None else e.copy(), ctx.box.copy()))
+        F_ref = torch.stack([fx, fy, fz], 1).cpu().numpy()
+        X_ref = torch.stack([x, y, z], 1).cpu().numpy()
+    x, y, z = (_dev(torch, d["pos"][:, k]) for k in range(3))
+    got = []
+    with rb.Context(d["q"], d["L"], d["rc"], P=60, seed=5) as ctx:
+        tickets = []
+        for s, mu in enumerate(mus):
+            tickets.append((ctx.step_async(s, mu, x, y, z, fx, fy, fz, energy=energy), ctx.box.copy()))
+            if len(tickets) > 1:
+                t, box = tickets.pop(0)
+                got.append((*ctx.step_wait(t, energy=energy), box))
+        t, box = tickets.pop(0)
+        got.append((*ctx.step_wait(t, energy=energy), box))
+        # a ticket may be read again while its slot holds it
+        P_again, _ = ctx.step_wait(t)
+        assert np.array_equal(P_again, got[-1][0])
+        # slots are reused after four steps
+        with pytest.raises(rb.RBSOGError) as err:
+            ctx.step_wait(0)
+        assert err.value.code == -1
+        with pytest.raises(rb.RBSOGError):
+            ctx.step_wait(t + 1)  # never issued
+        assert np.array_equal(torch.stack([fx, fy, fz], 1).cpu().numpy(), F_ref)
+        assert np.array_equal(torch.stack([x, y, z], 1).cpu().numpy(), X_ref)
+    assert len(got) == len(ref)
+    for k, ((P1, e1, b1), (P2, e2, b2)) in enumerate(zip(ref, got)):
+        assert np.array_equal(P1, P2), k
+        assert np.array_equal(b1, b2), k
+        if energy:
+            assert np.array_equal(e1, e2), k
