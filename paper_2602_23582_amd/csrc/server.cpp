@@ -123,6 +123,11 @@ struct rbsog_server {
     char *pool_mem = nullptr;
     char *stage = nullptr;  // pinned, kStageBytes (null if it could not be allocated)
     size_t stage_used = 0;
+    // pinned, kStageBytes: the forces of requests a tick completes, copied
+    // there behind the step and handed to the requests while the next tick
+    // runs (null if it could not be allocated)
+    char *dstage = nullptr;
+    size_t dstage_used = 0;
     Pool pool;
     Batch batch;
     std::mutex mu;
@@ -278,14 +283,29 @@ int tick_launch(rbsog_server *sv, std::string &err)
     return RBSOG_OK;
 }
 
-// Queue the copies of the forces of the requests this step completes (the
-// copies into pageable memory may hold the host until the step is done, so
-// they come after everything else the tick queues).
-int copy_forces(rbsog_server *sv, std::vector<Request *> &finished, std::string &err)
+// Queue the copies of the forces of the requests this step completes: into
+// the pinned download staging while it has room (outbox: handed over after
+// the synchronisation), else into the requests' pageable buffers (finished;
+// such copies may hold the host until the step is done, so they come after
+// everything else the tick queues).
+int copy_forces(rbsog_server *sv, std::vector<Request *> &finished, std::vector<std::pair<Request *, size_t>> &outbox,
+                std::string &err)
 {
     for (Request *r : sv->active) {
         if (r->k + 1 < r->nsteps) continue;
         const int64_t n = r->n;
+        const size_t bytes = 3 * n * sizeof(double);
+        if (sv->dstage && sv->dstage_used + bytes <= kStageBytes) {
+            const hipError_t e = hipMemcpyAsync(sv->dstage + sv->dstage_used, r->d_frc, bytes, hipMemcpyDeviceToHost,
+                                                sv->stream);
+            if (e != hipSuccess) {
+                err = std::string("force copy: ") + hipGetErrorString(e);
+                return RBSOG_EDEVICE;
+            }
+            outbox.emplace_back(r, sv->dstage_used);
+            sv->dstage_used += align_up(bytes);
+            continue;
+        }
         r->fx.resize(n);
         r->fy.resize(n);
         r->fz.resize(n);
@@ -331,17 +351,48 @@ int tick_finish(rbsog_server *sv, double &atom_steps, std::string &err)
     return RBSOG_OK;
 }
 
+// Hand the forces staged by the last tick to their requests (their copies ran
+// before that tick's synchronisation) and complete them.
+void deliver(rbsog_server *sv, std::vector<std::pair<Request *, size_t>> &outbox)
+{
+    for (auto &[r, off] : outbox) {
+        const double *f = reinterpret_cast<const double *>(sv->dstage + off);
+        const int64_t n = r->n;
+        r->fx.assign(f, f + n);
+        r->fy.assign(f + n, f + 2 * n);
+        r->fz.assign(f + 2 * n, f + 3 * n);
+    }
+    sv->dstage_used = 0;
+    if (outbox.empty()) return;
+    const Clock::time_point t = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (auto &[r, off] : outbox) {
+            r->t_done = t;
+            r->done = true;
+            sv->completed += 1;
+        }
+    }
+    outbox.clear();
+    sv->cv_done.notify_all();
+}
+
 // Every tick: the requests uploaded during the previous tick join, the step
-// is launched, and while it runs the requests that arrived meanwhile are
-// admitted and their uploads queued behind it; one synchronisation then
-// covers the step, its results, the completed requests' forces and those
-// uploads.  Only when nothing is active does admission wait for nothing else.
+// is launched, and while it runs the forces the last tick completed are handed
+// over and the requests that arrived meanwhile are admitted, their uploads
+// queued behind it; one synchronisation then covers the step, its results,
+// the completed requests' force copies and those uploads.  Only when nothing
+// is active does admission wait for nothing else.
 void worker_main(rbsog_server *sv)
 {
     (void)hipSetDevice(sv->device);
     std::string err;
     std::vector<Request *> ready;  // uploaded and synchronised, joining the next tick
+    std::vector<std::pair<Request *, size_t>> outbox;  // forces in the download staging, not yet handed over
     for (;;) {
+        // no tick follows at once: hand the staged forces over now (only this
+        // thread changes the active list)
+        if (!outbox.empty() && sv->active.empty() && ready.empty()) deliver(sv, outbox);
         std::vector<Request *> admitted, next, finished;
         sv->stage_used = 0;  // every copy from the staging area ran before the last synchronisation
         {
@@ -349,7 +400,11 @@ void worker_main(rbsog_server *sv)
             sv->cv_work.wait(lk, [&] {
                 return sv->stop || !sv->pending.empty() || !sv->active.empty() || !ready.empty();
             });
-            if (sv->stop) break;
+            if (sv->stop) {
+                lk.unlock();
+                deliver(sv, outbox);
+                break;
+            }
             if (sv->active.empty() && ready.empty()) take_admissions(sv, 0, admitted);
         }
         const Clock::time_point t0 = Clock::now();
@@ -369,6 +424,7 @@ void worker_main(rbsog_server *sv)
             if (rc == RBSOG_OK) rc = tick_launch(sv, err);
             const Clock::time_point tl = Clock::now();
             launch_s = std::chrono::duration<double>(tl - ta).count();
+            deliver(sv, outbox);  // while the step runs
             if (rc == RBSOG_OK) {
                 size_t completing = 0;
                 for (Request *r : sv->active) completing += r->k + 1 >= r->nsteps;
@@ -390,7 +446,7 @@ void worker_main(rbsog_server *sv)
             }
             const Clock::time_point tw = Clock::now();
             admit2_s = std::chrono::duration<double>(tw - tl).count();
-            if (rc == RBSOG_OK) rc = copy_forces(sv, finished, err);
+            if (rc == RBSOG_OK) rc = copy_forces(sv, finished, outbox, err);
             if (rc == RBSOG_OK) rc = tick_finish(sv, atom_steps, err);
             wait_s = std::chrono::duration<double>(Clock::now() - tw).count();
         }
@@ -412,6 +468,7 @@ void worker_main(rbsog_server *sv)
             // a failed tick fails every request it held or had admitted; the
             // worker stops once nothing queued still reads their host copies
             (void)hipStreamSynchronize(sv->stream);
+            outbox.clear();  // this tick's requests: failed with the rest below
             sv->worker_err = err;
             for (const std::vector<Request *> *v : {&sv->active, &ready, &admitted, &next})
                 for (Request *r : *v) {
@@ -428,8 +485,11 @@ void worker_main(rbsog_server *sv)
             sv->pool.release(r->off, r->bytes);
             sv->completed += 1;
         }
-        if (!finished.empty()) {
-            sv->active.erase(std::remove_if(sv->active.begin(), sv->active.end(), [](Request *r) { return r->done; }),
+        // staged forces are in host memory: their device memory is free now
+        for (auto &ro : outbox) sv->pool.release(ro.first->off, ro.first->bytes);
+        if (!finished.empty() || !outbox.empty()) {
+            sv->active.erase(std::remove_if(sv->active.begin(), sv->active.end(),
+                                            [](Request *r) { return r->done || r->k >= r->nsteps; }),
                              sv->active.end());
             std::vector<System *> sys;
             for (Request *r : sv->active) sys.push_back(&r->sys);
@@ -441,6 +501,11 @@ void worker_main(rbsog_server *sv)
                         r->status = RBSOG_EDEVICE;
                         r->done = true;
                     }
+                for (auto &ro : outbox) {
+                    ro.first->status = RBSOG_EDEVICE;
+                    ro.first->done = true;
+                }
+                outbox.clear();
                 sv->active.clear();
                 sv->cv_done.notify_all();
                 break;
@@ -478,6 +543,10 @@ int rbsog_server_create(int32_t precision, int64_t pool_bytes, int32_t max_activ
     if (rc == RBSOG_OK && hipHostMalloc(reinterpret_cast<void **>(&sv->stage), kStageBytes) != hipSuccess) {
         (void)hipGetLastError();  // uploads then come from the requests' own buffers
         sv->stage = nullptr;
+    }
+    if (rc == RBSOG_OK && hipHostMalloc(reinterpret_cast<void **>(&sv->dstage), kStageBytes) != hipSuccess) {
+        (void)hipGetLastError();  // forces then go straight to the requests' own buffers
+        sv->dstage = nullptr;
     }
     if (rc != RBSOG_OK) {
         rbsog::batch_free(sv->batch);
@@ -656,6 +725,7 @@ int rbsog_server_destroy(rbsog_server *sv)
     rbsog::batch_free(sv->batch);
     if (sv->pool_mem) (void)hipFree(sv->pool_mem);
     if (sv->stage) (void)hipHostFree(sv->stage);
+    if (sv->dstage) (void)hipHostFree(sv->dstage);
     delete sv;
     return RBSOG_OK;
 }
