@@ -123,11 +123,16 @@ struct rbsog_server {
     char *pool_mem = nullptr;
     char *stage = nullptr;  // pinned, kStageBytes (null if it could not be allocated)
     size_t stage_used = 0;
-    // pinned, kStageBytes: the forces of requests a tick completes, copied
-    // there behind the step and handed to the requests while the next tick
-    // runs (null if it could not be allocated)
+    // pinned, two slots of kStageBytes (one per tick in flight or being
+    // read): the forces of requests a tick completes, copied there behind the
+    // step and handed to the requests while the next tick runs (null if it
+    // could not be allocated)
     char *dstage = nullptr;
-    size_t dstage_used = 0;
+    // pinned results of the two ticks in flight or being read, and the
+    // events that mark each tick's end
+    rbsog::StepResults *h_tres[2] = {nullptr, nullptr};
+    size_t res_cap[2] = {0, 0};
+    hipEvent_t tick_ev[2] = {nullptr, nullptr};
     Pool pool;
     Batch batch;
     std::mutex mu;
@@ -283,87 +288,126 @@ int tick_launch(rbsog_server *sv, std::string &err)
     return RBSOG_OK;
 }
 
-// Queue the copies of the forces of the requests this step completes: into
-// the pinned download staging while it has room (outbox: handed over after
-// the synchronisation), else into the requests' pageable buffers (finished;
-// such copies may hold the host until the step is done, so they come after
-// everything else the tick queues).
-int copy_forces(rbsog_server *sv, std::vector<Request *> &finished, std::vector<std::pair<Request *, size_t>> &outbox,
-                std::string &err)
+// A launched tick whose results the worker has not read yet.
+struct Tick {
+    std::vector<Request *> reqs;   // batch order: request i's results are slot entry i
+    std::vector<int> steps;        // each request's step index in this tick
+    std::vector<Request *> admitted;  // admitted while it ran, their uploads queued behind it
+    std::vector<Request *> finished;  // completed by it, forces copied into their own buffers
+    std::vector<std::pair<Request *, size_t>> outbox;  // completed by it, forces in its download staging slot
+    int slot = 0;                  // results and download staging slot
+};
+
+// Make reqs the batch and launch their step (each at its own step index).
+int start_tick(rbsog_server *sv, const std::vector<Request *> &reqs, int slot, Tick &t, std::string &err)
 {
-    for (Request *r : sv->active) {
-        if (r->k + 1 < r->nsteps) continue;
+    std::vector<System *> sys;
+    for (Request *r : reqs) sys.push_back(&r->sys);
+    bool same = sv->batch.sys.size() == sys.size();
+    for (size_t i = 0; same && i < sys.size(); ++i) same = sv->batch.sys[i] == sys[i];
+    if (!same) {
+        const int rc = rbsog::batch_set_systems(sv->batch, sys, err);
+        if (rc) return rc;
+    }
+    sv->active = reqs;
+    t = Tick{};
+    t.reqs = reqs;
+    for (Request *r : reqs) t.steps.push_back(r->k);
+    t.slot = slot;
+    return tick_launch(sv, err);
+}
+
+// Queue behind the tick the copies of the forces of the requests it completes
+// (into its pinned download staging slot while that has room, else into the
+// requests' pageable buffers) and of its results, then mark the tick's end.
+int queue_tick_outputs(rbsog_server *sv, Tick &t, std::string &err)
+{
+    char *stage = sv->dstage ? sv->dstage + t.slot * kStageBytes : nullptr;
+    size_t used = 0;
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < t.reqs.size() && e == hipSuccess; ++i) {
+        Request *r = t.reqs[i];
+        if (t.steps[i] + 1 < r->nsteps) continue;
         const int64_t n = r->n;
         const size_t bytes = 3 * n * sizeof(double);
-        if (sv->dstage && sv->dstage_used + bytes <= kStageBytes) {
-            const hipError_t e = hipMemcpyAsync(sv->dstage + sv->dstage_used, r->d_frc, bytes, hipMemcpyDeviceToHost,
-                                                sv->stream);
-            if (e != hipSuccess) {
-                err = std::string("force copy: ") + hipGetErrorString(e);
-                return RBSOG_EDEVICE;
-            }
-            outbox.emplace_back(r, sv->dstage_used);
-            sv->dstage_used += align_up(bytes);
+        if (stage && used + bytes <= kStageBytes) {
+            e = hipMemcpyAsync(stage + used, r->d_frc, bytes, hipMemcpyDeviceToHost, sv->stream);
+            t.outbox.emplace_back(r, used);
+            used += align_up(bytes);
             continue;
         }
         r->fx.resize(n);
         r->fy.resize(n);
         r->fz.resize(n);
-        hipError_t e = hipMemcpyAsync(r->fx.data(), r->d_frc, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
+        e = hipMemcpyAsync(r->fx.data(), r->d_frc, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(r->fy.data(), r->d_frc + n, n * sizeof(double), hipMemcpyDeviceToHost, sv->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(r->fz.data(), r->d_frc + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost,
                                sv->stream);
-        if (e != hipSuccess) {
-            err = std::string("force copy: ") + hipGetErrorString(e);
-            return RBSOG_EDEVICE;
-        }
-        finished.push_back(r);
+        t.finished.push_back(r);
+    }
+    // the slot's last copy ran before the tick that used it was read
+    if (e == hipSuccess && sv->res_cap[t.slot] < t.reqs.size()) {
+        if (sv->h_tres[t.slot]) (void)hipHostFree(sv->h_tres[t.slot]);
+        sv->h_tres[t.slot] = nullptr;
+        sv->res_cap[t.slot] = 0;
+        const size_t cap = std::max<size_t>(2 * t.reqs.size(), 64);
+        e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_tres[t.slot]), cap * sizeof(rbsog::StepResults));
+        if (e == hipSuccess) sv->res_cap[t.slot] = cap;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sv->h_tres[t.slot], sv->batch.d_res, t.reqs.size() * sizeof(rbsog::StepResults),
+                           hipMemcpyDeviceToHost, sv->stream);
+    if (e == hipSuccess) e = hipEventRecord(sv->tick_ev[t.slot], sv->stream);
+    if (e != hipSuccess) {
+        err = std::string("tick outputs: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
     }
     return RBSOG_OK;
 }
 
-// Wait for the step (and everything queued behind it) and record its results.
-int tick_finish(rbsog_server *sv, double &atom_steps, std::string &err)
+// Wait for the tick's end and record its results.
+int record_tick(rbsog_server *sv, const Tick &t, double &atom_steps, std::string &err)
 {
-    Batch &bt = sv->batch;
-    const int rc = rbsog::batch_fetch_results(bt, err);
-    if (rc) return rc;
-    const bool shared = sv->active.size() > 1;
-    for (size_t i = 0; i < sv->active.size(); ++i) {
-        Request *r = sv->active[i];
-        const rbsog::StepResults &res = bt.h_res[i];
+    const hipError_t e = hipEventSynchronize(sv->tick_ev[t.slot]);
+    if (e != hipSuccess) {
+        err = std::string("tick: ") + hipGetErrorString(e);
+        return RBSOG_EDEVICE;
+    }
+    const bool shared = t.reqs.size() > 1;
+    for (size_t i = 0; i < t.reqs.size(); ++i) {
+        Request *r = t.reqs[i];
+        const int k = t.steps[i];
+        const rbsog::StepResults &res = sv->h_tres[t.slot][i];
         if (res.status != 0) {
             err = "sampler found no nonzero initial state";
             return RBSOG_EDEVICE;
         }
-        for (int k = 0; k < 9; ++k) r->P[9 * r->k + k] = res.Ptot[k];
+        for (int c = 0; c < 9; ++c) r->P[9 * k + c] = res.Ptot[c];
         if (sv->energy) {
-            r->U[3 * r->k] = res.UN;
-            r->U[3 * r->k + 1] = res.UF;
-            r->U[3 * r->k + 2] = res.Uself;
+            r->U[3 * k] = res.UN;
+            r->U[3 * k + 1] = res.UF;
+            r->U[3 * k + 2] = res.Uself;
         }
         r->shared_ticks += shared;
         atom_steps += static_cast<double>(r->n);
-        r->k += 1;
     }
     return RBSOG_OK;
 }
 
-// Hand the forces staged by the last tick to their requests (their copies ran
-// before that tick's synchronisation) and complete them.
-void deliver(rbsog_server *sv, std::vector<std::pair<Request *, size_t>> &outbox)
+// Hand forces staged in download slot `slot` to their requests and complete them.
+void deliver(rbsog_server *sv, std::vector<std::pair<Request *, size_t>> &outbox, int slot)
 {
+    if (outbox.empty()) return;
+    const char *stage = sv->dstage + slot * kStageBytes;
     for (auto &[r, off] : outbox) {
-        const double *f = reinterpret_cast<const double *>(sv->dstage + off);
+        const double *f = reinterpret_cast<const double *>(stage + off);
         const int64_t n = r->n;
         r->fx.assign(f, f + n);
         r->fy.assign(f + n, f + 2 * n);
         r->fz.assign(f + 2 * n, f + 3 * n);
     }
-    sv->dstage_used = 0;
-    if (outbox.empty()) return;
     const Clock::time_point t = Clock::now();
     {
         std::lock_guard<std::mutex> lk(sv->mu);
@@ -377,100 +421,117 @@ void deliver(rbsog_server *sv, std::vector<std::pair<Request *, size_t>> &outbox
     sv->cv_done.notify_all();
 }
 
-// Every tick: the requests uploaded during the previous tick join, the step
-// is launched, and while it runs the forces the last tick completed are handed
-// over and the requests that arrived meanwhile are admitted, their uploads
-// queued behind it; one synchronisation then covers the step, its results,
-// the completed requests' force copies and those uploads.  Only when nothing
-// is active does admission wait for nothing else.
+// Ticks are pipelined: while tick k runs, the worker hands over the forces
+// tick k - 1 completed, admits the requests that arrived (their uploads
+// queued behind tick k), queues tick k's force and result copies, and
+// launches tick k + 1 (the requests that continue, at their next step, and
+// the admitted ones) before it waits for tick k's end.  The device thus
+// always has the next tick queued while the host reads the last one.  Only
+// an idle server admits before launching.
 void worker_main(rbsog_server *sv)
 {
     (void)hipSetDevice(sv->device);
     std::string err;
-    std::vector<Request *> ready;  // uploaded and synchronised, joining the next tick
-    std::vector<std::pair<Request *, size_t>> outbox;  // forces in the download staging, not yet handed over
+    Tick cur;              // the tick in flight, when running
+    bool running = false;
+    std::vector<std::pair<Request *, size_t>> handover;  // forces staged by the last read tick
+    int handover_slot = 0, next_slot = 0;
     for (;;) {
-        // no tick follows at once: hand the staged forces over now (only this
-        // thread changes the active list)
-        if (!outbox.empty() && sv->active.empty() && ready.empty()) deliver(sv, outbox);
-        std::vector<Request *> admitted, next, finished;
-        sv->stage_used = 0;  // every copy from the staging area ran before the last synchronisation
-        {
-            std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv_work.wait(lk, [&] {
-                return sv->stop || !sv->pending.empty() || !sv->active.empty() || !ready.empty();
-            });
-            if (sv->stop) {
-                lk.unlock();
-                deliver(sv, outbox);
-                break;
-            }
-            if (sv->active.empty() && ready.empty()) take_admissions(sv, 0, admitted);
-        }
         const Clock::time_point t0 = Clock::now();
         int rc = RBSOG_OK;
-        for (Request *r : admitted)
-            if (rc == RBSOG_OK) rc = admit(sv, r, err);  // stream order puts the uploads before the step
-        const Clock::time_point ta = Clock::now();
-        double launch_s = 0.0, admit2_s = 0.0, wait_s = 0.0, atom_steps = 0.0;
+        double admit_s = 0.0, launch_s = 0.0, wait_s = 0.0, atom_steps = 0.0;
+        std::vector<Request *> admitted;
+        if (!running) {
+            deliver(sv, handover, handover_slot);
+            sv->stage_used = 0;  // nothing is in flight
+            cur = Tick{};
+            {
+                std::unique_lock<std::mutex> lk(sv->mu);
+                sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
+                if (sv->stop) break;
+                take_admissions(sv, 0, admitted);
+            }
+            if (admitted.empty()) continue;  // (an empty pool holds the queue's head)
+            for (Request *r : admitted)
+                if (rc == RBSOG_OK) rc = admit(sv, r, err);  // stream order puts the uploads before the step
+            const Clock::time_point ta = Clock::now();
+            admit_s += std::chrono::duration<double>(ta - t0).count();
+            if (rc == RBSOG_OK) rc = start_tick(sv, admitted, next_slot, cur, err);
+            launch_s += std::chrono::duration<double>(Clock::now() - ta).count();
+            next_slot ^= 1;
+            running = rc == RBSOG_OK;
+        }
+        Tick nxt;
+        bool launched = false;
+        std::vector<Request *> next;
         if (rc == RBSOG_OK) {
-            sv->active.insert(sv->active.end(), ready.begin(), ready.end());
-            sv->active.insert(sv->active.end(), admitted.begin(), admitted.end());
-            std::vector<System *> sys;
-            for (Request *r : sv->active) sys.push_back(&r->sys);
-            if (!ready.empty() || !admitted.empty() || sv->batch.sys.size() != sys.size())
-                rc = rbsog::batch_set_systems(sv->batch, sys, err);
-            ready.clear();
-            if (rc == RBSOG_OK) rc = tick_launch(sv, err);
-            const Clock::time_point tl = Clock::now();
-            launch_s = std::chrono::duration<double>(tl - ta).count();
-            deliver(sv, outbox);  // while the step runs
-            if (rc == RBSOG_OK) {
-                size_t completing = 0;
-                for (Request *r : sv->active) completing += r->k + 1 >= r->nsteps;
-                {
-                    std::lock_guard<std::mutex> lk(sv->mu);
-                    take_admissions(sv, sv->active.size() - completing, next);
+            const Clock::time_point tb = Clock::now();
+            deliver(sv, handover, handover_slot);  // while the tick runs
+            size_t completing = 0;
+            for (size_t i = 0; i < cur.reqs.size(); ++i) completing += cur.steps[i] + 1 >= cur.reqs[i]->nsteps;
+            bool stopping = false;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                stopping = sv->stop;  // finish the tick in flight, launch and admit nothing more
+                if (!stopping) take_admissions(sv, cur.reqs.size() - completing, next);
+            }
+            for (Request *r : next)
+                if (rc == RBSOG_OK) rc = admit(sv, r, err);  // behind the tick in flight
+            // the next step's box, cell grid, normalisation sums and start
+            // bounds of every request that continues (the tick's SysStep is
+            // already in its upload buffer, so the host copy is free to change)
+            for (size_t i = 0; i < cur.reqs.size(); ++i) {
+                Request *r = cur.reqs[i];
+                if (cur.steps[i] + 1 < r->nsteps) {
+                    rbsog::system_set_box(r->sys, &r->boxes[3 * (cur.steps[i] + 1)]);
+                    r->box_step = cur.steps[i] + 1;
                 }
-                for (Request *r : next)
-                    if (rc == RBSOG_OK) rc = admit(sv, r, err);
-                // while the step runs: the next step's box, cell grid,
-                // normalisation sums and start bounds of every request that
-                // continues (this step's SysStep is already in its upload
-                // buffer, so the host copy is free to change)
-                for (Request *r : sv->active)
-                    if (r->k + 1 < r->nsteps) {
-                        rbsog::system_set_box(r->sys, &r->boxes[3 * (r->k + 1)]);
-                        r->box_step = r->k + 1;
-                    }
+            }
+            if (rc == RBSOG_OK) rc = queue_tick_outputs(sv, cur, err);
+            const Clock::time_point tl = Clock::now();
+            admit_s += std::chrono::duration<double>(tl - tb).count();
+            // the next tick: continuing requests at their next step, then the admitted ones
+            std::vector<Request *> reqs;
+            for (size_t i = 0; i < cur.reqs.size(); ++i)
+                if (cur.steps[i] + 1 < cur.reqs[i]->nsteps) {
+                    cur.reqs[i]->k = cur.steps[i] + 1;
+                    reqs.push_back(cur.reqs[i]);
+                }
+            reqs.insert(reqs.end(), next.begin(), next.end());
+            if (rc == RBSOG_OK && !reqs.empty() && !stopping) {
+                rc = start_tick(sv, reqs, next_slot, nxt, err);
+                launched = rc == RBSOG_OK;
             }
             const Clock::time_point tw = Clock::now();
-            admit2_s = std::chrono::duration<double>(tw - tl).count();
-            if (rc == RBSOG_OK) rc = copy_forces(sv, finished, outbox, err);
-            if (rc == RBSOG_OK) rc = tick_finish(sv, atom_steps, err);
+            launch_s += std::chrono::duration<double>(tw - tl).count();
+            if (rc == RBSOG_OK) rc = record_tick(sv, cur, atom_steps, err);
             wait_s = std::chrono::duration<double>(Clock::now() - tw).count();
         }
         const Clock::time_point t1 = Clock::now();
         if (rc == RBSOG_OK) {
+            // the tick's end covers the uploads queued before and behind it
+            // (and every copy out of the upload staging)
+            sv->stage_used = 0;
             uploads_done(admitted, t1);
             uploads_done(next, t1);
-            ready = next;
+            for (Request *r : cur.finished) sv->pool.release(r->off, r->bytes);
+            for (auto &ro : cur.outbox) sv->pool.release(ro.first->off, ro.first->bytes);
         }
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->busy_s += std::chrono::duration<double>(t1 - t0).count();
-        sv->phase_s[0] += std::chrono::duration<double>(ta - t0).count() + admit2_s;
+        sv->phase_s[0] += admit_s;
         sv->phase_s[1] += launch_s;
         sv->phase_s[2] += wait_s;
         sv->atom_steps += atom_steps;
         sv->ticks += 1;
-        sv->peak_active = std::max<int64_t>(sv->peak_active, static_cast<int64_t>(sv->active.size()));
+        sv->peak_active = std::max<int64_t>(sv->peak_active, static_cast<int64_t>(cur.reqs.size()));
         if (rc != RBSOG_OK) {
-            // a failed tick fails every request it held or had admitted; the
-            // worker stops once nothing queued still reads their host copies
+            // a failed tick fails every request it held, launched or had
+            // admitted; the worker stops once nothing queued still reads
+            // their host copies
             (void)hipStreamSynchronize(sv->stream);
-            outbox.clear();  // this tick's requests: failed with the rest below
             sv->worker_err = err;
-            for (const std::vector<Request *> *v : {&sv->active, &ready, &admitted, &next})
+            for (const std::vector<Request *> *v : {&cur.reqs, &nxt.reqs, &admitted, &next})
                 for (Request *r : *v) {
                     r->status = rc;
                     r->done = true;
@@ -479,40 +540,23 @@ void worker_main(rbsog_server *sv)
             sv->cv_done.notify_all();
             break;
         }
-        for (Request *r : finished) {
+        for (Request *r : cur.finished) {
             r->t_done = t1;
             r->done = true;
-            sv->pool.release(r->off, r->bytes);
             sv->completed += 1;
         }
-        // staged forces are in host memory: their device memory is free now
-        for (auto &ro : outbox) sv->pool.release(ro.first->off, ro.first->bytes);
-        if (!finished.empty() || !outbox.empty()) {
-            sv->active.erase(std::remove_if(sv->active.begin(), sv->active.end(),
-                                            [](Request *r) { return r->done || r->k >= r->nsteps; }),
-                             sv->active.end());
-            std::vector<System *> sys;
-            for (Request *r : sv->active) sys.push_back(&r->sys);
-            std::string e2;
-            if (rbsog::batch_set_systems(sv->batch, sys, e2) != RBSOG_OK) {
-                sv->worker_err = e2;
-                for (const std::vector<Request *> *v : {&sv->active, &ready})
-                    for (Request *r : *v) {
-                        r->status = RBSOG_EDEVICE;
-                        r->done = true;
-                    }
-                for (auto &ro : outbox) {
-                    ro.first->status = RBSOG_EDEVICE;
-                    ro.first->done = true;
-                }
-                outbox.clear();
-                sv->active.clear();
-                sv->cv_done.notify_all();
-                break;
-            }
-            sv->cv_done.notify_all();
+        if (!cur.finished.empty()) sv->cv_done.notify_all();
+        handover.swap(cur.outbox);  // handed over while the next tick runs, or before waiting for work
+        handover_slot = cur.slot;
+        if (launched) {
+            cur = std::move(nxt);
+            next_slot ^= 1;
+        } else {
+            sv->active.clear();
         }
+        running = launched;
     }
+    deliver(sv, handover, handover_slot);
 }
 
 }  // namespace
@@ -544,10 +588,12 @@ int rbsog_server_create(int32_t precision, int64_t pool_bytes, int32_t max_activ
         (void)hipGetLastError();  // uploads then come from the requests' own buffers
         sv->stage = nullptr;
     }
-    if (rc == RBSOG_OK && hipHostMalloc(reinterpret_cast<void **>(&sv->dstage), kStageBytes) != hipSuccess) {
+    if (rc == RBSOG_OK && hipHostMalloc(reinterpret_cast<void **>(&sv->dstage), 2 * kStageBytes) != hipSuccess) {
         (void)hipGetLastError();  // forces then go straight to the requests' own buffers
         sv->dstage = nullptr;
     }
+    for (hipEvent_t &e : sv->tick_ev)
+        if (rc == RBSOG_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = RBSOG_EDEVICE;
     if (rc != RBSOG_OK) {
         rbsog::batch_free(sv->batch);
         delete sv;
@@ -726,6 +772,10 @@ int rbsog_server_destroy(rbsog_server *sv)
     if (sv->pool_mem) (void)hipFree(sv->pool_mem);
     if (sv->stage) (void)hipHostFree(sv->stage);
     if (sv->dstage) (void)hipHostFree(sv->dstage);
+    for (int k = 0; k < 2; ++k) {
+        if (sv->h_tres[k]) (void)hipHostFree(sv->h_tres[k]);
+        if (sv->tick_ev[k]) (void)hipEventDestroy(sv->tick_ev[k]);
+    }
     delete sv;
     return RBSOG_OK;
 }
