@@ -647,8 +647,9 @@ int rbsog_server_wait(rbsog_server *s, int64_t ticket, double timeout_s, double 
  * host_stats[11]: requests submitted, completed, ticks run, atom-steps done,
  * seconds the worker spent in ticks, peak active requests, peak pool bytes
  * in use, requests waiting now, and the ticks' seconds split three ways:
- * uploading admitted requests, setting up and launching the batched steps,
- * waiting for their results and the completed requests' forces.
+ * handing over completed requests' forces, admitting and uploading requests
+ * and queuing a tick's copies (while a tick runs); setting up and launching
+ * the batched steps; waiting for a tick's end.
  */
 int rbsog_server_stats(rbsog_server *s, double *host_stats);
 
