@@ -125,6 +125,11 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.rbsog_pressure(None, None, None) == -1
     assert lib.rbsog_destroy(None) == 0
     assert lib.rbsog_last_error(None) == b"null context"
+    assert lib.rbsog_step(None, 0, None, None, None, None, None, None, None, None, None, None) == -1
+    t = C.c_int64(-1)
+    assert lib.rbsog_step_async(None, 0, None, None, None, None, None, None, None, None, 0, C.byref(t)) == -1
+    assert t.value == -1
+    assert lib.rbsog_step_wait(None, 0, None, None) == -1
 
 
 def test_binding_fails_loudly_without_the_library(tmp_path):
