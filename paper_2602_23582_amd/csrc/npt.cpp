@@ -172,9 +172,10 @@ int evaluate(rbsog_ctx *c, const double *x, const double *y, const double *z, co
 {
     const int64_t n = c->sys.n;
     double *F = c->npt.d_F;
-    NPT_TRY(rbsog_sample_modes(c, step, L, nullptr, nullptr, nullptr));
-    NPT_TRY(rbsog_force_virial(c, x, y, z, F, F + n, F + 2 * n, nullptr, nullptr));
-    return rbsog_pressure(c, P, nullptr);
+    // sampling, forces and pressure in one call (no rescale: x, y, z are only read)
+    double box[3] = {L[0], L[1], L[2]};
+    return rbsog_step(c, step, nullptr, box, const_cast<double *>(x), const_cast<double *>(y), const_cast<double *>(z),
+                      F, F + n, F + 2 * n, P, nullptr);
 }
 
 // kinetic tensor sum p p^T / m (row-major 3x3)
