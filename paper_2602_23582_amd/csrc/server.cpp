@@ -292,7 +292,6 @@ int tick_launch(rbsog_server *sv, std::string &err)
 struct Tick {
     std::vector<Request *> reqs;   // batch order: request i's results are slot entry i
     std::vector<int> steps;        // each request's step index in this tick
-    std::vector<Request *> admitted;  // admitted while it ran, their uploads queued behind it
     std::vector<Request *> finished;  // completed by it, forces copied into their own buffers
     std::vector<std::pair<Request *, size_t>> outbox;  // completed by it, forces in its download staging slot
     int slot = 0;                  // results and download staging slot
