@@ -840,6 +840,10 @@ static int build_plans(Batch &b, std::string &err)
     }
     if (total > b.cap_plan) {
         const int64_t cap = std::max<int64_t>(total, 2 * b.cap_plan);
+        // a step still queued (a queued context step, a pipelined served
+        // tick) may read the old plans: let both streams drain first
+        (void)hipStreamSynchronize(b.aux);
+        (void)hipStreamSynchronize(b.stream);
         if (b.d_plan) (void)hipFree(b.d_plan);
         if (b.h_plan) (void)hipHostFree(b.h_plan);
         b.d_plan = nullptr;
