@@ -1760,14 +1760,15 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
         auto walk = [&](auto rel_tag) {
             constexpr bool kRel = decltype(rel_tag)::value;
             int w = 0;
-            int wb = 1;  // the relative tile's slot of candidate 32 w
+            // byte offset in the relative tile of candidate 32 w (slot 33 w + 1)
+            int wb = static_cast<int>(sizeof(float4));
             uint32_t cur = words > 0 ? sh.mask[0][lane] : 0u;
             for (;;) {
                 bool adv = (cur == 0u) & (w + 1 < words);
                 while (__any(adv)) {
                     if (adv) {
                         ++w;
-                        wb += 33;
+                        wb += 33 * static_cast<int>(sizeof(float4));
                         cur = sh.mask[w][lane];
                     }
                     adv = (cur == 0u) & (w + 1 < words);
@@ -1785,7 +1786,9 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
                     cur &= ~(0x80000000u >> (k1 & 31));
                     // FP32 block-relative coordinates: the difference of two exact
                     // minimum-image offsets from o, each rounded once to FP32
-                    const float4 t0 = sh.rtile[wb + k0], t1 = sh.rtile[wb + k1];
+                    const char *tb = reinterpret_cast<const char *>(sh.rtile) + wb;
+                    const float4 t0 = *reinterpret_cast<const float4 *>(tb + k0 * static_cast<int>(sizeof(float4)));
+                    const float4 t1 = *reinterpret_cast<const float4 *>(tb + k1 * static_cast<int>(sizeof(float4)));
                     uint64_t in0, in1;
                     pair_eval_d<T, M, E, false>(xi - t0.x, yi - t0.y, zi - t0.z, t0.w, true, rc2, W, acc, &in0);
                     pair_eval_d<T, M, E, false>(xi - t1.x, yi - t1.y, zi - t1.z, t1.w, true, rc2, W, acc, &in1);
