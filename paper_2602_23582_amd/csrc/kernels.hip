@@ -1765,13 +1765,15 @@ __device__ __forceinline__ void pair_block(PairShared<T> &sh, const SysDesc &D, 
             uint32_t cur = words > 0 ? sh.mask[0][lane] : 0u;
             for (;;) {
                 bool adv = (cur == 0u) & (w + 1 < words);
-                while (__any(adv)) {
-                    if (adv) {
-                        ++w;
-                        wb += 33 * static_cast<int>(sizeof(float4));
-                        cur = sh.mask[w][lane];
-                    }
-                    adv = (cur == 0u) & (w + 1 < words);
+                if (__any(adv)) {  // a lane's word is spent and it has more: the rarer case
+                    do {
+                        if (adv) {
+                            ++w;
+                            wb += 33 * static_cast<int>(sizeof(float4));
+                            cur = sh.mask[w][lane];
+                        }
+                        adv = (cur == 0u) & (w + 1 < words);
+                    } while (__any(adv));
                 }
                 if (!__any(cur != 0u)) break;
                 if constexpr (kRel) {
